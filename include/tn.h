@@ -1,0 +1,283 @@
+/*
+ * tn.h - C ABI of the MI355X (gfx950) temporal component-matrix library.
+ *
+ * The library computes, for a temporal network of n nodes and m events
+ * (u, v, t), the component matrix of Sec. 3 of "Temporal network compression
+ * via network hashing": bit (u, w) is 1 iff node w is reachable from node u by
+ * a time-respecting path (Sec. 2.1).  The matrix is built by streaming the
+ * events in reverse chronological order (Sec. 3.4), each event OR-ing one
+ * bit-packed row into another (Algorithm 1's update), so that row u is the
+ * maximum out-component of u and column w the in-component of w.  On top of
+ * it sit the hashing framework of Sec. 4 (H hashed proxy networks of K
+ * super-nodes, built in one batched launch, Sec. 4.1 and 4.3) and the fusion
+ * estimator of Sec. 4.2, plus a learned combiner (a small MLP) that maps the
+ * H per-hash lifted sizes to a size estimate.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: tn_status, 0 on success, a negative code otherwise; the
+ *   thread-local message of the last failure is tn_last_error().  Arguments
+ *   are validated on the host before any device work is enqueued; on error
+ *   nothing is enqueued and no output is touched.
+ * - Memory: pointers documented HOST are ordinary host memory, borrowed for
+ *   the duration of the call.  Pointers documented DEVICE are device memory
+ *   on the context's device, owned by the caller and never freed by the
+ *   library.  The context owns all scratch memory it allocates.
+ * - Ordering: device work is enqueued on the context's stream (tn_create /
+ *   tn_set_stream) and is asynchronous unless stated otherwise;
+ *   tn_sync() waits for it and reports a device-side error.
+ * - Bit layout: a bit matrix of R rows is R rows of ld uint64 words,
+ *   row-major; node w is bit (w & 63) of word (w >> 6); ld >= ceil(n/64);
+ *   every bit at a column >= n, and every word beyond ceil(n/64), is 0 in
+ *   every output.
+ * - Events: src/dst uint32 node ids < n; t int64 integer time steps
+ *   (Sec. 2.1), non-decreasing (the time-ordered list of Algorithm 1).
+ *   Unless TN_TIES_SEQUENTIAL is set, events at the same time step are not
+ *   adjacent (Sec. 2.1): information crosses at most one event per time
+ *   step.  Self-loops are no-ops; repeated events are idempotent.
+ * - Determinism: every integer output is bit-exact and independent of launch
+ *   configuration; MLP outputs are deterministic for a given input.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tn_status;
+enum {
+    TN_OK = 0,
+    TN_E_ARG = -1,         /* bad size, null pointer, ld too small, ...      */
+    TN_E_RANGE = -2,       /* a node id >= n                                 */
+    TN_E_ORDER = -3,       /* event times decrease                           */
+    TN_E_NOMEM = -4,       /* host or device allocation failed               */
+    TN_E_HIP = -5,         /* a HIP runtime call failed                      */
+    TN_E_UNSUPPORTED = -6  /* outside the supported sizes                    */
+};
+
+/* Event flags. */
+enum {
+    TN_DIRECTED = 1u,        /* event (u, v, t) carries information u -> v only
+                                (the non-mutual sharing of the footnote in Sec. 3) */
+    TN_TIES_SEQUENTIAL = 2u  /* list order is strict time order: Algorithm 1 read
+                                literally, events at one time step chain          */
+};
+
+typedef struct tn_ctx tn_ctx;     /* device, stream, scratch, autotune cache   */
+typedef struct tn_plan tn_plan;   /* one network's device-resident schedule    */
+typedef struct tn_batch tn_batch; /* many networks' schedules, one launch      */
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Thread-local text of the last error (never NULL). */
+const char *tn_last_error(void);
+
+/* Creates a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the null stream).  *out receives the context. */
+tn_status tn_create(int device, void *stream, tn_ctx **out);
+
+/* Changes the stream subsequent calls enqueue on. */
+tn_status tn_set_stream(tn_ctx *ctx, void *stream);
+
+/* Waits for the context's stream; reports a device error as TN_E_HIP. */
+tn_status tn_sync(tn_ctx *ctx);
+
+/* Frees the context's scratch memory.  Plans and batches must be destroyed
+ * first.  NULL is ignored. */
+void tn_destroy(tn_ctx *ctx);
+
+/* Kernel timing on the context's stream.  While enabled, every kernel the
+ * context launches is bracketed by two HIP events recorded on its stream.
+ * tn_profile_take waits for the stream, writes up to `cap` records (kernel
+ * id, milliseconds) in launch order to HOST arrays ids / ms, clears all
+ * records and returns how many it wrote (or a negative tn_status). */
+enum {
+    TN_K_IDENTITY = 1,     /* C <- I                                        */
+    TN_K_ROWOR = 2,        /* the level-by-level row-OR stream              */
+    TN_K_OUT_SIZES = 3,    /* row popcounts                                 */
+    TN_K_IN_SIZES = 4,     /* column popcounts                              */
+    TN_K_BATCH = 5,        /* persistent multi-network row-OR               */
+    TN_K_HASH = 6,         /* bucket map and bucket counts                  */
+    TN_K_RECOMBINE = 7,    /* fusion of the hashed proxies                  */
+    TN_K_MLP_FORWARD = 8,
+    TN_K_MLP_BACKWARD = 9,
+    TN_K_MLP_ADAM = 10,
+    TN_K_AUX = 11          /* small fills, features, reductions             */
+};
+tn_status tn_profile_enable(tn_ctx *ctx, int enable);
+int32_t tn_profile_take(tn_ctx *ctx, int32_t *ids, float *ms, int32_t cap);
+
+/* ---- exact component matrix (Sec. 3, Algorithm 1, reverse time Sec. 3.4) */
+
+/* Plans the reverse-time stream of one network on the host: groups the events
+ * of each time step into independent items (two-node pairs, or compound
+ * groups where a node meets several others at one time step, which must read
+ * every old row before writing any), and assigns each item the earliest
+ * level after every earlier item (in reverse time) that shares a node, so
+ * the items of one level touch disjoint rows.  The schedule is copied to the
+ * device (synchronously) and kept in the plan.
+ * src, dst, t: HOST, m entries.  flags: TN_DIRECTED | TN_TIES_SEQUENTIAL.
+ * Errors: TN_E_ARG (n == 0, null arrays with m > 0, bad flags),
+ * TN_E_RANGE, TN_E_ORDER, TN_E_UNSUPPORTED (m >= 2^32 or n >= 2^31). */
+tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m,
+                         const uint32_t *src, const uint32_t *dst,
+                         const int64_t *t, uint32_t flags, tn_plan **out);
+
+typedef struct tn_plan_stats {
+    uint32_t n;
+    int64_t m;
+    int64_t levels;          /* dependency levels of the schedule          */
+    int64_t pairs;           /* two-node items                             */
+    int64_t gathers;         /* rows written by compound items             */
+    int64_t gather_sources;  /* rows read by compound items                */
+    int64_t compound_items;  /* time-step groups of >= 3 nodes             */
+    int64_t max_level_items; /* widest level (pairs + gathers)             */
+    int64_t max_level_gathers;
+    int64_t device_bytes;    /* size of the device-resident schedule       */
+    double host_seconds;     /* planning time on the host                  */
+    int64_t directed_pairs;  /* pairs that update one row only             */
+} tn_plan_stats;
+
+tn_status tn_plan_get_stats(const tn_plan *plan, tn_plan_stats *out);
+
+/* Host-only form of the planning step (no device needed): builds the same
+ * level schedule tn_plan_create uploads and exposes it for inspection.
+ * Level l (0-based, l < levels) owns pair items [lvl_pair[l], lvl_pair[l+1])
+ * of `pairs` (2 uint32 each: u, then v with bit 31 set for a one-way
+ * directed pair that only updates row u) and gathers [lvl_gat[l],
+ * lvl_gat[l+1]); gather g writes row gat_tgt[g] with the OR of rows
+ * gat_src[gat_ptr[g] .. gat_ptr[g+1]) as they were before the level.
+ * The arrays are owned by the schedule and valid until its destruction. */
+typedef struct tn_host_schedule tn_host_schedule;
+tn_status tn_schedule_build(uint32_t n, int64_t m, const uint32_t *src,
+                            const uint32_t *dst, const int64_t *t,
+                            uint32_t flags, tn_host_schedule **out);
+tn_status tn_schedule_arrays(const tn_host_schedule *s, tn_plan_stats *stats,
+                             const uint32_t **lvl_pair, const uint32_t **lvl_gat,
+                             const uint32_t **pairs, const uint32_t **gat_tgt,
+                             const uint32_t **gat_ptr, const uint32_t **gat_src);
+void tn_schedule_destroy(tn_host_schedule *s);
+
+/* Destroys a plan (frees its device schedule).  NULL is ignored. */
+void tn_plan_destroy(tn_plan *plan);
+
+/* Runs a plan: C <- I_n, then every level of row ORs in order.
+ * C: DEVICE, n x ld uint64, written entirely (including padding words).
+ * slice_words: words of every row one workgroup owns (0 = tuned default);
+ * any value gives the same bits.  Errors: TN_E_ARG (ld < ceil(n/64)). */
+tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C,
+                          int64_t ld, uint32_t slice_words);
+
+/* One call: plan, execute, destroy.  Inputs HOST, C DEVICE as above. */
+tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m,
+                                    const uint32_t *src, const uint32_t *dst,
+                                    const int64_t *t, uint32_t flags,
+                                    uint64_t *C, int64_t ld);
+
+/* Component sizes (Sec. 3.1, Eq. 1): out_sizes[u] = ones in row u (the
+ * maximum out-component size of u), in_sizes[w] = ones in column w (the
+ * in-component size of w).  C: DEVICE n x ld.  out_sizes, in_sizes: DEVICE
+ * int32[n], either may be NULL.  Padding bits of C must be 0. */
+tn_status tn_component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C,
+                             int64_t ld, int32_t *out_sizes, int32_t *in_sizes);
+
+/* ---- many networks in one persistent launch ---------------------------- */
+
+/* Plans B networks (host threads) and uploads their schedules.  Arrays of B
+ * entries: n[b], m[b], and HOST pointers src[b], dst[b], t[b] as in
+ * tn_plan_create.  Errors as tn_plan_create, for the first failing b. */
+tn_status tn_batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n,
+                          const int64_t *m, const uint32_t *const *src,
+                          const uint32_t *const *dst, const int64_t *const *t,
+                          uint32_t flags, tn_batch **out);
+
+/* Builds all B component matrices in one persistent launch: workgroups take
+ * (network, column slice) tiles from a device work queue, largest first,
+ * keep the slice in LDS when it fits, and write it back to C[b].  The first
+ * call tunes the tile shape on the device and captures the launch in a HIP
+ * graph; later calls with the same C / ld replay it.  C: HOST array of B
+ * DEVICE pointers, ld: HOST array of B leading dimensions. */
+tn_status tn_batch_execute(tn_ctx *ctx, tn_batch *batch, uint64_t *const *C,
+                           const int64_t *ld);
+
+/* Per-batch statistics: total levels, pairs, tiles and the chosen shape.
+ * stats: HOST array of B entries, or NULL.  tiles, lds_tiles may be NULL. */
+tn_status tn_batch_get_stats(const tn_batch *batch, tn_plan_stats *stats,
+                             int64_t *tiles, int64_t *lds_tiles);
+
+void tn_batch_destroy(tn_batch *batch);
+
+/* One call: batch create, execute, destroy. */
+tn_status tn_build_component_matrix_batched(tn_ctx *ctx, int32_t B,
+                                            const uint32_t *n, const int64_t *m,
+                                            const uint32_t *const *src,
+                                            const uint32_t *const *dst,
+                                            const int64_t *const *t,
+                                            uint32_t flags, uint64_t *const *C,
+                                            const int64_t *ld);
+
+/* ---- hashing framework (Sec. 4) ----------------------------------------- */
+
+/* Network hashing (Sec. 4.1): H independent hash functions map the n nodes
+ * to K super-nodes, h_j(u) = (acc_0(x0) ^ acc_1(x1) ^ acc_2(x2)) mod K with
+ * x0 / x1 the low / high 32 bits of u, x2 = x0 + x1, and acc_i a polynomial
+ * of `order` coefficients evaluated by repeated (x * acc + a) mod (2^61 - 1).
+ * coeffs: HOST, H x 3 x order uint64, each < 2^61 - 1 (the random table A).
+ * Writes bucket[j*n + u] = h_j(u) (DEVICE uint32[H*n]) and
+ * count[j*K + r] = |h_j^{-1}(r)| (DEVICE int32[H*K]), then plans the H
+ * hashed networks (super-events (h_j(u), h_j(v), t)) as one batch, returned
+ * in *proxies; build them with tn_batch_execute into H matrices of K rows.
+ * src, dst, t: HOST events as in tn_plan_create.
+ * Errors: TN_E_ARG (H == 0, K == 0, order < 1), TN_E_UNSUPPORTED
+ * (K > 65536), TN_E_RANGE, TN_E_ORDER. */
+tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m,
+                           const uint32_t *src, const uint32_t *dst,
+                           const int64_t *t, uint32_t flags, uint32_t H,
+                           uint32_t K, const uint64_t *coeffs, int32_t order,
+                           uint32_t *bucket, int32_t *count,
+                           tn_batch **proxies);
+
+/* Fusion (Sec. 4.2, Eqs. DefInvHComp and DefEstOCMerge):
+ * est[u] = |{w < n : P_j[h_j(u)][h_j(w)] = 1 for every j < H}|, the size of
+ * the estimated out-component (a superset of the true one), and, if lifted
+ * is not NULL, lifted[j*n + u] = |h_j^{-1}(OC_j(h_j(u)))| =
+ * sum of count[j][r] over the super-nodes r in row h_j(u) of P_j.
+ * P: DEVICE, H matrices of K rows x ldK words, matrix j at P + j*K*ldK.
+ * bucket, count: DEVICE as written by tn_hash_compress.
+ * est: DEVICE int32[n].  lifted: DEVICE int32[H*n] or NULL. */
+tn_status tn_recombine(tn_ctx *ctx, uint32_t n, uint32_t H, uint32_t K,
+                       const uint64_t *P, int64_t ldK, const uint32_t *bucket,
+                       const int32_t *count, int32_t *est, int32_t *lifted);
+
+/* ---- learned combiner (a 16 -> 64 -> 64 -> 1 ReLU MLP, FP32) ------------ */
+
+/* Number of float parameters: per layer W (out x in, row-major) then b. */
+int32_t tn_mlp_param_count(void);
+
+/* Features x[u*H + j] = ln(lifted[j*n + u] / n) as float.  lifted: DEVICE
+ * int32[H*n]; x: DEVICE float[n*H].  H must be 16. */
+tn_status tn_mlp_features(tn_ctx *ctx, uint32_t n, uint32_t H,
+                          const int32_t *lifted, float *x);
+
+/* yhat[i] = MLP(x[i*16 .. i*16+15]).  params, x, yhat: DEVICE. */
+tn_status tn_mlp_forward(tn_ctx *ctx, const float *params, const float *x,
+                         int64_t N, float *yhat);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, 1-based
+ * step) on the mean squared error over the N samples (x, y).
+ * params, adam_m, adam_v: DEVICE float[tn_mlp_param_count()], updated in
+ * place.  loss: DEVICE float[1] or NULL, receives the loss before the step.
+ * grad: DEVICE float[param count] or NULL, receives the gradient. */
+tn_status tn_mlp_train_step(tn_ctx *ctx, float *params, float *adam_m,
+                            float *adam_v, int64_t step, const float *x,
+                            const float *y, int64_t N, float lr, float *loss,
+                            float *grad);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H */

@@ -1,0 +1,198 @@
+"""Python binding of the C ABI: host arrays are numpy, device buffers are torch
+tensors on a HIP device, the stream is torch's current stream.  Argument
+marshalling only; every step of the computation runs in the library."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import DIRECTED, KERNELS, TIES_SEQUENTIAL, PlanStats, TNError, check, lib
+
+__all__ = ["Context", "Plan", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+           "build_component_matrix", "component_sizes", "get_context"]
+
+
+def words(n: int) -> int:
+    return (int(n) + 63) // 64
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hp(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def _dp(t: torch.Tensor | None):
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("device buffer expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous device buffer expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context on one device, enqueuing on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        check(lib.tn_create(self.device, ctypes.c_void_p(self._stream()), ctypes.byref(h)))
+        self.h = h
+
+    def _stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def bind_stream(self):
+        """Points the context at torch's current stream (call before enqueuing)."""
+        check(lib.tn_set_stream(self.h, ctypes.c_void_p(self._stream())))
+        return self.h
+
+    def sync(self):
+        check(lib.tn_sync(self.h))
+
+    def profile(self, enable: bool = True):
+        """Times every kernel this context launches with HIP events on its stream."""
+        check(lib.tn_profile_enable(self.h, int(bool(enable))))
+
+    def profile_take(self, cap: int = 1 << 16):
+        """[(kernel name, ms)] in launch order since the last take (waits for the stream)."""
+        ids = np.zeros(cap, dtype=np.int32)
+        ms = np.zeros(cap, dtype=np.float32)
+        k = lib.tn_profile_take(self.h, _hp(ids), _hp(ms), cap)
+        if k < 0:
+            check(k)
+        return [(KERNELS.get(int(i), str(int(i))), float(x)) for i, x in zip(ids[:k], ms[:k])]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict[int, Context] = {}
+
+
+def get_context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    c = _contexts.get(device)
+    if c is None:
+        c = _contexts[device] = Context(device)
+    return c
+
+
+def _events(src, dst, t):
+    src, dst, t = _host(src, np.uint32), _host(dst, np.uint32), _host(t, np.int64)
+    if not (src.shape == dst.shape == t.shape) or src.ndim != 1:
+        raise ValueError("src, dst, t must be 1-D arrays of one length")
+    return src, dst, t
+
+
+def alloc_matrix(n: int, ld: int | None = None, device: int | None = None, rows: int | None = None):
+    if device is None:
+        device = torch.cuda.current_device()
+    if ld is None:
+        ld = words(n)
+    return torch.empty((n if rows is None else rows, ld), dtype=torch.int64,
+                       device=f"cuda:{device}")
+
+
+class Plan:
+    """The device-resident level schedule of one network (tn_plan_create)."""
+
+    def __init__(self, n: int, src, dst, t, flags: int = 0, ctx: Context | None = None):
+        self.ctx = ctx or get_context()
+        self.n = int(n)
+        src, dst, t = _events(src, dst, t)
+        h = ctypes.c_void_p()
+        check(lib.tn_plan_create(self.ctx.bind_stream(), self.n, src.shape[0], _hp(src),
+                                 _hp(dst), _hp(t), int(flags), ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def stats(self) -> dict:
+        s = PlanStats()
+        check(lib.tn_plan_get_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def execute(self, C: torch.Tensor | None = None, slice_words: int = 0) -> torch.Tensor:
+        if C is None:
+            C = alloc_matrix(self.n, device=self.ctx.device)
+        if C.dtype != torch.int64 or C.dim() != 2 or C.shape[0] != self.n:
+            raise ValueError("C must be an int64 (n, ld) device tensor")
+        check(lib.tn_plan_execute(self.ctx.bind_stream(), self.h, _dp(C), C.stride(0),
+                                  int(slice_words)))
+        return C
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tn_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_component_matrix(n: int, src, dst, t, flags: int = 0, C: torch.Tensor | None = None,
+                           ctx: Context | None = None) -> torch.Tensor:
+    """Reverse-time component matrix: row u = out-component of u (int64 view of uint64 words)."""
+    ctx = ctx or get_context()
+    src, dst, t = _events(src, dst, t)
+    if C is None:
+        C = alloc_matrix(n, device=ctx.device)
+    check(lib.tn_build_component_matrix(ctx.bind_stream(), int(n), src.shape[0], _hp(src),
+                                        _hp(dst), _hp(t), int(flags), _dp(C), C.stride(0)))
+    return C
+
+
+def component_sizes(C: torch.Tensor, n: int, out: bool = True, inn: bool = True,
+                    ctx: Context | None = None):
+    """(out_sizes, in_sizes) int32 device tensors (None where not asked for)."""
+    ctx = ctx or get_context()
+    o = torch.empty(n, dtype=torch.int32, device=C.device) if out else None
+    i = torch.empty(n, dtype=torch.int32, device=C.device) if inn else None
+    check(lib.tn_component_sizes(ctx.bind_stream(), int(n), _dp(C), C.stride(0), _dp(o), _dp(i)))
+    return o, i
+
+
+def host_schedule(n: int, src, dst, t, flags: int = 0) -> dict:
+    """The level schedule the planner builds (host only, no device), as numpy arrays."""
+    src, dst, t = _events(src, dst, t)
+    h = ctypes.c_void_p()
+    check(lib.tn_schedule_build(int(n), src.shape[0], _hp(src), _hp(dst), _hp(t), int(flags),
+                                ctypes.byref(h)))
+    try:
+        st = PlanStats()
+        ptrs = [ctypes.c_void_p() for _ in range(6)]
+        check(lib.tn_schedule_arrays(h, ctypes.byref(st), *[ctypes.byref(p) for p in ptrs]))
+        L, P, G = st.levels, st.pairs, st.gathers
+
+        def arr(p, k):
+            if k == 0 or not p.value:
+                return np.zeros(0, dtype=np.uint32)
+            return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint32)),
+                                         shape=(k,)).copy()
+        lvl_pair = arr(ptrs[0], L + 1)
+        lvl_gat = arr(ptrs[1], L + 1)
+        gat_ptr = arr(ptrs[4], G + 1)
+        out = dict(stats=st.as_dict(), lvl_pair=lvl_pair, lvl_gat=lvl_gat,
+                   pairs=arr(ptrs[2], 2 * P).reshape(P, 2), gat_tgt=arr(ptrs[3], G),
+                   gat_ptr=gat_ptr, gat_src=arr(ptrs[5], int(gat_ptr[-1]) if G else 0))
+    finally:
+        lib.tn_schedule_destroy(h)
+    return out

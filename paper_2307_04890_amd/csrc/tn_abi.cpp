@@ -1,0 +1,368 @@
+// C ABI: context, plans, validation and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "tn_internal.h"
+
+namespace {
+thread_local std::string g_err;
+
+tn_status fail(tn_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+tn_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return TN_E_HIP;
+}
+
+// Makes the context's device current for the scope of an entry point.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+struct tn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    // kernel timing (tn_profile_enable)
+    bool profiling = false;
+    struct Rec {
+        int32_t id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace tn {
+// Brackets one kernel launch with events on the context's stream when
+// profiling is on.
+struct ProfScope {
+    tn_ctx *c;
+    size_t idx = (size_t)-1;
+    ProfScope(tn_ctx *ctx, int32_t id) : c(ctx) {
+        if (!c->profiling) return;
+        hipEvent_t ev[2];
+        for (int i = 0; i < 2; ++i) {
+            if (!c->pool.empty()) {
+                ev[i] = c->pool.back();
+                c->pool.pop_back();
+            } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+                for (int k = 0; k < i; ++k) c->pool.push_back(ev[k]);
+                return;
+            }
+        }
+        (void)hipEventRecord(ev[0], c->stream);
+        c->recs.push_back({id, ev[0], ev[1]});
+        idx = c->recs.size() - 1;
+    }
+    ~ProfScope() {
+        if (idx != (size_t)-1) (void)hipEventRecord(c->recs[idx].b, c->stream);
+    }
+};
+}  // namespace tn
+
+struct tn_plan {
+    int device = 0;
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    tn::DevSchedule view{};
+    tn_plan_stats stats{};
+};
+
+namespace tn {
+tn_status not_built(const char *what) {
+    return fail(TN_E_UNSUPPORTED, std::string(what) + " is not built in this library version");
+}
+
+// Grows the context scratch to at least `bytes` (waits for the stream first,
+// since queued kernels may still use the old buffer).
+tn_status ensure_scratch(tn_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->scratch_bytes) return TN_OK;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    e = hipMalloc(&ctx->scratch, want);
+    if (e != hipSuccess) {
+        ctx->scratch = nullptr;
+        return fail(TN_E_NOMEM, "scratch allocation of " + std::to_string(want) + " bytes failed");
+    }
+    ctx->scratch_bytes = want;
+    return TN_OK;
+}
+}  // namespace tn
+
+namespace {
+void fill_stats(const tn::HostSchedule &hs, tn_plan_stats &s);
+}
+
+extern "C" {
+
+const char *tn_last_error(void) { return g_err.c_str(); }
+
+tn_status tn_create(int device, void *stream, tn_ctx **out) {
+    if (!out) return fail(TN_E_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(TN_E_ARG, "no such device");
+    tn_ctx *c = new (std::nothrow) tn_ctx();
+    if (!c) return fail(TN_E_NOMEM, "context allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return TN_OK;
+}
+
+tn_status tn_set_stream(tn_ctx *ctx, void *stream) {
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+    return TN_OK;
+}
+
+tn_status tn_sync(tn_ctx *ctx) {
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return TN_OK;
+}
+
+void tn_destroy(tn_ctx *ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    for (auto &r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+tn_status tn_profile_enable(tn_ctx *ctx, int enable) {
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    ctx->profiling = enable != 0;
+    return TN_OK;
+}
+
+int32_t tn_profile_take(tn_ctx *ctx, int32_t *ids, float *ms, int32_t cap) {
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    if (cap < 0 || (cap > 0 && (!ids || !ms))) return fail(TN_E_ARG, "bad output arrays");
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int32_t k = 0;
+    for (auto &r : ctx->recs) {
+        if (k < cap) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, r.a, r.b);
+            ids[k] = r.id;
+            ms[k] = (e == hipSuccess) ? t : -1.f;
+            ++k;
+        }
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    return k;
+}
+
+tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
+                         const uint32_t *dst, const int64_t *t, uint32_t flags,
+                         tn_plan **out) {
+    if (!ctx || !out) return fail(TN_E_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    tn::HostSchedule hs;
+    std::string err;
+    tn_status st = tn::plan_events(n, m, src, dst, t, flags, hs, err);
+    if (st != TN_OK) return fail(st, err);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    tn_plan *p = new (std::nothrow) tn_plan();
+    if (!p) return fail(TN_E_NOMEM, "plan allocation failed");
+    p->device = ctx->device;
+    std::vector<unsigned char> img;
+    tn::schedule_pack(hs, img);
+    p->dev_bytes = img.size();
+    hipError_t e = hipMalloc(&p->dev, p->dev_bytes);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(TN_E_NOMEM, "device schedule allocation failed");
+    }
+    e = hipMemcpyAsync(p->dev, img.data(), img.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(p->dev);
+        delete p;
+        return hip_fail(e, "schedule upload");
+    }
+    p->view = tn::schedule_view(hs, p->dev);
+    fill_stats(hs, p->stats);
+    *out = p;
+    return TN_OK;
+}
+
+namespace {
+void fill_stats(const tn::HostSchedule &hs, tn_plan_stats &s) {
+    s.n = hs.n;
+    s.m = hs.m;
+    s.levels = hs.L;
+    s.pairs = (int64_t)hs.pairs.size() / 2;
+    s.gathers = (int64_t)hs.gat_tgt.size();
+    s.gather_sources = (int64_t)hs.gat_src.size();
+    s.compound_items = hs.compound_items;
+    s.max_level_items = hs.max_level_items;
+    s.max_level_gathers = hs.max_level_gathers;
+    s.device_bytes = (int64_t)tn::schedule_device_bytes(hs);
+    s.host_seconds = hs.host_seconds;
+    s.directed_pairs = hs.directed_pairs;
+}
+}  // namespace
+
+struct tn_host_schedule {
+    tn::HostSchedule hs;
+};
+
+tn_status tn_schedule_build(uint32_t n, int64_t m, const uint32_t *src, const uint32_t *dst,
+                            const int64_t *t, uint32_t flags, tn_host_schedule **out) {
+    if (!out) return fail(TN_E_ARG, "out is NULL");
+    *out = nullptr;
+    tn_host_schedule *s = new (std::nothrow) tn_host_schedule();
+    if (!s) return fail(TN_E_NOMEM, "schedule allocation failed");
+    std::string err;
+    tn_status st = tn::plan_events(n, m, src, dst, t, flags, s->hs, err);
+    if (st != TN_OK) {
+        delete s;
+        return fail(st, err);
+    }
+    *out = s;
+    return TN_OK;
+}
+
+tn_status tn_schedule_arrays(const tn_host_schedule *s, tn_plan_stats *stats,
+                             const uint32_t **lvl_pair, const uint32_t **lvl_gat,
+                             const uint32_t **pairs, const uint32_t **gat_tgt,
+                             const uint32_t **gat_ptr, const uint32_t **gat_src) {
+    if (!s) return fail(TN_E_ARG, "schedule is NULL");
+    if (stats) fill_stats(s->hs, *stats);
+    if (lvl_pair) *lvl_pair = s->hs.lvl_pair.data();
+    if (lvl_gat) *lvl_gat = s->hs.lvl_gat.data();
+    if (pairs) *pairs = s->hs.pairs.data();
+    if (gat_tgt) *gat_tgt = s->hs.gat_tgt.data();
+    if (gat_ptr) *gat_ptr = s->hs.gat_ptr.data();
+    if (gat_src) *gat_src = s->hs.gat_src.data();
+    return TN_OK;
+}
+
+void tn_schedule_destroy(tn_host_schedule *s) { delete s; }
+
+tn_status tn_plan_get_stats(const tn_plan *plan, tn_plan_stats *out) {
+    if (!plan || !out) return fail(TN_E_ARG, "plan or out is NULL");
+    *out = plan->stats;
+    return TN_OK;
+}
+
+void tn_plan_destroy(tn_plan *plan) {
+    if (!plan) return;
+    DeviceGuard g(plan->device);
+    if (plan->dev) (void)hipFree(plan->dev);
+    delete plan;
+}
+
+tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t ld,
+                          uint32_t slice_words) {
+    if (!ctx || !plan) return fail(TN_E_ARG, "ctx or plan is NULL");
+    if (!C) return fail(TN_E_ARG, "C is NULL");
+    const uint32_t n = plan->stats.n;
+    const int64_t nwords = (n + 63) / 64;
+    if (ld < nwords) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
+    if (plan->device != ctx->device) return fail(TN_E_ARG, "plan lives on another device");
+    if (slice_words == 0) slice_words = tn::default_slice_words(n, ld);
+    if (slice_words > 64 || (slice_words & (slice_words - 1)))
+        return fail(TN_E_ARG, "slice_words must be a power of two <= 64");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    if (plan->stats.max_level_gathers > 0) {
+        tn_status st = tn::ensure_scratch(
+            ctx, (size_t)plan->stats.max_level_gathers * (size_t)nwords * sizeof(uint64_t));
+        if (st != TN_OK) return st;
+    }
+    hipError_t e;
+    {
+        tn::ProfScope ps(ctx, TN_K_IDENTITY);
+        e = tn::launch_identity(C, n, ld, ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "identity kernel launch");
+    {
+        tn::ProfScope ps(ctx, TN_K_ROWOR);
+        e = tn::launch_rowor_global(plan->view, C, ld, slice_words, (uint64_t *)ctx->scratch,
+                                    ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "row-OR kernel launch");
+    return TN_OK;
+}
+
+tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
+                                    const uint32_t *dst, const int64_t *t, uint32_t flags,
+                                    uint64_t *C, int64_t ld) {
+    if (!C) return fail(TN_E_ARG, "C is NULL");
+    if (ld < (int64_t)((n + 63) / 64)) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
+    tn_plan *p = nullptr;
+    tn_status st = tn_plan_create(ctx, n, m, src, dst, t, flags, &p);
+    if (st != TN_OK) return st;
+    st = tn_plan_execute(ctx, p, C, ld, 0);
+    if (st == TN_OK) {
+        // the plan's schedule must outlive the queued kernels
+        DeviceGuard g(ctx->device);
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    tn_plan_destroy(p);
+    return st;
+}
+
+tn_status tn_component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C, int64_t ld,
+                             int32_t *out_sizes, int32_t *in_sizes) {
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    if (n == 0) return fail(TN_E_ARG, "n must be > 0");
+    if (!C) return fail(TN_E_ARG, "C is NULL");
+    if (ld < (int64_t)((n + 63) / 64)) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
+    if (!out_sizes && !in_sizes) return TN_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    if (out_sizes) {
+        tn::ProfScope ps(ctx, TN_K_OUT_SIZES);
+        hipError_t e = tn::launch_out_sizes(C, n, ld, out_sizes, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "out-size kernel launch");
+    }
+    if (in_sizes) {
+        tn::ProfScope ps(ctx, TN_K_IN_SIZES);
+        hipError_t e = tn::launch_in_sizes(C, n, ld, in_sizes, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "in-size kernel launch");
+    }
+    return TN_OK;
+}
+
+}  // extern "C"

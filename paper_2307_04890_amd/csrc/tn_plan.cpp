@@ -1,0 +1,350 @@
+// Host planner: turns a time-ordered event list into a level schedule of
+// row-OR items for the reverse-time component matrix (Sec. 3.4).
+//
+// Reverse time, strict ties (Sec. 2.1): events of one time step are not
+// adjacent, so every row touched at a time step must be updated from the
+// rows as they were before that step.  The events of a step split into
+// connected components over their nodes:
+//   * a component of two nodes is a pair item: one row OR (both rows for an
+//     undirected or two-way pair, only the source row for a one-way directed
+//     pair, since event (u -> v) gives u's out-component everything v reaches
+//     later);
+//   * a component of three or more nodes is a compound item: each node x
+//     gets the OR of its own row and its partners' old rows, so all of them
+//     are read before any is written (gathers through scratch rows).
+// Row ORs on disjoint rows commute, so each item is placed on the earliest
+// level after the last level that touched any of its rows; the items of a
+// level then touch pairwise disjoint rows and run concurrently.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+namespace {
+
+struct Planner {
+    uint32_t n;
+    bool directed;
+    std::vector<uint32_t> last;  // last level (1-based) that touched a row
+    uint32_t L = 0;
+
+    // items in reverse-stream order
+    std::vector<uint32_t> pu, pv, plev;
+    struct Gather {
+        uint32_t level, tgt, s0, s1;
+    };
+    std::vector<Gather> gtmp;
+    std::vector<uint32_t> gsrc;
+    int64_t compound_items = 0;
+
+    // per-group scratch
+    std::vector<uint32_t> stamp, local;
+    uint32_t gid = 0;
+    std::vector<uint32_t> lnode, parent, comp, comp_nodes_ptr, comp_nodes,
+        comp_ev_ptr, comp_ev, fill, nbr_ptr, nbr;
+    std::vector<uint32_t> es, ed;  // group events without self-loops
+
+    explicit Planner(uint32_t n_, bool dir) : n(n_), directed(dir), last(n_, 0),
+                                              stamp(n_, 0xffffffffu), local(n_, 0) {}
+
+    uint32_t find(uint32_t x) {
+        while (parent[x] != x) {
+            parent[x] = parent[parent[x]];
+            x = parent[x];
+        }
+        return x;
+    }
+
+    void add_pair(uint32_t u, uint32_t v, bool uv, bool vu) {
+        // uv: information reaches u's row from v (event u -> v in reverse time)
+        uint32_t lvl = 1 + std::max(last[u], last[v]);
+        last[u] = last[v] = lvl;
+        if (lvl > L) L = lvl;
+        if (!directed || (uv && vu)) {
+            pu.push_back(u);
+            pv.push_back(v);
+        } else if (uv) {
+            pu.push_back(u);
+            pv.push_back(v | kDirBit);
+        } else {
+            pu.push_back(v);
+            pv.push_back(u | kDirBit);
+        }
+        plev.push_back(lvl);
+    }
+
+    // events [a, b) share one time step (or a == b - 1 in sequential mode)
+    void group(const uint32_t *src, const uint32_t *dst, int64_t a, int64_t b) {
+        es.clear();
+        ed.clear();
+        for (int64_t e = a; e < b; ++e)
+            if (src[e] != dst[e]) {
+                es.push_back(src[e]);
+                ed.push_back(dst[e]);
+            }
+        const size_t k = es.size();
+        if (k == 0) return;
+        if (k == 1) {
+            add_pair(es[0], ed[0], true, false);
+            return;
+        }
+        ++gid;
+        if (gid == 0xffffffffu) {  // stamp wrap: reset
+            std::fill(stamp.begin(), stamp.end(), 0xffffffffu);
+            gid = 0;
+        }
+        lnode.clear();
+        parent.clear();
+        auto lid = [&](uint32_t x) {
+            if (stamp[x] != gid) {
+                stamp[x] = gid;
+                local[x] = (uint32_t)lnode.size();
+                lnode.push_back(x);
+                parent.push_back(local[x]);
+            }
+            return local[x];
+        };
+        for (size_t i = 0; i < k; ++i) {
+            uint32_t ra = find(lid(es[i])), rb = find(lid(ed[i]));
+            if (ra != rb) parent[ra] = rb;
+        }
+        const uint32_t nl = (uint32_t)lnode.size();
+        // component ids 0..nc-1 in order of first node
+        comp.assign(nl, 0xffffffffu);
+        std::vector<uint32_t> &root_id = fill;
+        root_id.assign(nl, 0xffffffffu);
+        uint32_t nc = 0;
+        for (uint32_t i = 0; i < nl; ++i) {
+            uint32_t r = find(i);
+            if (root_id[r] == 0xffffffffu) root_id[r] = nc++;
+            comp[i] = root_id[r];
+        }
+        // nodes per component (CSR)
+        comp_nodes_ptr.assign(nc + 1, 0);
+        for (uint32_t i = 0; i < nl; ++i) comp_nodes_ptr[comp[i] + 1]++;
+        for (uint32_t c = 0; c < nc; ++c) comp_nodes_ptr[c + 1] += comp_nodes_ptr[c];
+        comp_nodes.resize(nl);
+        {
+            std::vector<uint32_t> pos(comp_nodes_ptr.begin(), comp_nodes_ptr.end() - 1);
+            for (uint32_t i = 0; i < nl; ++i) comp_nodes[pos[comp[i]]++] = i;
+        }
+        // events per component (CSR)
+        comp_ev_ptr.assign(nc + 1, 0);
+        for (size_t i = 0; i < k; ++i) comp_ev_ptr[comp[local[es[i]]] + 1]++;
+        for (uint32_t c = 0; c < nc; ++c) comp_ev_ptr[c + 1] += comp_ev_ptr[c];
+        comp_ev.resize(k);
+        {
+            std::vector<uint32_t> pos(comp_ev_ptr.begin(), comp_ev_ptr.end() - 1);
+            for (size_t i = 0; i < k; ++i) comp_ev[pos[comp[local[es[i]]]]++] = (uint32_t)i;
+        }
+        for (uint32_t c = 0; c < nc; ++c) {
+            const uint32_t n0 = comp_nodes_ptr[c], n1 = comp_nodes_ptr[c + 1];
+            const uint32_t e0 = comp_ev_ptr[c], e1 = comp_ev_ptr[c + 1];
+            if (n1 - n0 == 2) {
+                uint32_t x = lnode[comp_nodes[n0]], y = lnode[comp_nodes[n0 + 1]];
+                bool xy = false, yx = false;
+                for (uint32_t q = e0; q < e1; ++q) {
+                    uint32_t i = comp_ev[q];
+                    if (es[i] == x) xy = true; else yx = true;
+                }
+                add_pair(x, y, xy, yx);
+                continue;
+            }
+            compound(n0, n1, e0, e1);
+        }
+    }
+
+    void compound(uint32_t n0, uint32_t n1, uint32_t e0, uint32_t e1) {
+        ++compound_items;
+        uint32_t lvl = 0;
+        for (uint32_t q = n0; q < n1; ++q) lvl = std::max(lvl, last[lnode[comp_nodes[q]]]);
+        ++lvl;
+        if (lvl > L) L = lvl;
+        for (uint32_t q = n0; q < n1; ++q) last[lnode[comp_nodes[q]]] = lvl;
+        // partners of each local node: event s -> d gives new[s] |= old[d]
+        // (and new[d] |= old[s] when undirected)
+        const uint32_t cn = n1 - n0;
+        // position of local node inside the component
+        for (uint32_t q = n0; q < n1; ++q) fill[comp_nodes[q]] = q - n0;
+        nbr_ptr.assign(cn + 1, 0);
+        for (uint32_t q = e0; q < e1; ++q) {
+            uint32_t i = comp_ev[q];
+            nbr_ptr[fill[local[es[i]]] + 1]++;
+            if (!directed) nbr_ptr[fill[local[ed[i]]] + 1]++;
+        }
+        for (uint32_t c = 0; c < cn; ++c) nbr_ptr[c + 1] += nbr_ptr[c];
+        nbr.resize(nbr_ptr[cn]);
+        std::vector<uint32_t> pos(nbr_ptr.begin(), nbr_ptr.end() - 1);
+        for (uint32_t q = e0; q < e1; ++q) {
+            uint32_t i = comp_ev[q];
+            nbr[pos[fill[local[es[i]]]]++] = ed[i];
+            if (!directed) nbr[pos[fill[local[ed[i]]]]++] = es[i];
+        }
+        for (uint32_t c = 0; c < cn; ++c) {
+            uint32_t b0 = nbr_ptr[c], b1 = nbr_ptr[c + 1];
+            if (b0 == b1) continue;  // no incoming information: row unchanged
+            std::sort(nbr.begin() + b0, nbr.begin() + b1);
+            uint32_t x = lnode[comp_nodes[n0 + c]];
+            Gather g;
+            g.level = lvl;
+            g.tgt = x;
+            g.s0 = (uint32_t)gsrc.size();
+            gsrc.push_back(x);
+            for (uint32_t q = b0; q < b1; ++q)
+                if (q == b0 || nbr[q] != nbr[q - 1])
+                    if (nbr[q] != x) gsrc.push_back(nbr[q]);
+            g.s1 = (uint32_t)gsrc.size();
+            gtmp.push_back(g);
+        }
+    }
+};
+
+}  // namespace
+
+tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
+                      const uint32_t *dst, const int64_t *t, uint32_t flags,
+                      HostSchedule &out, std::string &err) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (n == 0) { err = "n must be > 0"; return TN_E_ARG; }
+    if (m < 0) { err = "m must be >= 0"; return TN_E_ARG; }
+    if (m > 0 && (!src || !dst || !t)) { err = "null event array"; return TN_E_ARG; }
+    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL)) { err = "unknown flag bits"; return TN_E_ARG; }
+    if (n > kNodeMask) { err = "n must be < 2^31"; return TN_E_UNSUPPORTED; }
+    if (m >= (int64_t)0xffffffffLL) { err = "m must be < 2^32 - 1"; return TN_E_UNSUPPORTED; }
+    for (int64_t e = 0; e < m; ++e) {
+        if (src[e] >= n || dst[e] >= n) {
+            err = "event " + std::to_string(e) + " has a node id >= n";
+            return TN_E_RANGE;
+        }
+        if (e > 0 && t[e] < t[e - 1]) {
+            err = "event " + std::to_string(e) + " is earlier than its predecessor";
+            return TN_E_ORDER;
+        }
+    }
+    const bool directed = flags & TN_DIRECTED;
+    const bool seq = flags & TN_TIES_SEQUENTIAL;
+    Planner p(n, directed);
+    p.pu.reserve((size_t)m);
+    p.pv.reserve((size_t)m);
+    p.plev.reserve((size_t)m);
+    int64_t b = m;
+    while (b > 0) {
+        int64_t a = b - 1;
+        if (!seq)
+            while (a > 0 && t[a - 1] == t[b - 1]) --a;
+        p.group(src, dst, a, b);
+        b = a;
+    }
+    // counting sort by level
+    const uint32_t L = p.L;
+    out.n = n;
+    out.m = m;
+    out.flags = flags;
+    out.L = L;
+    out.lvl_pair.assign((size_t)L + 1, 0);
+    out.lvl_gat.assign((size_t)L + 1, 0);
+    for (uint32_t lv : p.plev) out.lvl_pair[lv]++;  // level lv (1-based) -> slot lv
+    for (auto &g : p.gtmp) out.lvl_gat[g.level]++;
+    out.max_level_items = 0;
+    out.max_level_gathers = 0;
+    for (uint32_t l = 1; l <= L; ++l) {
+        int64_t w = (int64_t)out.lvl_pair[l] + out.lvl_gat[l];
+        out.max_level_items = std::max(out.max_level_items, w);
+        out.max_level_gathers = std::max<int64_t>(out.max_level_gathers, out.lvl_gat[l]);
+    }
+    for (uint32_t l = 0; l < L; ++l) {
+        out.lvl_pair[l + 1] += out.lvl_pair[l];
+        out.lvl_gat[l + 1] += out.lvl_gat[l];
+    }
+    const size_t P = p.pu.size();
+    out.pairs.resize(2 * P);
+    {
+        std::vector<uint32_t> pos(out.lvl_pair.begin(), out.lvl_pair.end() - 1);
+        for (size_t i = 0; i < P; ++i) {
+            uint32_t q = pos[p.plev[i] - 1]++;
+            out.pairs[2 * (size_t)q] = p.pu[i];
+            out.pairs[2 * (size_t)q + 1] = p.pv[i];
+        }
+    }
+    const size_t G = p.gtmp.size();
+    out.gat_tgt.resize(G);
+    out.gat_ptr.assign(G + 1, 0);
+    out.gat_src.resize(p.gsrc.size());
+    {
+        std::vector<uint32_t> order(G);
+        std::vector<uint32_t> pos(out.lvl_gat.begin(), out.lvl_gat.end() - 1);
+        for (size_t i = 0; i < G; ++i) order[pos[p.gtmp[i].level - 1]++] = (uint32_t)i;
+        uint32_t s = 0;
+        for (size_t q = 0; q < G; ++q) {
+            const auto &g = p.gtmp[order[q]];
+            out.gat_tgt[q] = g.tgt;
+            out.gat_ptr[q] = s;
+            for (uint32_t r = g.s0; r < g.s1; ++r) out.gat_src[s++] = p.gsrc[r];
+        }
+        out.gat_ptr[G] = s;
+    }
+    out.compound_items = p.compound_items;
+    out.directed_pairs = 0;
+    for (size_t i = 0; i < P; ++i) out.directed_pairs += (p.pv[i] & kDirBit) ? 1 : 0;
+    out.host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return TN_OK;
+}
+
+namespace {
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t lvl_pair, lvl_gat, pairs, gat_tgt, gat_ptr, gat_src, total;
+};
+
+Layout layout_of(const HostSchedule &s) {
+    Layout o;
+    size_t off = 0;
+    o.lvl_pair = off; off = align256(off + 4 * s.lvl_pair.size());
+    o.lvl_gat = off;  off = align256(off + 4 * s.lvl_gat.size());
+    o.pairs = off;    off = align256(off + 4 * s.pairs.size());
+    o.gat_tgt = off;  off = align256(off + 4 * s.gat_tgt.size());
+    o.gat_ptr = off;  off = align256(off + 4 * s.gat_ptr.size());
+    o.gat_src = off;  off = align256(off + 4 * s.gat_src.size());
+    o.total = std::max<size_t>(off, 256);
+    return o;
+}
+}  // namespace
+
+size_t schedule_device_bytes(const HostSchedule &s) { return layout_of(s).total; }
+
+void schedule_pack(const HostSchedule &s, std::vector<unsigned char> &img) {
+    Layout o = layout_of(s);
+    img.assign(o.total, 0);
+    auto put = [&](size_t off, const std::vector<uint32_t> &v) {
+        if (!v.empty()) std::memcpy(img.data() + off, v.data(), 4 * v.size());
+    };
+    put(o.lvl_pair, s.lvl_pair);
+    put(o.lvl_gat, s.lvl_gat);
+    put(o.pairs, s.pairs);
+    put(o.gat_tgt, s.gat_tgt);
+    put(o.gat_ptr, s.gat_ptr);
+    put(o.gat_src, s.gat_src);
+}
+
+DevSchedule schedule_view(const HostSchedule &s, const void *dev_base) {
+    Layout o = layout_of(s);
+    const unsigned char *b = (const unsigned char *)dev_base;
+    DevSchedule d;
+    d.n = s.n;
+    d.L = s.L;
+    d.max_gat = (uint32_t)s.max_level_gathers;
+    d.pad_ = 0;
+    d.lvl_pair = (const uint32_t *)(b + o.lvl_pair);
+    d.lvl_gat = (const uint32_t *)(b + o.lvl_gat);
+    d.pairs = (const uint2 *)(b + o.pairs);
+    d.gat_tgt = (const uint32_t *)(b + o.gat_tgt);
+    d.gat_ptr = (const uint32_t *)(b + o.gat_ptr);
+    d.gat_src = (const uint32_t *)(b + o.gat_src);
+    return d;
+}
+
+}  // namespace tn

@@ -1,0 +1,172 @@
+"""GPU parity of the exact component-matrix path against the CPU oracle:
+bit-exact matrices and sizes, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tn_inputs as T
+
+pytestmark = pytest.mark.gpu
+
+tn = pytest.importorskip("paper_2307_04890_amd")
+
+
+def host(C):
+    torch.cuda.synchronize()
+    return C.cpu().numpy().view(np.uint64)
+
+
+def gpu_matrix(n, s, d, t, flags=0, ld=None, slice_words=0):
+    p = tn.Plan(n, s, d, t, flags)
+    C = tn.api.alloc_matrix(n, ld=ld)
+    p.execute(C, slice_words=slice_words)
+    out = host(C)
+    p.close()
+    return out
+
+
+def flag_kw(flags):
+    return dict(directed=bool(flags & tn.DIRECTED), sequential=bool(flags & tn.TIES_SEQUENTIAL))
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_tiny_tie_heavy_suites(flags):
+    for case in range(40):
+        n = 2 + (case * 11) % 200
+        m = (case * 37) % 600
+        s, d, t = T.random_tiny(n, m, 1 + case % 15, seed=9100 + case, allow_self=case % 3 == 0)
+        got = gpu_matrix(n, s, d, t, flags)
+        want = oracle.reverse_matrix(n, s, d, t, **flag_kw(flags))
+        assert (got == want).all(), (flags, case, n, m)
+
+
+def test_uniform_pairs_n1000_matrix_and_sizes():
+    s, d, t = T.make_workload("uniform_n1000_m20000")
+    C = tn.build_component_matrix(1000, s, d, t)
+    out, inn = tn.component_sizes(C, 1000)
+    want = oracle.reverse_matrix(1000, s, d, t)
+    assert (host(C) == want).all()
+    wo, wi = oracle.sizes(want, 1000)
+    assert (out.cpu().numpy() == wo).all() and (inn.cpu().numpy() == wi).all()
+
+
+@pytest.mark.parametrize("n,m,T_", [(5000, 12000, 3000), (20000, 40000, 20000)])
+def test_sparse_activity_driven_all_slice_widths(n, m, T_):
+    s, d, t = T.activity_driven(n, m, T_, seed=n)
+    want = oracle.reverse_matrix(n, s, d, t)
+    wo, wi = oracle.sizes(want, n)
+    assert len(np.unique(wo)) > 10  # out-components of many sizes
+    p = tn.Plan(n, s, d, t)
+    for sw in (1, 2, 4, 8, 16, 32, 64):
+        C = p.execute(slice_words=sw)
+        assert (host(C) == want).all(), sw
+        out, inn = tn.component_sizes(C, n)
+        assert (out.cpu().numpy() == wo).all() and (inn.cpu().numpy() == wi).all()
+    p.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 129, 1000, 4097])
+def test_ragged_sizes_and_padding(n):
+    s, d, t = T.random_tiny(max(n, 2), 3 * n, 7, seed=n)
+    if n == 1:
+        s, d, t = np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.int64)
+    want = oracle.reverse_matrix(n, s, d, t)
+    ld = oracle.words(n) + 3
+    got = gpu_matrix(n, s, d, t, ld=ld)
+    assert (got[:, :oracle.words(n)] == want).all()
+    assert not got[:, oracle.words(n):].any()
+
+
+def test_no_events_gives_identity():
+    C = tn.build_component_matrix(300, [], [], [])
+    assert (oracle.to_dense(host(C), 300) == np.eye(300, dtype=bool)).all()
+    out, inn = tn.component_sizes(C, 300)
+    assert (out.cpu().numpy() == 1).all() and (inn.cpu().numpy() == 1).all()
+
+
+def test_deterministic_repeat():
+    s, d, t = T.activity_driven(8000, 30000, 2000, seed=5)
+    p = tn.Plan(8000, s, d, t)
+    a = host(p.execute())
+    b = host(p.execute(slice_words=1))
+    assert (a == b).all()
+
+
+def test_errors_enqueue_nothing():
+    with pytest.raises(tn.TNError) as e:
+        tn.Plan(4, [0], [4], [0])
+    assert e.value.code == -2
+    with pytest.raises(tn.TNError) as e:
+        tn.Plan(4, [0, 1], [1, 2], [5, 1])
+    assert e.value.code == -3
+    p = tn.Plan(100, [0], [1], [0])
+    C = torch.zeros((100, 1), dtype=torch.int64, device="cuda")  # ld 1 < 2 words
+    rc = tn.lib.tn_plan_execute(tn.get_context().bind_stream(), p.h, tn.api._dp(C), 1, 0)
+    assert rc == -1
+    big = torch.zeros((100, 2), dtype=torch.int64, device="cuda")
+    with pytest.raises(tn.TNError):
+        p.execute(big, slice_words=3)  # not a power of two
+    torch.cuda.synchronize()
+    assert (C.cpu() == 0).all() and (big.cpu() == 0).all()  # nothing was enqueued
+    p.execute(big)
+    assert oracle.to_dense(host(big), 100)[0, 1]
+
+
+def test_profile_records_each_kernel():
+    ctx = tn.get_context()
+    s, d, t = T.uniform_pairs(2000, 5000, 100, seed=3)
+    p = tn.Plan(2000, s, d, t)
+    ctx.profile(True)
+    C = p.execute()
+    tn.component_sizes(C, 2000)
+    recs = ctx.profile_take()
+    ctx.profile(False)
+    names = [r[0] for r in recs]
+    assert names == ["identity", "rowor", "out_sizes", "in_sizes"]
+    assert all(ms >= 0 for _, ms in recs)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    s, d, t = T.make_workload("activity_n100000_m10M")
+    p = tn.Plan(100_000, s, d, t)
+    C = p.execute()
+    out, inn = tn.component_sizes(C, 100_000)
+    torch.cuda.synchronize()
+    yield dict(s=s, d=d, t=t, C=C, out=out.cpu().numpy(), inn=inn.cpu().numpy(), plan=p)
+    p.close()
+
+
+def test_full_size_sampled_columns(c2):
+    n = 100_000
+    nw = oracle.words(n)
+    for w0, k in ((0, 2), (700, 1), (nw - 2, 2)):
+        want = oracle.reverse_matrix(n, c2["s"], c2["d"], c2["t"], w0=w0, nw=k)
+        got = c2["C"][:, w0:w0 + k].cpu().numpy().view(np.uint64)
+        assert (got == want).all(), w0
+        cols = oracle.col_counts(want)
+        lo, hi = 64 * w0, min(n, 64 * (w0 + k))
+        assert (c2["inn"][lo:hi] == cols[:hi - lo]).all()
+
+
+def test_full_size_sampled_rows(c2):
+    # rows of C are columns of the forward matrix S (the transpose identity)
+    n = 100_000
+    for w0 in (3, 1000):
+        S = oracle.forward_matrix(n, c2["s"], c2["d"], c2["t"], w0=w0, nw=1)
+        Sd = oracle.to_dense(S, 64)  # n x 64: column b = source 64*w0 + b
+        rows = c2["C"][64 * w0:64 * w0 + 64].cpu().numpy().view(np.uint64)
+        Rd = oracle.to_dense(rows, n)  # 64 x n
+        assert (Rd == Sd.T).all(), w0
+        assert (c2["out"][64 * w0:64 * w0 + 64] == Sd.sum(axis=0)).all()
+
+
+def test_full_size_invariants(c2):
+    n = 100_000
+    assert c2["out"].sum() == c2["inn"].sum()
+    assert (c2["out"] >= 1).all() and (c2["out"] <= n).all()
+    diag = torch.arange(n, device="cuda")
+    words_ = c2["C"][diag, diag // 64]
+    assert bool((((words_ >> (diag % 64)) & 1) == 1).all())
+    assert not bool((c2["C"][:, -1] >> (n % 64)).any())
