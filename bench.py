@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of single-thread oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -130,6 +132,15 @@ def main():
         tn._lib.check(tn.lib.tn_component_sizes(ctx.bind_stream(), n, cp(C), C.stride(0),
                                                 cp(out), cp(inn)))
 
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        a = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del a, b
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

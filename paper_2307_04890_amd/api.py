@@ -10,7 +10,7 @@ import torch
 
 from ._lib import DIRECTED, KERNELS, TIES_SEQUENTIAL, PlanStats, TNError, check, lib
 
-__all__ = ["Context", "Plan", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+__all__ = ["Context", "Plan", "Batch", "hash_compress", "recombine", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
 
@@ -196,3 +196,122 @@ def host_schedule(n: int, src, dst, t, flags: int = 0) -> dict:
     finally:
         lib.tn_schedule_destroy(h)
     return out
+
+
+class Batch:
+    """Schedules of many networks built in one persistent launch (tn_batch_create).
+
+    ``nets`` is a sequence of (n, src, dst, t).  The first execute() tunes the
+    tile shape on the device and captures the launch in a HIP graph."""
+
+    def __init__(self, nets, flags: int = 0, ctx: Context | None = None, _handle=None):
+        self.ctx = ctx or get_context()
+        if _handle is not None:
+            self.h = _handle
+            self.ns = [int(x) for x in nets]
+            return
+        evs = [_events(s, d, t) for (_, s, d, t) in nets]
+        self.ns = [int(n) for (n, _, _, _) in nets]
+        B = len(nets)
+        n_arr = np.asarray(self.ns, dtype=np.uint32)
+        m_arr = np.asarray([e[0].shape[0] for e in evs], dtype=np.int64)
+        ptr = lambda k: (ctypes.c_void_p * B)(*[e[k].ctypes.data for e in evs])
+        self._keep = evs
+        h = ctypes.c_void_p()
+        check(lib.tn_batch_create(self.ctx.bind_stream(), B, _hp(n_arr), _hp(m_arr), ptr(0),
+                                  ptr(1), ptr(2), int(flags), ctypes.byref(h)))
+        self._keep = None
+        self.h = h
+
+    def __len__(self):
+        return len(self.ns)
+
+    def stats(self):
+        B = len(self.ns)
+        st = (PlanStats * B)()
+        tiles = ctypes.c_int64()
+        lds = ctypes.c_int64()
+        check(lib.tn_batch_get_stats(self.h, st, ctypes.byref(tiles), ctypes.byref(lds)))
+        return [s.as_dict() for s in st], int(tiles.value), int(lds.value)
+
+    def alloc(self):
+        return [alloc_matrix(n, device=self.ctx.device) for n in self.ns]
+
+    def execute(self, Cs=None):
+        if Cs is None:
+            Cs = self.alloc()
+        B = len(self.ns)
+        if len(Cs) != B:
+            raise ValueError("one matrix per network expected")
+        for C, n in zip(Cs, self.ns):
+            if C.dtype != torch.int64 or C.dim() != 2 or C.shape[0] != n or not C.is_contiguous():
+                raise ValueError("C must be contiguous int64 (n, ld) device tensors")
+        cp = (ctypes.c_void_p * B)(*[C.data_ptr() for C in Cs])
+        ld = np.asarray([C.stride(0) for C in Cs], dtype=np.int64)
+        check(lib.tn_batch_execute(self.ctx.bind_stream(), self.h, cp, _hp(ld)))
+        return Cs
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_component_matrix_batched(nets, flags: int = 0, Cs=None, ctx: Context | None = None):
+    """One call: plan, tune, build and free a batch; returns the matrices."""
+    ctx = ctx or get_context()
+    evs = [_events(s, d, t) for (_, s, d, t) in nets]
+    ns = [int(n) for (n, _, _, _) in nets]
+    B = len(nets)
+    if Cs is None:
+        Cs = [alloc_matrix(n, device=ctx.device) for n in ns]
+    n_arr = np.asarray(ns, dtype=np.uint32)
+    m_arr = np.asarray([e[0].shape[0] for e in evs], dtype=np.int64)
+    ptr = lambda k: (ctypes.c_void_p * B)(*[e[k].ctypes.data for e in evs])
+    cp = (ctypes.c_void_p * B)(*[C.data_ptr() for C in Cs])
+    ld = np.asarray([C.stride(0) for C in Cs], dtype=np.int64)
+    check(lib.tn_build_component_matrix_batched(ctx.bind_stream(), B, _hp(n_arr), _hp(m_arr),
+                                                ptr(0), ptr(1), ptr(2), int(flags), cp, _hp(ld)))
+    return Cs
+
+
+def hash_compress(n: int, src, dst, t, coeffs, K: int, flags: int = 0,
+                  ctx: Context | None = None):
+    """Network hashing (Sec. 4.1): returns (bucket (H, n) int32 view of uint32,
+    count (H, K) int32, proxies Batch of H networks on K super-nodes).
+    ``coeffs`` is the (H, 3, order) uint64 random table of the hash family."""
+    ctx = ctx or get_context()
+    src, dst, t = _events(src, dst, t)
+    A = np.ascontiguousarray(coeffs, dtype=np.uint64)
+    if A.ndim != 3 or A.shape[1] != 3:
+        raise ValueError("coeffs must have shape (H, 3, order)")
+    H, _, order = A.shape
+    dev = f"cuda:{ctx.device}"
+    bucket = torch.empty((H, n), dtype=torch.int32, device=dev)
+    count = torch.empty((H, K), dtype=torch.int32, device=dev)
+    h = ctypes.c_void_p()
+    check(lib.tn_hash_compress(ctx.bind_stream(), int(n), src.shape[0], _hp(src), _hp(dst), _hp(t),
+                               int(flags), H, int(K), _hp(A), order, _dp(bucket), _dp(count),
+                               ctypes.byref(h)))
+    return bucket, count, Batch([K] * H, ctx=ctx, _handle=h)
+
+
+def recombine(P: torch.Tensor, bucket: torch.Tensor, count: torch.Tensor, n: int,
+              lifted: bool = True, ctx: Context | None = None):
+    """Fusion (Sec. 4.2): |estimated OC(u)| for every node and, optionally, the
+    per-hash lifted sizes.  P is (H, K, ldK) int64 on the device."""
+    ctx = ctx or get_context()
+    if P.dim() != 3 or not P.is_contiguous():
+        raise ValueError("P must be a contiguous (H, K, ldK) tensor")
+    H, K, ldK = P.shape
+    est = torch.empty(n, dtype=torch.int32, device=P.device)
+    lif = torch.empty((H, n), dtype=torch.int32, device=P.device) if lifted else None
+    check(lib.tn_recombine(ctx.bind_stream(), int(n), H, K, _dp(P), ldK, _dp(bucket), _dp(count),
+                           _dp(est), _dp(lif)))
+    return est, lif

@@ -9,7 +9,9 @@
 
 namespace {
 thread_local std::string g_err;
+}  // namespace
 
+namespace tn {
 tn_status fail(tn_status code, const std::string &msg) {
     g_err = msg;
     return code;
@@ -19,72 +21,11 @@ tn_status hip_fail(hipError_t e, const char *what) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
     return TN_E_HIP;
 }
-
-// Makes the context's device current for the scope of an entry point.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-}  // namespace
-
-struct tn_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    void *scratch = nullptr;
-    size_t scratch_bytes = 0;
-    // kernel timing (tn_profile_enable)
-    bool profiling = false;
-    struct Rec {
-        int32_t id;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> pool;
-};
-
-namespace tn {
-// Brackets one kernel launch with events on the context's stream when
-// profiling is on.
-struct ProfScope {
-    tn_ctx *c;
-    size_t idx = (size_t)-1;
-    ProfScope(tn_ctx *ctx, int32_t id) : c(ctx) {
-        if (!c->profiling) return;
-        hipEvent_t ev[2];
-        for (int i = 0; i < 2; ++i) {
-            if (!c->pool.empty()) {
-                ev[i] = c->pool.back();
-                c->pool.pop_back();
-            } else if (hipEventCreate(&ev[i]) != hipSuccess) {
-                for (int k = 0; k < i; ++k) c->pool.push_back(ev[k]);
-                return;
-            }
-        }
-        (void)hipEventRecord(ev[0], c->stream);
-        c->recs.push_back({id, ev[0], ev[1]});
-        idx = c->recs.size() - 1;
-    }
-    ~ProfScope() {
-        if (idx != (size_t)-1) (void)hipEventRecord(c->recs[idx].b, c->stream);
-    }
-};
 }  // namespace tn
 
-struct tn_plan {
-    int device = 0;
-    void *dev = nullptr;
-    size_t dev_bytes = 0;
-    tn::DevSchedule view{};
-    tn_plan_stats stats{};
-};
+using tn::DeviceGuard;
+using tn::fail;
+using tn::hip_fail;
 
 namespace tn {
 tn_status not_built(const char *what) {
@@ -111,10 +52,6 @@ tn_status ensure_scratch(tn_ctx *ctx, size_t bytes) {
 }
 }  // namespace tn
 
-namespace {
-void fill_stats(const tn::HostSchedule &hs, tn_plan_stats &s);
-}
-
 extern "C" {
 
 const char *tn_last_error(void) { return g_err.c_str(); }
@@ -130,6 +67,12 @@ tn_status tn_create(int device, void *stream, tn_ctx **out) {
     if (!c) return fail(TN_E_NOMEM, "context allocation failed");
     c->device = device;
     c->stream = (hipStream_t)stream;
+    {
+        DeviceGuard g(device);
+        if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess)
+            c->num_cus = 256;
+    }
     *out = c;
     return TN_OK;
 }
@@ -219,13 +162,15 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         return hip_fail(e, "schedule upload");
     }
     p->view = tn::schedule_view(hs, p->dev);
-    fill_stats(hs, p->stats);
+    tn::fill_stats(hs, p->stats);
     *out = p;
     return TN_OK;
 }
 
-namespace {
-void fill_stats(const tn::HostSchedule &hs, tn_plan_stats &s) {
+}  // extern "C"
+
+namespace tn {
+void fill_stats(const HostSchedule &hs, tn_plan_stats &s) {
     s.n = hs.n;
     s.m = hs.m;
     s.levels = hs.L;
@@ -239,7 +184,9 @@ void fill_stats(const tn::HostSchedule &hs, tn_plan_stats &s) {
     s.host_seconds = hs.host_seconds;
     s.directed_pairs = hs.directed_pairs;
 }
-}  // namespace
+}  // namespace tn
+
+extern "C" {
 
 struct tn_host_schedule {
     tn::HostSchedule hs;
@@ -266,7 +213,7 @@ tn_status tn_schedule_arrays(const tn_host_schedule *s, tn_plan_stats *stats,
                              const uint32_t **pairs, const uint32_t **gat_tgt,
                              const uint32_t **gat_ptr, const uint32_t **gat_src) {
     if (!s) return fail(TN_E_ARG, "schedule is NULL");
-    if (stats) fill_stats(s->hs, *stats);
+    if (stats) tn::fill_stats(s->hs, *stats);
     if (lvl_pair) *lvl_pair = s->hs.lvl_pair.data();
     if (lvl_gat) *lvl_gat = s->hs.lvl_gat.data();
     if (pairs) *pairs = s->hs.pairs.data();

@@ -1,0 +1,341 @@
+// Network hashing (Sec. 4.1) and fusion of the hashed proxies (Sec. 4.2).
+//
+// Hash: h_j(u) = (acc_0(x0) ^ acc_1(x1) ^ acc_2(x2)) mod K, where x0 / x1 are
+// the low / high 32 bits of u, x2 = x0 + x1, and acc_i folds the coefficients
+// of row i of table A_j with (x * acc + a) mod (2^61 - 1).  The product is
+// formed exactly in 128 bits and reduced with 2^61 = 1 (mod 2^61 - 1).
+//
+// Fusion: the estimated out-component of u keeps node w iff bit h_j(w) of row
+// h_j(u) of every proxy P_j is set.  For a chunk q of 64 nodes w and a hash
+// j, the lifted table Lt[q][j][r] packs those 64 bits for every super-node
+// r; it is the transpose of the 64 proxy columns h_j(w), so it is built from
+// the transposed proxies with 64 x 64 bit transposes inside a wavefront.  The
+// estimate of u is then sum_q popcount(AND_j Lt[q][j][h_j(u)]), evaluated
+// with the tables of a chunk staged in LDS.
+#include <hip/hip_runtime.h>
+
+#include "tn_hash.h"
+
+namespace tn {
+
+namespace {
+
+constexpr uint64_t kP61 = (1ull << 61) - 1;
+
+// (x * acc + a) mod (2^61 - 1), x < 2^34, acc < 2^61, a < 2^61 - 1.
+__device__ __forceinline__ uint64_t mult_add_mod(uint64_t x, uint64_t acc, uint64_t a) {
+    uint64_t lo = x * acc;
+    uint64_t hi = __umul64hi(x, acc);
+    const uint64_t lo2 = lo + a;
+    hi += (lo2 < lo) ? 1ull : 0ull;
+    lo = lo2;
+    // value = hi * 2^64 + lo;  2^64 = 8 (mod p), 2^61 = 1 (mod p)
+    uint64_t r = (lo & kP61) + (lo >> 61) + (hi << 3);
+    r = (r & kP61) + (r >> 61);
+    return r >= kP61 ? r - kP61 : r;
+}
+
+__device__ __forceinline__ uint64_t poly(const uint64_t *__restrict__ Ai, int order, uint64_t x) {
+    uint64_t acc = Ai[0] % kP61;
+    for (int l = 1; l < order; ++l) acc = mult_add_mod(x, acc, Ai[l]);
+    return acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_hash_buckets(uint32_t n, uint32_t H, const uint64_t *__restrict__ coeffs, int order, uint32_t K,
+               uint32_t *__restrict__ bucket) {
+    const size_t total = (size_t)n * H;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)(i / n);
+        const uint64_t u = i - (size_t)j * n;
+        const uint64_t *A = coeffs + (size_t)j * 3 * order;
+        const uint64_t x0 = u & 0xffffffffull, x1 = u >> 32, x2 = x0 + x1;
+        const uint64_t h = poly(A, order, x0) ^ poly(A + order, order, x1) ^
+                           poly(A + 2 * order, order, x2);
+        bucket[i] = (uint32_t)(h % K);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zero_i32(int32_t *__restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_bucket_counts(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bucket,
+                int32_t *__restrict__ count) {
+    const size_t total = (size_t)n * H;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)(i / n);
+        atomicAdd(count + (size_t)j * K + bucket[i], 1);
+    }
+}
+
+// Transposes the 64 x 64 bit block held one row per lane (bit b of lane i's
+// word is entry (i, b)); afterwards lane b holds column b.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t masks[6] = {0x00000000ffffffffull, 0x0000ffff0000ffffull,
+                               0x00ff00ff00ff00ffull, 0x0f0f0f0f0f0f0f0full,
+                               0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const uint32_t s = 32u >> k;
+        const uint64_t y = (uint64_t)__shfl_xor((unsigned long long)x, (int)s, 64);
+        if (lane & s) {
+            const uint64_t t = ((y >> s) ^ x) & masks[k];
+            x ^= t;
+        } else {
+            const uint64_t t = ((x >> s) ^ y) & masks[k];
+            x ^= t << s;
+        }
+    }
+    return x;
+}
+
+// PT_j = transpose of P_j (K x K bits): one wavefront per 64 x 64 block.
+__global__ void __launch_bounds__(256)
+k_transpose_proxies(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ P,
+                    uint64_t *__restrict__ PT) {
+    const uint32_t kw = (K + 63) / 64;
+    const size_t blocks = (size_t)H * kw * kw;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (size_t bidx = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; bidx < blocks;
+         bidx += ((size_t)gridDim.x * blockDim.x) >> 6) {
+        const uint32_t j = (uint32_t)(bidx / ((size_t)kw * kw));
+        const uint32_t rem = (uint32_t)(bidx - (size_t)j * kw * kw);
+        const uint32_t br = rem / kw, bc = rem % kw;  // row block, column-word block
+        const uint64_t *Pj = P + (size_t)j * K * ldK;
+        const uint32_t r = br * 64 + lane;
+        const uint64_t x = r < K ? Pj[(size_t)r * ldK + bc] : 0ull;
+        const uint64_t y = wave_transpose64(x);  // lane b: bits r of column 64*bc + b
+        const uint32_t c = bc * 64 + lane;
+        if (c < K) PT[(size_t)j * K * ldK + (size_t)c * ldK + br] = y;
+    }
+}
+
+// rowsum[j][r] = sum of count[j][r'] over the super-nodes r' set in row r of P_j.
+__global__ void __launch_bounds__(256)
+k_lifted_row_sums(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ P,
+                  const int32_t *__restrict__ count, int32_t *__restrict__ rowsum) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const size_t rows = (size_t)H * K;
+    const uint32_t kw = (K + 63) / 64;
+    for (size_t row = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < rows;
+         row += ((size_t)gridDim.x * blockDim.x) >> 6) {
+        const uint32_t j = (uint32_t)(row / K);
+        const uint64_t *Pr = P + (size_t)j * K * ldK + (row - (size_t)j * K) * ldK;
+        const int32_t *cj = count + (size_t)j * K;
+        int32_t acc = 0;
+        for (uint32_t wd = 0; wd < kw; ++wd) {
+            const uint64_t word = Pr[wd];
+            const uint32_t c = wd * 64 + lane;
+            if (c < K && ((word >> lane) & 1ull)) acc += cj[c];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) rowsum[row] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_lifted_sizes(uint32_t n, uint32_t H, const uint32_t *__restrict__ bucket,
+               const int32_t *__restrict__ rowsum, uint32_t K, int32_t *__restrict__ lifted) {
+    const size_t total = (size_t)n * H;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)(i / n);
+        lifted[i] = rowsum[(size_t)j * K + bucket[i]];
+    }
+}
+
+// Lt[(q - q0) * H * K + j * K + r], bit i = P_j[r][h_j(64 q + i)] (0 past n):
+// one wavefront per (q, j, 64-row block); lane i gathers word br of the
+// transposed proxy row h_j(64 q + i), then the block is transposed.
+__global__ void __launch_bounds__(256)
+k_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ PT,
+               const uint32_t *__restrict__ bucket, uint32_t q0, uint32_t nq,
+               uint64_t *__restrict__ Lt) {
+    const uint32_t kw = (K + 63) / 64;
+    const size_t jobs = (size_t)nq * H * kw;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (size_t job = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; job < jobs;
+         job += ((size_t)gridDim.x * blockDim.x) >> 6) {
+        const uint32_t br = (uint32_t)(job % kw);
+        const uint32_t j = (uint32_t)((job / kw) % H);
+        const uint32_t qq = (uint32_t)(job / ((size_t)kw * H));
+        const uint64_t w = (uint64_t)(q0 + qq) * 64 + lane;
+        uint64_t x = 0;
+        if (w < n) {
+            const uint32_t c = bucket[(size_t)j * n + w];
+            x = PT[(size_t)j * K * ldK + (size_t)c * ldK + br];
+        }
+        const uint64_t y = wave_transpose64(x);
+        const uint32_t r = br * 64 + lane;
+        if (r < K) Lt[((size_t)qq * H + j) * K + r] = y;
+    }
+}
+
+// est[u] += sum over the chunks q of this launch of popcount(AND_j Lt[q][j][h_j(u)]).
+// A workgroup owns kUPT nodes u per thread and a range of chunks; the tables
+// of G hashes of one chunk are staged in LDS at a time, and the AND of a
+// chunk is carried in registers across the hash groups.
+constexpr int kUPT = 8;
+constexpr int kQB = 4;
+__global__ void __launch_bounds__(512)
+k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *__restrict__ bucket,
+                const uint64_t *__restrict__ Lt, uint32_t q_begin, uint32_t q_end, uint32_t q0,
+                int32_t *__restrict__ est) {
+    extern __shared__ uint64_t tab[];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t ubase = (uint64_t)blockIdx.x * blockDim.x * kUPT;
+    uint32_t u[kUPT];
+    int32_t cnt[kUPT];
+#pragma unroll
+    for (int k = 0; k < kUPT; ++k) {
+        const uint64_t uu = ubase + tid + (uint64_t)k * blockDim.x;
+        u[k] = uu < n ? (uint32_t)uu : 0xffffffffu;
+        cnt[k] = 0;
+    }
+    for (uint32_t qb = q_begin; qb < q_end; qb += kQB) {
+        const uint32_t nqb = min((uint32_t)kQB, q_end - qb);
+        uint64_t acc[kQB][kUPT];
+#pragma unroll
+        for (int a = 0; a < kQB; ++a) {
+            // nodes past n in the last chunk never count
+            const uint64_t first = (uint64_t)(qb + a) * 64;
+            const uint64_t valid = (a < (int)nqb && first < n)
+                                       ? ((n - first >= 64) ? ~0ull : ((1ull << (n - first)) - 1ull))
+                                       : 0ull;
+#pragma unroll
+            for (int k = 0; k < kUPT; ++k) acc[a][k] = valid;
+        }
+        for (uint32_t j0 = 0; j0 < H; j0 += G) {
+            const uint32_t g = min(G, H - j0);
+            uint32_t b[kUPT][4];
+            // buckets of this hash group (G <= 4)
+#pragma unroll
+            for (int k = 0; k < kUPT; ++k)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    b[k][jj] = (u[k] != 0xffffffffu && jj < (int)g) ? bucket[(size_t)(j0 + jj) * n + u[k]] : 0u;
+#pragma unroll
+            for (int a = 0; a < kQB; ++a) {
+                if (a >= (int)nqb) break;
+                const uint64_t *src = Lt + ((size_t)(qb + a - q0) * H + j0) * K;
+                __syncthreads();
+                for (uint32_t i = tid; i < g * K; i += blockDim.x) tab[i] = src[i];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kUPT; ++k)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        if (jj < (int)g) acc[a][k] &= tab[(size_t)jj * K + b[k][jj]];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < kQB; ++a)
+#pragma unroll
+            for (int k = 0; k < kUPT; ++k) cnt[k] += __popcll(acc[a][k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kUPT; ++k)
+        if (u[k] != 0xffffffffu && cnt[k]) atomicAdd(est + u[k], cnt[k]);
+}
+
+uint32_t grid_for(size_t items, uint32_t per_block, uint32_t cap = 65536) {
+    size_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+hipError_t launch_hash_buckets(uint32_t n, uint32_t H, const uint64_t *coeffs, int order, uint32_t K,
+                               uint32_t *bucket, int32_t *count, hipStream_t st) {
+    const size_t total = (size_t)n * H;
+    hipLaunchKernelGGL(k_hash_buckets, dim3(grid_for(total, 256)), dim3(256), 0, st, n, H, coeffs,
+                       order, K, bucket);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for((size_t)H * K, 256)), dim3(256), 0, st, count,
+                       (size_t)H * K);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_counts, dim3(grid_for(total, 256)), dim3(256), 0, st, n, H, K,
+                       bucket, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_proxies(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
+                                    uint64_t *PT, hipStream_t st) {
+    const size_t kw = (K + 63) / 64;
+    hipLaunchKernelGGL(k_transpose_proxies, dim3(grid_for((size_t)H * kw * kw * 64, 256)), dim3(256),
+                       0, st, H, K, ldK, P, PT);
+    return hipGetLastError();
+}
+
+hipError_t launch_lifted_sizes(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
+                               const uint32_t *bucket, const int32_t *count, int32_t *rowsum,
+                               int32_t *lifted, hipStream_t st) {
+    hipLaunchKernelGGL(k_lifted_row_sums, dim3(grid_for((size_t)H * K * 64, 256)), dim3(256), 0, st,
+                       H, K, ldK, P, count, rowsum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lifted_sizes, dim3(grid_for((size_t)n * H, 256)), dim3(256), 0, st, n, H,
+                       bucket, rowsum, K, lifted);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t *p, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *PT,
+                               const uint32_t *bucket, uint32_t q0, uint32_t nq, uint64_t *Lt,
+                               hipStream_t st) {
+    const size_t kw = (K + 63) / 64;
+    hipLaunchKernelGGL(k_build_lifted, dim3(grid_for((size_t)nq * H * kw * 64, 256)), dim3(256), 0,
+                       st, n, H, K, ldK, PT, bucket, q0, nq, Lt);
+    return hipGetLastError();
+}
+
+uint32_t recombine_group(uint32_t K) {
+    const size_t budget = 160 * 1024;
+    size_t g = budget / ((size_t)K * 8);
+    if (g > 4) g = 4;
+    return (uint32_t)g;
+}
+
+hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32_t *bucket,
+                                const uint64_t *Lt, uint32_t q0, uint32_t nq, int32_t *est,
+                                hipStream_t st) {
+    const uint32_t G = recombine_group(K);
+    const size_t lds = (size_t)G * K * 8;
+    hipError_t e = hipFuncSetAttribute((const void *)k_recombine_est,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const uint32_t threads = 512;
+    const uint32_t utiles = (uint32_t)((n + (size_t)threads * kUPT - 1) / ((size_t)threads * kUPT));
+    // split the chunk range so that the launch has enough workgroups
+    uint32_t splits = 1;
+    while ((size_t)utiles * splits < 1024 && splits * kQB * 2 <= nq) splits *= 2;
+    const uint32_t per = ((nq + splits - 1) / splits + kQB - 1) / kQB * kQB;
+    for (uint32_t s = 0; s < splits; ++s) {
+        const uint32_t qb = q0 + s * per;
+        const uint32_t qe = min(q0 + nq, qb + per);
+        if (qb >= qe) break;
+        hipLaunchKernelGGL(k_recombine_est, dim3(utiles), dim3(threads), lds, st, n, H, K, G, bucket,
+                           Lt, qb, qe, q0, est);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace tn

@@ -55,14 +55,93 @@ struct DevSchedule {
 
 // Validates events and builds the schedule.  Returns TN_OK or an error code
 // with `err` set.
+// With `map`, event endpoints are ids < n_src sent through map[] to the n
+// nodes of a hashed network.
 tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
                       const uint32_t *dst, const int64_t *t, uint32_t flags,
-                      HostSchedule &out, std::string &err);
+                      HostSchedule &out, std::string &err,
+                      const uint32_t *map = nullptr, uint32_t n_src = 0);
 
 // Size in bytes of the device image of a schedule and its packing.
 size_t schedule_device_bytes(const HostSchedule &s);
 void schedule_pack(const HostSchedule &s, std::vector<unsigned char> &image);
 DevSchedule schedule_view(const HostSchedule &s, const void *dev_base);
+
+// ---- error reporting and device scope (tn_abi.cpp) ---------------------
+tn_status fail(tn_status code, const std::string &msg);
+tn_status hip_fail(hipError_t e, const char *what);
+tn_status not_built(const char *what);
+
+// Makes a device current for the scope of an entry point.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace tn
+
+struct tn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int num_cus = 0;
+    // kernel timing (tn_profile_enable)
+    bool profiling = false;
+    struct Rec {
+        int32_t id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+struct tn_plan {
+    int device = 0;
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    tn::DevSchedule view{};
+    tn_plan_stats stats{};
+};
+
+namespace tn {
+// Brackets one kernel launch with events on the context's stream when
+// profiling is on.
+struct ProfScope {
+    tn_ctx *c;
+    size_t idx = (size_t)-1;
+    ProfScope(tn_ctx *ctx, int32_t id) : c(ctx) {
+        if (!c->profiling) return;
+        hipEvent_t ev[2];
+        for (int i = 0; i < 2; ++i) {
+            if (!c->pool.empty()) {
+                ev[i] = c->pool.back();
+                c->pool.pop_back();
+            } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+                for (int k = 0; k < i; ++k) c->pool.push_back(ev[k]);
+                return;
+            }
+        }
+        (void)hipEventRecord(ev[0], c->stream);
+        c->recs.push_back({id, ev[0], ev[1]});
+        idx = c->recs.size() - 1;
+    }
+    ~ProfScope() {
+        if (idx != (size_t)-1) (void)hipEventRecord(c->recs[idx].b, c->stream);
+    }
+};
+
+// Grows the context scratch to at least `bytes`.
+tn_status ensure_scratch(tn_ctx *ctx, size_t bytes);
+void fill_stats(const HostSchedule &hs, tn_plan_stats &s);
 
 // ---- kernel launchers (tn_kernels.hip) ---------------------------------
 hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, hipStream_t st);

@@ -35,62 +35,143 @@ __global__ void __launch_bounds__(256) k_identity(uint64_t *__restrict__ C, uint
 
 // One workgroup per slice of SW word columns; SW consecutive lanes update the
 // SW words of one item's rows, so each row access is one contiguous
-// 8*SW-byte segment.  Each lane group takes U items of a level at a time and
-// issues all their loads before any store.
-template <int SW, int U>
+// 8*SW-byte segment.  Per level, a lane group holds up to U pair items (and
+// UG compound-item gathers) in registers and issues all their row loads before
+// any store.  The level boundaries are staged in LDS a window ahead and the
+// items of the next level are loaded while the current level runs, so a level
+// costs one round trip for its rows plus the store acknowledgement its
+// closing barrier waits for.  A level with compound items keeps the gathered
+// rows in registers across one extra barrier (read all, then write all).
+constexpr uint32_t kLevelWindow = 512;
+
+template <int U>
+__device__ __forceinline__ void load_items(uint2 (&it)[U], const uint2 *__restrict__ pairs,
+                                           uint32_t first, uint32_t end, uint32_t ngrp) {
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const uint32_t idx = first + k * ngrp;
+        it[k] = (idx < end) ? pairs[idx] : make_uint2(0xffffffffu, 0u);
+    }
+}
+
+template <int U>
+__device__ __forceinline__ void load_rows(const uint64_t *__restrict__ C, size_t ldz, uint32_t w,
+                                          bool wok, const uint2 (&it)[U], uint64_t (&a)[U],
+                                          uint64_t (&b)[U]) {
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        if (it[k].x != 0xffffffffu && wok) {
+            a[k] = C[(size_t)it[k].x * ldz + w];
+            b[k] = C[(size_t)(it[k].y & kNodeMask) * ldz + w];
+        }
+    }
+}
+
+template <int U>
+__device__ __forceinline__ void store_rows(uint64_t *__restrict__ C, size_t ldz, uint32_t w, bool wok,
+                                           const uint2 (&it)[U], const uint64_t (&a)[U],
+                                           const uint64_t (&b)[U]) {
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        if (it[k].x != 0xffffffffu && wok) {
+            const uint64_t r = a[k] | b[k];
+            C[(size_t)it[k].x * ldz + w] = r;
+            if (!(it[k].y & kDirBit)) C[(size_t)(it[k].y & kNodeMask) * ldz + w] = r;
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t gather_row(const uint64_t *__restrict__ C, size_t ldz, uint32_t w,
+                                               const DevSchedule &s, uint32_t gi) {
+    uint64_t acc = 0;
+    const uint32_t s0 = s.gat_ptr[gi], s1 = s.gat_ptr[gi + 1];
+    for (uint32_t q = s0; q < s1; ++q) acc |= C[(size_t)s.gat_src[q] * ldz + w];
+    return acc;
+}
+
+template <int SW, int U, int UG>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevSchedule s,
                uint64_t *__restrict__ scratch) {
+    __shared__ uint32_t win_p[2][kLevelWindow];
+    __shared__ uint32_t win_g[2][kLevelWindow];
     const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
     const uint32_t w = slice * SW + (threadIdx.x % SW);
     const bool wok = w < nwords;
     const uint32_t grp = threadIdx.x / SW;
     const uint32_t ngrp = blockDim.x / SW;
+    const uint32_t chunk = ngrp * U;
     const size_t ldz = (size_t)ld;
-    uint32_t p0 = s.lvl_pair[0];
-    uint32_t g0 = s.lvl_gat[0];
-    for (uint32_t l = 0; l < s.L; ++l) {
-        const uint32_t p1 = s.lvl_pair[l + 1];
-        const uint32_t g1 = s.lvl_gat[l + 1];
-        for (uint32_t base = p0 + grp; base < p1; base += ngrp * U) {
-            uint2 it[U];
-            uint64_t a[U], b[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const uint32_t idx = base + k * ngrp;
-                it[k] = (idx < p1) ? s.pairs[idx] : make_uint2(0xffffffffu, 0u);
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                if (it[k].x != 0xffffffffu && wok) {
-                    a[k] = C[(size_t)it[k].x * ldz + w];
-                    b[k] = C[(size_t)(it[k].y & kNodeMask) * ldz + w];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                if (it[k].x != 0xffffffffu && wok) {
-                    const uint64_t r = a[k] | b[k];
-                    C[(size_t)it[k].x * ldz + w] = r;
-                    if (!(it[k].y & kDirBit)) C[(size_t)(it[k].y & kNodeMask) * ldz + w] = r;
-                }
+    const uint32_t L = s.L;
+    // level boundaries of window 0 and 1 (entries past L repeat entry L)
+    for (uint32_t i = threadIdx.x; i < 2 * kLevelWindow; i += blockDim.x) {
+        const uint32_t l = min(i, L);
+        win_p[i / kLevelWindow][i % kLevelWindow] = s.lvl_pair[l];
+        win_g[i / kLevelWindow][i % kLevelWindow] = s.lvl_gat[l];
+    }
+    __syncthreads();
+    auto lp = [&](uint32_t l) { return win_p[(l / kLevelWindow) & 1u][l % kLevelWindow]; };
+    auto lg = [&](uint32_t l) { return win_g[(l / kLevelWindow) & 1u][l % kLevelWindow]; };
+    uint32_t p0 = lp(0), p1 = lp(1);
+    uint32_t g0 = lg(0);
+    uint2 cur[U];
+    load_items<U>(cur, s.pairs, p0 + grp, p1, ngrp);
+    for (uint32_t l = 0; l < L; ++l) {
+        if (l % kLevelWindow == 0 && l > 0) {
+            // refill the buffer of the window before this one with the window
+            // after it; it was last read three levels ago, before a barrier
+            const uint32_t nb = l / kLevelWindow + 1;
+            for (uint32_t i = threadIdx.x; i < kLevelWindow; i += blockDim.x) {
+                const uint32_t ll = min(nb * kLevelWindow + i, L);
+                win_p[nb & 1u][i] = s.lvl_pair[ll];
+                win_g[nb & 1u][i] = s.lvl_gat[ll];
             }
         }
-        if (g1 > g0) {
-            // compound items: read every old row, then write (two phases)
-            for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp) {
-                uint64_t acc = 0;
-                const uint32_t s0 = s.gat_ptr[gi], s1 = s.gat_ptr[gi + 1];
-                if (wok)
-                    for (uint32_t q = s0; q < s1; ++q) acc |= C[(size_t)s.gat_src[q] * ldz + w];
-                if (wok) scratch[(size_t)(gi - g0) * nwords + w] = acc;
+        const uint32_t p2 = lp(min(l + 2, L));
+        const uint32_t g1 = lg(l + 1);
+        uint2 nxt[U];
+        load_items<U>(nxt, s.pairs, p1 + grp, p2, ngrp);
+        uint64_t a[U], b[U];
+        load_rows<U>(C, ldz, w, wok, cur, a, b);
+        const uint32_t ng = g1 - g0;
+        uint64_t gacc[UG];
+        if (ng > 0 && ng <= ngrp * UG) {
+#pragma unroll
+            for (int k = 0; k < UG; ++k) {
+                const uint32_t gi = g0 + grp + k * ngrp;
+                if (gi < g1 && wok) gacc[k] = gather_row(C, ldz, w, s, gi);
             }
-            __syncthreads();
-            for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp)
-                if (wok) C[(size_t)s.gat_tgt[gi] * ldz + w] = scratch[(size_t)(gi - g0) * nwords + w];
+        }
+        store_rows<U>(C, ldz, w, wok, cur, a, b);
+        // levels wider than one register chunk
+        for (uint32_t base = p0 + chunk + grp; base < p1; base += chunk) {
+            uint2 more[U];
+            load_items<U>(more, s.pairs, base, p1, ngrp);
+            load_rows<U>(C, ldz, w, wok, more, a, b);
+            store_rows<U>(C, ldz, w, wok, more, a, b);
+        }
+        if (ng > 0) {
+            if (ng <= ngrp * UG) {
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < UG; ++k) {
+                    const uint32_t gi = g0 + grp + k * ngrp;
+                    if (gi < g1 && wok) C[(size_t)s.gat_tgt[gi] * ldz + w] = gacc[k];
+                }
+            } else {
+                // more gathers than register slots: stage through scratch rows
+                for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp)
+                    if (wok) scratch[(size_t)(gi - g0) * nwords + w] = gather_row(C, ldz, w, s, gi);
+                __syncthreads();
+                for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp)
+                    if (wok) C[(size_t)s.gat_tgt[gi] * ldz + w] = scratch[(size_t)(gi - g0) * nwords + w];
+            }
         }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < U; ++k) cur[k] = nxt[k];
         p0 = p1;
+        p1 = p2;
         g0 = g1;
     }
 }
@@ -166,11 +247,11 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
     }
 }
 
-template <int SW, int U>
+template <int SW, int U, int UG = 1>
 hipError_t rowor_variant(const DevSchedule &s, uint64_t *C, int64_t ld, uint32_t nwords,
                          uint64_t *scratch, hipStream_t st) {
     const uint32_t slices = (nwords + SW - 1) / SW;
-    hipLaunchKernelGGL((k_rowor_global<SW, U>), dim3(slices), dim3(1024), 0, st, C, ld, nwords, s,
+    hipLaunchKernelGGL((k_rowor_global<SW, U, UG>), dim3(slices), dim3(1024), 0, st, C, ld, nwords, s,
                        scratch);
     return hipGetLastError();
 }
@@ -200,9 +281,9 @@ hipError_t launch_rowor_global(const DevSchedule &s, uint64_t *C, int64_t ld, ui
     const uint32_t nwords = (s.n + 63) / 64;
     if (s.L == 0) return hipSuccess;
     switch (slice_words) {
-        case 1: return rowor_variant<1, 4>(s, C, ld, nwords, scratch, st);
-        case 2: return rowor_variant<2, 4>(s, C, ld, nwords, scratch, st);
-        case 4: return rowor_variant<4, 8>(s, C, ld, nwords, scratch, st);
+        case 1: return rowor_variant<1, 2>(s, C, ld, nwords, scratch, st);
+        case 2: return rowor_variant<2, 2>(s, C, ld, nwords, scratch, st);
+        case 4: return rowor_variant<4, 4>(s, C, ld, nwords, scratch, st);
         case 8: return rowor_variant<8, 8>(s, C, ld, nwords, scratch, st);
         case 16: return rowor_variant<16, 8>(s, C, ld, nwords, scratch, st);
         case 32: return rowor_variant<32, 8>(s, C, ld, nwords, scratch, st);

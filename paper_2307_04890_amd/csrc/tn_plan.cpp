@@ -76,15 +76,20 @@ struct Planner {
         plev.push_back(lvl);
     }
 
-    // events [a, b) share one time step (or a == b - 1 in sequential mode)
-    void group(const uint32_t *src, const uint32_t *dst, int64_t a, int64_t b) {
+    // events [a, b) share one time step (or a == b - 1 in sequential mode);
+    // node ids pass through `map` when it is given (hashed networks)
+    void group(const uint32_t *src, const uint32_t *dst, const uint32_t *map, int64_t a,
+               int64_t b) {
         es.clear();
         ed.clear();
-        for (int64_t e = a; e < b; ++e)
-            if (src[e] != dst[e]) {
-                es.push_back(src[e]);
-                ed.push_back(dst[e]);
+        for (int64_t e = a; e < b; ++e) {
+            const uint32_t x = map ? map[src[e]] : src[e];
+            const uint32_t y = map ? map[dst[e]] : dst[e];
+            if (x != y) {
+                es.push_back(x);
+                ed.push_back(y);
             }
+        }
         const size_t k = es.size();
         if (k == 0) return;
         if (k == 1) {
@@ -206,7 +211,8 @@ struct Planner {
 
 tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
                       const uint32_t *dst, const int64_t *t, uint32_t flags,
-                      HostSchedule &out, std::string &err) {
+                      HostSchedule &out, std::string &err, const uint32_t *map,
+                      uint32_t n_src) {
     auto t0 = std::chrono::steady_clock::now();
     if (n == 0) { err = "n must be > 0"; return TN_E_ARG; }
     if (m < 0) { err = "m must be >= 0"; return TN_E_ARG; }
@@ -214,8 +220,15 @@ tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
     if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL)) { err = "unknown flag bits"; return TN_E_ARG; }
     if (n > kNodeMask) { err = "n must be < 2^31"; return TN_E_UNSUPPORTED; }
     if (m >= (int64_t)0xffffffffLL) { err = "m must be < 2^32 - 1"; return TN_E_UNSUPPORTED; }
+    const uint32_t id_limit = map ? n_src : n;
+    if (map)
+        for (uint32_t x = 0; x < n_src; ++x)
+            if (map[x] >= n) {
+                err = "node map sends node " + std::to_string(x) + " past the last super-node";
+                return TN_E_RANGE;
+            }
     for (int64_t e = 0; e < m; ++e) {
-        if (src[e] >= n || dst[e] >= n) {
+        if (src[e] >= id_limit || dst[e] >= id_limit) {
             err = "event " + std::to_string(e) + " has a node id >= n";
             return TN_E_RANGE;
         }
@@ -235,7 +248,7 @@ tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
         int64_t a = b - 1;
         if (!seq)
             while (a > 0 && t[a - 1] == t[b - 1]) --a;
-        p.group(src, dst, a, b);
+        p.group(src, dst, map, a, b);
         b = a;
     }
     // counting sort by level

@@ -1,0 +1,100 @@
+"""GPU parity of the persistent multi-network kernel (LDS and global tiles,
+work queues, autotuned shape, HIP graph replays) against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tn_inputs as T
+
+pytestmark = pytest.mark.gpu
+
+tn = pytest.importorskip("paper_2307_04890_amd")
+
+
+def host(C):
+    torch.cuda.synchronize()
+    return C.cpu().numpy().view(np.uint64)
+
+
+def suite(seed=0):
+    nets = []
+    sizes = [2, 3, 63, 64, 65, 129, 500, 1000, 2047, 5000, 20000, 30000]
+    for i, n in enumerate(sizes):
+        m = min(3 * n, 60000)
+        if i % 3 == 0:
+            s, d, t = T.uniform_pairs(n, m, max(1, m // 4), seed=seed + i)
+        elif i % 3 == 1:
+            s, d, t = T.activity_driven(n, m, max(1, m // 5), seed=seed + i)
+        else:
+            s, d, t = T.random_tiny(n, m, max(1, m // 3), seed=seed + i, allow_self=True)
+        nets.append((n, s, d, t))
+    nets.append((700, np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.int64)))
+    return nets
+
+
+def check(nets, Cs, **kw):
+    for (n, s, d, t), C in zip(nets, Cs):
+        got = host(C)
+        want = oracle.reverse_matrix(n, s, d, t, **kw)
+        assert (got[:, :oracle.words(n)] == want).all(), n
+        assert not got[:, oracle.words(n):].any(), n
+
+
+def test_batch_matches_oracle_and_uses_both_tile_kinds():
+    nets = suite()
+    b = tn.Batch(nets)
+    stats, tiles, lds_tiles = b.stats()
+    assert tiles >= len(nets) and 0 < lds_tiles < tiles  # n = 30000 needs global tiles
+    Cs = b.execute()
+    check(nets, Cs)
+    b.close()
+
+
+@pytest.mark.parametrize("flags", [tn.DIRECTED, tn.TIES_SEQUENTIAL, tn.DIRECTED | tn.TIES_SEQUENTIAL])
+def test_batch_flags(flags):
+    nets = [net for net in suite(100) if net[0] <= 5000]
+    Cs = tn.build_component_matrix_batched(nets, flags=flags)
+    check(nets, Cs, directed=bool(flags & 1), sequential=bool(flags & 2))
+
+
+def test_graph_replays_and_rebinding():
+    nets = suite(200)
+    b = tn.Batch(nets)
+    Cs = b.alloc()
+    for rep in range(3):
+        for C in Cs:
+            C.fill_(-1)  # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        b.execute(Cs)
+        check(nets, Cs)
+        assert torch.isfinite(junk)
+    # new outputs with padded rows
+    Ds = [torch.full((n, oracle.words(n) + 2), -1, dtype=torch.int64, device="cuda")
+          for (n, _, _, _) in nets]
+    b.execute(Ds)
+    check(nets, Ds)
+    b.execute(Cs)
+    check(nets, Cs)
+    b.close()
+
+
+def test_many_uneven_networks_one_launch():
+    specs = T.batched_suite(48, seed=4000, n_range=(500, 6000), m_range=(10_000, 60_000))
+    nets = [(sp.n,) + sp.generate() for sp in specs]
+    Cs = tn.Batch(nets).execute()
+    for (n, s, d, t), C in zip(nets[::6], Cs[::6]):
+        assert (host(C) == oracle.reverse_matrix(n, s, d, t)).all(), n
+    for (n, s, d, t), C in zip(nets, Cs):
+        out, inn = tn.component_sizes(C, n)
+        o, i = out.cpu().numpy(), inn.cpu().numpy()
+        assert o.sum() == i.sum() and (o >= 1).all()
+
+
+def test_batch_errors():
+    with pytest.raises(tn.TNError) as e:
+        tn.Batch([(10, [0], [11], [0])])
+    assert e.value.code == -2
+    with pytest.raises(tn.TNError) as e:
+        tn.Batch([(10, [0, 1], [1, 2], [3, 2])])
+    assert e.value.code == -3

@@ -1,0 +1,111 @@
+"""GPU parity of network hashing (Sec. 4.1), the hashed proxies built in one
+batched launch (Sec. 4.3) and the fusion estimator (Sec. 4.2) against the CPU
+oracle; bit-exact buckets, proxies and estimates."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tn_inputs as T
+
+pytestmark = pytest.mark.gpu
+
+tn = pytest.importorskip("paper_2307_04890_amd")
+
+
+def host(C):
+    torch.cuda.synchronize()
+    return C.cpu().numpy().view(np.uint64)
+
+
+def run_hashed(n, s, d, t, H, K, seed, flags=0):
+    A = T.hash_coefficients(H, seed=seed)
+    bucket, count, proxies = tn.hash_compress(n, s, d, t, A, K, flags=flags)
+    ldK = oracle.words(K)
+    P = torch.empty((H, K, ldK), dtype=torch.int64, device="cuda")
+    proxies.execute([P[j] for j in range(H)])
+    est, lifted = tn.recombine(P, bucket, count, n)
+    torch.cuda.synchronize()
+    return A, bucket.cpu().numpy().view(np.uint32), count.cpu().numpy(), host(P), \
+        est.cpu().numpy(), lifted.cpu().numpy(), proxies
+
+
+@pytest.mark.parametrize("n,m,H,K", [(300, 900, 3, 40), (2000, 8000, 4, 64), (5000, 30000, 5, 1500),
+                                     (3000, 12000, 2, 4096)])
+def test_hash_proxies_and_recombine_match_oracle(n, m, H, K):
+    s, d, t = T.uniform_pairs(n, m, m // 3, seed=n + K)
+    A, bucket, count, P, est, lifted, _ = run_hashed(n, s, d, t, H, K, seed=K)
+    wb = oracle.hash_nodes(n, A, K)
+    assert (bucket == wb).all()
+    assert (count == oracle.bucket_counts(wb, K)).all()
+    WP = oracle.proxies(K, s, d, t, wb)
+    assert (P == WP).all()
+    us = np.arange(n) if n <= 2000 else T.rng(1).choice(n, 300, replace=False)
+    we, wl = oracle.recombine(n, WP, wb, us)
+    assert (est[us] == we).all()
+    assert (lifted[:, us] == wl).all()
+
+
+def test_estimator_properties_against_exact_gpu_path():
+    n, m, H, K = 6000, 15000, 8, 300
+    s, d, t = T.activity_driven(n, m, 2000, seed=12)
+    A, bucket, count, P, est, lifted, _ = run_hashed(n, s, d, t, H, K, seed=13)
+    C = tn.build_component_matrix(n, s, d, t)
+    exact, _ = tn.component_sizes(C, n, inn=False)
+    exact = exact.cpu().numpy()
+    assert (exact <= est).all()                 # superset property (Sec. 4.2)
+    assert (est <= lifted.min(axis=0)).all() and (lifted <= n).all()
+    assert (est >= 1).all()
+
+
+def test_identity_and_single_bucket_maps():
+    n = 700
+    s, d, t = T.uniform_pairs(n, 1200, 500, seed=3)
+    C = tn.build_component_matrix(n, s, d, t)
+    exact, _ = tn.component_sizes(C, n, inn=False)
+    ident = torch.arange(n, dtype=torch.int32, device="cuda")[None, :].contiguous()
+    cnt = torch.ones((1, n), dtype=torch.int32, device="cuda")
+    est, lifted = tn.recombine(C[None].contiguous(), ident, cnt, n)
+    assert (est == exact).all() and (lifted[0] == exact).all()
+    P1 = torch.ones((2, 1, 1), dtype=torch.int64, device="cuda")
+    zero = torch.zeros((2, n), dtype=torch.int32, device="cuda")
+    cnt1 = torch.full((2, 1), n, dtype=torch.int32, device="cuda")
+    est1, lifted1 = tn.recombine(P1, zero, cnt1, n)
+    assert (est1 == n).all() and (lifted1 == n).all()
+
+
+def test_hashed_directed_and_sequential():
+    n, m, H, K = 1500, 5000, 3, 100
+    s, d, t = T.random_tiny(n, m, 800, seed=9)
+    for flags in (1, 2):
+        A, bucket, count, P, est, lifted, _ = run_hashed(n, s, d, t, H, K, seed=flags, flags=flags)
+        WP = oracle.proxies(K, s, d, t, oracle.hash_nodes(n, A, K), directed=bool(flags & 1),
+                            sequential=bool(flags & 2))
+        assert (P == WP).all()
+
+
+def test_activity_driven_scaled_hashed_workload():
+    # the shape of the n = 10^6, m = 10^8, H = 16, K = 4096 workload at 1/20 of the events
+    n, m, H, K = 200_000, 5_000_000, 16, 4096
+    s, d, t = T.activity_driven(n, m, 500_000, seed=3)
+    A, bucket, count, P, est, lifted, proxies = run_hashed(n, s, d, t, H, K, seed=1003)
+    wb = oracle.hash_nodes(n, A, K)
+    assert (bucket == wb).all()
+    for j in (0, 7):
+        assert (P[j] == oracle.reverse_matrix(K, wb[j][s], wb[j][d], t)).all(), j
+    us = T.rng(5).choice(n, 64, replace=False)
+    we, wl = oracle.recombine(n, P, wb, us)
+    assert (est[us] == we).all() and (lifted[:, us] == wl).all()
+    stats, tiles, lds_tiles = proxies.stats()
+    assert lds_tiles == tiles  # K = 4096 proxies are LDS-resident
+
+
+def test_hash_errors():
+    with pytest.raises(tn.TNError) as e:
+        tn.hash_compress(10, [0], [1], [0], T.hash_coefficients(2, 1), 70000)
+    assert e.value.code == -6
+    bad = T.hash_coefficients(1, 1)
+    bad[0, 0, 0] = (1 << 61) - 1
+    with pytest.raises(tn.TNError) as e:
+        tn.hash_compress(10, [0], [1], [0], bad, 8)
+    assert e.value.code == -1
