@@ -266,15 +266,29 @@ tn_status tn_mlp_features(tn_ctx *ctx, uint32_t n, uint32_t H,
 tn_status tn_mlp_forward(tn_ctx *ctx, const float *params, const float *x,
                          int64_t N, float *yhat);
 
+/* Size estimates from the network's output: sizes[i] = n_nodes * exp(yhat)
+ * where yhat = MLP(x[i]), clamped to [1, est[i]] when est is not NULL (the
+ * fusion estimate is an upper bound of the true size) and to [1, n_nodes]
+ * otherwise.  params, x: DEVICE; est: DEVICE int32[N] or NULL; sizes:
+ * DEVICE float[N]. */
+tn_status tn_mlp_predict(tn_ctx *ctx, const float *params, const float *x,
+                         int64_t N, uint32_t n_nodes, const int32_t *est,
+                         float *sizes);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, 1-based
- * step) on the mean squared error over the N samples (x, y).
- * params, adam_m, adam_v: DEVICE float[tn_mlp_param_count()], updated in
- * place.  loss: DEVICE float[1] or NULL, receives the loss before the step.
- * grad: DEVICE float[param count] or NULL, receives the gradient. */
+ * step) on the mean squared error over N samples.  Sample s is row idx[s] of
+ * x / entry idx[s] of y when idx is not NULL (a minibatch drawn from a
+ * resident dataset; every idx[s] must index a row of x), else row s.
+ * params, adam_m, adam_v: DEVICE
+ * float[tn_mlp_param_count()], updated in place.  x: DEVICE float rows of
+ * 16; y: DEVICE float; idx: DEVICE int32[N] or NULL.  loss: DEVICE float[1]
+ * or NULL, receives the loss before the step.  grad: DEVICE float[param
+ * count] or NULL, receives the gradient.  The gradient is summed in a fixed
+ * order, so equal inputs give bit-equal results. */
 tn_status tn_mlp_train_step(tn_ctx *ctx, float *params, float *adam_m,
                             float *adam_v, int64_t step, const float *x,
-                            const float *y, int64_t N, float lr, float *loss,
-                            float *grad);
+                            const float *y, const int32_t *idx, int64_t N,
+                            float lr, float *loss, float *grad);
 
 #ifdef __cplusplus
 }

@@ -80,7 +80,8 @@ SIGNATURES = {
     "tn_mlp_param_count": (_i32, []),
     "tn_mlp_features": (_i32, [_P, _u32, _u32, _P, _P]),
     "tn_mlp_forward": (_i32, [_P, _P, _P, _i64, _P]),
-    "tn_mlp_train_step": (_i32, [_P, _P, _P, _P, _i64, _P, _P, _i64, _f32, _P, _P]),
+    "tn_mlp_predict": (_i32, [_P, _P, _P, _i64, _u32, _P, _P]),
+    "tn_mlp_train_step": (_i32, [_P, _P, _P, _P, _i64, _P, _P, _P, _i64, _f32, _P, _P]),
 }
 
 

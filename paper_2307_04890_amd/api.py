@@ -10,7 +10,7 @@ import torch
 
 from ._lib import DIRECTED, KERNELS, TIES_SEQUENTIAL, PlanStats, TNError, check, lib
 
-__all__ = ["Context", "Plan", "Batch", "hash_compress", "recombine", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+__all__ = ["Context", "Plan", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
 
@@ -315,3 +315,46 @@ def recombine(P: torch.Tensor, bucket: torch.Tensor, count: torch.Tensor, n: int
     check(lib.tn_recombine(ctx.bind_stream(), int(n), H, K, _dp(P), ldK, _dp(bucket), _dp(count),
                            _dp(est), _dp(lif)))
     return est, lif
+
+
+MLP_PARAMS = 5313
+
+
+def mlp_features(lifted: torch.Tensor, n: int, ctx: Context | None = None) -> torch.Tensor:
+    """x[u, j] = ln(lifted[j, u] / n) for H = 16 hashes: (n, 16) float32."""
+    ctx = ctx or get_context()
+    H = lifted.shape[0]
+    x = torch.empty((n, H), dtype=torch.float32, device=lifted.device)
+    check(lib.tn_mlp_features(ctx.bind_stream(), int(n), H, _dp(lifted), _dp(x)))
+    return x
+
+
+def mlp_forward(params: torch.Tensor, x: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
+    ctx = ctx or get_context()
+    N = x.shape[0]
+    yhat = torch.empty(N, dtype=torch.float32, device=x.device)
+    check(lib.tn_mlp_forward(ctx.bind_stream(), _dp(params), _dp(x), N, _dp(yhat)))
+    return yhat
+
+
+def mlp_train_step(params, adam_m, adam_v, step: int, x, y, idx=None, lr: float = 1e-3,
+                   want_grad: bool = False, ctx: Context | None = None):
+    """One Adam step in place; returns (loss (1,) tensor, gradient or None)."""
+    ctx = ctx or get_context()
+    N = x.shape[0] if idx is None else idx.shape[0]
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device) if want_grad else None
+    check(lib.tn_mlp_train_step(ctx.bind_stream(), _dp(params), _dp(adam_m), _dp(adam_v),
+                                int(step), _dp(x), _dp(y), _dp(idx), N, float(lr), _dp(loss),
+                                _dp(grad)))
+    return loss, grad
+
+
+def mlp_predict(params, x, n: int, est=None, ctx: Context | None = None) -> torch.Tensor:
+    """Size estimates n * exp(MLP(x)) clamped to [1, est] (or [1, n])."""
+    ctx = ctx or get_context()
+    N = x.shape[0]
+    sizes = torch.empty(N, dtype=torch.float32, device=x.device)
+    check(lib.tn_mlp_predict(ctx.bind_stream(), _dp(params), _dp(x), N, int(n), _dp(est),
+                             _dp(sizes)))
+    return sizes

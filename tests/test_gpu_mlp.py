@@ -1,0 +1,96 @@
+"""GPU parity of the learned combiner's FP32 kernels against the float64
+reference: forward, gradient, Adam update, determinism, training progress."""
+import numpy as np
+import pytest
+import torch
+
+import tn_inputs as T
+from oracle import mlp as ref
+
+pytestmark = pytest.mark.gpu
+
+tn = pytest.importorskip("paper_2307_04890_amd")
+
+
+def batch(N, seed):
+    g = T.rng(seed)
+    x = g.normal(size=(N, 16)).astype(np.float32)
+    y = (np.tanh(x[:, :4].sum(axis=1)) + 0.1 * g.normal(size=N)).astype(np.float32)
+    return x, y
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_param_count_and_layout():
+    assert tn.lib.tn_mlp_param_count() == tn.MLP_PARAMS == T.mlp_param_count()
+
+
+@pytest.mark.parametrize("N", [1, 63, 64, 65, 1000, 4096])
+def test_forward_matches_reference(N):
+    p = T.mlp_init(1)
+    x, _ = batch(N, 2)
+    got = tn.mlp_forward(dev(p), dev(x)).cpu().numpy()
+    want, _ = ref.forward(p.astype(np.float64), x.astype(np.float64))
+    assert np.allclose(got, want, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("N", [64, 100, 4096])
+def test_gradient_and_adam_step_match_reference(N):
+    p = T.mlp_init(3)
+    x, y = batch(N, 4)
+    P, M, V = dev(p), torch.zeros(tn.MLP_PARAMS, device="cuda"), torch.zeros(tn.MLP_PARAMS, device="cuda")
+    pd = p.astype(np.float64)
+    m = np.zeros_like(pd)
+    v = np.zeros_like(pd)
+    for step in (1, 2, 3):
+        loss, g = tn.mlp_train_step(P, M, V, step, dev(x), dev(y), lr=1e-3, want_grad=True)
+        gr = ref.grad(pd, x.astype(np.float64), y.astype(np.float64))
+        lref = ref.loss(pd, x.astype(np.float64), y.astype(np.float64))
+        g = g.cpu().numpy()
+        assert np.max(np.abs(g - gr)) <= 1e-4 * np.max(np.abs(gr)) + 1e-7
+        assert abs(loss.item() - lref) <= 1e-5 * max(1.0, lref)
+        pd, m, v = ref.adam_step(pd, m, v, g.astype(np.float64), step)
+        got = P.cpu().numpy()
+        # same gradient in, so the update agrees to FP32 rounding
+        assert np.max(np.abs(got - pd)) <= 1e-6 + 1e-5 * np.max(np.abs(pd))
+
+
+def test_minibatch_indices_equal_gathered_rows():
+    p = T.mlp_init(5)
+    x, y = batch(3000, 6)
+    idx = T.rng(7).permutation(3000)[:1024].astype(np.int32)
+    P1, P2 = dev(p), dev(p)
+    z = lambda: torch.zeros(tn.MLP_PARAMS, device="cuda")
+    M1, V1, M2, V2 = z(), z(), z(), z()
+    l1, g1 = tn.mlp_train_step(P1, M1, V1, 1, dev(x), dev(y), idx=dev(idx), want_grad=True)
+    l2, g2 = tn.mlp_train_step(P2, M2, V2, 1, dev(x[idx]), dev(y[idx]), want_grad=True)
+    assert torch.equal(g1, g2) and torch.equal(P1, P2) and torch.equal(l1, l2)
+
+
+def test_training_is_deterministic_and_learns():
+    x, y = batch(8192, 8)
+    X, Y = dev(x), dev(y)
+    runs = []
+    for _ in range(2):
+        P = dev(T.mlp_init(9))
+        M, V = torch.zeros_like(P), torch.zeros_like(P)
+        losses = []
+        order = T.rng(10).permutation(8192).astype(np.int32)
+        I = dev(order)
+        for step in range(1, 301):
+            k = (step - 1) % 8
+            loss, _ = tn.mlp_train_step(P, M, V, step, X, Y, idx=I[k * 1024:(k + 1) * 1024], lr=3e-3)
+            losses.append(loss.item())
+        runs.append((P.cpu().numpy().copy(), losses))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    l = runs[0][1]
+    assert np.mean(l[-20:]) < 0.3 * np.mean(l[:20])
+
+
+def test_features_are_log_fractions():
+    n, H = 1000, 16
+    lifted = T.rng(11).integers(1, n + 1, size=(H, n)).astype(np.int32)
+    x = tn.mlp_features(dev(lifted), n).cpu().numpy()
+    assert np.allclose(x, np.log(lifted.T / n), rtol=1e-6, atol=1e-6)
