@@ -1,16 +1,29 @@
 #!/usr/bin/env python3
-"""Benchmark of the exact component-matrix path on one MI355X.
+"""Benchmarks of the temporal component-matrix library on one MI355X.
 
-One step = one pass of the exact path over the resident schedule of one
-network: C <- I, every level of reverse-time row ORs, then the out- and
-in-component sizes.  The default workload is the activity-driven network with
-n = 100,000 nodes and m = 10,000,000 events (T = 10^6 ticks).  The events,
-the schedule and the matrix are in HBM when the timed region starts; host
-planning time is reported separately.
+Default (--mode exact): one step = one pass of the exact path over the
+resident schedule of one network: C <- I, every level of reverse-time row
+ORs, then the out- and in-component sizes.  The workload is the
+activity-driven network with n = 100,000 nodes and m = 10,000,000 events
+(T = 10^6 ticks).  Events, schedule and matrix are in HBM when the timed
+region starts; host planning time is reported separately.
 
-Prints one JSON line: events/s over the timed steps, the roofline of the
-row-OR kernel (timed with HIP events on its own stream), and the CPU oracle's
-rate on a bounded column sample of the same workload.
+Other modes (each prints its own single JSON line):
+  --mode hashed    n = 10^6, m = 10^8 activity-driven, H = 16 hashes to
+                   K = 4096 super-nodes: all proxies in one persistent launch,
+                   then the fusion estimator.
+  --mode batched   256 uneven networks (n log-uniform in [500, 20000], m in
+                   [10^4, 10^6], uniform-pair and activity-driven) in one
+                   persistent autotuned launch under a HIP graph, against
+                   the plain kernel run network by network.
+  --mode combiner  the learned combiner trained on 64 networks (n = 20,000,
+                   m = 10^6) and evaluated on 4 held-out networks
+                   (n = 100,000, m = 10^7) against the exact sizes, beside the
+                   fusion estimate and the smallest lifted size.
+
+Each line carries the roofline of the mode's dominant kernel, timed with HIP
+events on the stream it runs on, and the CPU oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -25,6 +38,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
 METRIC = "events/s (exact & hashed) + % HBM roofline; combiner rel. err vs exact"
 
 
@@ -32,32 +47,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files) -> str:
     h = hashlib.sha256()
-    for f in ("tn_kernels.hip", "tn_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2307_04890_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM bytes per row-OR launch from committed rocprofv3 counters, if they
-    were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"rowor_{workload}_pmc.json")
+KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h"),
+                  "batch": ("tn_batch.hip", "tn_batch.h", "tn_internal.h"),
+                  "recombine": ("tn_hash.hip", "tn_hash.h")}
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counters
+    (profiles/<kernel>_<workload>_pmc.json), if they were taken on the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha") != kernel_source_hash():
+    if rec.get("kernel_source_sha") != kernel_source_hash(KERNEL_SOURCES[kernel]):
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
 def algorithmic_bytes(st: dict, n: int) -> float:
-    """Row transfers the definition needs per launch: an undirected pair reads
-    and writes two rows (4), a one-way pair reads two and writes one (3), a
-    compound gather reads its sources and writes its target; plus the schedule
-    read once."""
+    """Row transfers the definition needs: an undirected pair reads and writes
+    two rows (4), a one-way pair reads two and writes one (3), a compound
+    gather reads its sources and writes its target; plus the schedule once."""
     row = 8.0 * ((n + 63) // 64)
     sym = st["pairs"] - st["directed_pairs"]
     rows = 4.0 * sym + 3.0 * st["directed_pairs"] + st["gather_sources"] + st["gathers"]
@@ -66,7 +86,35 @@ def algorithmic_bytes(st: dict, n: int) -> float:
     return rows * row + sched
 
 
-def cpu_baseline(n, s, d, t, budget_s: float):
+def base_result(args, value, unit, steps, ms_per_step, config, dtype="u64"):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def timed(ctx, fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    recs = ctx.profile_take()
+    ctx.profile(False)
+    per = {}
+    for name, ms in recs:
+        per.setdefault(name, []).append(ms)
+    return elapsed, {k: sum(v) / len(v) for k, v in per.items()}, per
+
+
+# ---------------------------------------------------------------------------
+def cpu_baseline_exact(n, s, d, t, budget_s: float):
     import oracle
     nwords = (n + 63) // 64
     t0 = time.perf_counter()
@@ -81,38 +129,21 @@ def cpu_baseline(n, s, d, t, budget_s: float):
             "sample": f"reverse-time recurrence on word columns [0,{k}) of {nwords} "
                       f"({100.0 * k / nwords:.1f}% of the matrix), all {s.shape[0]} events; "
                       f"{dt:.2f} s single-threaded, scaled to the full width",
-            "seconds": dt}
+            "seconds": dt, "host_nproc": os.cpu_count()}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="activity_n100000_m10M")
-    ap.add_argument("--slice-words", type=int, default=0)
-    ap.add_argument("--cpu-budget", type=float, default=12.0,
-                    help="seconds of single-thread oracle work for the CPU baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="run one plain device copy of this size first (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "column sharding is a design, not built here", file=sys.stderr)
-        sys.exit(2)
-
+def run_exact(args):
     import numpy as np
     import torch
 
     import paper_2307_04890_amd as tn
     import tn_inputs as T
 
-    torch.cuda.set_device(0)
-    spec = T.WORKLOADS[args.workload]
+    workload = args.workload or "activity_n100000_m10M"
+    spec = T.WORKLOADS[workload]
     n = spec["n"]
-    log(f"[bench] generating {args.workload}")
-    s, d, t = T.make_workload(args.workload)
+    log(f"[bench] generating {workload}")
+    s, d, t = T.make_workload(workload)
     m = int(s.shape[0])
     log("[bench] planning on the host")
     t0 = time.perf_counter()
@@ -133,73 +164,376 @@ def main():
                                                 cp(out), cp(inn)))
 
     if args.calibrate_copy_mib:
-        nbytes = args.calibrate_copy_mib << 20
-        a = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
-        del a, b
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    recs = ctx.profile_take()
-    ctx.profile(False)
+        calibrate_copy(args.calibrate_copy_mib)
+    elapsed, kms, _ = timed(ctx, step, args.steps, args.warmup)
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
-    rowor = [ms for name, ms in recs if name == "rowor"]
-    avg_ms = float(np.mean(rowor))
-    per_kernel = {}
-    for name, ms in recs:
-        per_kernel.setdefault(name, []).append(ms)
     alg = algorithmic_bytes(st, n)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload)
-    o = out.cpu().numpy()
-    i = inn.cpu().numpy()
+    achieved = alg / (kms["rowor"] * 1e-3) / 1e9
+    o, i = out.cpu().numpy(), inn.cpu().numpy()
     assert o.sum() == i.sum(), "sum of out-sizes differs from sum of in-sizes"
-
-    result = {
-        "metric": METRIC,
-        "value": m * args.steps / elapsed,
-        "unit": "events/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "T": spec["T"],
-                   "generator": spec["kind"], "seed": spec["seed"], "flags": "undirected,strict-ties",
-                   "slice_words": args.slice_words or "auto", "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+    config = {"workload": workload, "n": n, "m": m, "T": spec["T"], "generator": spec["kind"],
+              "seed": spec["seed"], "flags": "undirected,strict-ties",
+              "slice_words": args.slice_words or "auto", "parallelism": "single-gpu"}
+    r = base_result(args, m * args.steps / elapsed, "events/s", args.steps,
+                    1e3 * elapsed / args.steps, config)
+    r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("rowor", workload),
                      "kernel": "k_rowor_global", "algorithmic_bytes": alg,
-                     "avg_launch_ms": avg_ms},
-        "kernels_ms": {k: float(np.mean(v)) for k, v in per_kernel.items()},
-        "plan": {"levels": st["levels"], "pairs": st["pairs"], "gathers": st["gathers"],
+                     "avg_launch_ms": kms["rowor"]}
+    r["kernels_ms"] = kms
+    r["plan"] = {"levels": st["levels"], "pairs": st["pairs"], "gathers": st["gathers"],
                  "host_seconds": st["host_seconds"], "wall_seconds": plan_wall,
-                 "end_to_end_events_per_s": m / (st["host_seconds"] + 1e-3 * sum(
-                     float(np.mean(v)) for v in per_kernel.values()))},
-        "mean_out_size": float(o.mean()),
-    }
+                 "end_to_end_events_per_s": m / (st["host_seconds"] + 1e-3 * sum(kms.values()))}
+    r["mean_out_size"] = float(o.mean())
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
-        result["cpu_baseline"] = cpu_baseline(n, s, d, t, args.cpu_budget)
-        result["cpu_baseline"]["host"] = {"nproc": os.cpu_count()}
+        r["cpu_baseline"] = cpu_baseline_exact(n, s, d, t, args.cpu_budget)
     plan.close()
-    print(json.dumps(result), flush=True)
+    return r
+
+
+def calibrate_copy(mib):
+    import torch
+    nbytes = mib << 20
+    a = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+
+
+# ---------------------------------------------------------------------------
+def run_hashed(args):
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+
+    workload = args.workload or "activity_n1M_m100M"
+    spec = T.WORKLOADS[workload]
+    n, H, K = spec["n"], args.hashes, args.buckets
+    log(f"[bench] generating {workload}")
+    s, d, t = T.make_workload(workload)
+    m = int(s.shape[0])
+    A = T.hash_coefficients(H, seed=1003)
+    ctx = tn.get_context()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    bucket, count, proxies = tn.hash_compress(n, s, d, t, A, K)
+    torch.cuda.synchronize()
+    compress_wall = time.perf_counter() - t0
+    hash_ms = sum(ms for k, ms in ctx.profile_take() if k == "hash")
+    ctx.profile(False)
+    stats, tiles, lds_tiles = proxies.stats()
+    log(f"[bench] hashed and planned {H} proxies in {compress_wall:.2f} s; {tiles} tiles "
+        f"({lds_tiles} in LDS); levels per proxy {np.mean([x['levels'] for x in stats]):.0f}")
+    ldK = tn.words(K)
+    P = torch.empty((H, K, ldK), dtype=torch.int64, device="cuda")
+    Ps = [P[j] for j in range(H)]
+    t0 = time.perf_counter()
+    proxies.execute(Ps)  # tunes the tile shape, captures the graph
+    torch.cuda.synchronize()
+    tune_wall = time.perf_counter() - t0
+
+    def step():
+        proxies.execute(Ps)
+        tn.recombine(P, bucket, count, n)
+
+    elapsed, kms, per = timed(ctx, step, args.steps, args.warmup)
+    est, lifted = tn.recombine(P, bucket, count, n)
+    proxy_ms = kms["batch"]
+    rec_ms = sum(float(np.sum(v)) for k, v in per.items() if k in ("recombine", "aux")) / args.steps
+    dense = sum(algorithmic_bytes(x, K) for x in stats)
+    achieved = dense / (proxy_ms * 1e-3) / 1e9
+    config = {"workload": workload, "n": n, "m": m, "T": spec["T"], "generator": spec["kind"],
+              "seed": spec["seed"], "H": H, "K": K, "hash_seed": 1003,
+              "flags": "undirected,strict-ties", "parallelism": "single-gpu"}
+    r = base_result(args, m / (proxy_ms * 1e-3), "events/s", args.steps,
+                    1e3 * elapsed / args.steps, config)
+    r["value_note"] = "m / time of the one launch that builds all H proxies"
+    r["roofline"] = {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": load_traffic("batch", workload),
+                     "kernel": "k_batch_persistent", "algorithmic_bytes": dense,
+                     "bytes_note": "dense-equivalent row transfers of the H proxy streams, "
+                                   "served from LDS-resident slices",
+                     "hbm_equivalent_frac": achieved / HBM_PEAK_GBS,
+                     "avg_launch_ms": proxy_ms}
+    r["hashed"] = {"H_times_m_events_per_s": H * m / (proxy_ms * 1e-3),
+                   "recombine_ms": rec_ms,
+                   "end_to_end_ms": 1e3 * compress_wall + proxy_ms + rec_ms,
+                   "hash_kernel_ms": hash_ms, "host_compress_wall_s": compress_wall,
+                   "autotune_and_capture_s": tune_wall, "tiles": tiles, "lds_tiles": lds_tiles,
+                   "mean_estimate": float(est.float().mean().item())}
+    r["kernels_ms"] = kms
+    if not args.no_cpu_baseline:
+        import oracle
+        log("[bench] timing the CPU oracle on one proxy column slice")
+        b0 = bucket[0].cpu().numpy().view(np.uint32)
+        hs, hd = b0[s], b0[d]
+        nwk = tn.words(K)
+        t0 = time.perf_counter()
+        oracle.reverse_matrix(K, hs, hd, t, w0=0, nw=1)
+        dt = time.perf_counter() - t0
+        full = dt * nwk * H
+        r["cpu_baseline"] = {"value": m / full, "unit": "events/s", "cores": 1, "kind": "oracle",
+                             "sample": f"proxy 0 of {H}, word column 0 of {nwk}, all {m} events; "
+                                       f"{dt:.2f} s single-threaded, scaled by {nwk * H}",
+                             "seconds": dt, "host_nproc": os.cpu_count()}
+    proxies.close()
+    return r
+
+
+# ---------------------------------------------------------------------------
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+
+    specs = T.batched_suite(args.networks, seed=4000)
+    log(f"[bench] generating {len(specs)} networks")
+    nets = [(sp.n,) + sp.generate() for sp in specs]
+    m_total = sum(int(x[1].shape[0]) for x in nets)
+    ctx = tn.get_context()
+    t0 = time.perf_counter()
+    b = tn.Batch(nets)
+    plan_wall = time.perf_counter() - t0
+    stats, tiles, lds_tiles = b.stats()
+    Cs = b.alloc()
+    t0 = time.perf_counter()
+    b.execute(Cs)  # tunes and captures
+    torch.cuda.synchronize()
+    tune_wall = time.perf_counter() - t0
+    elapsed, kms, _ = timed(ctx, lambda: b.execute(Cs), args.steps, args.warmup)
+    batch_ms = kms["batch"]
+    # the plain one-network kernel, network by network, on the same matrices
+    plans = [tn.Plan(n, s, d, t) for (n, s, d, t) in nets]
+
+    def plain():
+        for p, C in zip(plans, Cs):
+            p.execute(C)
+
+    p_elapsed, pkms, pper = timed(ctx, plain, 1, 1)
+    plain_ms = 1e3 * p_elapsed
+    dense = sum(algorithmic_bytes(x, sp.n) for x, sp in zip(stats, specs))
+    achieved = dense / (batch_ms * 1e-3) / 1e9
+    config = {"workload": f"batched_{len(specs)}_uneven", "networks": len(specs),
+              "n_range": [500, 20000], "m_range": [10_000, 1_000_000], "m_total": m_total,
+              "generators": "uniform pairs (even b) and activity-driven (odd b)",
+              "flags": "undirected,strict-ties", "parallelism": "single-gpu"}
+    r = base_result(args, m_total / (batch_ms * 1e-3), "events/s", args.steps,
+                    1e3 * elapsed / args.steps, config)
+    r["roofline"] = {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": load_traffic("batch", "batched"),
+                     "kernel": "k_batch_persistent", "algorithmic_bytes": dense,
+                     "hbm_equivalent_frac": achieved / HBM_PEAK_GBS, "avg_launch_ms": batch_ms}
+    r["batched"] = {"graph_launch_ms": batch_ms, "plain_network_by_network_ms": plain_ms,
+                    "speedup_vs_plain": plain_ms / batch_ms, "tiles": tiles,
+                    "lds_tiles": lds_tiles, "host_plan_wall_s": plan_wall,
+                    "autotune_and_capture_s": tune_wall}
+    for p in plans:
+        p.close()
+    if not args.no_cpu_baseline:
+        import oracle
+        log("[bench] timing the CPU oracle on a sample of the networks")
+        t0 = time.perf_counter()
+        done_m = 0
+        k = 0
+        while time.perf_counter() - t0 < args.cpu_budget and k < len(nets):
+            n, s, d, t = nets[k]
+            oracle.reverse_matrix(n, s, d, t)
+            done_m += int(s.shape[0])
+            k += 1
+        dt = time.perf_counter() - t0
+        r["cpu_baseline"] = {"value": done_m / dt, "unit": "events/s", "cores": 1,
+                             "kind": "oracle",
+                             "sample": f"full matrices of the first {k} of {len(nets)} networks "
+                                       f"({done_m} events), {dt:.2f} s single-threaded",
+                             "seconds": dt, "host_nproc": os.cpu_count()}
+    b.close()
+    return r
+
+
+# ---------------------------------------------------------------------------
+def run_combiner(args):
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+    from paper_2307_04890_amd import combiner as cb
+
+    H, K = args.hashes, args.buckets
+    ctx = tn.get_context()
+
+    def features(n, m, Tm, seed, hseed):
+        s, d, t = T.activity_driven(n, m, Tm, seed=seed)
+        f = cb.hashed_features(n, s, d, t, T.hash_coefficients(H, seed=hseed), K)
+        exact = cb.exact_out_sizes(n, s, d, t)
+        lifted_min = f["lifted"].min(dim=0).values
+        return f["x"], exact, f["est"], lifted_min
+
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    for i in range(args.train_networks):
+        x, exact, _, _ = features(20_000, 1_000_000, 100_000, 5000 + i, 7000 + i)
+        xs.append(x)
+        ys.append(torch.log(exact.float() / 20_000))
+        log(f"[bench] training network {i + 1}/{args.train_networks}")
+    X, Y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+    data_s = time.perf_counter() - t0
+    comb = cb.Combiner(T.mlp_init(1))
+    g = T.rng(2)
+    orders = [g.permutation(X.shape[0]) for _ in range(args.epochs)]
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    losses = comb.fit(X, Y, orders, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    recs = ctx.profile_take()
+    ctx.profile(False)
+    bwd = [ms for k, ms in recs if k == "mlp_backward"]
+    steps = len(bwd)
+    errs = {"combiner_clamped": [], "combiner": [], "fusion_estimate": [], "min_lifted": []}
+    for i in range(args.heldout_networks):
+        n = 100_000
+        x, exact, est, lmin = features(n, 10_000_000, 1_000_000, 6000 + i, 8000 + i)
+        e = exact.cpu().numpy()
+        errs["combiner_clamped"].append(cb.relative_errors(comb.predict(x, n, est=est).cpu().numpy(), e))
+        errs["combiner"].append(cb.relative_errors(comb.predict(x, n).cpu().numpy(), e))
+        errs["fusion_estimate"].append(cb.relative_errors(est.cpu().numpy(), e))
+        errs["min_lifted"].append(cb.relative_errors(lmin.cpu().numpy(), e))
+        log(f"[bench] held-out network {i + 1}/{args.heldout_networks}")
+    summary = {k: {q: float(np.mean([r[q] for r in v])) for q in v[0]} for k, v in errs.items()}
+    # forward+backward FLOPs per sample: 2 * (16*64 + 64*64 + 64) * 3
+    flop = 2.0 * (16 * 64 + 64 * 64 + 64) * 3 * X.shape[0] * args.epochs
+    bwd_ms = float(np.sum(bwd))
+    achieved = flop / (bwd_ms * 1e-3) / 1e12
+    config = {"workload": "combiner_train64_n20000_m1M_eval4_n100000_m10M", "H": H, "K": K,
+              "train_rows": int(X.shape[0]), "epochs": args.epochs, "batch": 4096,
+              "lr": 1e-3, "parallelism": "single-gpu"}
+    r = base_result(args, summary["combiner_clamped"]["mean"], "mean relative error", steps,
+                    1e3 * train_s / max(steps, 1), config, dtype="f32")
+    r["higher_is_better"] = False
+    r["errors"] = summary
+    r["roofline"] = {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": achieved / 157.3, "traffic": None, "kernel": "k_mlp_backward",
+                     "avg_launch_ms": bwd_ms / max(steps, 1)}
+    r["combiner"] = {"dataset_seconds": data_s, "train_seconds": train_s,
+                     "final_loss": float(np.mean(losses[-50:])), "first_loss": losses[0]}
+    if not args.no_cpu_baseline:
+        from oracle import mlp as ref
+        xs_ = X[:4096].double().cpu().numpy()
+        ys_ = Y[:4096].double().cpu().numpy()
+        p = T.mlp_init(1).astype(np.float64)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < min(args.cpu_budget, 5.0):
+            ref.grad(p, xs_, ys_)
+            k += 1
+        dt = time.perf_counter() - t0
+        r["cpu_baseline"] = {"value": k * 4096 / dt, "unit": "samples/s (forward+backward)",
+                             "cores": 1, "kind": "oracle",
+                             "sample": f"{k} float64 gradient evaluations of a 4096-row batch",
+                             "seconds": dt, "host_nproc": os.cpu_count()}
+    return r
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (run on the CSV files a profiled bench run wrote)
+def _read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib):
+    """HBM bytes per launch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch, one --pmc run each), each scaled by what the same counter read
+    for the plain device copy of calib_mib MiB in the same run."""
+    match = {"rowor": "k_rowor_global", "batch": "k_batch_persistent",
+             "recombine": "k_recombine_est"}[kernel]
+    out = {"kernel": match, "workload": workload, "command": command,
+           "kernel_source_sha": kernel_source_hash(KERNEL_SOURCES[kernel])}
+    known_kib = calib_mib * 1024.0
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _read_csv(path) if r["Counter_Name"] == name]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                  or "elementwise" in r["Kernel_Name"]]
+        # the calibration copy is the largest copy dispatch of the run
+        calib = max(copies) if copies else float("nan")
+        vals = [float(r["Counter_Value"]) for r in rows if match in r["Kernel_Name"]]
+        factor = known_kib / calib
+        out[name] = {"kib_per_dispatch": vals, "calibration_kib": calib, "factor": factor,
+                     "bytes_per_launch": 1024.0 * factor * sum(vals) / max(len(vals), 1)}
+    out["hbm_bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + \
+        out["WRITE_SIZE"]["bytes_per_launch"]
+    return out
+
+
+def summarize_trace(stats_csv, command, top=12):
+    rows = _read_csv(stats_csv)
+    lines = [f"command: {command}", "",
+             f"{'calls':>6} {'avg ms':>10} {'total ms':>10} {'%':>6}  kernel"]
+    for r in rows[:top]:
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:10.3f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}  "
+                     f"{r['Name'][:110]}")
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-pmc", "--summarize-trace"):
+        what = sys.argv[1]
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--fetch")
+        sp.add_argument("--write")
+        sp.add_argument("--stats")
+        sp.add_argument("--kernel", default="rowor")
+        sp.add_argument("--workload", default="activity_n100000_m10M")
+        sp.add_argument("--command", required=True)
+        sp.add_argument("--calib-mib", type=int, default=1024)
+        sp.add_argument("--out", required=True)
+        a = sp.parse_args(sys.argv[2:])
+        if what == "--summarize-pmc":
+            rec = summarize_pmc(a.fetch, a.write, a.kernel, a.workload, a.command, a.calib_mib)
+            with open(a.out, "w") as f:
+                json.dump(rec, f, indent=1)
+        else:
+            with open(a.out, "w") as f:
+                f.write(summarize_trace(a.stats, a.command))
+        return
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="exact", choices=["exact", "hashed", "batched", "combiner"])
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--slice-words", type=int, default=0)
+    ap.add_argument("--hashes", type=int, default=16)
+    ap.add_argument("--buckets", type=int, default=4096)
+    ap.add_argument("--networks", type=int, default=256)
+    ap.add_argument("--train-networks", type=int, default=64)
+    ap.add_argument("--heldout-networks", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of single-thread oracle work for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "column sharding is a design, not built here", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    run = {"exact": run_exact, "hashed": run_hashed, "batched": run_batched,
+           "combiner": run_combiner}[args.mode]
+    print(json.dumps(run(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -247,7 +247,10 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m,
  * sum of count[j][r] over the super-nodes r in row h_j(u) of P_j.
  * P: DEVICE, H matrices of K rows x ldK words, matrix j at P + j*K*ldK.
  * bucket, count: DEVICE as written by tn_hash_compress.
- * est: DEVICE int32[n].  lifted: DEVICE int32[H*n] or NULL. */
+ * est: DEVICE int32[n].  lifted: DEVICE int32[H*n] or NULL.
+ * A node whose proxy row is full in every hash keeps every node (est = n)
+ * and skips the AND over the chunks; the call waits for the context's
+ * stream once, to size that work. */
 tn_status tn_recombine(tn_ctx *ctx, uint32_t n, uint32_t H, uint32_t K,
                        const uint64_t *P, int64_t ldK, const uint32_t *bucket,
                        const int32_t *count, int32_t *est, int32_t *lifted);

@@ -16,9 +16,14 @@ hipError_t launch_zero_i32(int32_t *p, size_t n, hipStream_t st);
 hipError_t launch_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *PT,
                                const uint32_t *bucket, uint32_t q0, uint32_t nq, uint64_t *Lt,
                                hipStream_t st);
+// est[u] = n for nodes whose proxy rows are full in every hash; the others
+// get est[u] = 0 and are listed in list[0 .. *count).
+hipError_t launch_split_full(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
+                             const uint32_t *bucket, uint8_t *full, int32_t *est, uint32_t *list,
+                             uint32_t *count, hipStream_t st);
 hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32_t *bucket,
-                                const uint64_t *Lt, uint32_t q0, uint32_t nq, int32_t *est,
-                                hipStream_t st);
+                                const uint64_t *Lt, uint32_t q0, uint32_t nq, const uint32_t *list,
+                                uint32_t nlist, int32_t *est, hipStream_t st);
 uint32_t recombine_group(uint32_t K);
 
 }  // namespace tn

@@ -179,6 +179,41 @@ k_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *
     }
 }
 
+// full[j * K + r] = 1 iff row r of P_j has all K bits set.
+__global__ void __launch_bounds__(256)
+k_rows_full(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ P,
+            uint8_t *__restrict__ full) {
+    const size_t rows = (size_t)H * K;
+    const uint32_t kw = (K + 63) / 64;
+    const uint64_t last = (K % 64) ? ((1ull << (K % 64)) - 1ull) : ~0ull;
+    for (size_t row = (size_t)blockIdx.x * blockDim.x + threadIdx.x; row < rows;
+         row += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)(row / K);
+        const uint64_t *Pr = P + (size_t)j * K * ldK + (row - (size_t)j * K) * ldK;
+        bool all = true;
+        for (uint32_t wd = 0; wd + 1 < kw && all; ++wd) all = Pr[wd] == ~0ull;
+        full[row] = (all && Pr[kw - 1] == last) ? 1 : 0;
+    }
+}
+
+// A node whose proxy row is full in every hash keeps every node: est = n.
+// Every other node is appended to `list` for the AND/popcount kernel.
+__global__ void __launch_bounds__(256)
+k_split_full(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bucket,
+             const uint8_t *__restrict__ full, int32_t *__restrict__ est,
+             uint32_t *__restrict__ list, uint32_t *__restrict__ count) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        bool all = true;
+        for (uint32_t j = 0; j < H && all; ++j) all = full[(size_t)j * K + bucket[(size_t)j * n + u]] != 0;
+        if (all) {
+            est[u] = (int32_t)n;
+        } else {
+            est[u] = 0;
+            list[atomicAdd(count, 1u)] = u;
+        }
+    }
+}
+
 // est[u] += sum over the chunks q of this launch of popcount(AND_j Lt[q][j][h_j(u)]).
 // A workgroup owns kUPT nodes u per thread and a range of chunks; the tables
 // of G hashes of one chunk are staged in LDS at a time, and the AND of a
@@ -188,16 +223,17 @@ constexpr int kQB = 4;
 __global__ void __launch_bounds__(512)
 k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *__restrict__ bucket,
                 const uint64_t *__restrict__ Lt, uint32_t q_begin, uint32_t q_end, uint32_t q0,
-                int32_t *__restrict__ est) {
+                const uint32_t *__restrict__ list, uint32_t nlist, int32_t *__restrict__ est) {
     extern __shared__ uint64_t tab[];
     const uint32_t tid = threadIdx.x;
     const uint64_t ubase = (uint64_t)blockIdx.x * blockDim.x * kUPT;
+    if (ubase >= nlist) return;  // uniform: the whole workgroup leaves
     uint32_t u[kUPT];
     int32_t cnt[kUPT];
 #pragma unroll
     for (int k = 0; k < kUPT; ++k) {
-        const uint64_t uu = ubase + tid + (uint64_t)k * blockDim.x;
-        u[k] = uu < n ? (uint32_t)uu : 0xffffffffu;
+        const uint64_t i = ubase + tid + (uint64_t)k * blockDim.x;
+        u[k] = i < nlist ? list[i] : 0xffffffffu;
         cnt[k] = 0;
     }
     for (uint32_t qb = q_begin; qb < q_end; qb += kQB) {
@@ -312,16 +348,32 @@ uint32_t recombine_group(uint32_t K) {
     return (uint32_t)g;
 }
 
+hipError_t launch_split_full(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
+                             const uint32_t *bucket, uint8_t *full, int32_t *est, uint32_t *list,
+                             uint32_t *count, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (int32_t *)count, (size_t)1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rows_full, dim3(grid_for((size_t)H * K, 256)), dim3(256), 0, st, H, K, ldK,
+                       P, full);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_full, dim3(grid_for(n, 256)), dim3(256), 0, st, n, H, K, bucket, full,
+                       est, list, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32_t *bucket,
-                                const uint64_t *Lt, uint32_t q0, uint32_t nq, int32_t *est,
-                                hipStream_t st) {
+                                const uint64_t *Lt, uint32_t q0, uint32_t nq, const uint32_t *list,
+                                uint32_t nlist, int32_t *est, hipStream_t st) {
     const uint32_t G = recombine_group(K);
     const size_t lds = (size_t)G * K * 8;
     hipError_t e = hipFuncSetAttribute((const void *)k_recombine_est,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const uint32_t threads = 512;
-    const uint32_t utiles = (uint32_t)((n + (size_t)threads * kUPT - 1) / ((size_t)threads * kUPT));
+    const uint32_t utiles = (uint32_t)((nlist + (size_t)threads * kUPT - 1) / ((size_t)threads * kUPT));
+    if (utiles == 0) return hipSuccess;
     // split the chunk range so that the launch has enough workgroups
     uint32_t splits = 1;
     while ((size_t)utiles * splits < 1024 && splits * kQB * 2 <= nq) splits *= 2;
@@ -331,7 +383,7 @@ hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32
         const uint32_t qe = min(q0 + nq, qb + per);
         if (qb >= qe) break;
         hipLaunchKernelGGL(k_recombine_est, dim3(utiles), dim3(threads), lds, st, n, H, K, G, bucket,
-                           Lt, qb, qe, q0, est);
+                           Lt, qb, qe, q0, list, nlist, est);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

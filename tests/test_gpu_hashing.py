@@ -30,10 +30,13 @@ def run_hashed(n, s, d, t, H, K, seed, flags=0):
         est.cpu().numpy(), lifted.cpu().numpy(), proxies
 
 
-@pytest.mark.parametrize("n,m,H,K", [(300, 900, 3, 40), (2000, 8000, 4, 64), (5000, 30000, 5, 1500),
-                                     (3000, 12000, 2, 4096)])
-def test_hash_proxies_and_recombine_match_oracle(n, m, H, K):
-    s, d, t = T.uniform_pairs(n, m, m // 3, seed=n + K)
+@pytest.mark.parametrize("n,m,H,K,mixed", [(300, 900, 3, 40, False), (2000, 8000, 4, 64, False),
+                                           (5000, 30000, 5, 1500, False),
+                                           (3000, 12000, 2, 4096, False), (2000, 300, 2, 64, True),
+                                           (3000, 250, 2, 40, True)])
+def test_hash_proxies_and_recombine_match_oracle(n, m, H, K, mixed):
+    Tm = m if mixed else m // 3
+    s, d, t = T.uniform_pairs(n, m, Tm, seed=n + K)
     A, bucket, count, P, est, lifted, _ = run_hashed(n, s, d, t, H, K, seed=K)
     wb = oracle.hash_nodes(n, A, K)
     assert (bucket == wb).all()
@@ -42,6 +45,10 @@ def test_hash_proxies_and_recombine_match_oracle(n, m, H, K):
     assert (P == WP).all()
     us = np.arange(n) if n <= 2000 else T.rng(1).choice(n, 300, replace=False)
     we, wl = oracle.recombine(n, WP, wb, us)
+    if mixed:
+        # a mix of nodes whose proxy rows are full in every hash (estimate n)
+        # and nodes that need the AND over all chunks
+        assert (we == n).any() and (we < n).any()
     assert (est[us] == we).all()
     assert (lifted[:, us] == wl).all()
 
