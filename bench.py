@@ -169,6 +169,11 @@ def run_exact(args):
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
     alg = algorithmic_bytes(st, n)
     achieved = alg / (kms["rowor"] * 1e-3) / 1e9
+    # what the kernel actually had to move: its own counters of row words
+    # loaded and stored (saturated rows skipped), plus the schedule once
+    ld_w, st_w = ctx.last_traffic()
+    moved = 8.0 * (ld_w + st_w) + 16.0 * st["ops"] + 4.0 * (st["op_levels"] + 1)
+    moved_gbs = moved / (kms["rowor"] * 1e-3) / 1e9
     o, i = out.cpu().numpy(), inn.cpu().numpy()
     assert o.sum() == i.sum(), "sum of out-sizes differs from sum of in-sizes"
     config = {"workload": workload, "n": n, "m": m, "T": spec["T"], "generator": spec["kind"],
@@ -179,9 +184,13 @@ def run_exact(args):
     r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("rowor", workload),
                      "kernel": "k_rowor_global", "algorithmic_bytes": alg,
-                     "avg_launch_ms": kms["rowor"]}
+                     "avg_launch_ms": kms["rowor"], "moved_bytes": moved,
+                     "moved_achieved": moved_gbs, "moved_frac": moved_gbs / HBM_PEAK_GBS,
+                     "levels": st["op_levels"],
+                     "us_per_level": 1e3 * kms["rowor"] / max(1, st["op_levels"])}
     r["kernels_ms"] = kms
-    r["plan"] = {"levels": st["levels"], "pairs": st["pairs"], "gathers": st["gathers"],
+    r["plan"] = {"levels": st["levels"], "op_levels": st["op_levels"], "ops": st["ops"],
+                 "pairs": st["pairs"], "gathers": st["gathers"],
                  "host_seconds": st["host_seconds"], "wall_seconds": plan_wall,
                  "end_to_end_events_per_s": m / (st["host_seconds"] + 1e-3 * sum(kms.values()))}
     r["mean_out_size"] = float(o.mean())

@@ -115,10 +115,12 @@ int32_t tn_profile_take(tn_ctx *ctx, int32_t *ids, float *ms, int32_t cap);
 /* Plans the reverse-time stream of one network on the host: groups the events
  * of each time step into independent items (two-node pairs, or compound
  * groups where a node meets several others at one time step, which must read
- * every old row before writing any), and assigns each item the earliest
- * level after every earlier item (in reverse time) that shares a node, so
- * the items of one level touch disjoint rows.  The schedule is copied to the
- * device (synchronously) and kept in the plan.
+ * every old row before writing any), turns them into binary row-OR ops
+ * (compound groups fold through scratch rows), and places each op on the
+ * earliest level after the last write of every row it reads and the last
+ * access of every row it writes, so the ops of one level are independent;
+ * levels hold at most 1024 ops.  The schedule is copied to the device
+ * (synchronously) and kept in the plan.
  * src, dst, t: HOST, m entries.  flags: TN_DIRECTED | TN_TIES_SEQUENTIAL.
  * Errors: TN_E_ARG (n == 0, null arrays with m > 0, bad flags),
  * TN_E_RANGE, TN_E_ORDER, TN_E_UNSUPPORTED (m >= 2^32 or n >= 2^31). */
@@ -139,6 +141,9 @@ typedef struct tn_plan_stats {
     int64_t device_bytes;    /* size of the device-resident schedule       */
     double host_seconds;     /* planning time on the host                  */
     int64_t directed_pairs;  /* pairs that update one row only             */
+    int64_t ops;             /* binary ops of the device schedule          */
+    int64_t op_levels;       /* levels of the binary-op schedule           */
+    int64_t scratch_rows;    /* scratch rows compound time steps fold into */
 } tn_plan_stats;
 
 tn_status tn_plan_get_stats(const tn_plan *plan, tn_plan_stats *out);
@@ -159,6 +164,16 @@ tn_status tn_schedule_arrays(const tn_host_schedule *s, tn_plan_stats *stats,
                              const uint32_t **lvl_pair, const uint32_t **lvl_gat,
                              const uint32_t **pairs, const uint32_t **gat_tgt,
                              const uint32_t **gat_ptr, const uint32_t **gat_src);
+/* The binary-op form of the same schedule, the one tn_plan_create uploads:
+ * level l (l < stats.op_levels) owns ops [lvl_op[l], lvl_op[l+1]) of `ops`,
+ * 4 uint32 each {a, b, d1, d2}: r = row a | row b, then rows d1 and d2 get r
+ * (d2 = 0xffffffff: none).  A row id with bit 31 set is scratch row
+ * (id & 0x7fffffff); an undirected pair is (u, v, u, v), a one-way pair
+ * (u, v, u, none), and a compound time step folds each target's old row and
+ * its partners' old rows into a scratch row, then copies it back.  Ops of
+ * one level read rows no op of that level writes. */
+tn_status tn_schedule_op_arrays(const tn_host_schedule *s,
+                                const uint32_t **lvl_op, const uint32_t **ops);
 void tn_schedule_destroy(tn_host_schedule *s);
 
 /* Destroys a plan (frees its device schedule).  NULL is ignored. */
@@ -170,6 +185,21 @@ void tn_plan_destroy(tn_plan *plan);
  * any value gives the same bits.  Errors: TN_E_ARG (ld < ceil(n/64)). */
 tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C,
                           int64_t ld, uint32_t slice_words);
+
+/* Saturated rows (Sec. 3.4: rows of the reverse-time matrix only gain bits,
+ * and an OR with a row that already holds every column of a slice gives that
+ * full slice).  Enabled by default: tn_plan_execute then skips the row loads
+ * such an operand makes redundant and the stores of full results into rows
+ * already full; the matrix it writes is identical either way.  enable = 0
+ * makes every op load and store its rows.  Errors: TN_E_ARG (ctx NULL). */
+tn_status tn_set_saturation(tn_ctx *ctx, int enable);
+
+/* Row traffic of the last tn_plan_execute on this context: words[0] = uint64
+ * row words its row-OR kernel loaded, words[1] = row words it stored (words
+ * of the padding columns past ceil(n/64) are not counted).  words: HOST
+ * uint64[2], zeros before the first execute.  Waits for the context's
+ * stream.  Errors: TN_E_ARG, TN_E_HIP. */
+tn_status tn_plan_last_traffic(tn_ctx *ctx, uint64_t *words);
 
 /* One call: plan, execute, destroy.  Inputs HOST, C DEVICE as above. */
 tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m,

@@ -41,6 +41,9 @@ class PlanStats(ctypes.Structure):
         ("device_bytes", ctypes.c_int64),
         ("host_seconds", ctypes.c_double),
         ("directed_pairs", ctypes.c_int64),
+        ("ops", ctypes.c_int64),
+        ("op_levels", ctypes.c_int64),
+        ("scratch_rows", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -66,7 +69,10 @@ SIGNATURES = {
     "tn_schedule_build": (_i32, [_u32, _i64, _P, _P, _P, _u32, _PP]),
     "tn_schedule_arrays": (_i32, [_P, ctypes.POINTER(PlanStats), _PP, _PP, _PP, _PP, _PP, _PP]),
     "tn_schedule_destroy": (None, [_P]),
+    "tn_schedule_op_arrays": (_i32, [_P, _PP, _PP]),
     "tn_plan_execute": (_i32, [_P, _P, _P, _i64, _u32]),
+    "tn_set_saturation": (_i32, [_P, ctypes.c_int]),
+    "tn_plan_last_traffic": (_i32, [_P, _P]),
     "tn_build_component_matrix": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _P, _i64]),
     "tn_component_sizes": (_i32, [_P, _u32, _P, _i64, _P, _P]),
     "tn_batch_create": (_i32, [_P, _i32, _P, _P, _P, _P, _P, _u32, _PP]),

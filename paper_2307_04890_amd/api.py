@@ -60,6 +60,16 @@ class Context:
         """Times every kernel this context launches with HIP events on its stream."""
         check(lib.tn_profile_enable(self.h, int(bool(enable))))
 
+    def saturation(self, enable: bool = True):
+        """Skips the row traffic saturated rows make redundant (on by default)."""
+        check(lib.tn_set_saturation(self.h, int(bool(enable))))
+
+    def last_traffic(self) -> tuple[int, int]:
+        """(row words loaded, row words stored) by the last plan execution (waits)."""
+        w = np.zeros(2, dtype=np.uint64)
+        check(lib.tn_plan_last_traffic(self.h, _hp(w)))
+        return int(w[0]), int(w[1])
+
     def profile_take(self, cap: int = 1 << 16):
         """[(kernel name, ms)] in launch order since the last take (waits for the stream)."""
         ids = np.zeros(cap, dtype=np.int32)
@@ -187,12 +197,16 @@ def host_schedule(n: int, src, dst, t, flags: int = 0) -> dict:
                 return np.zeros(0, dtype=np.uint32)
             return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint32)),
                                          shape=(k,)).copy()
+        optr = [ctypes.c_void_p() for _ in range(2)]
+        check(lib.tn_schedule_op_arrays(h, ctypes.byref(optr[0]), ctypes.byref(optr[1])))
+        Lo, nops = st.op_levels, st.ops
         lvl_pair = arr(ptrs[0], L + 1)
         lvl_gat = arr(ptrs[1], L + 1)
         gat_ptr = arr(ptrs[4], G + 1)
         out = dict(stats=st.as_dict(), lvl_pair=lvl_pair, lvl_gat=lvl_gat,
                    pairs=arr(ptrs[2], 2 * P).reshape(P, 2), gat_tgt=arr(ptrs[3], G),
-                   gat_ptr=gat_ptr, gat_src=arr(ptrs[5], int(gat_ptr[-1]) if G else 0))
+                   gat_ptr=gat_ptr, gat_src=arr(ptrs[5], int(gat_ptr[-1]) if G else 0),
+                   lvl_op=arr(optr[0], Lo + 1), ops=arr(optr[1], 4 * nops).reshape(nops, 4))
     finally:
         lib.tn_schedule_destroy(h)
     return out

@@ -96,6 +96,7 @@ void tn_destroy(tn_ctx *ctx) {
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->traffic) (void)hipFree(ctx->traffic);
     for (auto &r : ctx->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -139,7 +140,7 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
     *out = nullptr;
     tn::HostSchedule hs;
     std::string err;
-    tn_status st = tn::plan_events(n, m, src, dst, t, flags, hs, err);
+    tn_status st = tn::plan_events(n, m, src, dst, t, flags, hs, err, nullptr, 0, tn::kFormOps);
     if (st != TN_OK) return fail(st, err);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
@@ -147,7 +148,7 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
     if (!p) return fail(TN_E_NOMEM, "plan allocation failed");
     p->device = ctx->device;
     std::vector<unsigned char> img;
-    tn::schedule_pack(hs, img);
+    tn::ops_pack(hs, img);
     p->dev_bytes = img.size();
     hipError_t e = hipMalloc(&p->dev, p->dev_bytes);
     if (e != hipSuccess) {
@@ -161,7 +162,8 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         delete p;
         return hip_fail(e, "schedule upload");
     }
-    p->view = tn::schedule_view(hs, p->dev);
+    p->view = tn::ops_view(hs, p->dev);
+    p->scratch_rows = hs.scratch_rows;
     tn::fill_stats(hs, p->stats);
     *out = p;
     return TN_OK;
@@ -173,16 +175,35 @@ namespace tn {
 void fill_stats(const HostSchedule &hs, tn_plan_stats &s) {
     s.n = hs.n;
     s.m = hs.m;
-    s.levels = hs.L;
-    s.pairs = (int64_t)hs.pairs.size() / 2;
-    s.gathers = (int64_t)hs.gat_tgt.size();
-    s.gather_sources = (int64_t)hs.gat_src.size();
-    s.compound_items = hs.compound_items;
-    s.max_level_items = hs.max_level_items;
-    s.max_level_gathers = hs.max_level_gathers;
-    s.device_bytes = (int64_t)tn::schedule_device_bytes(hs);
+    const bool ops_only = hs.L == 0 && !hs.lvl_op.empty();
+    if (ops_only) {
+        s.levels = hs.Lops;
+        s.pairs = hs.op_pairs;
+        s.gathers = hs.op_targets;
+        s.gather_sources = hs.op_sources;
+        s.compound_items = hs.op_compound;
+        s.directed_pairs = hs.op_directed;
+        s.max_level_gathers = 0;
+        int64_t widest = 0;
+        for (size_t l = 0; l + 1 < hs.lvl_op.size(); ++l)
+            widest = std::max<int64_t>(widest, hs.lvl_op[l + 1] - hs.lvl_op[l]);
+        s.max_level_items = widest;
+        s.device_bytes = (int64_t)ops_device_bytes(hs);
+    } else {
+        s.levels = hs.L;
+        s.pairs = (int64_t)hs.pairs.size() / 2;
+        s.gathers = (int64_t)hs.gat_tgt.size();
+        s.gather_sources = (int64_t)hs.gat_src.size();
+        s.compound_items = hs.compound_items;
+        s.directed_pairs = hs.directed_pairs;
+        s.max_level_items = hs.max_level_items;
+        s.max_level_gathers = hs.max_level_gathers;
+        s.device_bytes = (int64_t)schedule_device_bytes(hs);
+    }
     s.host_seconds = hs.host_seconds;
-    s.directed_pairs = hs.directed_pairs;
+    s.ops = (int64_t)hs.ops.size() / 4;
+    s.op_levels = hs.Lops;
+    s.scratch_rows = hs.scratch_rows;
 }
 }  // namespace tn
 
@@ -199,7 +220,8 @@ tn_status tn_schedule_build(uint32_t n, int64_t m, const uint32_t *src, const ui
     tn_host_schedule *s = new (std::nothrow) tn_host_schedule();
     if (!s) return fail(TN_E_NOMEM, "schedule allocation failed");
     std::string err;
-    tn_status st = tn::plan_events(n, m, src, dst, t, flags, s->hs, err);
+    tn_status st = tn::plan_events(n, m, src, dst, t, flags, s->hs, err, nullptr, 0,
+                                   tn::kFormGather | tn::kFormOps);
     if (st != TN_OK) {
         delete s;
         return fail(st, err);
@@ -220,6 +242,14 @@ tn_status tn_schedule_arrays(const tn_host_schedule *s, tn_plan_stats *stats,
     if (gat_tgt) *gat_tgt = s->hs.gat_tgt.data();
     if (gat_ptr) *gat_ptr = s->hs.gat_ptr.data();
     if (gat_src) *gat_src = s->hs.gat_src.data();
+    return TN_OK;
+}
+
+tn_status tn_schedule_op_arrays(const tn_host_schedule *s, const uint32_t **lvl_op,
+                                const uint32_t **ops) {
+    if (!s) return fail(TN_E_ARG, "schedule is NULL");
+    if (lvl_op) *lvl_op = s->hs.lvl_op.data();
+    if (ops) *ops = s->hs.ops.data();
     return TN_OK;
 }
 
@@ -251,23 +281,55 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         return fail(TN_E_ARG, "slice_words must be a power of two <= 64");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
-    if (plan->stats.max_level_gathers > 0) {
-        tn_status st = tn::ensure_scratch(
-            ctx, (size_t)plan->stats.max_level_gathers * (size_t)nwords * sizeof(uint64_t));
+    {
+        // per-workgroup sink words, then the compound scratch rows
+        const size_t words = (size_t)tn::rowor_workgroups(n, slice_words) * tn::kRoworSinkWords +
+                             (size_t)plan->scratch_rows * (size_t)nwords;
+        tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * words);
         if (st != TN_OK) return st;
     }
     hipError_t e;
+    if (!ctx->traffic) {
+        e = hipMalloc((void **)&ctx->traffic, 2 * sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            ctx->traffic = nullptr;
+            return fail(TN_E_NOMEM, "traffic counter allocation failed");
+        }
+    }
     {
         tn::ProfScope ps(ctx, TN_K_IDENTITY);
-        e = tn::launch_identity(C, n, ld, ctx->stream);
+        e = tn::launch_identity(C, n, ld, ctx->traffic, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "identity kernel launch");
     {
         tn::ProfScope ps(ctx, TN_K_ROWOR);
-        e = tn::launch_rowor_global(plan->view, C, ld, slice_words, (uint64_t *)ctx->scratch,
+        e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
+                                    plan->scratch_rows, ctx->traffic, ctx->saturation,
                                     ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "row-OR kernel launch");
+    return TN_OK;
+}
+
+tn_status tn_set_saturation(tn_ctx *ctx, int enable) {
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    ctx->saturation = enable != 0;
+    return TN_OK;
+}
+
+tn_status tn_plan_last_traffic(tn_ctx *ctx, uint64_t *words) {
+    if (!ctx || !words) return fail(TN_E_ARG, "ctx or words is NULL");
+    words[0] = words[1] = 0;
+    if (!ctx->traffic) return TN_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    unsigned long long h[2];
+    e = hipMemcpy(h, ctx->traffic, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "traffic counter copy");
+    words[0] = h[0];
+    words[1] = h[1];
     return TN_OK;
 }
 

@@ -16,6 +16,16 @@ namespace tn {
 constexpr uint32_t kDirBit = 0x80000000u;
 constexpr uint32_t kNodeMask = 0x7fffffffu;
 
+// Binary-op encoding {a, b, d1, d2}: r = row[a] | row[b]; row[d1] = r;
+// row[d2] = r unless d2 == kNoRow.  A row id with kScratchBit set names a
+// scratch row (compound items fold through them).  Levels hold at most
+// kOpsLevelCap ops.
+constexpr uint32_t kScratchBit = 0x80000000u;
+constexpr uint32_t kNoRow = 0xffffffffu;
+constexpr uint32_t kOpsLevelCap = 1024;
+constexpr uint32_t kOpsScratchRows = 1024;
+enum : int { kFormGather = 1, kFormOps = 2 };
+
 // A single network's schedule on the host.  Items are sorted by level;
 // level l owns pairs [lvl_pair[l], lvl_pair[l+1]) and gathers
 // [lvl_gat[l], lvl_gat[l+1]).  Gather g writes row gat_tgt[g] with the OR of
@@ -34,6 +44,14 @@ struct HostSchedule {
     std::vector<uint32_t> gat_src;   // S
     int64_t compound_items = 0;
     int64_t directed_pairs = 0;
+    // binary-op form (kFormOps): level l owns ops [lvl_op[l], lvl_op[l+1]),
+    // 4 uint32 each
+    uint32_t Lops = 0;
+    uint32_t op_levels_unsplit = 0;
+    uint32_t scratch_rows = 0;
+    std::vector<uint32_t> lvl_op;  // Lops + 1
+    std::vector<uint32_t> ops;     // 4 * nops
+    int64_t op_pairs = 0, op_directed = 0, op_targets = 0, op_sources = 0, op_compound = 0;
     int64_t max_level_items = 0;
     int64_t max_level_gathers = 0;
     double host_seconds = 0.0;
@@ -53,19 +71,33 @@ struct DevSchedule {
     const uint32_t *gat_src;
 };
 
+// Device view of a binary-op schedule: level l owns ops [lvl[l], lvl[l+1]).
+struct DevOps {
+    uint32_t L;
+    uint32_t nops;
+    const uint32_t *lvl;
+    const uint4 *ops;
+};
+
 // Validates events and builds the schedule.  Returns TN_OK or an error code
 // with `err` set.
 // With `map`, event endpoints are ids < n_src sent through map[] to the n
 // nodes of a hashed network.
+// `forms` selects the gather form (pairs + gathers, for the batched kernel),
+// the binary-op form (for the global kernel), or both.
 tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
                       const uint32_t *dst, const int64_t *t, uint32_t flags,
                       HostSchedule &out, std::string &err,
-                      const uint32_t *map = nullptr, uint32_t n_src = 0);
+                      const uint32_t *map = nullptr, uint32_t n_src = 0,
+                      int forms = kFormGather);
 
 // Size in bytes of the device image of a schedule and its packing.
 size_t schedule_device_bytes(const HostSchedule &s);
 void schedule_pack(const HostSchedule &s, std::vector<unsigned char> &image);
 DevSchedule schedule_view(const HostSchedule &s, const void *dev_base);
+size_t ops_device_bytes(const HostSchedule &s);
+void ops_pack(const HostSchedule &s, std::vector<unsigned char> &image);
+DevOps ops_view(const HostSchedule &s, const void *dev_base);
 
 // ---- error reporting and device scope (tn_abi.cpp) ---------------------
 tn_status fail(tn_status code, const std::string &msg);
@@ -93,6 +125,9 @@ struct tn_ctx {
     hipStream_t stream = nullptr;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // row words loaded / stored by the last tn_plan_execute (device)
+    unsigned long long *traffic = nullptr;
+    bool saturation = true;
     int num_cus = 0;
     // kernel timing (tn_profile_enable)
     bool profiling = false;
@@ -108,7 +143,8 @@ struct tn_plan {
     int device = 0;
     void *dev = nullptr;
     size_t dev_bytes = 0;
-    tn::DevSchedule view{};
+    tn::DevOps view{};
+    uint32_t scratch_rows = 0;
     tn_plan_stats stats{};
 };
 
@@ -144,10 +180,24 @@ tn_status ensure_scratch(tn_ctx *ctx, size_t bytes);
 void fill_stats(const HostSchedule &hs, tn_plan_stats &s);
 
 // ---- kernel launchers (tn_kernels.hip) ---------------------------------
-hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, hipStream_t st);
-hipError_t launch_rowor_global(const DevSchedule &s, uint64_t *C, int64_t ld,
+// traffic (nullable): two device counters the identity kernel zeroes.
+hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, unsigned long long *traffic,
+                           hipStream_t st);
+constexpr size_t kRoworSinkWords = 1024;
+// LDS bytes the saturation bitmap may take next to the op frames and work
+// lists (gfx950: 160 KiB per workgroup).
+constexpr size_t kRoworSatLds = 163840 - 40960;
+// scratch: kRoworSinkWords words per workgroup, then scratch_rows rows of
+// ceil(n/64) words.  rowor_workgroups gives the number of workgroups.
+// The kernel adds the row words it loaded to traffic[0] and stored to
+// traffic[1] (device counters, zeroed by the caller).  With saturation, and
+// when a bit per row and scratch row fits kRoworSatLds, it skips the loads
+// and stores that saturated rows make redundant.
+uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words);
+hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                                uint32_t slice_words, uint64_t *scratch,
-                               hipStream_t st);
+                               uint32_t scratch_rows, unsigned long long *traffic,
+                               bool saturation, hipStream_t st);
 hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld,
                             int32_t *out_sizes, hipStream_t st);
 hipError_t launch_in_sizes(const uint64_t *C, uint32_t n, int64_t ld,

@@ -24,7 +24,9 @@ __device__ __forceinline__ uint32_t xcd_slice(uint32_t b, uint32_t nb) {
     return x * q + min(x, r) + k;
 }
 
-__global__ void __launch_bounds__(256) k_identity(uint64_t *__restrict__ C, uint32_t n, int64_t ld) {
+__global__ void __launch_bounds__(256) k_identity(uint64_t *__restrict__ C, uint32_t n, int64_t ld,
+                                                  unsigned long long *__restrict__ traffic) {
+    if (traffic && blockIdx.x == 0 && threadIdx.x < 2) traffic[threadIdx.x] = 0;
     for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
         uint64_t *row = C + (size_t)r * (size_t)ld;
         const int64_t diag = (int64_t)(r >> 6);
@@ -33,146 +35,291 @@ __global__ void __launch_bounds__(256) k_identity(uint64_t *__restrict__ C, uint
     }
 }
 
-// One workgroup per slice of SW word columns; SW consecutive lanes update the
-// SW words of one item's rows, so each row access is one contiguous
-// 8*SW-byte segment.  Per level, a lane group holds up to U pair items (and
-// UG compound-item gathers) in registers and issues all their row loads before
-// any store.  The level boundaries are staged in LDS a window ahead and the
-// items of the next level are loaded while the current level runs, so a level
-// costs one round trip for its rows plus the store acknowledgement its
-// closing barrier waits for.  A level with compound items keeps the gathered
-// rows in registers across one extra barrier (read all, then write all).
-constexpr uint32_t kLevelWindow = 512;
+// One workgroup per slice of SW word columns runs every level of the
+// binary-op schedule; SW consecutive lanes update the SW words of one op's
+// rows, so each row access is one contiguous 8*SW-byte segment.  An op is
+// r = row[a] | row[b]; row[d1] = r; row[d2] = r: an undirected pair is
+// (u, v, u, v), a one-way pair (u, v, u, -), and a compound time step folds
+// its old rows into scratch rows and copies them back, so every level is the
+// same straight-line code over at most kOpsLevelCap independent ops.
+//
+// Saturation.  Rows only gain bits in reverse time, and once an
+// out-component covers every column of a slice, any OR with it is that full
+// slice again.  With SAT, each workgroup keeps one LDS bit per row (and per
+// scratch row) meaning "this row is all ones in my slice".  An op with a
+// saturated operand loads nothing and gives a full result; a store of a full
+// result into a row already marked full is dropped.  Every write refreshes
+// the destination's bit, so a bit of 1 is always true (0 only means "not
+// known"), and the matrix in memory is exactly the plain recurrence's.
+// Kernel counters record the row words actually loaded and stored.
+//
+// The waves of a workgroup specialise.  Two loader waves stream the ops of
+// level l + 1 into an LDS frame while the compute waves run level l from the
+// other frame, and they already hold the ops of level l + 2 in registers.
+// Compute waves issue only row loads and stores.  On gfx9 loads and stores
+// share one in-order completion counter, so this split keeps the loaders'
+// waits from ever covering row stores, and the compute waves never wait for
+// a schedule load.  Every compute memory op is unconditional: a lane with no
+// op, a skipped access, no second destination, or a word past the last word
+// column reads and writes its own sink word.  The barrier that ends a level
+// orders the workgroup's row stores and bit updates before the next level.
+constexpr uint32_t kLoaderThreads = 128;
+constexpr uint32_t kLoaderOps = kOpsLevelCap / kLoaderThreads;  // ops per loader lane and level
 
-template <int U>
-__device__ __forceinline__ void load_items(uint2 (&it)[U], const uint2 *__restrict__ pairs,
-                                           uint32_t first, uint32_t end, uint32_t ngrp) {
+// One op {a, b, d1, d2} as a native 4-lane vector.
+typedef uint32_t op4 __attribute__((ext_vector_type(4)));
+
+struct OpArgs {
+    uint64_t *C;
+    size_t ldz;
+    uint64_t *rows;  // scratch rows, nwords words each
+    uint64_t *sink;  // this thread's sink word
+    uint32_t w, nwords, grp, ngrp;
+    bool wok;
+    // saturation bits (SAT only)
+    uint32_t *sat;      // LDS bitmap: real rows from bit 0, scratch rows from bit sbase
+    uint32_t sbase;     // first bit of the scratch rows (n rounded up to 32)
+    uint32_t sbits;     // bits in the bitmap
+    uint64_t fullw;     // this lane's word when its row slice is full (0 past the last word)
+    uint64_t gmask;     // ballot bits of this lane's group
+    uint32_t loaded, stored;  // row words this lane moved
+    bool lead;                // first lane of its group
+};
+
+// Branch-free: every candidate address is formed, then one is selected, so
+// the load or store that uses it is issued by every lane.
+__device__ __forceinline__ uint64_t *op_addr(const OpArgs &A, uint32_t id, bool valid) {
+    const uint64_t row = (uint64_t)(id & kNodeMask);
+    const uintptr_t real = (uintptr_t)(A.C + row * A.ldz + A.w);
+    const uintptr_t scr = (uintptr_t)(A.rows + row * A.nwords + A.w);
+    const uintptr_t pick = (id & kScratchBit) ? scr : real;
+    const bool ok = valid && A.wok && id != kNoRow;
+    return (uint64_t *)(ok ? pick : (uintptr_t)A.sink);
+}
+
+__device__ __forceinline__ uint32_t sat_index(const OpArgs &A, uint32_t id) {
+    const uint32_t i = (id & kScratchBit) ? A.sbase + (id & kNodeMask) : id;
+    return min(i, A.sbits - 1);  // kNoRow and stale frame entries stay in range
+}
+
+__device__ __forceinline__ bool sat_get(const OpArgs &A, uint32_t id) {
+    const uint32_t i = sat_index(A, id);
+    return (A.sat[i >> 5] >> (i & 31u)) & 1u;
+}
+
+// Plain path: ops [base, n) of the current frame, UC per lane group, every
+// op loading and storing its rows.
+template <int UC>
+__device__ __forceinline__ void apply_frame(OpArgs &A, const op4 *frame, uint32_t base,
+                                            uint32_t n) {
+    op4 o[UC];
+    uint64_t x[UC], y[UC];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-        const uint32_t idx = first + k * ngrp;
-        it[k] = (idx < end) ? pairs[idx] : make_uint2(0xffffffffu, 0u);
+    for (int k = 0; k < UC; ++k) o[k] = frame[min(base + A.grp + k * A.ngrp, kOpsLevelCap - 1)];
+#pragma unroll
+    for (int k = 0; k < UC; ++k) {
+        const bool v = base + A.grp + k * A.ngrp < n;
+        x[k] = *op_addr(A, o[k].x, v);
+        y[k] = *op_addr(A, o[k].y, v);
+        A.loaded += (v && A.wok) ? 2u : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < UC; ++k) {
+        const bool v = base + A.grp + k * A.ngrp < n;
+        const uint64_t r = x[k] | y[k];
+        *op_addr(A, o[k].z, v) = r;
+        *op_addr(A, o[k].w, v) = r;
+        A.stored += ((v && A.wok && o[k].z != kNoRow) ? 1u : 0u) +
+                    ((v && A.wok && o[k].w != kNoRow) ? 1u : 0u);
     }
 }
 
-template <int U>
-__device__ __forceinline__ void load_rows(const uint64_t *__restrict__ C, size_t ldz, uint32_t w,
-                                          bool wok, const uint2 (&it)[U], uint64_t (&a)[U],
-                                          uint64_t (&b)[U]) {
+// Saturation path, per compute wave: classify a contiguous share of the
+// level's ops by their saturation bits (LDS only), keep those that still
+// need a row load or store in a per-wave list (ballot compaction), then run
+// only those, U per lane group at a time, loads before stores.
+constexpr uint32_t kComputeWaves = (1024 - kLoaderThreads) / 64;
+constexpr uint32_t kWaveShare = (kOpsLevelCap + kComputeWaves - 1) / kComputeWaves;
+constexpr uint32_t kWorkSkip = 1u << 16, kWorkF1 = 1u << 17, kWorkF2 = 1u << 18;
+
+__device__ __forceinline__ void sat_set(const OpArgs &A, uint32_t id, bool full) {
+    const uint32_t i = sat_index(A, id);
+    if (full) atomicOr(&A.sat[i >> 5], 1u << (i & 31u));
+    else atomicAnd(&A.sat[i >> 5], ~(1u << (i & 31u)));
+}
+
+template <int SW, int U>
+__device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint32_t *work,
+                                         uint32_t nwork) {
+    constexpr uint32_t G = 64 / SW;  // lane groups per wave
+    const uint32_t g = (threadIdx.x & 63u) / SW;
+    for (uint32_t base = 0; base < nwork; base += G * U) {
+        uint32_t e[U];
+        op4 o[U];
+        uint64_t x[U], y[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-        if (it[k].x != 0xffffffffu && wok) {
-            a[k] = C[(size_t)it[k].x * ldz + w];
-            b[k] = C[(size_t)(it[k].y & kNodeMask) * ldz + w];
+        for (int k = 0; k < U; ++k) {
+            const uint32_t j = base + g + k * G;
+            e[k] = work[min(j, kWaveShare - 1)];
+            o[k] = frame[e[k] & 1023u];
+            const bool v = j < nwork, ld = v && !(e[k] & kWorkSkip);
+            x[k] = *op_addr(A, o[k].x, ld);
+            y[k] = *op_addr(A, o[k].y, ld);
+            A.loaded += (ld && A.wok) ? 2u : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint32_t j = base + g + k * G;
+            const bool v = j < nwork, skip = e[k] & kWorkSkip;
+            const uint64_t r = skip ? A.fullw : (x[k] | y[k]);
+            const uint64_t ball = __ballot(r == A.fullw || !A.wok);
+            const bool full = (ball & A.gmask) == A.gmask;
+            const bool f1 = e[k] & kWorkF1, f2 = e[k] & kWorkF2;
+            const bool s1 = v && o[k].z != kNoRow && !(full && f1);
+            const bool s2 = v && o[k].w != kNoRow && !(full && f2);
+            *op_addr(A, o[k].z, s1) = r;
+            *op_addr(A, o[k].w, s2) = r;
+            A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+            if (v && A.lead) {
+                if (o[k].z != kNoRow && f1 != full) sat_set(A, o[k].z, full);
+                if (o[k].w != kNoRow && f2 != full) sat_set(A, o[k].w, full);
+            }
         }
     }
 }
 
-template <int U>
-__device__ __forceinline__ void store_rows(uint64_t *__restrict__ C, size_t ldz, uint32_t w, bool wok,
-                                           const uint2 (&it)[U], const uint64_t (&a)[U],
-                                           const uint64_t (&b)[U]) {
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-        if (it[k].x != 0xffffffffu && wok) {
-            const uint64_t r = a[k] | b[k];
-            C[(size_t)it[k].x * ldz + w] = r;
-            if (!(it[k].y & kDirBit)) C[(size_t)(it[k].y & kNodeMask) * ldz + w] = r;
-        }
+// Classify ops [lo, hi) of the frame (hi - lo <= kWaveShare) into this
+// wave's work list; returns the list length (wave-uniform).
+__device__ __forceinline__ uint32_t classify(const OpArgs &A, const op4 *frame, uint32_t lo,
+                                             uint32_t hi, uint32_t *work) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t nwork = 0;
+    for (uint32_t r0 = lo; r0 < hi; r0 += 64) {
+        const uint32_t i = r0 + lane;
+        const bool v = i < hi;
+        const op4 o = frame[min(i, kOpsLevelCap - 1)];
+        const bool skip = sat_get(A, o.x) || sat_get(A, o.y);
+        const bool f1 = o.z != kNoRow && sat_get(A, o.z);
+        const bool f2 = o.w != kNoRow && sat_get(A, o.w);
+        const bool need = v && (!skip || (o.z != kNoRow && !f1) || (o.w != kNoRow && !f2));
+        const uint64_t m = __ballot(need);
+        const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (need)
+            work[nwork + pos] = i | (skip ? kWorkSkip : 0u) | (f1 ? kWorkF1 : 0u) |
+                                (f2 ? kWorkF2 : 0u);
+        nwork += (uint32_t)__popcll(m);
     }
+    return nwork;
 }
 
-__device__ __forceinline__ uint64_t gather_row(const uint64_t *__restrict__ C, size_t ldz, uint32_t w,
-                                               const DevSchedule &s, uint32_t gi) {
-    uint64_t acc = 0;
-    const uint32_t s0 = s.gat_ptr[gi], s1 = s.gat_ptr[gi + 1];
-    for (uint32_t q = s0; q < s1; ++q) acc |= C[(size_t)s.gat_src[q] * ldz + w];
-    return acc;
+// Loader lanes hold a level's ops in registers.
+struct HeldOps {
+    op4 r[kLoaderOps];
+};
+
+// The ops of one level into registers (clamped, unconditional).
+__device__ __forceinline__ HeldOps fetch_level(const DevOps &s, uint32_t l, uint32_t lane) {
+    const uint32_t p0 = s.lvl[min(l, s.L)];
+    const uint32_t last = s.nops - 1;
+    const op4 *ops = reinterpret_cast<const op4 *>(s.ops);
+    HeldOps h;
+#pragma unroll
+    for (int k = 0; k < (int)kLoaderOps; ++k) h.r[k] = ops[min(p0 + lane + k * kLoaderThreads, last)];
+    return h;
 }
 
-template <int SW, int U, int UG>
+__device__ __forceinline__ void put_level(op4 *frame, const HeldOps &h, uint32_t lane) {
+#pragma unroll
+    for (int k = 0; k < (int)kLoaderOps; ++k) frame[lane + k * kLoaderThreads] = h.r[k];
+}
+
+// Wave sum of a per-lane count, added once per wave to a device counter.
+__device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
+    unsigned long long v = x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63u) == 0 && v) atomicAdd(ctr, v);
+}
+
+template <int SW, int UC, int UW, bool SAT>
 __global__ void __launch_bounds__(1024)
-k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevSchedule s,
-               uint64_t *__restrict__ scratch) {
-    __shared__ uint32_t win_p[2][kLevelWindow];
-    __shared__ uint32_t win_g[2][kLevelWindow];
-    const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
-    const uint32_t w = slice * SW + (threadIdx.x % SW);
-    const bool wok = w < nwords;
-    const uint32_t grp = threadIdx.x / SW;
-    const uint32_t ngrp = blockDim.x / SW;
-    const uint32_t chunk = ngrp * U;
-    const size_t ldz = (size_t)ld;
+k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
+               uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
+               unsigned long long *__restrict__ traffic) {
+    __shared__ op4 frame[2][kOpsLevelCap];
+    __shared__ uint32_t fcount[2];
+    __shared__ uint32_t worklist[SAT ? kComputeWaves : 1][kWaveShare];
+    extern __shared__ uint32_t satbits[];
     const uint32_t L = s.L;
-    // level boundaries of window 0 and 1 (entries past L repeat entry L)
-    for (uint32_t i = threadIdx.x; i < 2 * kLevelWindow; i += blockDim.x) {
-        const uint32_t l = min(i, L);
-        win_p[i / kLevelWindow][i % kLevelWindow] = s.lvl_pair[l];
-        win_g[i / kLevelWindow][i % kLevelWindow] = s.lvl_gat[l];
+    if (L == 0 || s.nops == 0) return;
+    const uint32_t tid = threadIdx.x;
+    const bool loader = tid < kLoaderThreads;
+    const uint32_t ctid = tid - kLoaderThreads;  // compute-thread index
+    const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
+    OpArgs A;
+    A.C = C;
+    A.ldz = (size_t)ld;
+    A.nwords = nwords;
+    A.w = slice * SW + (ctid % SW);
+    A.wok = !loader && A.w < nwords;
+    A.grp = ctid / SW;
+    A.ngrp = (blockDim.x - kLoaderThreads) / SW;
+    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
+    A.rows = scratch + (size_t)gridDim.x * kRoworSinkWords;
+    A.sat = satbits;
+    A.sbase = sbase;
+    A.sbits = sbits;
+    A.loaded = A.stored = 0;
+    A.lead = (ctid % SW) == 0;
+    {
+        const uint32_t tail = n & 63u;
+        const uint64_t last = tail ? (1ull << tail) - 1ull : ~0ull;
+        A.fullw = !A.wok ? 0ull : (A.w + 1 < nwords ? ~0ull : last);
+        A.gmask = (SW == 64 ? ~0ull : ((1ull << SW) - 1ull)) << ((tid & 63u) / SW * SW);
+    }
+    if (SAT)
+        for (uint32_t i = tid; i < (sbits + 31) / 32; i += blockDim.x) satbits[i] = 0;
+    constexpr bool WIDE = ((1024 - kLoaderThreads) / SW) * UC < kOpsLevelCap;
+    HeldOps held;
+    if (loader) {
+        // level 0 straight into its frame, level 1 into registers
+        put_level(frame[0], fetch_level(s, 0, tid), tid);
+        if (tid == 0) fcount[0] = s.lvl[1] - s.lvl[0];
+        held = fetch_level(s, 1, tid);
     }
     __syncthreads();
-    auto lp = [&](uint32_t l) { return win_p[(l / kLevelWindow) & 1u][l % kLevelWindow]; };
-    auto lg = [&](uint32_t l) { return win_g[(l / kLevelWindow) & 1u][l % kLevelWindow]; };
-    uint32_t p0 = lp(0), p1 = lp(1);
-    uint32_t g0 = lg(0);
-    uint2 cur[U];
-    load_items<U>(cur, s.pairs, p0 + grp, p1, ngrp);
     for (uint32_t l = 0; l < L; ++l) {
-        if (l % kLevelWindow == 0 && l > 0) {
-            // refill the buffer of the window before this one with the window
-            // after it; it was last read three levels ago, before a barrier
-            const uint32_t nb = l / kLevelWindow + 1;
-            for (uint32_t i = threadIdx.x; i < kLevelWindow; i += blockDim.x) {
-                const uint32_t ll = min(nb * kLevelWindow + i, L);
-                win_p[nb & 1u][i] = s.lvl_pair[ll];
-                win_g[nb & 1u][i] = s.lvl_gat[ll];
-            }
-        }
-        const uint32_t p2 = lp(min(l + 2, L));
-        const uint32_t g1 = lg(l + 1);
-        uint2 nxt[U];
-        load_items<U>(nxt, s.pairs, p1 + grp, p2, ngrp);
-        uint64_t a[U], b[U];
-        load_rows<U>(C, ldz, w, wok, cur, a, b);
-        const uint32_t ng = g1 - g0;
-        uint64_t gacc[UG];
-        if (ng > 0 && ng <= ngrp * UG) {
-#pragma unroll
-            for (int k = 0; k < UG; ++k) {
-                const uint32_t gi = g0 + grp + k * ngrp;
-                if (gi < g1 && wok) gacc[k] = gather_row(C, ldz, w, s, gi);
-            }
-        }
-        store_rows<U>(C, ldz, w, wok, cur, a, b);
-        // levels wider than one register chunk
-        for (uint32_t base = p0 + chunk + grp; base < p1; base += chunk) {
-            uint2 more[U];
-            load_items<U>(more, s.pairs, base, p1, ngrp);
-            load_rows<U>(C, ldz, w, wok, more, a, b);
-            store_rows<U>(C, ldz, w, wok, more, a, b);
-        }
-        if (ng > 0) {
-            if (ng <= ngrp * UG) {
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < UG; ++k) {
-                    const uint32_t gi = g0 + grp + k * ngrp;
-                    if (gi < g1 && wok) C[(size_t)s.gat_tgt[gi] * ldz + w] = gacc[k];
-                }
+        const uint32_t cur = l & 1u;
+        if (loader) {
+            // past the last level the frame and count are never read, and
+            // fetch_level clamps its level index to L
+            put_level(frame[cur ^ 1u], held, tid);
+            if (tid == 0) fcount[cur ^ 1u] = s.lvl[min(l + 2, L)] - s.lvl[min(l + 1, L)];
+            held = fetch_level(s, l + 2, tid);
+        } else {
+            const uint32_t cnt = fcount[cur];
+            if (SAT) {
+                const uint32_t cw = ctid >> 6;
+                const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
+                const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
+                uint32_t *work = worklist[SAT ? cw : 0];
+                const uint32_t nwork = classify(A, frame[cur], lo, hi, work);
+                run_work<SW, UW>(A, frame[cur], work, nwork);
             } else {
-                // more gathers than register slots: stage through scratch rows
-                for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp)
-                    if (wok) scratch[(size_t)(gi - g0) * nwords + w] = gather_row(C, ldz, w, s, gi);
-                __syncthreads();
-                for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp)
-                    if (wok) C[(size_t)s.gat_tgt[gi] * ldz + w] = scratch[(size_t)(gi - g0) * nwords + w];
+                apply_frame<UC>(A, frame[cur], 0, cnt);
+                if (WIDE) {
+                    const uint32_t chunk = A.ngrp * UC;
+                    for (uint32_t base = chunk; base < cnt; base += chunk)
+                        apply_frame<UC>(A, frame[cur], base, cnt);
+                }
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < U; ++k) cur[k] = nxt[k];
-        p0 = p1;
-        p1 = p2;
-        g0 = g1;
+    }
+    if (!loader) {
+        count_add(traffic, A.loaded);
+        count_add(traffic + 1, A.stored);
     }
 }
 
@@ -247,12 +394,26 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
     }
 }
 
-template <int SW, int U, int UG = 1>
-hipError_t rowor_variant(const DevSchedule &s, uint64_t *C, int64_t ld, uint32_t nwords,
-                         uint64_t *scratch, hipStream_t st) {
+template <int SW, int UC, int UW>
+hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, uint64_t *scratch,
+                         uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
+                         hipStream_t st) {
+    const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
-    hipLaunchKernelGGL((k_rowor_global<SW, U, UG>), dim3(slices), dim3(1024), 0, st, C, ld, nwords, s,
-                       scratch);
+    const uint32_t sbase = (n + 31u) & ~31u;
+    const uint64_t sbits = (uint64_t)sbase + scratch_rows + 1;
+    const size_t lds = (size_t)((sbits + 31) / 32) * 4;
+    if (saturation && lds <= kRoworSatLds) {
+        auto k = k_rowor_global<SW, UC, UW, true>;
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, n, nwords, s, scratch,
+                           sbase, (uint32_t)sbits, traffic);
+    } else {
+        hipLaunchKernelGGL((k_rowor_global<SW, UC, UW, false>), dim3(slices), dim3(1024), 0, st, C,
+                           ld, n, nwords, s, scratch, 0u, 1u, traffic);
+    }
     return hipGetLastError();
 }
 
@@ -270,24 +431,31 @@ uint32_t default_slice_words(uint32_t n, int64_t ld) {
     return 1;
 }
 
-hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, hipStream_t st) {
+hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, unsigned long long *traffic,
+                           hipStream_t st) {
     const uint32_t blocks = n < 65536u ? n : 65536u;
-    hipLaunchKernelGGL(k_identity, dim3(blocks), dim3(256), 0, st, C, n, ld);
+    hipLaunchKernelGGL(k_identity, dim3(blocks), dim3(256), 0, st, C, n, ld, traffic);
     return hipGetLastError();
 }
 
-hipError_t launch_rowor_global(const DevSchedule &s, uint64_t *C, int64_t ld, uint32_t slice_words,
-                               uint64_t *scratch, hipStream_t st) {
-    const uint32_t nwords = (s.n + 63) / 64;
+uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words) {
+    const uint32_t nwords = (n + 63) / 64;
+    return (nwords + slice_words - 1) / slice_words;
+}
+
+hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
+                               uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
+                               unsigned long long *traffic, bool saturation, hipStream_t st) {
     if (s.L == 0) return hipSuccess;
     switch (slice_words) {
-        case 1: return rowor_variant<1, 2>(s, C, ld, nwords, scratch, st);
-        case 2: return rowor_variant<2, 2>(s, C, ld, nwords, scratch, st);
-        case 4: return rowor_variant<4, 4>(s, C, ld, nwords, scratch, st);
-        case 8: return rowor_variant<8, 8>(s, C, ld, nwords, scratch, st);
-        case 16: return rowor_variant<16, 8>(s, C, ld, nwords, scratch, st);
-        case 32: return rowor_variant<32, 8>(s, C, ld, nwords, scratch, st);
-        case 64: return rowor_variant<64, 8>(s, C, ld, nwords, scratch, st);
+        // UC: ops per lane group and level, so that (896 / SW) * UC >= 1024
+        case 1: return rowor_variant<1, 2, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 2: return rowor_variant<2, 3, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 4: return rowor_variant<4, 5, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 8: return rowor_variant<8, 10, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 16: return rowor_variant<16, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 32: return rowor_variant<32, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 64: return rowor_variant<64, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
         default: return hipErrorInvalidValue;
     }
 }

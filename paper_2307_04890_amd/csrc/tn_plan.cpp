@@ -28,8 +28,15 @@ namespace {
 struct Planner {
     uint32_t n;
     bool directed;
-    std::vector<uint32_t> last;  // last level (1-based) that touched a row
+    bool ops_mode;               // emit binary ops instead of pairs + gathers
+    std::vector<uint32_t> last;  // gather form: last level (1-based) that touched a row
     uint32_t L = 0;
+
+    // ops form: last level that wrote / read each row and scratch row
+    std::vector<uint32_t> lw, lr, slw, slr;
+    uint32_t S = 0, next_scratch = 0;
+    std::vector<uint32_t> oa, ob, od1, od2, olev;
+    int64_t n_pairs = 0, n_dir = 0, n_targets = 0, n_sources = 0;
 
     // items in reverse-stream order
     std::vector<uint32_t> pu, pv, plev;
@@ -46,9 +53,47 @@ struct Planner {
     std::vector<uint32_t> lnode, parent, comp, comp_nodes_ptr, comp_nodes,
         comp_ev_ptr, comp_ev, fill, nbr_ptr, nbr;
     std::vector<uint32_t> es, ed;  // group events without self-loops
+    std::vector<uint32_t> tgt, tscr;
 
-    explicit Planner(uint32_t n_, bool dir) : n(n_), directed(dir), last(n_, 0),
-                                              stamp(n_, 0xffffffffu), local(n_, 0) {}
+    Planner(uint32_t n_, bool dir, bool ops)
+        : n(n_), directed(dir), ops_mode(ops), stamp(n_, 0xffffffffu), local(n_, 0) {
+        if (ops) {
+            lw.assign(n_, 0);
+            lr.assign(n_, 0);
+            grow_scratch(kOpsScratchRows);
+        } else {
+            last.assign(n_, 0);
+        }
+    }
+
+    void grow_scratch(uint32_t rows) {
+        if (rows <= S) return;
+        S = rows;
+        slw.resize(S, 0);
+        slr.resize(S, 0);
+    }
+    uint32_t &W(uint32_t id) { return (id & kScratchBit) ? slw[id & kNodeMask] : lw[id]; }
+    uint32_t &R(uint32_t id) { return (id & kScratchBit) ? slr[id & kNodeMask] : lr[id]; }
+
+    // Places one op r = row[a] | row[b] -> row[d1], row[d2] (d2 may be
+    // kNoRow) on the earliest level after the last write of every row it
+    // reads and after the last read or write of every row it writes.
+    void emit(uint32_t a, uint32_t b, uint32_t d1, uint32_t d2) {
+        uint32_t lev = std::max(W(a), W(b));
+        lev = std::max(lev, std::max(W(d1), R(d1)));
+        if (d2 != kNoRow) lev = std::max(lev, std::max(W(d2), R(d2)));
+        ++lev;
+        R(a) = std::max(R(a), lev);
+        R(b) = std::max(R(b), lev);
+        W(d1) = lev;
+        if (d2 != kNoRow) W(d2) = lev;
+        if (lev > L) L = lev;
+        oa.push_back(a);
+        ob.push_back(b);
+        od1.push_back(d1);
+        od2.push_back(d2);
+        olev.push_back(lev);
+    }
 
     uint32_t find(uint32_t x) {
         while (parent[x] != x) {
@@ -60,6 +105,17 @@ struct Planner {
 
     void add_pair(uint32_t u, uint32_t v, bool uv, bool vu) {
         // uv: information reaches u's row from v (event u -> v in reverse time)
+        if (ops_mode) {
+            ++n_pairs;
+            if (!directed || (uv && vu)) {
+                emit(u, v, u, v);
+            } else {
+                ++n_dir;
+                if (uv) emit(u, v, u, kNoRow);
+                else emit(v, u, v, kNoRow);
+            }
+            return;
+        }
         uint32_t lvl = 1 + std::max(last[u], last[v]);
         last[u] = last[v] = lvl;
         if (lvl > L) L = lvl;
@@ -162,17 +218,11 @@ struct Planner {
         }
     }
 
-    void compound(uint32_t n0, uint32_t n1, uint32_t e0, uint32_t e1) {
-        ++compound_items;
-        uint32_t lvl = 0;
-        for (uint32_t q = n0; q < n1; ++q) lvl = std::max(lvl, last[lnode[comp_nodes[q]]]);
-        ++lvl;
-        if (lvl > L) L = lvl;
-        for (uint32_t q = n0; q < n1; ++q) last[lnode[comp_nodes[q]]] = lvl;
-        // partners of each local node: event s -> d gives new[s] |= old[d]
-        // (and new[d] |= old[s] when undirected)
+    // partners of each node of a compound item: event s -> d gives
+    // new[s] |= old[d] (and new[d] |= old[s] when undirected); fills nbr /
+    // nbr_ptr indexed by the node's position in the item
+    void partners(uint32_t n0, uint32_t n1, uint32_t e0, uint32_t e1) {
         const uint32_t cn = n1 - n0;
-        // position of local node inside the component
         for (uint32_t q = n0; q < n1; ++q) fill[comp_nodes[q]] = q - n0;
         nbr_ptr.assign(cn + 1, 0);
         for (uint32_t q = e0; q < e1; ++q) {
@@ -188,10 +238,56 @@ struct Planner {
             nbr[pos[fill[local[es[i]]]]++] = ed[i];
             if (!directed) nbr[pos[fill[local[ed[i]]]]++] = es[i];
         }
+        for (uint32_t c = 0; c < cn; ++c) std::sort(nbr.begin() + nbr_ptr[c], nbr.begin() + nbr_ptr[c + 1]);
+    }
+
+    // Compound item as binary ops: each target folds its old row and its
+    // partners' old rows into a scratch row (all folds read only old rows),
+    // then every target copies its scratch row back.
+    void compound_ops(uint32_t n0, uint32_t n1, uint32_t e0, uint32_t e1) {
+        partners(n0, n1, e0, e1);
+        const uint32_t cn = n1 - n0;
+        grow_scratch(cn);
+        tgt.clear();
+        tscr.clear();
+        for (uint32_t c = 0; c < cn; ++c) {
+            const uint32_t b0 = nbr_ptr[c], b1 = nbr_ptr[c + 1];
+            if (b0 == b1) continue;  // no incoming information: row unchanged
+            const uint32_t x = lnode[comp_nodes[n0 + c]];
+            const uint32_t tsc = (next_scratch++ % S) | kScratchBit;
+            uint32_t acc = x;
+            int64_t k = 0;
+            for (uint32_t q = b0; q < b1; ++q) {
+                if ((q > b0 && nbr[q] == nbr[q - 1]) || nbr[q] == x) continue;
+                emit(acc, nbr[q], tsc, kNoRow);
+                acc = tsc;
+                ++k;
+            }
+            if (k == 0) continue;
+            ++n_targets;
+            n_sources += k + 1;
+            tgt.push_back(x);
+            tscr.push_back(tsc);
+        }
+        for (size_t i = 0; i < tgt.size(); ++i) emit(tscr[i], tscr[i], tgt[i], kNoRow);
+    }
+
+    void compound(uint32_t n0, uint32_t n1, uint32_t e0, uint32_t e1) {
+        ++compound_items;
+        if (ops_mode) {
+            compound_ops(n0, n1, e0, e1);
+            return;
+        }
+        uint32_t lvl = 0;
+        for (uint32_t q = n0; q < n1; ++q) lvl = std::max(lvl, last[lnode[comp_nodes[q]]]);
+        ++lvl;
+        if (lvl > L) L = lvl;
+        for (uint32_t q = n0; q < n1; ++q) last[lnode[comp_nodes[q]]] = lvl;
+        partners(n0, n1, e0, e1);
+        const uint32_t cn = n1 - n0;
         for (uint32_t c = 0; c < cn; ++c) {
             uint32_t b0 = nbr_ptr[c], b1 = nbr_ptr[c + 1];
             if (b0 == b1) continue;  // no incoming information: row unchanged
-            std::sort(nbr.begin() + b0, nbr.begin() + b1);
             uint32_t x = lnode[comp_nodes[n0 + c]];
             Gather g;
             g.level = lvl;
@@ -209,10 +305,47 @@ struct Planner {
 
 }  // namespace
 
+namespace {
+
+// Binary-op form: levels of at most kOpsLevelCap ops (a wider level is split
+// into consecutive levels; its ops are independent, so any split is exact).
+void finish_ops(Planner &p, HostSchedule &out) {
+    const uint32_t L = p.L;
+    const size_t P = p.oa.size();
+    std::vector<uint32_t> cnt((size_t)L + 1, 0);
+    for (uint32_t lv : p.olev) cnt[lv]++;
+    std::vector<uint32_t> base((size_t)L + 2, 0);  // first split level of level l
+    for (uint32_t l = 1; l <= L; ++l)
+        base[l + 1] = base[l] + std::max<uint32_t>(1, (cnt[l] + kOpsLevelCap - 1) / kOpsLevelCap);
+    const uint32_t Lf = base[L + 1];
+    std::vector<uint32_t> fcnt(Lf, 0), rank((size_t)L + 1, 0), flev(P);
+    for (size_t i = 0; i < P; ++i) {
+        const uint32_t lv = p.olev[i];
+        flev[i] = base[lv] + rank[lv]++ / kOpsLevelCap;
+        fcnt[flev[i]]++;
+    }
+    out.Lops = Lf;
+    out.lvl_op.assign((size_t)Lf + 1, 0);
+    for (uint32_t l = 0; l < Lf; ++l) out.lvl_op[l + 1] = out.lvl_op[l] + fcnt[l];
+    out.ops.resize(4 * P);
+    std::vector<uint32_t> pos(out.lvl_op.begin(), out.lvl_op.end() - 1);
+    for (size_t i = 0; i < P; ++i) {
+        const size_t q = pos[flev[i]]++;
+        out.ops[4 * q] = p.oa[i];
+        out.ops[4 * q + 1] = p.ob[i];
+        out.ops[4 * q + 2] = p.od1[i];
+        out.ops[4 * q + 3] = p.od2[i];
+    }
+    out.scratch_rows = p.S;
+    out.op_levels_unsplit = L;
+}
+
+}  // namespace
+
 tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
                       const uint32_t *dst, const int64_t *t, uint32_t flags,
                       HostSchedule &out, std::string &err, const uint32_t *map,
-                      uint32_t n_src) {
+                      uint32_t n_src, int forms) {
     auto t0 = std::chrono::steady_clock::now();
     if (n == 0) { err = "n must be > 0"; return TN_E_ARG; }
     if (m < 0) { err = "m must be >= 0"; return TN_E_ARG; }
@@ -239,23 +372,51 @@ tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
     }
     const bool directed = flags & TN_DIRECTED;
     const bool seq = flags & TN_TIES_SEQUENTIAL;
-    Planner p(n, directed);
-    p.pu.reserve((size_t)m);
-    p.pv.reserve((size_t)m);
-    p.plev.reserve((size_t)m);
-    int64_t b = m;
-    while (b > 0) {
-        int64_t a = b - 1;
-        if (!seq)
-            while (a > 0 && t[a - 1] == t[b - 1]) --a;
-        p.group(src, dst, map, a, b);
-        b = a;
-    }
-    // counting sort by level
-    const uint32_t L = p.L;
     out.n = n;
     out.m = m;
     out.flags = flags;
+    auto walk = [&](Planner &pl) {
+        int64_t b = m;
+        while (b > 0) {
+            int64_t a = b - 1;
+            if (!seq)
+                while (a > 0 && t[a - 1] == t[b - 1]) --a;
+            pl.group(src, dst, map, a, b);
+            b = a;
+        }
+    };
+    if (forms & kFormOps) {
+        Planner po(n, directed, true);
+        po.oa.reserve((size_t)m);
+        po.ob.reserve((size_t)m);
+        po.od1.reserve((size_t)m);
+        po.od2.reserve((size_t)m);
+        po.olev.reserve((size_t)m);
+        walk(po);
+        finish_ops(po, out);
+        out.op_pairs = po.n_pairs;
+        out.op_directed = po.n_dir;
+        out.op_targets = po.n_targets;
+        out.op_sources = po.n_sources;
+        out.op_compound = po.compound_items;
+        if (!(forms & kFormGather)) {
+            out.L = 0;
+            out.lvl_pair.assign(1, 0);
+            out.lvl_gat.assign(1, 0);
+            out.compound_items = po.compound_items;
+            out.directed_pairs = po.n_dir;
+            out.host_seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            return TN_OK;
+        }
+    }
+    Planner p(n, directed, false);
+    p.pu.reserve((size_t)m);
+    p.pv.reserve((size_t)m);
+    p.plev.reserve((size_t)m);
+    walk(p);
+    // counting sort by level
+    const uint32_t L = p.L;
     out.L = L;
     out.lvl_pair.assign((size_t)L + 1, 0);
     out.lvl_gat.assign((size_t)L + 1, 0);
@@ -328,6 +489,27 @@ Layout layout_of(const HostSchedule &s) {
 }  // namespace
 
 size_t schedule_device_bytes(const HostSchedule &s) { return layout_of(s).total; }
+
+size_t ops_device_bytes(const HostSchedule &s) {
+    return align256(4 * s.lvl_op.size()) + align256(4 * std::max<size_t>(s.ops.size(), 4));
+}
+
+void ops_pack(const HostSchedule &s, std::vector<unsigned char> &img) {
+    img.assign(ops_device_bytes(s), 0);
+    std::memcpy(img.data(), s.lvl_op.data(), 4 * s.lvl_op.size());
+    if (!s.ops.empty())
+        std::memcpy(img.data() + align256(4 * s.lvl_op.size()), s.ops.data(), 4 * s.ops.size());
+}
+
+DevOps ops_view(const HostSchedule &s, const void *dev_base) {
+    const unsigned char *b = (const unsigned char *)dev_base;
+    DevOps d;
+    d.L = s.Lops;
+    d.nops = (uint32_t)(s.ops.size() / 4);
+    d.lvl = (const uint32_t *)b;
+    d.ops = (const uint4 *)(b + align256(4 * s.lvl_op.size()));
+    return d;
+}
 
 void schedule_pack(const HostSchedule &s, std::vector<unsigned char> &img) {
     Layout o = layout_of(s);

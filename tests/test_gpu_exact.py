@@ -127,6 +127,31 @@ def test_profile_records_each_kernel():
     assert all(ms >= 0 for _, ms in recs)
 
 
+@pytest.mark.parametrize("flags", [0, 1, 2])
+def test_saturation_counts_match_host_model(flags):
+    # the kernel's own traffic counters against the host model of its skip
+    # rule, with skipping on and off, on networks that saturate and ragged n
+    import satmodel
+    ctx = tn.get_context()
+    cases = [(300, 4000, 1500), (200, 3000, 5), (1000, 20000, 6000), (130, 50, 40)]
+    try:
+        for case, (n, m, Tm) in enumerate(cases):
+            s, d, t = T.random_tiny(n, m, Tm, seed=8300 + case)
+            sch = tn.host_schedule(n, s, d, t, flags)
+            want = oracle.reverse_matrix(n, s, d, t, **flag_kw(flags))
+            p = tn.Plan(n, s, d, t, flags)
+            for sat in (True, False):
+                ctx.saturation(sat)
+                for sw in (1, 4, 8, 64):
+                    C = p.execute(slice_words=sw)
+                    assert (host(C) == want).all(), (case, sat, sw)
+                    _, ld, st = satmodel.replay(n, sch, sw, saturation=sat)
+                    assert ctx.last_traffic() == (ld, st), (case, sat, sw)
+            p.close()
+    finally:
+        ctx.saturation(True)
+
+
 @pytest.fixture(scope="module")
 def c2():
     s, d, t = T.make_workload("activity_n100000_m10M")
@@ -170,3 +195,20 @@ def test_full_size_invariants(c2):
     words_ = c2["C"][diag, diag // 64]
     assert bool((((words_ >> (diag % 64)) & 1) == 1).all())
     assert not bool((c2["C"][:, -1] >> (n % 64)).any())
+
+
+def test_full_size_saturation_off_gives_same_matrix(c2):
+    ctx = tn.get_context()
+    C = c2["plan"].execute()
+    ld_on, st_on = ctx.last_traffic()
+    ctx.saturation(False)
+    try:
+        C0 = c2["plan"].execute()
+        ld_off, st_off = ctx.last_traffic()
+    finally:
+        ctx.saturation(True)
+    assert torch.equal(C, c2["C"]) and torch.equal(C0, c2["C"])
+    st = c2["plan"].stats
+    nw = oracle.words(100_000)
+    assert ld_off == 2 * st["ops"] * nw
+    assert ld_on < ld_off and st_on < st_off

@@ -34,6 +34,58 @@ def simulate(n, sch):
     return C
 
 
+NOROW = 0xFFFFFFFF
+SCR = 0x80000000
+
+
+def simulate_ops(n, sch):
+    """Apply the binary-op form level by level: every op of a level reads
+    the rows as they were before the level, then all writes happen."""
+    nw = oracle.words(n)
+    C = oracle.from_dense(np.eye(n, dtype=bool)) if n else np.zeros((0, nw), np.uint64)
+    S = np.zeros((sch["stats"]["scratch_rows"] + 1, nw), dtype=np.uint64)
+    lv, ops = sch["lvl_op"], sch["ops"].astype(np.int64)
+
+    def get(ids):
+        ids = np.asarray(ids, dtype=np.int64)
+        out = np.empty((ids.shape[0], nw), dtype=np.uint64)
+        sc = (ids & SCR) != 0
+        out[~sc] = C[ids[~sc]]
+        out[sc] = S[ids[sc] & 0x7FFFFFFF]
+        return out
+
+    def put(ids, vals):
+        ids = np.asarray(ids, dtype=np.int64)
+        keep = ids != NOROW
+        ids, vals = ids[keep], vals[keep]
+        sc = (ids & SCR) != 0
+        C[ids[~sc]] = vals[~sc]
+        S[ids[sc] & 0x7FFFFFFF] = vals[sc]
+
+    for l in range(sch["stats"]["op_levels"]):
+        O = ops[lv[l]:lv[l + 1]]
+        r = get(O[:, 0]) | get(O[:, 1])
+        put(O[:, 2], r)
+        put(O[:, 3], r)
+    return C
+
+
+def check_ops_independent(sch):
+    lv, ops = sch["lvl_op"], sch["ops"].astype(np.int64)
+    for l in range(sch["stats"]["op_levels"]):
+        O = ops[lv[l]:lv[l + 1]]
+        assert 0 < O.shape[0] <= 1024, l
+        writer = {}
+        for i, (a, b, d1, d2) in enumerate(O):
+            for d in (d1, d2):
+                if d != NOROW:
+                    assert d not in writer, (l, "two writes")
+                    writer[d] = i
+        for i, (a, b, _, _) in enumerate(O):
+            for x in (a, b):
+                assert writer.get(x, i) == i, (l, "read of a row another op writes")
+
+
 def check_disjoint(n, sch):
     lp, lg = sch["lvl_pair"], sch["lvl_gat"]
     pairs, gt, gp, gs = sch["pairs"], sch["gat_tgt"], sch["gat_ptr"], sch["gat_src"]
@@ -60,25 +112,32 @@ def test_schedule_replay_matches_oracle(flags):
         s, d, t = T.random_tiny(n, m, Tm, seed=7000 + case, allow_self=(case % 4 == 0))
         sch = tn.host_schedule(n, s, d, t, flags)
         check_disjoint(n, sch)
+        check_ops_independent(sch)
         got = simulate(n, sch)
         want = oracle.reverse_matrix(n, s, d, t, directed=directed, sequential=seq)
         assert (got == want).all(), case
+        assert (simulate_ops(n, sch) == want).all(), case
 
 
 def test_schedule_replay_uniform_workload():
     s, d, t = T.make_workload("uniform_n1000_m20000")
     sch = tn.host_schedule(1000, s, d, t)
     check_disjoint(1000, sch)
+    check_ops_independent(sch)
     assert sch["stats"]["compound_items"] > 0  # the workload has shared-node ties
-    assert (simulate(1000, sch) == oracle.reverse_matrix(1000, s, d, t)).all()
+    want = oracle.reverse_matrix(1000, s, d, t)
+    assert (simulate(1000, sch) == want).all()
+    assert (simulate_ops(1000, sch) == want).all()
 
 
 def test_schedule_replay_activity_driven_sparse():
     s, d, t = T.activity_driven(3000, 6000, 500, seed=77)
     sch = tn.host_schedule(3000, s, d, t)
     check_disjoint(3000, sch)
-    got = simulate(3000, sch)
-    assert (got == oracle.reverse_matrix(3000, s, d, t)).all()
+    check_ops_independent(sch)
+    want = oracle.reverse_matrix(3000, s, d, t)
+    assert (simulate(3000, sch) == want).all()
+    assert (simulate_ops(3000, sch) == want).all()
 
 
 def test_items_cover_every_event_once_on_distinct_times():
@@ -121,3 +180,42 @@ def test_planner_rejects_bad_input():
     with pytest.raises(tn.TNError) as e:
         tn.host_schedule(4, [0], [1], [0], flags=8)
     assert e.value.code == -1
+
+
+def test_wide_levels_are_split_and_big_compound_items_fold():
+    # one time step with 3000 events on 600 nodes: a single compound item of
+    # many targets, and a first level far wider than the cap
+    g = T.rng(12)
+    n, m = 600, 3000
+    s_ = g.integers(0, n, m).astype(np.uint32)
+    d_ = g.integers(0, n, m).astype(np.uint32)
+    t_ = np.zeros(m, dtype=np.int64)
+    s2, d2, t2 = T.uniform_pairs(n, 5000, 10, seed=13)
+    s_ = np.concatenate([s_, s2])
+    d_ = np.concatenate([d_, d2])
+    t_ = np.concatenate([t_, t2 + 1])
+    sch = tn.host_schedule(n, s_, d_, t_)
+    check_ops_independent(sch)
+    assert sch["stats"]["scratch_rows"] >= 500
+    assert (simulate_ops(n, sch) == oracle.reverse_matrix(n, s_, d_, t_)).all()
+
+
+@pytest.mark.parametrize("sw", [1, 2, 8])
+def test_saturation_skips_keep_the_matrix(sw):
+    # skipping the loads of saturated operands and the stores of full results
+    # into full rows must not change any bit; with skipping off the counts are
+    # the plain ones (2 row slices read per op, one written per destination)
+    import satmodel
+    for case, (n, m, Tm) in enumerate([(70, 900, 300), (300, 4000, 1500), (200, 3000, 5)]):
+        s, d, t = T.random_tiny(n, m, Tm, seed=8100 + case)
+        sch = tn.host_schedule(n, s, d, t)
+        want = oracle.reverse_matrix(n, s, d, t)
+        got, ld, st = satmodel.replay(n, sch, sw)
+        assert (got == want).all(), case
+        got0, ld0, st0 = satmodel.replay(n, sch, sw, saturation=False)
+        assert (got0 == want).all(), case
+        ops = sch["ops"]
+        nw = oracle.words(n)
+        assert ld0 == 2 * ops.shape[0] * nw
+        assert st0 == int((ops[:, 2:] != satmodel.NOROW).sum()) * nw
+        assert ld < ld0 and st < st0, case  # these networks saturate
