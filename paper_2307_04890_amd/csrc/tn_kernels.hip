@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(256) k_identity(uint64_t *__restrict__ C, uint
 //
 // The waves of a workgroup specialise.  Two loader waves stream the ops of
 // level l + 1 into an LDS frame while the compute waves run level l from the
-// other frame, and they already hold the ops of level l + 2 in registers.
+// other frame; the ops of levels l + 2 and l + 3 are already in flight into
+// the loaders' registers.
 // Compute waves issue only row loads and stores.  On gfx9 loads and stores
 // share one in-order completion counter, so this split keeps the loaders'
 // waits from ever covering row stores, and the compute waves never wait for
@@ -65,6 +66,7 @@ __global__ void __launch_bounds__(256) k_identity(uint64_t *__restrict__ C, uint
 // orders the workgroup's row stores and bit updates before the next level.
 constexpr uint32_t kLoaderThreads = 128;
 constexpr uint32_t kLoaderOps = kOpsLevelCap / kLoaderThreads;  // ops per loader lane and level
+constexpr uint32_t kFrames = 2;  // LDS op frames: the level being run and the next
 
 // One op {a, b, d1, d2} as a native 4-lane vector.
 typedef uint32_t op4 __attribute__((ext_vector_type(4)));
@@ -218,15 +220,20 @@ struct HeldOps {
     op4 r[kLoaderOps];
 };
 
-// The ops of one level into registers (clamped, unconditional).
-__device__ __forceinline__ HeldOps fetch_level(const DevOps &s, uint32_t l, uint32_t lane) {
-    const uint32_t p0 = s.lvl[min(l, s.L)];
+// The ops of the level that starts at op p0 into registers (clamped,
+// unconditional).
+__device__ __forceinline__ HeldOps fetch_ops(const DevOps &s, uint32_t p0, uint32_t lane) {
     const uint32_t last = s.nops - 1;
     const op4 *ops = reinterpret_cast<const op4 *>(s.ops);
     HeldOps h;
 #pragma unroll
     for (int k = 0; k < (int)kLoaderOps; ++k) h.r[k] = ops[min(p0 + lane + k * kLoaderThreads, last)];
     return h;
+}
+
+// First op of level l (l clamped to L, whose entry is nops).
+__device__ __forceinline__ uint32_t level_start(const DevOps &s, uint32_t l) {
+    return s.lvl[min(l, s.L)];
 }
 
 __device__ __forceinline__ void put_level(op4 *frame, const HeldOps &h, uint32_t lane) {
@@ -247,8 +254,8 @@ __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
                uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
                unsigned long long *__restrict__ traffic) {
-    __shared__ op4 frame[2][kOpsLevelCap];
-    __shared__ uint32_t fcount[2];
+    __shared__ op4 frame[kFrames][kOpsLevelCap];
+    __shared__ uint32_t fcount[kFrames];
     __shared__ uint32_t worklist[SAT ? kComputeWaves : 1][kWaveShare];
     extern __shared__ uint32_t satbits[];
     const uint32_t L = s.L;
@@ -281,46 +288,72 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     if (SAT)
         for (uint32_t i = tid; i < (sbits + 31) / 32; i += blockDim.x) satbits[i] = 0;
     constexpr bool WIDE = ((1024 - kLoaderThreads) / SW) * UC < kOpsLevelCap;
-    HeldOps held;
+    // Loader and compute waves run separate loops with one barrier per level
+    // each (the branch is uniform per wave, and s_barrier only counts
+    // waves), so the compiler tracks the loaders' loads apart from the
+    // compute waves' row traffic.  Loader waves keep two levels in flight in
+    // registers (hA, hB): a schedule load has two level periods to land
+    // before its frame is written.  Their loop is unrolled by two so that hA
+    // and hB never change registers (a register copy would wait for the
+    // load).
     if (loader) {
-        // level 0 straight into its frame, level 1 into registers
-        put_level(frame[0], fetch_level(s, 0, tid), tid);
-        if (tid == 0) fcount[0] = s.lvl[1] - s.lvl[0];
-        held = fetch_level(s, 1, tid);
+        // Every loader lane reads the level starts too (the same address in
+        // all lanes); a start is loaded one level before the ops it locates,
+        // and ahead of them, so each wait below leaves the newer loads in
+        // flight.
+        uint32_t p1 = level_start(s, 1), p2 = level_start(s, 2);
+        put_level(frame[0], fetch_ops(s, level_start(s, 0), tid), tid);
+        if (tid == 0) fcount[0] = p1 - level_start(s, 0);
+        HeldOps hA = fetch_ops(s, p1, tid);
+        uint32_t p3 = level_start(s, 3);
+        HeldOps hB = fetch_ops(s, p2, tid);
+        __syncthreads();
+        // at level l: h holds the ops of level l + 1, p1..p3 the starts of
+        // levels l + 1 .. l + 3
+        auto feed = [&](uint32_t l, HeldOps &h) {
+            // past the last level frames and counts are never read, and the
+            // level starts clamp to L
+            const uint32_t nf = (l + 1) % kFrames;
+            put_level(frame[nf], h, tid);
+            if (tid == 0) fcount[nf] = p2 - p1;
+            const uint32_t q = p3;
+            p1 = p2;
+            p2 = q;
+            p3 = level_start(s, l + 4);
+            h = fetch_ops(s, q, tid);
+            __syncthreads();
+        };
+        uint32_t l = 0;
+        for (; l + 1 < L; l += 2) {
+            feed(l, hA);
+            feed(l + 1, hB);
+        }
+        if (l < L) feed(l, hA);
+        return;
     }
     __syncthreads();
     for (uint32_t l = 0; l < L; ++l) {
-        const uint32_t cur = l & 1u;
-        if (loader) {
-            // past the last level the frame and count are never read, and
-            // fetch_level clamps its level index to L
-            put_level(frame[cur ^ 1u], held, tid);
-            if (tid == 0) fcount[cur ^ 1u] = s.lvl[min(l + 2, L)] - s.lvl[min(l + 1, L)];
-            held = fetch_level(s, l + 2, tid);
+        const uint32_t cf = l % kFrames;
+        const uint32_t cnt = fcount[cf];
+        if (SAT) {
+            const uint32_t cw = ctid >> 6;
+            const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
+            const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
+            uint32_t *work = worklist[SAT ? cw : 0];
+            const uint32_t nwork = classify(A, frame[cf], lo, hi, work);
+            run_work<SW, UW>(A, frame[cf], work, nwork);
         } else {
-            const uint32_t cnt = fcount[cur];
-            if (SAT) {
-                const uint32_t cw = ctid >> 6;
-                const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
-                const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
-                uint32_t *work = worklist[SAT ? cw : 0];
-                const uint32_t nwork = classify(A, frame[cur], lo, hi, work);
-                run_work<SW, UW>(A, frame[cur], work, nwork);
-            } else {
-                apply_frame<UC>(A, frame[cur], 0, cnt);
-                if (WIDE) {
-                    const uint32_t chunk = A.ngrp * UC;
-                    for (uint32_t base = chunk; base < cnt; base += chunk)
-                        apply_frame<UC>(A, frame[cur], base, cnt);
-                }
+            apply_frame<UC>(A, frame[cf], 0, cnt);
+            if (WIDE) {
+                const uint32_t chunk = A.ngrp * UC;
+                for (uint32_t base = chunk; base < cnt; base += chunk)
+                    apply_frame<UC>(A, frame[cf], base, cnt);
             }
         }
         __syncthreads();
     }
-    if (!loader) {
-        count_add(traffic, A.loaded);
-        count_add(traffic + 1, A.stored);
-    }
+    count_add(traffic, A.loaded);
+    count_add(traffic + 1, A.stored);
 }
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
@@ -449,10 +482,10 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
     if (s.L == 0) return hipSuccess;
     switch (slice_words) {
         // UC: ops per lane group and level, so that (896 / SW) * UC >= 1024
-        case 1: return rowor_variant<1, 2, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 2: return rowor_variant<2, 3, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 4: return rowor_variant<4, 5, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 8: return rowor_variant<8, 10, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 1: return rowor_variant<1, 2, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 2: return rowor_variant<2, 3, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 4: return rowor_variant<4, 5, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 8: return rowor_variant<8, 10, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
         case 16: return rowor_variant<16, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
         case 32: return rowor_variant<32, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
         case 64: return rowor_variant<64, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
