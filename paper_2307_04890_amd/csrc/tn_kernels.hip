@@ -84,6 +84,7 @@ struct OpArgs {
     uint32_t sbits;     // bits in the bitmap
     uint64_t fullw;     // this lane's word when its row slice is full (0 past the last word)
     uint64_t gmask;     // ballot bits of this lane's group
+    int32_t *nfull;           // this level's change of the full real-row count
     uint32_t loaded, stored;  // row words this lane moved
     bool lead;                // first lane of its group
 };
@@ -139,53 +140,51 @@ __device__ __forceinline__ void apply_frame(OpArgs &A, const op4 *frame, uint32_
 // Saturation path, per compute wave: classify a contiguous share of the
 // level's ops by their saturation bits (LDS only), keep those that still
 // need a row load or store in a per-wave list (ballot compaction), then run
-// only those, U per lane group at a time, loads before stores.
+// only those.
 constexpr uint32_t kComputeWaves = (1024 - kLoaderThreads) / 64;
 constexpr uint32_t kWaveShare = (kOpsLevelCap + kComputeWaves - 1) / kComputeWaves;
 constexpr uint32_t kWorkSkip = 1u << 16, kWorkF1 = 1u << 17, kWorkF2 = 1u << 18;
 
+// Flips the bit of a row whose state changed; a real row also moves this
+// level's count of full real rows.
 __device__ __forceinline__ void sat_set(const OpArgs &A, uint32_t id, bool full) {
     const uint32_t i = sat_index(A, id);
     if (full) atomicOr(&A.sat[i >> 5], 1u << (i & 31u));
     else atomicAnd(&A.sat[i >> 5], ~(1u << (i & 31u)));
+    if (!(id & kScratchBit)) atomicAdd(A.nfull, full ? 1 : -1);
 }
 
-template <int SW, int U>
+// The wave's nwork items (wave-uniform), one per lane group at a time.
+// Batching several items' loads per lane before their stores measured
+// slower: in the phase where most ops still need rows, the time goes to
+// random row-segment traffic, not to serialized round trips.
+template <int SW>
 __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint32_t *work,
                                          uint32_t nwork) {
     constexpr uint32_t G = 64 / SW;  // lane groups per wave
     const uint32_t g = (threadIdx.x & 63u) / SW;
-    for (uint32_t base = 0; base < nwork; base += G * U) {
-        uint32_t e[U];
-        op4 o[U];
-        uint64_t x[U], y[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const uint32_t j = base + g + k * G;
-            e[k] = work[min(j, kWaveShare - 1)];
-            o[k] = frame[e[k] & 1023u];
-            const bool v = j < nwork, ld = v && !(e[k] & kWorkSkip);
-            x[k] = *op_addr(A, o[k].x, ld);
-            y[k] = *op_addr(A, o[k].y, ld);
-            A.loaded += (ld && A.wok) ? 2u : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const uint32_t j = base + g + k * G;
-            const bool v = j < nwork, skip = e[k] & kWorkSkip;
-            const uint64_t r = skip ? A.fullw : (x[k] | y[k]);
-            const uint64_t ball = __ballot(r == A.fullw || !A.wok);
-            const bool full = (ball & A.gmask) == A.gmask;
-            const bool f1 = e[k] & kWorkF1, f2 = e[k] & kWorkF2;
-            const bool s1 = v && o[k].z != kNoRow && !(full && f1);
-            const bool s2 = v && o[k].w != kNoRow && !(full && f2);
-            *op_addr(A, o[k].z, s1) = r;
-            *op_addr(A, o[k].w, s2) = r;
-            A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
-            if (v && A.lead) {
-                if (o[k].z != kNoRow && f1 != full) sat_set(A, o[k].z, full);
-                if (o[k].w != kNoRow && f2 != full) sat_set(A, o[k].w, full);
-            }
+    for (uint32_t j0 = 0; j0 < nwork; j0 += G) {
+        const uint32_t j = j0 + g;
+        const uint32_t e = work[min(j, kWaveShare - 1)];
+        const op4 o = frame[e & (kOpsLevelCap - 1)];
+        const bool v = j < nwork, skip = e & kWorkSkip, ld = v && !skip;
+        const uint64_t x = *op_addr(A, o.x, ld);
+        const uint64_t y = *op_addr(A, o.y, ld);
+        A.loaded += (ld && A.wok) ? 2u : 0u;
+        const uint64_t r = skip ? A.fullw : (x | y);
+        // the group's SW lanes agree on whether the whole row slice is full
+        const uint64_t ball = __ballot(r == A.fullw || !A.wok);
+        const bool full = (ball & A.gmask) == A.gmask;
+        const bool f1 = e & kWorkF1, f2 = e & kWorkF2;
+        const bool s1 = v && o.z != kNoRow && !(full && f1);
+        const bool s2 = v && o.w != kNoRow && !(full && f2);
+        *op_addr(A, o.z, s1) = r;
+        *op_addr(A, o.w, s2) = r;
+        A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+        // one lane per group refreshes the destinations' bits
+        if (v && A.lead) {
+            if (o.z != kNoRow && f1 != full) sat_set(A, o.z, full);
+            if (o.w != kNoRow && f2 != full) sat_set(A, o.w, full);
         }
     }
 }
@@ -249,7 +248,7 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
     if ((threadIdx.x & 63u) == 0 && v) atomicAdd(ctr, v);
 }
 
-template <int SW, int UC, int UW, bool SAT>
+template <int SW, int UC, bool SAT>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
                uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
@@ -257,6 +256,10 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     __shared__ op4 frame[kFrames][kOpsLevelCap];
     __shared__ uint32_t fcount[kFrames];
     __shared__ uint32_t worklist[SAT ? kComputeWaves : 1][kWaveShare];
+    // change of the number of full real rows in levels l, l+1, l+2 (mod 3):
+    // level l adds into slot l % 3, every wave reads it after the barrier
+    // that ends level l, and slot (l + 1) % 3 is cleared during level l
+    __shared__ int32_t fdelta[3];
     extern __shared__ uint32_t satbits[];
     const uint32_t L = s.L;
     if (L == 0 || s.nops == 0) return;
@@ -285,8 +288,24 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
         A.fullw = !A.wok ? 0ull : (A.w + 1 < nwords ? ~0ull : last);
         A.gmask = (SW == 64 ? ~0ull : ((1ull << SW) - 1ull)) << ((tid & 63u) / SW * SW);
     }
-    if (SAT)
-        for (uint32_t i = tid; i < (sbits + 31) / 32; i += blockDim.x) satbits[i] = 0;
+    // Once every real row is full in this slice, all later ops are full
+    // results into full rows: the workgroup stops.  A slice with a single
+    // valid column starts with that column's identity row full.
+    const uint32_t c0 = slice * SW * 64u;
+    const bool single = c0 + 1 == n;
+    int32_t nfull = single ? 1 : 0;
+    if (SAT) {
+        for (uint32_t i = tid; i < (sbits + 31) / 32; i += blockDim.x)
+            satbits[i] = (single && i == (c0 >> 5)) ? (1u << (c0 & 31u)) : 0u;
+        if (tid < 3) fdelta[tid] = 0;
+    }
+    A.nfull = fdelta;
+    // all waves add the same deltas at the same barriers, so they agree
+    auto done = [&](uint32_t l) -> bool {
+        if (!SAT) return false;
+        if (l > 0) nfull += fdelta[(l - 1) % 3];
+        return nfull == (int32_t)n;
+    };
     constexpr bool WIDE = ((1024 - kLoaderThreads) / SW) * UC < kOpsLevelCap;
     // Loader and compute waves run separate loops with one barrier per level
     // each (the branch is uniform per wave, and s_barrier only counts
@@ -323,25 +342,27 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
             h = fetch_ops(s, q, tid);
             __syncthreads();
         };
-        uint32_t l = 0;
-        for (; l + 1 < L; l += 2) {
+        for (uint32_t l = 0; l < L; l += 2) {
+            if (done(l)) break;
             feed(l, hA);
+            if (l + 1 >= L || done(l + 1)) break;
             feed(l + 1, hB);
         }
-        if (l < L) feed(l, hA);
         return;
     }
     __syncthreads();
     for (uint32_t l = 0; l < L; ++l) {
+        if (done(l)) break;
         const uint32_t cf = l % kFrames;
         const uint32_t cnt = fcount[cf];
         if (SAT) {
+            A.nfull = &fdelta[l % 3];
+            if (ctid == 0) fdelta[(l + 1) % 3] = 0;
             const uint32_t cw = ctid >> 6;
             const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
             const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
             uint32_t *work = worklist[SAT ? cw : 0];
-            const uint32_t nwork = classify(A, frame[cf], lo, hi, work);
-            run_work<SW, UW>(A, frame[cf], work, nwork);
+            run_work<SW>(A, frame[cf], work, classify(A, frame[cf], lo, hi, work));
         } else {
             apply_frame<UC>(A, frame[cf], 0, cnt);
             if (WIDE) {
@@ -427,7 +448,7 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
     }
 }
 
-template <int SW, int UC, int UW>
+template <int SW, int UC>
 hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, uint64_t *scratch,
                          uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
                          hipStream_t st) {
@@ -437,14 +458,14 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
     const uint64_t sbits = (uint64_t)sbase + scratch_rows + 1;
     const size_t lds = (size_t)((sbits + 31) / 32) * 4;
     if (saturation && lds <= kRoworSatLds) {
-        auto k = k_rowor_global<SW, UC, UW, true>;
+        auto k = k_rowor_global<SW, UC, true>;
         hipError_t e = hipFuncSetAttribute((const void *)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, n, nwords, s, scratch,
                            sbase, (uint32_t)sbits, traffic);
     } else {
-        hipLaunchKernelGGL((k_rowor_global<SW, UC, UW, false>), dim3(slices), dim3(1024), 0, st, C,
+        hipLaunchKernelGGL((k_rowor_global<SW, UC, false>), dim3(slices), dim3(1024), 0, st, C,
                            ld, n, nwords, s, scratch, 0u, 1u, traffic);
     }
     return hipGetLastError();
@@ -482,13 +503,13 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
     if (s.L == 0) return hipSuccess;
     switch (slice_words) {
         // UC: ops per lane group and level, so that (896 / SW) * UC >= 1024
-        case 1: return rowor_variant<1, 2, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 2: return rowor_variant<2, 3, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 4: return rowor_variant<4, 5, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 8: return rowor_variant<8, 10, 1>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 16: return rowor_variant<16, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 32: return rowor_variant<32, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 64: return rowor_variant<64, 8, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 1: return rowor_variant<1, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 2: return rowor_variant<2, 3>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 4: return rowor_variant<4, 5>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 8: return rowor_variant<8, 10>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
         default: return hipErrorInvalidValue;
     }
 }

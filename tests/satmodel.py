@@ -1,6 +1,7 @@
 """Host model of the row-OR kernel's saturation rule (no device): replays the
 binary-op schedule slice by slice, keeping one "row slice is all ones" flag per
-row and slice, and counts the row words the kernel must load and store.  The
+row and slice, and counts the row words the kernel must load and store.  A
+slice stops at the first level that starts with every real row full.  The
 matrix it ends with must be the plain recurrence's; the counts are what the
 kernel's own counters must report for the same slice width."""
 import numpy as np
@@ -24,6 +25,9 @@ def replay(n, sch, slice_words, saturation=True):
         full[nw - 1] = np.uint64((1 << (n % 64)) - 1)
     valid = np.minimum(slice_words, nw - np.arange(ns) * slice_words)  # words per slice
     flag = np.zeros((n + nscr, ns), dtype=bool)
+    if saturation and (n - 1) % (64 * slice_words) == 0:
+        flag[n - 1, (n - 1) // (64 * slice_words)] = True  # a one-column slice
+    alive = np.ones(ns, dtype=bool)
     lv, ops = sch["lvl_op"], sch["ops"].astype(np.int64)
     fullS = full.reshape(ns, slice_words)
     loads = stores = 0
@@ -35,10 +39,13 @@ def replay(n, sch, slice_words, saturation=True):
         return x
 
     for l in range(sch["stats"]["op_levels"]):
+        if saturation:
+            alive &= ~flag[:n].all(axis=0)
+        live = valid * alive
         O = ops[lv[l]:lv[l + 1]]
         a, b = idx(O[:, 0]), idx(O[:, 1])
         skip = (flag[a] | flag[b]) if saturation else np.zeros((O.shape[0], ns), bool)
-        loads += int(2 * (valid[None, :] * ~skip).sum())
+        loads += int(2 * (live[None, :] * ~skip).sum())
         r = (R[a] | R[b]).reshape(-1, ns, slice_words)
         r = np.where(skip[:, :, None], fullS[None], r)
         rf = (r == fullS[None]).all(axis=2)
@@ -47,9 +54,10 @@ def replay(n, sch, slice_words, saturation=True):
             keep = O[:, col] != NOROW
             d = idx(O[keep, col])
             st = ~(rf[keep] & flag[d]) if saturation else np.ones((d.shape[0], ns), bool)
-            stores += int((valid[None, :] * st).sum())
+            stores += int((live[None, :] * st).sum())
             writes.append((d, r[keep], rf[keep]))
+        cols = np.repeat(alive, slice_words)
         for d, rr, ff in writes:
-            R[d] = rr.reshape(-1, pad)
-            flag[d] = ff
+            R[np.ix_(d, cols)] = rr.reshape(-1, pad)[:, cols]
+            flag[np.ix_(d, alive)] = ff[:, alive]
     return R[:n, :nw], loads, stores

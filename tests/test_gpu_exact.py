@@ -133,7 +133,8 @@ def test_saturation_counts_match_host_model(flags):
     # rule, with skipping on and off, on networks that saturate and ragged n
     import satmodel
     ctx = tn.get_context()
-    cases = [(300, 4000, 1500), (200, 3000, 5), (1000, 20000, 6000), (130, 50, 40)]
+    cases = [(300, 4000, 1500), (200, 3000, 5), (1000, 20000, 6000), (130, 50, 40),
+             (129, 6000, 3000), (513, 9000, 4000)]
     try:
         for case, (n, m, Tm) in enumerate(cases):
             s, d, t = T.random_tiny(n, m, Tm, seed=8300 + case)

@@ -219,3 +219,19 @@ def test_saturation_skips_keep_the_matrix(sw):
         assert ld0 == 2 * ops.shape[0] * nw
         assert st0 == int((ops[:, 2:] != satmodel.NOROW).sum()) * nw
         assert ld < ld0 and st < st0, case  # these networks saturate
+
+
+def test_saturation_model_stops_full_slices():
+    # a slice whose rows are all full stops: no traffic after that level,
+    # same matrix; n = 64 k + 1 gives a last slice of one column whose only
+    # row starts full
+    import satmodel
+    n = 129
+    s, d, t = T.random_tiny(n, 6000, 3000, seed=8200)
+    sch = tn.host_schedule(n, s, d, t)
+    want = oracle.reverse_matrix(n, s, d, t)
+    assert oracle.sizes(want, n)[0].min() == n  # every row ends full
+    got, ld, st = satmodel.replay(n, sch, 1)
+    assert (got == want).all()
+    _, ld0, st0 = satmodel.replay(n, sch, 1, saturation=False)
+    assert ld < ld0 // 4
