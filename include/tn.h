@@ -188,10 +188,12 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C,
 
 /* Saturated rows (Sec. 3.4: rows of the reverse-time matrix only gain bits,
  * and an OR with a row that already holds every column of a slice gives that
- * full slice).  Enabled by default: tn_plan_execute then skips the row loads
- * such an operand makes redundant and the stores of full results into rows
- * already full; the matrix it writes is identical either way.  enable = 0
- * makes every op load and store its rows.  Errors: TN_E_ARG (ctx NULL). */
+ * full slice).  Enabled by default: tn_plan_execute and tn_batch_execute then
+ * skip the row loads such an operand makes redundant and the stores of full
+ * results into rows already full, and a workgroup stops once every row of its
+ * column slice is full; the matrices they write are identical either way.
+ * enable = 0 makes every op load and store its rows (a batch re-plans its
+ * launch shape at its next execution).  Errors: TN_E_ARG (ctx NULL). */
 tn_status tn_set_saturation(tn_ctx *ctx, int enable);
 
 /* Row traffic of the last tn_plan_execute on this context: words[0] = uint64

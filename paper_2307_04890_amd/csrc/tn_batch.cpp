@@ -33,6 +33,7 @@ struct tn_batch {
     uint32_t *d_counters = nullptr;
     uint64_t *d_gscratch = nullptr;
     std::vector<tn::NetDesc> h_nets;
+    bool sat = true;  // saturation setting of the current shape
     std::vector<uint2> h_tiles;
     uint32_t h_qptr[9] = {0};
     int64_t lds_tiles = 0;
@@ -64,10 +65,12 @@ uint32_t ilog2(uint32_t x) {
     return l;
 }
 
-// Widest power-of-two slice (<= 64 words) whose rows plus compound scratch fit
-// in LDS; 0 if none does.
-uint32_t lds_fit_words(uint32_t n, int64_t max_gat, uint32_t nwords) {
-    const size_t budget = kLdsLimit - batch_static_lds() - 256;
+size_t lds_budget() { return kLdsLimit - batch_static_lds() - 256; }
+
+// Widest power-of-two slice (<= 64 words) whose rows plus compound scratch
+// (plus the saturation bitmap when `sat`) fit in LDS; 0 if none does.
+uint32_t lds_fit_words(uint32_t n, int64_t max_gat, uint32_t nwords, bool sat) {
+    const size_t budget = lds_budget() - (sat ? sat_bitmap_bytes(n) : 0);
     uint32_t w = std::min<uint32_t>(64, pow2_ceil(nwords));
     for (; w >= 1; w >>= 1)
         if ((size_t)(n + (size_t)max_gat) * w * 8 <= budget) return w;
@@ -91,9 +94,11 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
     free_meta(b);
     b->policy = policy;
     b->threads = threads;
+    b->sat = ctx->saturation;
     const int32_t B = b->B;
     b->lw.assign(B, 0);
     b->mode.assign(B, kTileLds);
+    std::vector<uint32_t> sat_on(B, 0), sat_off(B, 0);
     size_t dyn = 0, gscr_words = 0;
     std::vector<size_t> gscr_off(B, 0);
     struct T {
@@ -104,7 +109,10 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
     b->lds_tiles = 0;
     for (int32_t i = 0; i < B; ++i) {
         const uint32_t nw = b->nwords[i];
-        uint32_t w = lds_fit_words(b->n[i], b->max_gat[i], nw);
+        const size_t bm = sat_bitmap_bytes(b->n[i]);
+        // the bitmap must fit beside the LDS tile, or alone for a global tile
+        sat_on[i] = b->sat && bm <= lds_budget();
+        uint32_t w = lds_fit_words(b->n[i], b->max_gat[i], nw, sat_on[i]);
         if (w == 0) {
             b->mode[i] = kTileGlobal;
             w = std::min<uint32_t>(8, pow2_ceil(nw));
@@ -115,8 +123,9 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
         }
         w = std::max<uint32_t>(1, w >> policy);
         b->lw[i] = ilog2(w);
-        if (b->mode[i] == kTileLds)
-            dyn = std::max(dyn, (size_t)(b->n[i] + (size_t)b->max_gat[i]) * w * 8);
+        const size_t tile = (b->mode[i] == kTileLds) ? (size_t)(b->n[i] + (size_t)b->max_gat[i]) * w * 8 : 0;
+        sat_off[i] = (uint32_t)(tile / 8);
+        dyn = std::max(dyn, tile + (sat_on[i] ? bm : 0));
         const uint32_t slices = (nw + w - 1) / w;
         const tn_plan_stats &st = b->stats[i];
         // modeled tile time: a per-level barrier cost plus per-word row work
@@ -180,6 +189,8 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
         nd.lw = b->lw[i];
         nd.mode = b->mode[i];
         nd.gscratch = b->d_gscratch + gscr_off[i];
+        nd.sat = sat_on[i];
+        nd.sat_off = sat_off[i];
     }
     e = hipMemcpy(b->d_tiles, b->h_tiles.data(), sizeof(uint2) * ntiles, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -377,6 +388,10 @@ tn_status batch_execute(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int6
     tn_status st;
     if (!b->tuned) {
         st = autotune(ctx, b, C, ld);
+        if (st != TN_OK) return st;
+    } else if (b->sat != ctx->saturation) {
+        // the context's saturation setting changed: rebuild the shape
+        st = apply_shape(ctx, b, b->policy, b->threads);
         if (st != TN_OK) return st;
     }
     st = bind_outputs(ctx, b, C, ld);

@@ -15,9 +15,14 @@ struct NetDesc {
     uint32_t nwords;      // ceil(n / 64)
     uint32_t lw;          // log2 of the slice width in words
     uint32_t mode;        // kTileLds or kTileGlobal
-    uint32_t pad_;
+    uint32_t sat;         // 1: track saturated rows in an LDS bitmap and stop early
     uint64_t *gscratch;   // global-mode compound scratch: max_gat x nwords words
+    uint32_t sat_off;     // bitmap offset in the dynamic LDS, in uint64 words
+    uint32_t pad_;
 };
+
+// Bytes of the saturation bitmap of an n-node network (one bit per row).
+inline size_t sat_bitmap_bytes(uint32_t n) { return (((size_t)n + 63) / 64) * 8; }
 
 // Plans B networks on host threads (node ids through maps[b] when given).
 tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t *m,

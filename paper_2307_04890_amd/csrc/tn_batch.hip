@@ -12,6 +12,14 @@
 // level) fits in LDS is built entirely in LDS: identity, every level, then a
 // single write-back of the slice.  Larger tiles run the same level loop on
 // the matrix in global memory.
+//
+// Saturation (Sec. 3.4: rows only gain bits in reverse time).  A tile keeps
+// one LDS bit per row meaning "this row is all ones in the slice": an item
+// with a saturated operand reads nothing and gives a full result, a full
+// result is not stored into a row already marked full, and every write
+// refreshes the bit of the row it writes, so a set bit is always true.
+// Once every row of the slice is full, nothing can change any more and the
+// tile stops.
 #include <hip/hip_runtime.h>
 
 #include "tn_batch.h"
@@ -39,15 +47,36 @@ struct GlobalRows {
     }
 };
 
+// Saturation state of one tile.
+struct Sat {
+    uint32_t *bits;  // LDS bitmap, bit r = row r is full in the slice
+    int32_t *delta;  // per-level change of the full-row count, 3 slots
+    uint64_t fullw;  // this lane's word of a full row slice
+    uint64_t gmask;  // ballot bits of this lane's group
+    bool lead;       // first lane of its group
+    __device__ __forceinline__ bool get(uint32_t r) const { return (bits[r >> 5] >> (r & 31u)) & 1u; }
+    __device__ __forceinline__ void flip(uint32_t r, bool full, uint32_t l) const {
+        if (full) atomicOr(&bits[r >> 5], 1u << (r & 31u));
+        else atomicAnd(&bits[r >> 5], ~(1u << (r & 31u)));
+        atomicAdd(&delta[l % 3], full ? 1 : -1);
+    }
+    // whether every lane of this lane's group has `mine` (all lanes of the
+    // group are active together)
+    __device__ __forceinline__ bool group_all(bool mine) const {
+        return (__ballot(mine) & gmask) == gmask;
+    }
+};
+
 // Runs every level of one network on one slice.  Rows and scratch are LDS or
 // global views; `ok` masks lanes whose word is past the last word column
 // (only needed for global views).  Lane groups of 2^lw lanes take the items
 // of a level in turn; the next level's first items are prefetched into
 // registers; level boundaries come from an LDS window refilled every kWin
 // levels.
-template <int U, class Rows>
+template <int U, bool SAT, class Rows>
 __device__ void run_levels(const DevSchedule &s, const Rows rows, const Rows scr, uint32_t lw,
-                           bool ok, uint32_t *winp, uint32_t *wing) {
+                           bool ok, uint32_t *winp, uint32_t *wing, const Sat &sat,
+                           int32_t nfull) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & ((1u << lw) - 1u);
     const uint32_t grp = tid >> lw;
@@ -70,6 +99,12 @@ __device__ void run_levels(const DevSchedule &s, const Rows rows, const Rows scr
         cur[k] = idx < p1 ? s.pairs[idx] : make_uint2(0xffffffffu, 0u);
     }
     for (uint32_t l = 0; l < L; ++l) {
+        if (SAT) {
+            // every thread adds the same settled deltas: a uniform decision
+            if (l > 0) nfull += sat.delta[(l - 1) % 3];
+            if (nfull == (int32_t)s.n) break;
+            if (tid == 0) sat.delta[(l + 1) % 3] = 0;
+        }
         if (l % kWin == 0 && l > 0) {
             const uint32_t nb = l / kWin + 1;
             for (uint32_t i = tid; i < kWin; i += blockDim.x) {
@@ -99,33 +134,64 @@ __device__ void run_levels(const DevSchedule &s, const Rows rows, const Rows scr
                 }
             }
             uint64_t a[U], b[U];
+            bool fx[U], fy[U];
 #pragma unroll
-            for (int k = 0; k < U; ++k)
-                if (it[k].x != 0xffffffffu && ok) {
-                    a[k] = rows.at(it[k].x, lane);
-                    b[k] = rows.at(it[k].y & kNodeMask, lane);
+            for (int k = 0; k < U; ++k) {
+                const bool v = it[k].x != 0xffffffffu;
+                const uint32_t x = it[k].x, y = it[k].y & kNodeMask;
+                fx[k] = SAT && v && sat.get(x);
+                fy[k] = SAT && v && sat.get(y);
+                a[k] = b[k] = 0;
+                if (v && ok && !fx[k] && !fy[k]) {
+                    a[k] = rows.at(x, lane);
+                    b[k] = rows.at(y, lane);
                 }
+            }
 #pragma unroll
-            for (int k = 0; k < U; ++k)
-                if (it[k].x != 0xffffffffu && ok) {
-                    const uint64_t r = a[k] | b[k];
-                    rows.at(it[k].x, lane) = r;
-                    if (!(it[k].y & kDirBit)) rows.at(it[k].y & kNodeMask, lane) = r;
+            for (int k = 0; k < U; ++k) {
+                const bool v = it[k].x != 0xffffffffu, dir = it[k].y & kDirBit;
+                const uint32_t x = it[k].x, y = it[k].y & kNodeMask;
+                const uint64_t r = (fx[k] || fy[k]) ? sat.fullw : (a[k] | b[k]);
+                bool full = false;
+                if (SAT) full = sat.group_all(!v || !ok || r == sat.fullw);
+                if (v && ok) {
+                    if (!(full && fx[k])) rows.at(x, lane) = r;
+                    if (!dir && !(full && fy[k])) rows.at(y, lane) = r;
                 }
+                if (SAT && v && sat.lead) {
+                    if (full != fx[k]) sat.flip(x, full, l);
+                    if (!dir && full != fy[k]) sat.flip(y, full, l);
+                }
+            }
         }
         if (g1 > g0) {
             // compound items: read every old row, then write
             for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp) {
                 uint64_t acc = 0;
                 const uint32_t s0 = s.gat_ptr[gi], s1 = s.gat_ptr[gi + 1];
+                bool any_full = false;
+                if (SAT)
+                    for (uint32_t q = s0; q < s1 && !any_full; ++q) any_full = sat.get(s.gat_src[q]);
                 if (ok) {
-                    for (uint32_t q = s0; q < s1; ++q) acc |= rows.at(s.gat_src[q], lane);
+                    if (any_full) acc = sat.fullw;
+                    else
+                        for (uint32_t q = s0; q < s1; ++q) acc |= rows.at(s.gat_src[q], lane);
                     scr.at(gi - g0, lane) = acc;
                 }
             }
             __syncthreads();
-            for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp)
-                if (ok) rows.at(s.gat_tgt[gi], lane) = scr.at(gi - g0, lane);
+            for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp) {
+                const uint32_t tg = s.gat_tgt[gi];
+                const uint64_t val = ok ? scr.at(gi - g0, lane) : 0ull;
+                if (!SAT) {
+                    if (ok) rows.at(tg, lane) = val;
+                    continue;
+                }
+                const bool ft = sat.get(tg);
+                const bool full = sat.group_all(!ok || val == sat.fullw);
+                if (ok && !(full && ft)) rows.at(tg, lane) = val;
+                if (sat.lead && full != ft) sat.flip(tg, full, l);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -136,15 +202,37 @@ __device__ void run_levels(const DevSchedule &s, const Rows rows, const Rows scr
     }
 }
 
-template <int U>
+template <int U, bool SAT>
 __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint32_t *winp,
-                         uint32_t *wing) {
+                         uint32_t *wing, int32_t *fdelta) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lw = nd.lw;
     const uint32_t w = 1u << lw;
     const uint32_t n = nd.s.n;
     const uint32_t word0 = slice << lw;
     const size_t ld = (size_t)nd.ld;
+    const uint32_t lane = tid & (w - 1u);
+    // saturation state; the bitmap is cleared before the first barrier
+    Sat sat;
+    int32_t nfull = 0;
+    if (SAT) {
+        sat.bits = (uint32_t *)(smem + nd.sat_off);
+        sat.delta = fdelta;
+        const uint32_t word = word0 + lane;
+        const uint32_t tail = n & 63u;
+        sat.fullw = word + 1 < nd.nwords ? ~0ull
+                                         : (word + 1 == nd.nwords ? (tail ? (1ull << tail) - 1ull : ~0ull)
+                                                                  : 0ull);
+        sat.gmask = (w == 64 ? ~0ull : ((1ull << w) - 1ull)) << ((tid & 63u) / w * w);
+        sat.lead = lane == 0;
+        // a slice with a single valid column starts with that row full
+        const uint32_t c0 = word0 * 64u;
+        const bool single = c0 + 1 == n;
+        nfull = single ? 1 : 0;
+        for (uint32_t i = tid; i < (n + 31) / 32; i += blockDim.x)
+            sat.bits[i] = (single && i == (c0 >> 5)) ? (1u << (c0 & 31u)) : 0u;
+        if (tid < 3) fdelta[tid] = 0;
+    }
     if (nd.mode == kTileLds) {
         // identity on the slice, in LDS
         const uint32_t total = n << lw;
@@ -155,14 +243,13 @@ __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint
         __syncthreads();
         LdsRows rows{smem, lw};
         LdsRows scr{smem + total, lw};
-        run_levels<U>(nd.s, rows, scr, lw, true, winp, wing);
+        run_levels<U, SAT>(nd.s, rows, scr, lw, true, winp, wing, sat, nfull);
         // write the slice back (the level loop ended with a barrier)
         for (uint32_t i = tid; i < total; i += blockDim.x) {
             const uint32_t r = i >> lw, word = word0 + (i & (w - 1u));
             if (word < nd.nwords) nd.C[(size_t)r * ld + word] = smem[i];
         }
     } else {
-        const uint32_t lane = tid & (w - 1u);
         const bool ok = word0 + lane < nd.nwords;
         for (uint32_t r = tid >> lw; r < n; r += blockDim.x >> lw)
             if (ok) {
@@ -172,7 +259,7 @@ __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint
         __syncthreads();
         GlobalRows rows{nd.C, ld, word0};
         GlobalRows scr{nd.gscratch, (size_t)nd.nwords, word0};
-        run_levels<U>(nd.s, rows, scr, lw, ok, winp, wing);
+        run_levels<U, SAT>(nd.s, rows, scr, lw, ok, winp, wing, sat, nfull);
     }
     // padding words past the last word column are zero
     if (word0 + w >= nd.nwords && (size_t)nd.nwords < ld) {
@@ -190,6 +277,7 @@ k_batch_persistent(const NetDesc *__restrict__ nets, const uint2 *__restrict__ t
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t winp[2 * kWin], wing[2 * kWin];
     __shared__ uint32_t sh_tile;
+    __shared__ int32_t fdelta[3];
     const uint32_t x = blockIdx.x & 7u;
     for (uint32_t k = 0; k < 8; ++k) {
         const uint32_t q = (x + k) & 7u;
@@ -201,7 +289,9 @@ k_batch_persistent(const NetDesc *__restrict__ nets, const uint2 *__restrict__ t
             __syncthreads();
             if (t >= qn) break;
             const uint2 tile = tiles[q0 + t];
-            run_tile<U>(nets[tile.x], tile.y, smem, winp, wing);
+            const NetDesc &nd = nets[tile.x];
+            if (nd.sat) run_tile<U, true>(nd, tile.y, smem, winp, wing, fdelta);
+            else run_tile<U, false>(nd, tile.y, smem, winp, wing, fdelta);
         }
     }
 }
@@ -212,7 +302,7 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n) {
 
 }  // namespace
 
-size_t batch_static_lds() { return sizeof(uint32_t) * (4 * kWin + 1); }
+size_t batch_static_lds() { return sizeof(uint32_t) * (4 * kWin + 1) + 3 * sizeof(int32_t); }
 
 hipError_t batch_occupancy(int threads, size_t dyn_lds, int *blocks_per_cu) {
     hipError_t e = hipFuncSetAttribute((const void *)k_batch_persistent<4>,

@@ -98,3 +98,28 @@ def test_batch_errors():
     with pytest.raises(tn.TNError) as e:
         tn.Batch([(10, [0, 1], [1, 2], [3, 2])])
     assert e.value.code == -3
+
+
+def test_saturating_networks_with_and_without_skipping():
+    # dense networks whose rows all fill up (tiles stop early), an n = 64 k + 1
+    # network whose last slice has one column, and a global-memory tile
+    nets = []
+    for i, (n, m) in enumerate([(129, 20000), (700, 60000), (2049, 150000), (30000, 600000)]):
+        s, d, t = T.activity_driven(n, m, max(1, m // 10), seed=300 + i)
+        nets.append((n, s, d, t))
+    want = [oracle.reverse_matrix(n, s, d, t) for n, s, d, t in nets]
+    assert all(oracle.sizes(w, n)[0].min() == n for w, (n, _, _, _) in zip(want[:3], nets))
+    ctx = tn.get_context()
+    b = tn.Batch(nets)
+    try:
+        for sat in (True, False, True):
+            ctx.saturation(sat)
+            Cs = b.execute()
+            for (n, _, _, _), C, w in zip(nets, Cs, want):
+                assert (host(C)[:, :oracle.words(n)] == w).all(), (sat, n)
+        for flags in (tn.DIRECTED, tn.DIRECTED | tn.TIES_SEQUENTIAL):
+            Cs = tn.build_component_matrix_batched(nets[:3], flags=flags)
+            check(nets[:3], Cs, directed=True, sequential=bool(flags & 2))
+    finally:
+        ctx.saturation(True)
+        b.close()
