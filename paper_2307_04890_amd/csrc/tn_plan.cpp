@@ -35,7 +35,11 @@ struct Planner {
     // ops form: last level that wrote / read each row and scratch row
     std::vector<uint32_t> lw, lr, slw, slr;
     uint32_t S = 0, next_scratch = 0;
-    std::vector<uint32_t> oa, ob, od1, od2, olev;
+    struct Op {
+        uint32_t a, b, d1, d2;
+    };
+    std::vector<Op> ops;          // ops form, in reverse-stream order
+    std::vector<uint32_t> olev;   // their levels (1-based)
     int64_t n_pairs = 0, n_dir = 0, n_targets = 0, n_sources = 0;
 
     // items in reverse-stream order
@@ -53,6 +57,7 @@ struct Planner {
     std::vector<uint32_t> lnode, parent, comp, comp_nodes_ptr, comp_nodes,
         comp_ev_ptr, comp_ev, fill, nbr_ptr, nbr;
     std::vector<uint32_t> es, ed;  // group events without self-loops
+    std::vector<uint32_t> posbuf;
     std::vector<uint32_t> tgt, tscr;
 
     Planner(uint32_t n_, bool dir, bool ops)
@@ -88,10 +93,18 @@ struct Planner {
         W(d1) = lev;
         if (d2 != kNoRow) W(d2) = lev;
         if (lev > L) L = lev;
-        oa.push_back(a);
-        ob.push_back(b);
-        od1.push_back(d1);
-        od2.push_back(d2);
+        ops.push_back({a, b, d1, d2});
+        olev.push_back(lev);
+    }
+    // emit() for a pair of real rows: (u, v, u, v) or (u, v, u, -)
+    void emit_pair(uint32_t u, uint32_t v, bool both) {
+        uint32_t lev = std::max(std::max(lw[u], lr[u]), std::max(lw[v], both ? lr[v] : 0u)) + 1;
+        lw[u] = lev;
+        lr[u] = std::max(lr[u], lev);
+        if (both) lw[v] = lev;
+        lr[v] = std::max(lr[v], lev);
+        if (lev > L) L = lev;
+        ops.push_back({u, v, u, both ? v : kNoRow});
         olev.push_back(lev);
     }
 
@@ -108,11 +121,11 @@ struct Planner {
         if (ops_mode) {
             ++n_pairs;
             if (!directed || (uv && vu)) {
-                emit(u, v, u, v);
+                emit_pair(u, v, true);
             } else {
                 ++n_dir;
-                if (uv) emit(u, v, u, kNoRow);
-                else emit(v, u, v, kNoRow);
+                if (uv) emit_pair(u, v, false);
+                else emit_pair(v, u, false);
             }
             return;
         }
@@ -157,6 +170,24 @@ struct Planner {
             std::fill(stamp.begin(), stamp.end(), 0xffffffffu);
             gid = 0;
         }
+        // common case: no node occurs twice, so every event is its own pair
+        // component (the stamps are then reused by the general path below)
+        {
+            bool disjoint = true;
+            for (size_t i = 0; i < k && disjoint; ++i) {
+                disjoint = stamp[es[i]] != gid && stamp[ed[i]] != gid;
+                stamp[es[i]] = stamp[ed[i]] = gid;
+            }
+            if (disjoint) {
+                for (size_t i = 0; i < k; ++i) add_pair(es[i], ed[i], true, false);
+                return;
+            }
+            ++gid;
+            if (gid == 0xffffffffu) {
+                std::fill(stamp.begin(), stamp.end(), 0xffffffffu);
+                gid = 0;
+            }
+        }
         lnode.clear();
         parent.clear();
         auto lid = [&](uint32_t x) {
@@ -189,7 +220,8 @@ struct Planner {
         for (uint32_t c = 0; c < nc; ++c) comp_nodes_ptr[c + 1] += comp_nodes_ptr[c];
         comp_nodes.resize(nl);
         {
-            std::vector<uint32_t> pos(comp_nodes_ptr.begin(), comp_nodes_ptr.end() - 1);
+            std::vector<uint32_t> &pos = posbuf;
+            pos.assign(comp_nodes_ptr.begin(), comp_nodes_ptr.end() - 1);
             for (uint32_t i = 0; i < nl; ++i) comp_nodes[pos[comp[i]]++] = i;
         }
         // events per component (CSR)
@@ -198,7 +230,8 @@ struct Planner {
         for (uint32_t c = 0; c < nc; ++c) comp_ev_ptr[c + 1] += comp_ev_ptr[c];
         comp_ev.resize(k);
         {
-            std::vector<uint32_t> pos(comp_ev_ptr.begin(), comp_ev_ptr.end() - 1);
+            std::vector<uint32_t> &pos = posbuf;
+            pos.assign(comp_ev_ptr.begin(), comp_ev_ptr.end() - 1);
             for (size_t i = 0; i < k; ++i) comp_ev[pos[comp[local[es[i]]]]++] = (uint32_t)i;
         }
         for (uint32_t c = 0; c < nc; ++c) {
@@ -232,7 +265,8 @@ struct Planner {
         }
         for (uint32_t c = 0; c < cn; ++c) nbr_ptr[c + 1] += nbr_ptr[c];
         nbr.resize(nbr_ptr[cn]);
-        std::vector<uint32_t> pos(nbr_ptr.begin(), nbr_ptr.end() - 1);
+        std::vector<uint32_t> &pos = posbuf;
+        pos.assign(nbr_ptr.begin(), nbr_ptr.end() - 1);
         for (uint32_t q = e0; q < e1; ++q) {
             uint32_t i = comp_ev[q];
             nbr[pos[fill[local[es[i]]]]++] = ed[i];
@@ -311,7 +345,7 @@ namespace {
 // into consecutive levels; its ops are independent, so any split is exact).
 void finish_ops(Planner &p, HostSchedule &out) {
     const uint32_t L = p.L;
-    const size_t P = p.oa.size();
+    const size_t P = p.ops.size();
     std::vector<uint32_t> cnt((size_t)L + 1, 0);
     for (uint32_t lv : p.olev) cnt[lv]++;
     std::vector<uint32_t> base((size_t)L + 2, 0);  // first split level of level l
@@ -331,10 +365,7 @@ void finish_ops(Planner &p, HostSchedule &out) {
     std::vector<uint32_t> pos(out.lvl_op.begin(), out.lvl_op.end() - 1);
     for (size_t i = 0; i < P; ++i) {
         const size_t q = pos[flev[i]]++;
-        out.ops[4 * q] = p.oa[i];
-        out.ops[4 * q + 1] = p.ob[i];
-        out.ops[4 * q + 2] = p.od1[i];
-        out.ops[4 * q + 3] = p.od2[i];
+        std::memcpy(&out.ops[4 * q], &p.ops[i], sizeof(Planner::Op));
     }
     out.scratch_rows = p.S;
     out.op_levels_unsplit = L;
@@ -387,11 +418,8 @@ tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
     };
     if (forms & kFormOps) {
         Planner po(n, directed, true);
-        po.oa.reserve((size_t)m);
-        po.ob.reserve((size_t)m);
-        po.od1.reserve((size_t)m);
-        po.od2.reserve((size_t)m);
-        po.olev.reserve((size_t)m);
+        po.ops.reserve((size_t)m + (size_t)m / 4);
+        po.olev.reserve((size_t)m + (size_t)m / 4);
         walk(po);
         finish_ops(po, out);
         out.op_pairs = po.n_pairs;
