@@ -307,6 +307,8 @@ def run_batched(args):
     nets = [(sp.n,) + sp.generate() for sp in specs]
     m_total = sum(int(x[1].shape[0]) for x in nets)
     ctx = tn.get_context()
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib)
     t0 = time.perf_counter()
     b = tn.Batch(nets)
     plan_wall = time.perf_counter() - t0
@@ -336,7 +338,8 @@ def run_batched(args):
     r = base_result(args, m_total / (batch_ms * 1e-3), "events/s", args.steps,
                     1e3 * elapsed / args.steps, config)
     r["roofline"] = {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": load_traffic("batch", "batched"),
+                     "frac": achieved / LDS_PEAK_GBS,
+                     "traffic": load_traffic("batch", config["workload"]),
                      "kernel": "k_batch_persistent", "algorithmic_bytes": dense,
                      "hbm_equivalent_frac": achieved / HBM_PEAK_GBS, "avg_launch_ms": batch_ms}
     r["batched"] = {"graph_launch_ms": batch_ms, "plain_network_by_network_ms": plain_ms,
@@ -459,10 +462,12 @@ def _read_csv(path):
         return list(csv.DictReader(f))
 
 
-def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib):
+def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, last=0):
     """HBM bytes per launch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB per
     dispatch, one --pmc run each), each scaled by what the same counter read
-    for the plain device copy of calib_mib MiB in the same run."""
+    for the plain device copy of calib_mib MiB in the same run.  last > 0
+    keeps only the kernel's last `last` dispatches (the timed ones, after
+    autotuning)."""
     match = {"rowor": "k_rowor_global", "batch": "k_batch_persistent",
              "recombine": "k_recombine_est"}[kernel]
     out = {"kernel": match, "workload": workload, "command": command,
@@ -475,6 +480,8 @@ def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib):
         # the calibration copy is the largest copy dispatch of the run
         calib = max(copies) if copies else float("nan")
         vals = [float(r["Counter_Value"]) for r in rows if match in r["Kernel_Name"]]
+        if last:
+            vals = vals[-last:]
         factor = known_kib / calib
         out[name] = {"kib_per_dispatch": vals, "calibration_kib": calib, "factor": factor,
                      "bytes_per_launch": 1024.0 * factor * sum(vals) / max(len(vals), 1)}
@@ -505,10 +512,12 @@ def main():
         sp.add_argument("--workload", default="activity_n100000_m10M")
         sp.add_argument("--command", required=True)
         sp.add_argument("--calib-mib", type=int, default=1024)
+        sp.add_argument("--last", type=int, default=0)
         sp.add_argument("--out", required=True)
         a = sp.parse_args(sys.argv[2:])
         if what == "--summarize-pmc":
-            rec = summarize_pmc(a.fetch, a.write, a.kernel, a.workload, a.command, a.calib_mib)
+            rec = summarize_pmc(a.fetch, a.write, a.kernel, a.workload, a.command, a.calib_mib,
+                                a.last)
             with open(a.out, "w") as f:
                 json.dump(rec, f, indent=1)
         else:
