@@ -203,11 +203,41 @@ tn_status tn_set_saturation(tn_ctx *ctx, int enable);
  * stream.  Errors: TN_E_ARG, TN_E_HIP. */
 tn_status tn_plan_last_traffic(tn_ctx *ctx, uint64_t *words);
 
-/* One call: plan, execute, destroy.  Inputs HOST, C DEVICE as above. */
+/* One call (Sec. 3.1 Algorithm 1 in reverse time, Sec. 3.4).  Inputs HOST,
+ * C DEVICE as above; the call returns once C is complete.  It runs the
+ * streamed build below with its default chunk size. */
 tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m,
                                     const uint32_t *src, const uint32_t *dst,
                                     const int64_t *t, uint32_t flags,
                                     uint64_t *C, int64_t ld);
+
+/* Streamed one-shot build (Sec. 3.4: the reverse-time recurrence consumes
+ * the event list from its end).  The list is cut into chunks of about
+ * chunk_events events on time-step boundaries (0 = max(2^18, m/64)); host
+ * threads plan chunks concurrently while the device applies them in
+ * reverse-time order to C.  Rows only gain bits, so once every row is all
+ * ones within a column slice nothing earlier in time can change it: such
+ * slices stop, and once all slices have, the remaining (earlier) chunks are
+ * neither planned further nor run.  The result equals tn_plan_execute's.
+ * Inputs HOST, borrowed for the call; C DEVICE, n x ld, written entirely.
+ * stats (HOST, may be NULL) reports what ran.  Errors as tn_plan_create,
+ * plus TN_E_ARG for ld < ceil(n/64) or chunk_events < 0; nothing is
+ * enqueued when validation fails. */
+typedef struct {
+    int64_t chunks;       /* chunks the list was cut into                   */
+    int64_t chunks_run;   /* chunks launched on the device                  */
+    int64_t events_run;   /* events in the launched chunks                  */
+    int64_t levels_run;   /* op levels in the launched chunks               */
+    int32_t saturated;    /* 1: every row ended all ones, and it was seen   */
+    int32_t slice_words;  /* words per row each workgroup owned             */
+    double seconds;       /* wall time of the call                          */
+} tn_stream_stats;
+tn_status tn_build_component_matrix_streamed(tn_ctx *ctx, uint32_t n, int64_t m,
+                                             const uint32_t *src, const uint32_t *dst,
+                                             const int64_t *t, uint32_t flags,
+                                             uint64_t *C, int64_t ld,
+                                             int64_t chunk_events,
+                                             tn_stream_stats *stats);
 
 /* Component sizes (Sec. 3.1, Eq. 1): out_sizes[u] = ones in row u (the
  * maximum out-component size of u), in_sizes[w] = ones in column w (the

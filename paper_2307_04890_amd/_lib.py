@@ -50,6 +50,21 @@ class PlanStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StreamStats(ctypes.Structure):
+    _fields_ = [
+        ("chunks", ctypes.c_int64),
+        ("chunks_run", ctypes.c_int64),
+        ("events_run", ctypes.c_int64),
+        ("levels_run", ctypes.c_int64),
+        ("saturated", ctypes.c_int32),
+        ("slice_words", ctypes.c_int32),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
@@ -74,6 +89,8 @@ SIGNATURES = {
     "tn_set_saturation": (_i32, [_P, ctypes.c_int]),
     "tn_plan_last_traffic": (_i32, [_P, _P]),
     "tn_build_component_matrix": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _P, _i64]),
+    "tn_build_component_matrix_streamed": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _P, _i64,
+                                                  _i64, ctypes.POINTER(StreamStats)]),
     "tn_component_sizes": (_i32, [_P, _u32, _P, _i64, _P, _P]),
     "tn_batch_create": (_i32, [_P, _i32, _P, _P, _P, _P, _P, _u32, _PP]),
     "tn_batch_execute": (_i32, [_P, _P, _P, _P]),

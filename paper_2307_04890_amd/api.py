@@ -8,9 +8,9 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import DIRECTED, KERNELS, TIES_SEQUENTIAL, PlanStats, TNError, check, lib
+from ._lib import DIRECTED, KERNELS, TIES_SEQUENTIAL, PlanStats, StreamStats, TNError, check, lib
 
-__all__ = ["Context", "Plan", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+__all__ = ["Context", "Plan", "build_component_matrix_streamed", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
 
@@ -168,6 +168,23 @@ def build_component_matrix(n: int, src, dst, t, flags: int = 0, C: torch.Tensor 
     check(lib.tn_build_component_matrix(ctx.bind_stream(), int(n), src.shape[0], _hp(src),
                                         _hp(dst), _hp(t), int(flags), _dp(C), C.stride(0)))
     return C
+
+
+def build_component_matrix_streamed(n: int, src, dst, t, flags: int = 0,
+                                    C: torch.Tensor | None = None, chunk_events: int = 0,
+                                    ctx: Context | None = None):
+    """Streamed one-shot build (tn_build_component_matrix_streamed): returns
+    (C, stats) once C is complete."""
+    ctx = ctx or get_context()
+    src, dst, t = _events(src, dst, t)
+    if C is None:
+        C = alloc_matrix(n, device=ctx.device)
+    st = StreamStats()
+    check(lib.tn_build_component_matrix_streamed(ctx.bind_stream(), int(n), src.shape[0],
+                                                 _hp(src), _hp(dst), _hp(t), int(flags), _dp(C),
+                                                 C.stride(0), int(chunk_events),
+                                                 ctypes.byref(st)))
+    return C, st.as_dict()
 
 
 def component_sizes(C: torch.Tensor, n: int, out: bool = True, inn: bool = True,

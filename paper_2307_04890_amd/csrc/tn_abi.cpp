@@ -305,7 +305,7 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         tn::ProfScope ps(ctx, TN_K_ROWOR);
         e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
                                     plan->scratch_rows, ctx->traffic, ctx->saturation,
-                                    ctx->stream);
+                                    nullptr, nullptr, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "row-OR kernel launch");
     return TN_OK;
@@ -336,20 +336,7 @@ tn_status tn_plan_last_traffic(tn_ctx *ctx, uint64_t *words) {
 tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
                                     const uint32_t *dst, const int64_t *t, uint32_t flags,
                                     uint64_t *C, int64_t ld) {
-    if (!C) return fail(TN_E_ARG, "C is NULL");
-    if (ld < (int64_t)((n + 63) / 64)) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
-    tn_plan *p = nullptr;
-    tn_status st = tn_plan_create(ctx, n, m, src, dst, t, flags, &p);
-    if (st != TN_OK) return st;
-    st = tn_plan_execute(ctx, p, C, ld, 0);
-    if (st == TN_OK) {
-        // the plan's schedule must outlive the queued kernels
-        DeviceGuard g(ctx->device);
-        hipError_t e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
-    }
-    tn_plan_destroy(p);
-    return st;
+    return tn::build_streamed(ctx, n, m, src, dst, t, flags, C, ld, 0, nullptr);
 }
 
 tn_status tn_component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C, int64_t ld,

@@ -180,6 +180,8 @@ tn_status ensure_scratch(tn_ctx *ctx, size_t bytes);
 void fill_stats(const HostSchedule &hs, tn_plan_stats &s);
 
 // ---- kernel launchers (tn_kernels.hip) ---------------------------------
+// p[0 .. count) = v (a kernel, so it may be captured in a graph).
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t st);
 // traffic (nullable): two device counters the identity kernel zeroes.
 hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, unsigned long long *traffic,
                            hipStream_t st);
@@ -192,12 +194,30 @@ constexpr size_t kRoworSatLds = 163840 - 40960;
 // The kernel adds the row words it loaded to traffic[0] and stored to
 // traffic[1] (device counters, zeroed by the caller).  With saturation, and
 // when a bit per row and scratch row fits kRoworSatLds, it skips the loads
-// and stores that saturated rows make redundant.
+// and stores that saturated rows make redundant.  persist (nullable, only
+// used with saturation): rowor_persist_words(n, slice_words) uint32 of
+// per-slice state carried between launches over consecutive chunks of one
+// stream, zero before the first; a slice that becomes all full sets its
+// done word and adds 1 to *done_count.
 uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words);
 hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                                uint32_t slice_words, uint64_t *scratch,
                                uint32_t scratch_rows, unsigned long long *traffic,
-                               bool saturation, hipStream_t st);
+                               bool saturation, uint32_t *persist, unsigned int *done_count,
+                               hipStream_t st);
+// uint32 words of persisted state: per slice, done + count + ceil(n/32) bits
+inline size_t rowor_persist_words(uint32_t n, uint32_t slice_words) {
+    return (size_t)rowor_workgroups(n, slice_words) * (((size_t)n + 31) / 32 + 2);
+}
+// streamed one-shot build (tn_stream.cpp)
+tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
+                         const uint32_t *dst, const int64_t *t, uint32_t flags, uint64_t *C,
+                         int64_t ld, int64_t chunk_events, tn_stream_stats *stats);
+// whether the saturating kernel can run for n rows and this many scratch rows
+inline bool rowor_saturates(uint32_t n, uint32_t scratch_rows) {
+    const uint64_t sbits = (((uint64_t)n + 31) & ~31ull) + scratch_rows + 1;
+    return ((sbits + 31) / 32) * 4 <= kRoworSatLds;
+}
 hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld,
                             int32_t *out_sizes, hipStream_t st);
 hipError_t launch_in_sizes(const uint64_t *C, uint32_t n, int64_t ld,

@@ -252,7 +252,8 @@ template <int SW, int UC, bool SAT>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
                uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
-               unsigned long long *__restrict__ traffic) {
+               unsigned long long *__restrict__ traffic, uint32_t *__restrict__ persist,
+               unsigned int *__restrict__ done_count) {
     __shared__ op4 frame[kFrames][kOpsLevelCap];
     __shared__ uint32_t fcount[kFrames];
     __shared__ uint32_t worklist[SAT ? kComputeWaves : 1][kWaveShare];
@@ -291,12 +292,27 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     // Once every real row is full in this slice, all later ops are full
     // results into full rows: the workgroup stops.  A slice with a single
     // valid column starts with that column's identity row full.
+    //
+    // persist (streamed builds, one chunk of the stream per launch): per
+    // slice {done, full-row count, real-row bits}, carried from the launch
+    // of the previous chunk; a slice already done returns at once.  Scratch
+    // rows never outlive a time step, so their bits start at zero.
     const uint32_t c0 = slice * SW * 64u;
     const bool single = c0 + 1 == n;
+    const uint32_t rwords = sbase / 32;  // words of real-row bits
+    uint32_t *pst = (SAT && persist) ? persist + (size_t)slice * (rwords + 2) : nullptr;
     int32_t nfull = single ? 1 : 0;
     if (SAT) {
-        for (uint32_t i = tid; i < (sbits + 31) / 32; i += blockDim.x)
-            satbits[i] = (single && i == (c0 >> 5)) ? (1u << (c0 & 31u)) : 0u;
+        if (pst) {
+            if (pst[0]) return;
+            nfull = (int32_t)pst[1];
+            if (single && !((pst[2 + (c0 >> 5)] >> (c0 & 31u)) & 1u)) ++nfull;
+        }
+        for (uint32_t i = tid; i < (sbits + 31) / 32; i += blockDim.x) {
+            uint32_t v = (pst && i < rwords) ? pst[2 + i] : 0u;
+            if (single && i == (c0 >> 5)) v |= 1u << (c0 & 31u);
+            satbits[i] = v;
+        }
         if (tid < 3) fdelta[tid] = 0;
     }
     A.nfull = fdelta;
@@ -351,8 +367,12 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
         return;
     }
     __syncthreads();
+    bool stopped = false;
     for (uint32_t l = 0; l < L; ++l) {
-        if (done(l)) break;
+        if (done(l)) {
+            stopped = true;
+            break;
+        }
         const uint32_t cf = l % kFrames;
         const uint32_t cnt = fcount[cf];
         if (SAT) {
@@ -375,6 +395,18 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     }
     count_add(traffic, A.loaded);
     count_add(traffic + 1, A.stored);
+    if (pst) {
+        // the last level's delta settled at the loop's final barrier
+        if (!stopped) nfull += fdelta[(L - 1) % 3];
+        for (uint32_t i = ctid; i < rwords; i += blockDim.x - kLoaderThreads) pst[2 + i] = satbits[i];
+        if (ctid == 0) {
+            pst[1] = (uint32_t)nfull;
+            if (nfull == (int32_t)n) {
+                pst[0] = 1u;
+                atomicAdd(done_count, 1u);
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
@@ -451,7 +483,7 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
 template <int SW, int UC>
 hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, uint64_t *scratch,
                          uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
-                         hipStream_t st) {
+                         uint32_t *persist, unsigned int *done_count, hipStream_t st) {
     const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
     const uint32_t sbase = (n + 31u) & ~31u;
@@ -463,10 +495,11 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, n, nwords, s, scratch,
-                           sbase, (uint32_t)sbits, traffic);
+                           sbase, (uint32_t)sbits, traffic, persist, done_count);
     } else {
         hipLaunchKernelGGL((k_rowor_global<SW, UC, false>), dim3(slices), dim3(1024), 0, st, C,
-                           ld, n, nwords, s, scratch, 0u, 1u, traffic);
+                           ld, n, nwords, s, scratch, 0u, 1u, traffic, (uint32_t *)nullptr,
+                           (unsigned int *)nullptr);
     }
     return hipGetLastError();
 }
@@ -485,6 +518,16 @@ uint32_t default_slice_words(uint32_t n, int64_t ld) {
     return 1;
 }
 
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    if (count > 0xffffffffull) return hipErrorInvalidValue;
+    uint32_t blocks = (uint32_t)((count + 255) / 256);
+    if (blocks > 4096u) blocks = 4096u;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, st, (int32_t *)p, (uint32_t)count,
+                       (int32_t)v);
+    return hipGetLastError();
+}
+
 hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, unsigned long long *traffic,
                            hipStream_t st) {
     const uint32_t blocks = n < 65536u ? n : 65536u;
@@ -499,17 +542,18 @@ uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words) {
 
 hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                                uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
-                               unsigned long long *traffic, bool saturation, hipStream_t st) {
+                               unsigned long long *traffic, bool saturation, uint32_t *persist,
+                               unsigned int *done_count, hipStream_t st) {
     if (s.L == 0) return hipSuccess;
     switch (slice_words) {
         // UC: ops per lane group and level, so that (896 / SW) * UC >= 1024
-        case 1: return rowor_variant<1, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 2: return rowor_variant<2, 3>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 4: return rowor_variant<4, 5>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 8: return rowor_variant<8, 10>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
-        case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, st);
+        case 1: return rowor_variant<1, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
+        case 2: return rowor_variant<2, 3>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
+        case 4: return rowor_variant<4, 5>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
+        case 8: return rowor_variant<8, 10>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
+        case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
+        case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
+        case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -213,3 +213,9 @@ def test_full_size_saturation_off_gives_same_matrix(c2):
     nw = oracle.words(100_000)
     assert ld_off == 2 * st["ops"] * nw
     assert ld_on < ld_off and st_on < st_off
+
+
+def test_full_size_streamed_build_stops_early(c2):
+    C, st = tn.build_component_matrix_streamed(100_000, c2["s"], c2["d"], c2["t"])
+    assert torch.equal(C, c2["C"])
+    assert st["saturated"] == 1 and st["events_run"] < 10_000_000
