@@ -404,59 +404,97 @@ def run_combiner(args):
         lifted_min = f["lifted"].min(dim=0).values
         return f["x"], exact, f["est"], lifted_min
 
-    t0 = time.perf_counter()
-    xs, ys = [], []
-    for i in range(args.train_networks):
-        x, exact, _, _ = features(20_000, 1_000_000, 100_000, 5000 + i, 7000 + i)
-        xs.append(x)
-        ys.append(torch.log(exact.float() / 20_000))
-        log(f"[bench] training network {i + 1}/{args.train_networks}")
-    X, Y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
-    data_s = time.perf_counter() - t0
-    comb = cb.Combiner(T.mlp_init(1))
-    g = T.rng(2)
-    orders = [g.permutation(X.shape[0]) for _ in range(args.epochs)]
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    losses = comb.fit(X, Y, orders, batch=4096, lr=1e-3)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    recs = ctx.profile_take()
-    ctx.profile(False)
-    bwd = [ms for k, ms in recs if k == "mlp_backward"]
-    steps = len(bwd)
-    errs = {"combiner_clamped": [], "combiner": [], "fusion_estimate": [], "min_lifted": []}
-    for i in range(args.heldout_networks):
-        n = 100_000
-        x, exact, est, lmin = features(n, 10_000_000, 1_000_000, 6000 + i, 8000 + i)
-        e = exact.cpu().numpy()
-        errs["combiner_clamped"].append(cb.relative_errors(comb.predict(x, n, est=est).cpu().numpy(), e))
-        errs["combiner"].append(cb.relative_errors(comb.predict(x, n).cpu().numpy(), e))
-        errs["fusion_estimate"].append(cb.relative_errors(est.cpu().numpy(), e))
-        errs["min_lifted"].append(cb.relative_errors(lmin.cpu().numpy(), e))
-        log(f"[bench] held-out network {i + 1}/{args.heldout_networks}")
-    summary = {k: {q: float(np.mean([r[q] for r in v])) for q in v[0]} for k, v in errs.items()}
+    def evaluate(train, heldouts, tag):
+        """Train on `train` = (n, m, T) networks, evaluate on each (n, m, T)
+        of `heldouts`."""
+        t0 = time.perf_counter()
+        xs, ys = [], []
+        for i in range(args.train_networks):
+            x, exact, _, _ = features(*train, 5000 + i, 7000 + i)
+            xs.append(x)
+            ys.append(torch.log(exact.float() / train[0]))
+        log(f"[bench] {tag}: {args.train_networks} training networks")
+        X, Y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+        data_s = time.perf_counter() - t0
+        comb = cb.Combiner(T.mlp_init(1))
+        g = T.rng(2)
+        orders = [g.permutation(X.shape[0]) for _ in range(args.epochs)]
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        losses = comb.fit(X, Y, orders, batch=4096, lr=1e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        recs = ctx.profile_take()
+        ctx.profile(False)
+        bwd = [ms for k, ms in recs if k == "mlp_backward"]
+        evals = []
+        for heldout in heldouts:
+            errs = {"combiner_clamped": [], "combiner": [], "fusion_estimate": [],
+                    "min_lifted": []}
+            sizes = []
+            for i in range(args.heldout_networks):
+                n = heldout[0]
+                x, exact, est, lmin = features(*heldout, 6000 + i, 8000 + i)
+                e = exact.cpu().numpy()
+                sizes.append(e)
+                errs["combiner_clamped"].append(
+                    cb.relative_errors(comb.predict(x, n, est=est).cpu().numpy(), e))
+                errs["combiner"].append(cb.relative_errors(comb.predict(x, n).cpu().numpy(), e))
+                errs["fusion_estimate"].append(cb.relative_errors(est.cpu().numpy(), e))
+                errs["min_lifted"].append(cb.relative_errors(lmin.cpu().numpy(), e))
+            log(f"[bench] {tag}: {args.heldout_networks} held-out networks {heldout}")
+            summary = {k: {q: float(np.mean([r[q] for r in v])) for q in v[0]}
+                       for k, v in errs.items()}
+            allsz = np.concatenate(sizes)
+            evals.append({"heldout": {"n": heldout[0], "m": heldout[1], "T": heldout[2],
+                                      "networks": args.heldout_networks},
+                          "exact_size_quantiles": [float(q) for q in
+                                                   np.percentile(allsz, [1, 10, 50, 90, 99])],
+                          "errors": summary})
+        return {"train": {"n": train[0], "m": train[1], "T": train[2],
+                          "networks": args.train_networks, "rows": int(X.shape[0])},
+                "evaluations": evals, "errors": evals[0]["errors"],
+                "exact_size_quantiles": evals[0]["exact_size_quantiles"],
+                "dataset_seconds": data_s, "train_seconds": train_s,
+                "first_loss": losses[0], "final_loss": float(np.mean(losses[-50:])),
+                "steps": len(bwd), "bwd_ms": float(np.sum(bwd)),
+                "train_rows": int(X.shape[0])}
+
+    # the stated workload: n = 20,000, m = 10^6 training networks, held-out
+    # n = 100,000 networks at the exact workload's density
+    main = evaluate((20_000, 1_000_000, 100_000), [(100_000, 10_000_000, 1_000_000)], "stated")
+    # the same sizes at 1.2 events per node, where out-components spread;
+    # held out at the same events per node, and at the same events per
+    # super-node (m / K) as the training networks
+    sparse = evaluate((20_000, 24_000, 20_000),
+                      [(100_000, 120_000, 100_000), (100_000, 24_000, 100_000)], "sparse")
+    steps = main["steps"]
     # forward+backward FLOPs per sample: 2 * (16*64 + 64*64 + 64) * 3
-    flop = 2.0 * (16 * 64 + 64 * 64 + 64) * 3 * X.shape[0] * args.epochs
-    bwd_ms = float(np.sum(bwd))
-    achieved = flop / (bwd_ms * 1e-3) / 1e12
+    flop = 2.0 * (16 * 64 + 64 * 64 + 64) * 3 * main["train_rows"] * args.epochs
+    achieved = flop / (main["bwd_ms"] * 1e-3) / 1e12
     config = {"workload": "combiner_train64_n20000_m1M_eval4_n100000_m10M", "H": H, "K": K,
-              "train_rows": int(X.shape[0]), "epochs": args.epochs, "batch": 4096,
+              "train_rows": main["train_rows"], "epochs": args.epochs, "batch": 4096,
               "lr": 1e-3, "parallelism": "single-gpu"}
-    r = base_result(args, summary["combiner_clamped"]["mean"], "mean relative error", steps,
-                    1e3 * train_s / max(steps, 1), config, dtype="f32")
+    r = base_result(args, main["errors"]["combiner_clamped"]["mean"], "mean relative error",
+                    steps, 1e3 * main["train_seconds"] / max(steps, 1), config, dtype="f32")
     r["higher_is_better"] = False
-    r["errors"] = summary
+    r["errors"] = main["errors"]
     r["roofline"] = {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
                      "frac": achieved / 157.3, "traffic": None, "kernel": "k_mlp_backward",
-                     "avg_launch_ms": bwd_ms / max(steps, 1)}
-    r["combiner"] = {"dataset_seconds": data_s, "train_seconds": train_s,
-                     "final_loss": float(np.mean(losses[-50:])), "first_loss": losses[0]}
+                     "avg_launch_ms": main["bwd_ms"] / max(steps, 1)}
+    r["combiner"] = {k: main[k] for k in ("dataset_seconds", "train_seconds", "first_loss",
+                                          "final_loss", "exact_size_quantiles")}
+    r["combiner"]["note"] = ("at this density every node reaches every node: exact sizes, "
+                             "estimates and predictions all equal n")
+    r["sparse"] = sparse
     if not args.no_cpu_baseline:
         from oracle import mlp as ref
-        xs_ = X[:4096].double().cpu().numpy()
-        ys_ = Y[:4096].double().cpu().numpy()
+        xs_ = np.zeros((4096, 16))
+        ys_ = np.zeros(4096)
         p = T.mlp_init(1).astype(np.float64)
+        g = T.rng(3)
+        xs_[:] = g.normal(size=xs_.shape)
+        ys_[:] = g.normal(size=ys_.shape)
         t0 = time.perf_counter()
         k = 0
         while time.perf_counter() - t0 < min(args.cpu_budget, 5.0):

@@ -302,6 +302,25 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m,
                            uint32_t *bucket, int32_t *count,
                            tn_batch **proxies);
 
+/* Hash and build all H proxies in one call, streamed (Sec. 4.1 hashing,
+ * Sec. 4.3 independent proxies, Sec. 3.4 reverse time).  bucket and count as
+ * in tn_hash_compress; P: DEVICE, H consecutive K x ldK uint64 matrices
+ * (proxy j at P + j*K*ldK), written entirely.  The event list is cut into
+ * chunks of whole time steps from its end (chunk_events as in
+ * tn_build_component_matrix_streamed); each chunk's H mapped sub-streams are
+ * planned on host threads and applied in one batched launch that resumes
+ * from the proxies.  Once every tile of every proxy is all ones the earlier
+ * chunks are skipped.  The proxies equal those of tn_hash_compress +
+ * tn_batch_execute.  stats (HOST, may be NULL) as for the streamed build.
+ * Errors as tn_hash_compress, plus TN_E_ARG for ldK < ceil(K/64). */
+tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m,
+                                const uint32_t *src, const uint32_t *dst,
+                                const int64_t *t, uint32_t flags, uint32_t H,
+                                uint32_t K, const uint64_t *coeffs, int32_t order,
+                                uint32_t *bucket, int32_t *count, uint64_t *P,
+                                int64_t ldK, int64_t chunk_events,
+                                tn_stream_stats *stats);
+
 /* Fusion (Sec. 4.2, Eqs. DefInvHComp and DefEstOCMerge):
  * est[u] = |{w < n : P_j[h_j(u)][h_j(w)] = 1 for every j < H}|, the size of
  * the estimated out-component (a superset of the true one), and, if lifted

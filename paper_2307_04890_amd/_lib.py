@@ -97,6 +97,8 @@ SIGNATURES = {
     "tn_batch_get_stats": (_i32, [_P, _P, _P, _P]),
     "tn_batch_destroy": (None, [_P]),
     "tn_build_component_matrix_batched": (_i32, [_P, _i32, _P, _P, _P, _P, _P, _u32, _P, _P]),
+    "tn_hash_build_proxies": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _u32, _u32, _P, _i32,
+                                     _P, _P, _P, _i64, _i64, ctypes.POINTER(StreamStats)]),
     "tn_hash_compress": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _u32, _u32, _P, _i32, _P, _P,
                                 _PP]),
     "tn_recombine": (_i32, [_P, _u32, _u32, _u32, _P, _i64, _P, _P, _P, _P]),

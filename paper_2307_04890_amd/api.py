@@ -10,7 +10,7 @@ import torch
 
 from ._lib import DIRECTED, KERNELS, TIES_SEQUENTIAL, PlanStats, StreamStats, TNError, check, lib
 
-__all__ = ["Context", "Plan", "build_component_matrix_streamed", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+__all__ = ["Context", "Plan", "build_component_matrix_streamed", "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
 
@@ -331,6 +331,32 @@ def hash_compress(n: int, src, dst, t, coeffs, K: int, flags: int = 0,
                                int(flags), H, int(K), _hp(A), order, _dp(bucket), _dp(count),
                                ctypes.byref(h)))
     return bucket, count, Batch([K] * H, ctx=ctx, _handle=h)
+
+
+def hash_build_proxies(n: int, src, dst, t, coeffs, K: int, flags: int = 0,
+                       chunk_events: int = 0, P: torch.Tensor | None = None,
+                       ctx: Context | None = None):
+    """Hashing plus the streamed build of all H proxies (tn_hash_build_proxies):
+    returns (bucket (H, n), count (H, K), P (H, K, ldK) int64, stats)."""
+    ctx = ctx or get_context()
+    src, dst, t = _events(src, dst, t)
+    A = np.ascontiguousarray(coeffs, dtype=np.uint64)
+    if A.ndim != 3 or A.shape[1] != 3:
+        raise ValueError("coeffs must have shape (H, 3, order)")
+    H, _, order = A.shape
+    dev = f"cuda:{ctx.device}"
+    bucket = torch.empty((H, n), dtype=torch.int32, device=dev)
+    count = torch.empty((H, K), dtype=torch.int32, device=dev)
+    if P is None:
+        P = torch.empty((H, K, words(K)), dtype=torch.int64, device=dev)
+    if P.dim() != 3 or not P.is_contiguous() or P.shape[0] != H or P.shape[1] != K:
+        raise ValueError("P must be a contiguous (H, K, ldK) tensor")
+    st = StreamStats()
+    check(lib.tn_hash_build_proxies(ctx.bind_stream(), int(n), src.shape[0], _hp(src), _hp(dst),
+                                    _hp(t), int(flags), H, int(K), _hp(A), order, _dp(bucket),
+                                    _dp(count), _dp(P), P.shape[2], int(chunk_events),
+                                    ctypes.byref(st)))
+    return bucket, count, P, st.as_dict()
 
 
 def recombine(P: torch.Tensor, bucket: torch.Tensor, count: torch.Tensor, n: int,

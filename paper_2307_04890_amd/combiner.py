@@ -20,16 +20,12 @@ from . import api
 
 
 def hashed_features(n, src, dst, t, coeffs, K, flags=0, ctx=None):
-    """Hash, build the H proxies in one batched launch, fuse.  Returns a dict
-    with the MLP features x (n, H), the fusion estimate est (n,), the lifted
-    sizes (H, n), and the proxies P (H, K, ldK)."""
+    """Hash, build the H proxies (streamed, all H per batched launch), fuse.
+    Returns a dict with the MLP features x (n, H), the fusion estimate est
+    (n,), the lifted sizes (H, n), and the proxies P (H, K, ldK)."""
     ctx = ctx or api.get_context()
-    bucket, count, proxies = api.hash_compress(n, src, dst, t, coeffs, K, flags=flags, ctx=ctx)
-    H = bucket.shape[0]
-    P = torch.empty((H, K, api.words(K)), dtype=torch.int64, device=bucket.device)
-    proxies.execute([P[j] for j in range(H)])
+    bucket, count, P, _ = api.hash_build_proxies(n, src, dst, t, coeffs, K, flags=flags, ctx=ctx)
     est, lifted = api.recombine(P, bucket, count, n, ctx=ctx)
-    proxies.close()
     x = api.mlp_features(lifted, n, ctx=ctx)
     return {"x": x, "est": est, "lifted": lifted, "P": P, "bucket": bucket, "count": count}
 

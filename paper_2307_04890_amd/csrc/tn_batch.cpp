@@ -34,6 +34,12 @@ struct tn_batch {
     uint64_t *d_gscratch = nullptr;
     std::vector<tn::NetDesc> h_nets;
     bool sat = true;  // saturation setting of the current shape
+    // streamed chunk (tn::BatchStream): forced slice widths, slice state
+    bool streamed = false;
+    std::vector<uint32_t> force_lw;
+    std::vector<uint32_t *> persist;
+    uint32_t resume = 0;
+    unsigned int *done_count = nullptr;
     std::vector<uint2> h_tiles;
     uint32_t h_qptr[9] = {0};
     int64_t lds_tiles = 0;
@@ -113,15 +119,20 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
         // the bitmap must fit beside the LDS tile, or alone for a global tile
         sat_on[i] = b->sat && bm <= lds_budget();
         uint32_t w = lds_fit_words(b->n[i], b->max_gat[i], nw, sat_on[i]);
-        if (w == 0) {
+        if (b->streamed && !b->force_lw.empty()) {
+            // the chunk keeps the stream's slices: LDS if that width fits
+            const uint32_t fw = 1u << b->force_lw[i];
+            if (w < fw) b->mode[i] = kTileGlobal;
+            w = fw;
+        } else if (w == 0) {
             b->mode[i] = kTileGlobal;
             w = std::min<uint32_t>(8, pow2_ceil(nw));
-            if (b->max_gat[i] > 0) {
-                gscr_off[i] = gscr_words;
-                gscr_words += (size_t)b->max_gat[i] * nw;
-            }
         }
-        w = std::max<uint32_t>(1, w >> policy);
+        if (b->mode[i] == kTileGlobal && b->max_gat[i] > 0) {
+            gscr_off[i] = gscr_words;
+            gscr_words += (size_t)b->max_gat[i] * nw;
+        }
+        if (!b->streamed) w = std::max<uint32_t>(1, w >> policy);
         b->lw[i] = ilog2(w);
         const size_t tile = (b->mode[i] == kTileLds) ? (size_t)(b->n[i] + (size_t)b->max_gat[i]) * w * 8 : 0;
         sat_off[i] = (uint32_t)(tile / 8);
@@ -191,6 +202,8 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
         nd.gscratch = b->d_gscratch + gscr_off[i];
         nd.sat = sat_on[i];
         nd.sat_off = sat_off[i];
+        nd.resume = b->streamed ? b->resume : 0u;
+        nd.persist = (b->streamed && sat_on[i] && !b->persist.empty()) ? b->persist[i] : nullptr;
     }
     e = hipMemcpy(b->d_tiles, b->h_tiles.data(), sizeof(uint2) * ntiles, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -222,7 +235,7 @@ tn_status bind_outputs(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64
 
 hipError_t launch_direct(tn_batch *b, hipStream_t st) {
     return launch_batch(b->d_nets, b->d_tiles, b->d_qptr, b->d_counters, b->grid, b->threads,
-                        b->dyn_lds, st);
+                        b->dyn_lds, b->done_count, st);
 }
 
 tn_status capture_graph(tn_batch *b) {
@@ -302,7 +315,7 @@ tn_status autotune(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64_t *
 tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t *m,
                        const uint32_t *const *src, const uint32_t *const *dst,
                        const int64_t *const *t, uint32_t flags, tn_batch **out,
-                       const uint32_t *const *maps, uint32_t n_src) {
+                       const uint32_t *const *maps, uint32_t n_src, const BatchStream *stream) {
     if (!ctx || !out) return fail(TN_E_ARG, "ctx or out is NULL");
     *out = nullptr;
     if (B <= 0) return fail(TN_E_ARG, "B must be > 0");
@@ -363,6 +376,14 @@ tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t 
         b->max_gat.push_back(hs[i].max_level_gathers);
         hs[i] = HostSchedule();  // release host memory early
     }
+    if (stream) {
+        b->streamed = true;
+        b->tuned = true;  // a chunk must run exactly once: no autotuning
+        b->resume = stream->resume;
+        b->done_count = stream->done_count;
+        if (stream->lw) b->force_lw.assign(stream->lw, stream->lw + B);
+        if (stream->persist) b->persist.assign(stream->persist, stream->persist + B);
+    }
     tn_status st = apply_shape(ctx, b, 0, 1024);
     if (st != TN_OK) {
         free_meta(b);
@@ -396,15 +417,31 @@ tn_status batch_execute(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int6
     }
     st = bind_outputs(ctx, b, C, ld);
     if (st != TN_OK) return st;
+    hipError_t e;
+    if (b->streamed) {
+        ProfScope ps(ctx, TN_K_BATCH);
+        e = launch_direct(b, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        return TN_OK;
+    }
     st = capture_graph(b);
     if (st != TN_OK) return st;
-    hipError_t e;
     {
         ProfScope ps(ctx, TN_K_BATCH);
         e = hipGraphLaunch(b->exec, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return TN_OK;
+}
+
+void batch_slice_log2(const tn_batch *b, std::vector<uint32_t> &lw) { lw = b->lw; }
+
+void batch_set_persist(tn_batch *b, uint32_t *const *persist, unsigned int *done_count) {
+    b->persist.assign(persist, persist + b->B);
+    b->done_count = done_count;
+    for (int32_t i = 0; i < b->B; ++i)
+        b->h_nets[i].persist = b->h_nets[i].sat ? persist[i] : nullptr;
+    b->last_C.clear();  // the next execution uploads the descriptors
 }
 
 void batch_destroy(tn_batch *b) {

@@ -73,10 +73,11 @@ struct Sat {
 // of a level in turn; the next level's first items are prefetched into
 // registers; level boundaries come from an LDS window refilled every kWin
 // levels.
+// Returns the number of full rows after the last level it ran (SAT).
 template <int U, bool SAT, class Rows>
-__device__ void run_levels(const DevSchedule &s, const Rows rows, const Rows scr, uint32_t lw,
-                           bool ok, uint32_t *winp, uint32_t *wing, const Sat &sat,
-                           int32_t nfull) {
+__device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows scr, uint32_t lw,
+                              bool ok, uint32_t *winp, uint32_t *wing, const Sat &sat,
+                              int32_t nfull) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & ((1u << lw) - 1u);
     const uint32_t grp = tid >> lw;
@@ -98,11 +99,15 @@ __device__ void run_levels(const DevSchedule &s, const Rows rows, const Rows scr
         const uint32_t idx = p0 + grp + k * ngrp;
         cur[k] = idx < p1 ? s.pairs[idx] : make_uint2(0xffffffffu, 0u);
     }
+    bool stopped = false;
     for (uint32_t l = 0; l < L; ++l) {
         if (SAT) {
             // every thread adds the same settled deltas: a uniform decision
             if (l > 0) nfull += sat.delta[(l - 1) % 3];
-            if (nfull == (int32_t)s.n) break;
+            if (nfull == (int32_t)s.n) {
+                stopped = true;
+                break;
+            }
             if (tid == 0) sat.delta[(l + 1) % 3] = 0;
         }
         if (l % kWin == 0 && l > 0) {
@@ -200,11 +205,14 @@ __device__ void run_levels(const DevSchedule &s, const Rows rows, const Rows scr
         p1 = p2;
         g0 = g1;
     }
+    // the last level's delta settled at the loop's final barrier
+    if (SAT && !stopped && L > 0) nfull += sat.delta[(L - 1) % 3];
+    return nfull;
 }
 
 template <int U, bool SAT>
 __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint32_t *winp,
-                         uint32_t *wing, int32_t *fdelta) {
+                         uint32_t *wing, int32_t *fdelta, unsigned int *done_count) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lw = nd.lw;
     const uint32_t w = 1u << lw;
@@ -212,7 +220,10 @@ __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint
     const uint32_t word0 = slice << lw;
     const size_t ld = (size_t)nd.ld;
     const uint32_t lane = tid & (w - 1u);
-    // saturation state; the bitmap is cleared before the first barrier
+    // saturation state; the bitmap is set up before the first barrier
+    const uint32_t rwords = (n + 31) / 32;
+    uint32_t *pst = (SAT && nd.persist) ? nd.persist + (size_t)slice * (rwords + 2) : nullptr;
+    if (pst && pst[0]) return;  // this slice is all ones already (uniform)
     Sat sat;
     int32_t nfull = 0;
     if (SAT) {
@@ -229,21 +240,31 @@ __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint
         const uint32_t c0 = word0 * 64u;
         const bool single = c0 + 1 == n;
         nfull = single ? 1 : 0;
-        for (uint32_t i = tid; i < (n + 31) / 32; i += blockDim.x)
-            sat.bits[i] = (single && i == (c0 >> 5)) ? (1u << (c0 & 31u)) : 0u;
+        if (pst) {
+            nfull = (int32_t)pst[1];
+            if (single && !((pst[2 + (c0 >> 5)] >> (c0 & 31u)) & 1u)) ++nfull;
+        }
+        for (uint32_t i = tid; i < rwords; i += blockDim.x) {
+            uint32_t v = pst ? pst[2 + i] : 0u;
+            if (single && i == (c0 >> 5)) v |= 1u << (c0 & 31u);
+            sat.bits[i] = v;
+        }
         if (tid < 3) fdelta[tid] = 0;
     }
     if (nd.mode == kTileLds) {
-        // identity on the slice, in LDS
+        // identity on the slice in LDS, or the slice as earlier chunks left it
         const uint32_t total = n << lw;
         for (uint32_t i = tid; i < total; i += blockDim.x) {
             const uint32_t r = i >> lw, word = word0 + (i & (w - 1u));
-            smem[i] = (word == (r >> 6)) ? (1ull << (r & 63u)) : 0ull;
+            if (nd.resume)
+                smem[i] = word < nd.nwords ? nd.C[(size_t)r * ld + word] : 0ull;
+            else
+                smem[i] = (word == (r >> 6)) ? (1ull << (r & 63u)) : 0ull;
         }
         __syncthreads();
         LdsRows rows{smem, lw};
         LdsRows scr{smem + total, lw};
-        run_levels<U, SAT>(nd.s, rows, scr, lw, true, winp, wing, sat, nfull);
+        nfull = run_levels<U, SAT>(nd.s, rows, scr, lw, true, winp, wing, sat, nfull);
         // write the slice back (the level loop ended with a barrier)
         for (uint32_t i = tid; i < total; i += blockDim.x) {
             const uint32_t r = i >> lw, word = word0 + (i & (w - 1u));
@@ -251,15 +272,26 @@ __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint
         }
     } else {
         const bool ok = word0 + lane < nd.nwords;
-        for (uint32_t r = tid >> lw; r < n; r += blockDim.x >> lw)
-            if (ok) {
-                const uint32_t word = word0 + lane;
-                nd.C[(size_t)r * ld + word] = (word == (r >> 6)) ? (1ull << (r & 63u)) : 0ull;
-            }
+        if (!nd.resume)
+            for (uint32_t r = tid >> lw; r < n; r += blockDim.x >> lw)
+                if (ok) {
+                    const uint32_t word = word0 + lane;
+                    nd.C[(size_t)r * ld + word] = (word == (r >> 6)) ? (1ull << (r & 63u)) : 0ull;
+                }
         __syncthreads();
         GlobalRows rows{nd.C, ld, word0};
         GlobalRows scr{nd.gscratch, (size_t)nd.nwords, word0};
-        run_levels<U, SAT>(nd.s, rows, scr, lw, ok, winp, wing, sat, nfull);
+        nfull = run_levels<U, SAT>(nd.s, rows, scr, lw, ok, winp, wing, sat, nfull);
+    }
+    if (pst) {
+        for (uint32_t i = tid; i < rwords; i += blockDim.x) pst[2 + i] = sat.bits[i];
+        if (tid == 0) {
+            pst[1] = (uint32_t)nfull;
+            if (nfull == (int32_t)n) {
+                pst[0] = 1u;
+                atomicAdd(done_count, 1u);
+            }
+        }
     }
     // padding words past the last word column are zero
     if (word0 + w >= nd.nwords && (size_t)nd.nwords < ld) {
@@ -273,7 +305,8 @@ __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint
 template <int U>
 __global__ void __launch_bounds__(1024)
 k_batch_persistent(const NetDesc *__restrict__ nets, const uint2 *__restrict__ tiles,
-                   const uint32_t *__restrict__ qptr, uint32_t *__restrict__ counters) {
+                   const uint32_t *__restrict__ qptr, uint32_t *__restrict__ counters,
+                   unsigned int *__restrict__ done_count) {
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t winp[2 * kWin], wing[2 * kWin];
     __shared__ uint32_t sh_tile;
@@ -290,8 +323,8 @@ k_batch_persistent(const NetDesc *__restrict__ nets, const uint2 *__restrict__ t
             if (t >= qn) break;
             const uint2 tile = tiles[q0 + t];
             const NetDesc &nd = nets[tile.x];
-            if (nd.sat) run_tile<U, true>(nd, tile.y, smem, winp, wing, fdelta);
-            else run_tile<U, false>(nd, tile.y, smem, winp, wing, fdelta);
+            if (nd.sat) run_tile<U, true>(nd, tile.y, smem, winp, wing, fdelta, done_count);
+            else run_tile<U, false>(nd, tile.y, smem, winp, wing, fdelta, done_count);
         }
     }
 }
@@ -314,12 +347,12 @@ hipError_t batch_occupancy(int threads, size_t dyn_lds, int *blocks_per_cu) {
 
 hipError_t launch_batch(const NetDesc *nets, const uint2 *tiles, const uint32_t *qptr,
                         uint32_t *counters, uint32_t grid, uint32_t threads, size_t dyn_lds,
-                        hipStream_t st) {
+                        unsigned int *done_count, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counters, 8u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_persistent<4>, dim3(grid), dim3(threads), dyn_lds, st, nets, tiles,
-                       qptr, counters);
+                       qptr, counters, done_count);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // C ABI of network hashing (Sec. 4.1) and fusion (Sec. 4.2).
 #include <algorithm>
+#include <chrono>
 #include <vector>
 
 #include "tn_batch.h"
@@ -56,6 +57,149 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *s
     for (uint32_t j = 0; j < H; ++j) maps[j] = hb.data() + (size_t)j * n;
     return batch_create(ctx, (int32_t)H, ns.data(), ms.data(), ss.data(), ds.data(), ts.data(),
                         flags, proxies, maps.data(), n);
+}
+
+// Streamed build of the H proxies (Sec. 4.3: the hashed networks are
+// independent and built in parallel; Sec. 3.4: each is a reverse-time
+// stream).  The event list is cut into chunks of whole time steps from its
+// end; for each chunk the H mapped sub-streams are planned on host threads
+// and applied in one batched launch that resumes from the proxies in HBM.
+// Every tile carries its saturation state from chunk to chunk, and the
+// build stops once every tile of every proxy is all ones.
+tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
+                                const uint32_t *dst, const int64_t *t, uint32_t flags,
+                                uint32_t H, uint32_t K, const uint64_t *coeffs, int32_t order,
+                                uint32_t *bucket, int32_t *count, uint64_t *P, int64_t ldK,
+                                int64_t chunk_events, tn_stream_stats *stats) {
+    using namespace tn;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    if (n == 0 || H == 0 || K == 0 || order < 1) return fail(TN_E_ARG, "n, H, K and order must be > 0");
+    if (K > 65536) return fail(TN_E_UNSUPPORTED, "K must be <= 65536");
+    if (!coeffs || !bucket || !count || !P) return fail(TN_E_ARG, "null coefficient or output array");
+    if (ldK < (int64_t)((K + 63) / 64)) return fail(TN_E_ARG, "ldK must be >= ceil(K/64)");
+    if (chunk_events < 0) return fail(TN_E_ARG, "chunk_events must be >= 0");
+    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL)) return fail(TN_E_ARG, "unknown flag bits");
+    for (size_t i = 0; i < (size_t)H * 3 * order; ++i)
+        if (coeffs[i] >= kP61) return fail(TN_E_ARG, "hash coefficients must be < 2^61 - 1");
+    if (m < 0 || (m > 0 && (!src || !dst || !t))) return fail(TN_E_ARG, "bad event arrays");
+    if (m >= (int64_t)0xffffffffLL) return fail(TN_E_UNSUPPORTED, "m must be < 2^32 - 1");
+    {
+        std::string err;
+        tn_status st = validate_events(n, m, src, dst, t, err);
+        if (st != TN_OK) return fail(st, err);
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    const size_t cbytes = sizeof(uint64_t) * H * 3 * order;
+    tn_status st = ensure_scratch(ctx, cbytes);
+    if (st != TN_OK) return st;
+    hipError_t e = hipMemcpyAsync(ctx->scratch, coeffs, cbytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "coefficient upload");
+    {
+        ProfScope ps(ctx, TN_K_HASH);
+        e = launch_hash_buckets(n, H, (const uint64_t *)ctx->scratch, order, K, bucket, count,
+                                ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "hash kernel launch");
+    std::vector<uint32_t> hb((size_t)H * n);
+    e = hipMemcpyAsync(hb.data(), bucket, sizeof(uint32_t) * hb.size(), hipMemcpyDeviceToHost,
+                       ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "bucket download");
+    if (chunk_events == 0) chunk_events = std::max<int64_t>(1 << 18, (m + 63) / 64);
+    std::vector<std::pair<int64_t, int64_t>> bounds;
+    stream_chunks(m, t, chunk_events, flags & TN_TIES_SEQUENTIAL, bounds);
+    if (bounds.empty()) bounds.emplace_back(0, 0);  // no events: identity proxies
+    std::vector<uint32_t> ns(H, K);
+    std::vector<const uint32_t *> maps(H);
+    std::vector<uint64_t *> Cs(H);
+    std::vector<int64_t> lds(H, ldK);
+    for (uint32_t j = 0; j < H; ++j) {
+        maps[j] = hb.data() + (size_t)j * n;
+        Cs[j] = P + (size_t)j * K * ldK;
+    }
+    std::vector<uint32_t> lw;
+    std::vector<uint32_t *> pst(H, nullptr);
+    uint32_t *state = nullptr;
+    unsigned int *done_host = nullptr;
+    unsigned int *done_dev = nullptr;
+    uint64_t tiles = 0;
+    int64_t launched = 0, run_events = 0, levels = 0;
+    bool all_done = false;
+    e = hipHostMalloc((void **)&done_host, sizeof(unsigned int), 0);
+    if (e != hipSuccess) return hip_fail(e, "pinned counter");
+    *done_host = 0;
+    for (size_t c = 0; c < bounds.size() && st == TN_OK; ++c) {
+        const int64_t a = bounds[c].first, mc = bounds[c].second - bounds[c].first;
+        std::vector<int64_t> ms(H, mc);
+        std::vector<const uint32_t *> ss(H, src ? src + a : nullptr), ds(H, dst ? dst + a : nullptr);
+        std::vector<const int64_t *> ts(H, t ? t + a : nullptr);
+        BatchStream bs;
+        bs.lw = c ? lw.data() : nullptr;
+        bs.persist = c ? pst.data() : nullptr;
+        bs.resume = c ? 1u : 0u;
+        bs.done_count = done_dev;
+        tn_batch *b = nullptr;
+        st = batch_create(ctx, (int32_t)H, ns.data(), ms.data(), ss.data(), ds.data(), ts.data(),
+                          flags, &b, maps.data(), n, &bs);
+        if (st != TN_OK) break;
+        if (c == 0) {
+            // slice state of every tile of every proxy, then the done counter
+            batch_slice_log2(b, lw);
+            std::vector<size_t> off(H + 1, 0);
+            for (uint32_t j = 0; j < H; ++j) {
+                off[j + 1] = off[j] + batch_persist_words(K, lw[j]);
+                tiles += (((K + 63) / 64) + (1u << lw[j]) - 1) >> lw[j];
+            }
+            e = hipMalloc((void **)&state, sizeof(uint32_t) * (off[H] + 1));
+            if (e != hipSuccess) {
+                batch_destroy(b);
+                st = fail(TN_E_NOMEM, "slice state allocation failed");
+                break;
+            }
+            for (uint32_t j = 0; j < H; ++j) pst[j] = state + off[j];
+            done_dev = state + off[H];
+            e = launch_fill_u32(state, off[H] + 1, 0u, ctx->stream);
+            if (e != hipSuccess) {
+                batch_destroy(b);
+                st = hip_fail(e, "slice state clear");
+                break;
+            }
+            batch_set_persist(b, pst.data(), done_dev);
+        }
+        st = batch_execute(ctx, b, Cs.data(), lds.data());
+        if (st == TN_OK) {
+            e = hipMemcpyAsync(done_host, done_dev, sizeof(unsigned int), hipMemcpyDeviceToHost,
+                               ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) st = hip_fail(e, "chunk completion");
+        }
+        std::vector<tn_plan_stats> bstats(H);
+        (void)tn_batch_get_stats(b, bstats.data(), nullptr, nullptr);
+        for (const auto &x : bstats) levels += x.levels;
+        batch_destroy(b);
+        if (st != TN_OK) break;
+        ++launched;
+        run_events += mc;
+        if (ctx->saturation && *done_host == tiles) {
+            all_done = true;
+            break;
+        }
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    if (state) (void)hipFree(state);
+    (void)hipHostFree(done_host);
+    if (stats) {
+        stats->chunks = (int64_t)bounds.size();
+        stats->chunks_run = launched;
+        stats->events_run = run_events;
+        stats->levels_run = levels;
+        stats->saturated = all_done ? 1 : 0;
+        stats->slice_words = lw.empty() ? 0 : (int32_t)(1u << lw[0]);
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
 }
 
 tn_status tn_recombine(tn_ctx *ctx, uint32_t n, uint32_t H, uint32_t K, const uint64_t *P,

@@ -209,6 +209,14 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
 inline size_t rowor_persist_words(uint32_t n, uint32_t slice_words) {
     return (size_t)rowor_workgroups(n, slice_words) * (((size_t)n + 31) / 32 + 2);
 }
+// ids < n and non-decreasing t for every event, checked on several host
+// threads; the message names the first offending event (tn_stream.cpp)
+tn_status validate_events(uint32_t n, int64_t m, const uint32_t *src, const uint32_t *dst,
+                          const int64_t *t, std::string &err);
+// chunks of a time-ordered list taken from its end: [a, b) pairs, each of
+// about `chunk` events and of whole time steps unless `sequential`
+void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, bool sequential,
+                   std::vector<std::pair<int64_t, int64_t>> &out);
 // streamed one-shot build (tn_stream.cpp)
 tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
                          const uint32_t *dst, const int64_t *t, uint32_t flags, uint64_t *C,

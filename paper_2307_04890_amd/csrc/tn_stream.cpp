@@ -51,10 +51,13 @@ struct Slot {
 
 constexpr int kRing = 4;
 
+}  // namespace
+
 // Validates every event (ids < n, non-decreasing t) on several threads and
 // reports the first offending event, as the single-threaded check would.
 tn_status validate_events(uint32_t n, int64_t m, const uint32_t *src, const uint32_t *dst,
                           const int64_t *t, std::string &err) {
+    if (m <= 0) return TN_OK;
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(hw, m / (1 << 20)));
     std::vector<int64_t> bad_id(parts, -1), bad_order(parts, -1);
@@ -88,7 +91,17 @@ tn_status validate_events(uint32_t n, int64_t m, const uint32_t *src, const uint
     return TN_OK;
 }
 
-}  // namespace
+void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, bool sequential,
+                   std::vector<std::pair<int64_t, int64_t>> &out) {
+    out.clear();
+    for (int64_t b = m; b > 0;) {
+        int64_t a = std::max<int64_t>(0, b - chunk);
+        if (!sequential)
+            while (a > 0 && t[a - 1] == t[a]) --a;
+        out.emplace_back(a, b);
+        b = a;
+    }
+}
 
 tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
                          const uint32_t *dst, const int64_t *t, uint32_t flags, uint64_t *C,
@@ -113,16 +126,14 @@ tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
     const bool seq = flags & TN_TIES_SEQUENTIAL;
     if (chunk_events == 0) chunk_events = std::max<int64_t>(1 << 18, (m + 63) / 64);
     // chunk boundaries from the end of the list, on time-step boundaries
+    std::vector<std::pair<int64_t, int64_t>> bounds;
+    stream_chunks(m, t, chunk_events, seq, bounds);
     std::vector<std::unique_ptr<Chunk>> chunks;
-    for (int64_t b = m; b > 0;) {
-        int64_t a = std::max<int64_t>(0, b - chunk_events);
-        if (!seq)
-            while (a > 0 && t[a - 1] == t[a]) --a;
+    for (const auto &ab : bounds) {
         auto c = std::make_unique<Chunk>();
-        c->a = a;
-        c->b = b;
+        c->a = ab.first;
+        c->b = ab.second;
         chunks.push_back(std::move(c));
-        b = a;
     }
     const int64_t nch = (int64_t)chunks.size();
 

@@ -116,3 +116,35 @@ def test_hash_errors():
     with pytest.raises(tn.TNError) as e:
         tn.hash_compress(10, [0], [1], [0], bad, 8)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2])
+def test_streamed_proxies_equal_the_batched_proxies(flags):
+    # the streamed build (chunks, resume from the proxies in HBM, stop once
+    # every tile is full) against the one-launch batch and the oracle
+    cases = [(2000, 8000, 4, 64, 2000, 500), (3000, 60000, 3, 100, 6000, 4096),
+             (1500, 5000, 2, 4096, 800, 700), (500, 0, 2, 50, 1, 0)]
+    for case, (n, m, H, K, Tm, chunk) in enumerate(cases):
+        s, d, t = T.random_tiny(n, max(m, 1), max(Tm, 1), seed=400 + case)
+        s, d, t = s[:m], d[:m], t[:m]
+        A = T.hash_coefficients(H, seed=40 + case)
+        bucket, count, P, st = tn.hash_build_proxies(n, s, d, t, A, K, flags=flags,
+                                                     chunk_events=chunk)
+        wb = oracle.hash_nodes(n, A, K)
+        assert (bucket.cpu().numpy().view(np.uint32) == wb).all()
+        WP = oracle.proxies(K, s, d, t, wb, directed=bool(flags & 1), sequential=bool(flags & 2))
+        assert (host(P) == WP).all(), case
+        assert st["chunks_run"] <= st["chunks"]
+        if case == 1 and flags == 0:
+            assert st["saturated"] == 1 and st["chunks_run"] < st["chunks"]
+
+
+def test_streamed_proxies_at_the_scaled_hashed_workload():
+    n, m, H, K = 200_000, 5_000_000, 16, 4096
+    s, d, t = T.activity_driven(n, m, 500_000, seed=3)
+    A = T.hash_coefficients(H, seed=1003)
+    bucket, count, P, st = tn.hash_build_proxies(n, s, d, t, A, K)
+    wb = oracle.hash_nodes(n, A, K)
+    for j in (0, 9):
+        assert (host(P[j]) == oracle.reverse_matrix(K, wb[j][s], wb[j][d], t)).all(), j
+    assert st["saturated"] == 1 and st["events_run"] < m
