@@ -292,6 +292,21 @@ def run_hashed(args):
                    "autotune_and_capture_s": tune_wall, "tiles": tiles, "lds_tiles": lds_tiles,
                    "mean_estimate": float(est.float().mean().item())}
     r["kernels_ms"] = kms
+    # the whole job from host events: hashing, the streamed proxy build
+    # (chunks planned on host threads, stop once every tile is full), fusion
+    P2 = torch.empty_like(P)
+    ee = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b2, c2, P2, sst = tn.hash_build_proxies(n, s, d, t, A, K, P=P2)
+        est2, _ = tn.recombine(P2, b2, c2, n)
+        torch.cuda.synchronize()
+        ee.append(time.perf_counter() - t0)
+    assert torch.equal(P2, P) and torch.equal(est2, est), "streamed proxies differ"
+    r["end_to_end"] = {"events_per_s": m / min(ee), "seconds": min(ee), "seconds_all": ee,
+                       "what": "host events -> hash -> streamed proxy build -> fusion",
+                       "stream": sst}
     if not args.no_cpu_baseline:
         import oracle
         log("[bench] timing the CPU oracle on one proxy column slice")
