@@ -531,14 +531,15 @@ def _read_csv(path):
         return list(csv.DictReader(f))
 
 
-def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, last=0):
+def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, last=0,
+                  match=None):
     """HBM bytes per launch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB per
     dispatch, one --pmc run each), each scaled by what the same counter read
     for the plain device copy of calib_mib MiB in the same run.  last > 0
     keeps only the kernel's last `last` dispatches (the timed ones, after
     autotuning)."""
-    match = {"rowor": "k_rowor_global", "batch": "k_batch_persistent",
-             "recombine": "k_recombine_est"}[kernel]
+    match = match or {"rowor": "k_rowor_global", "batch": "k_batch_persistent",
+                      "recombine": "k_recombine_est"}[kernel]
     out = {"kernel": match, "workload": workload, "command": command,
            "kernel_source_sha": kernel_source_hash(KERNEL_SOURCES[kernel])}
     known_kib = calib_mib * 1024.0
@@ -582,11 +583,12 @@ def main():
         sp.add_argument("--command", required=True)
         sp.add_argument("--calib-mib", type=int, default=1024)
         sp.add_argument("--last", type=int, default=0)
+        sp.add_argument("--match", default=None, help="kernel name substring")
         sp.add_argument("--out", required=True)
         a = sp.parse_args(sys.argv[2:])
         if what == "--summarize-pmc":
             rec = summarize_pmc(a.fetch, a.write, a.kernel, a.workload, a.command, a.calib_mib,
-                                a.last)
+                                a.last, a.match)
             with open(a.out, "w") as f:
                 json.dump(rec, f, indent=1)
         else:

@@ -248,7 +248,10 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
     if ((threadIdx.x & 63u) == 0 && v) atomicAdd(ctr, v);
 }
 
-template <int SW, int UC, bool SAT>
+// CHUNK: one launch per chunk of a streamed build, with the slice state in
+// `persist` (a separate instantiation, so traces and counters keep the two
+// kinds of launch apart).
+template <int SW, int UC, bool SAT, bool CHUNK>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
                uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
@@ -300,7 +303,7 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     const uint32_t c0 = slice * SW * 64u;
     const bool single = c0 + 1 == n;
     const uint32_t rwords = sbase / 32;  // words of real-row bits
-    uint32_t *pst = (SAT && persist) ? persist + (size_t)slice * (rwords + 2) : nullptr;
+    uint32_t *pst = (SAT && CHUNK) ? persist + (size_t)slice * (rwords + 2) : nullptr;
     int32_t nfull = single ? 1 : 0;
     if (SAT) {
         if (pst) {
@@ -490,15 +493,15 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
     const uint64_t sbits = (uint64_t)sbase + scratch_rows + 1;
     const size_t lds = (size_t)((sbits + 31) / 32) * 4;
     if (saturation && lds <= kRoworSatLds) {
-        auto k = k_rowor_global<SW, UC, true>;
+        auto k = persist ? k_rowor_global<SW, UC, true, true> : k_rowor_global<SW, UC, true, false>;
         hipError_t e = hipFuncSetAttribute((const void *)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, n, nwords, s, scratch,
                            sbase, (uint32_t)sbits, traffic, persist, done_count);
     } else {
-        hipLaunchKernelGGL((k_rowor_global<SW, UC, false>), dim3(slices), dim3(1024), 0, st, C,
-                           ld, n, nwords, s, scratch, 0u, 1u, traffic, (uint32_t *)nullptr,
+        hipLaunchKernelGGL((k_rowor_global<SW, UC, false, false>), dim3(slices), dim3(1024), 0,
+                           st, C, ld, n, nwords, s, scratch, 0u, 1u, traffic, (uint32_t *)nullptr,
                            (unsigned int *)nullptr);
     }
     return hipGetLastError();
