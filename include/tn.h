@@ -62,8 +62,13 @@ enum {
 enum {
     TN_DIRECTED = 1u,        /* event (u, v, t) carries information u -> v only
                                 (the non-mutual sharing of the footnote in Sec. 3) */
-    TN_TIES_SEQUENTIAL = 2u  /* list order is strict time order: Algorithm 1 read
+    TN_TIES_SEQUENTIAL = 2u, /* list order is strict time order: Algorithm 1 read
                                 literally, events at one time step chain          */
+    TN_FORWARD = 4u          /* Algorithm 1 in time order (Sec. 3.1): row x of the
+                                result is x's in-component (the nodes that can
+                                reach x) instead of its out-component; the result
+                                is the transpose of the reverse-time one
+                                (Sec. 3.4).  Not valid for hashing.            */
 };
 
 typedef struct tn_ctx tn_ctx;     /* device, stream, scratch, autotune cache   */
@@ -121,7 +126,8 @@ int32_t tn_profile_take(tn_ctx *ctx, int32_t *ids, float *ms, int32_t cap);
  * access of every row it writes, so the ops of one level are independent;
  * levels hold at most 1024 ops.  The schedule is copied to the device
  * (synchronously) and kept in the plan.
- * src, dst, t: HOST, m entries.  flags: TN_DIRECTED | TN_TIES_SEQUENTIAL.
+ * src, dst, t: HOST, m entries.  flags: TN_DIRECTED | TN_TIES_SEQUENTIAL |
+ * TN_FORWARD (the stream then runs in time order).
  * Errors: TN_E_ARG (n == 0, null arrays with m > 0, bad flags),
  * TN_E_RANGE, TN_E_ORDER, TN_E_UNSUPPORTED (m >= 2^32 or n >= 2^31). */
 tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m,
@@ -238,6 +244,36 @@ tn_status tn_build_component_matrix_streamed(tn_ctx *ctx, uint32_t n, int64_t m,
                                              uint64_t *C, int64_t ld,
                                              int64_t chunk_events,
                                              tn_stream_stats *stats);
+
+/* Online insertion (Sec. 3.5: the matrix algorithm takes new events, and new
+ * nodes as new identity rows, without recomputation).  tn_online_create
+ * writes C <- I (n rows; a node joins with its first event) and keeps the
+ * stream state of C: its column slices' saturation bits and a launch ring.
+ * Each tn_online_insert applies a batch of events to C as the next part of
+ * one stream, chunked and planned as in tn_build_component_matrix_streamed.
+ * With TN_FORWARD the stream runs in time order: every batch must be later
+ * than all events applied so far, and C's rows are in-components (Algorithm
+ * 1 as printed).  Without it the stream runs in reverse time: every batch
+ * must be earlier than all applied, and rows are out-components.  Events of
+ * one time step form one snapshot and must come in one batch (with
+ * TN_TIES_SEQUENTIAL a batch may continue the last time step).  Once every
+ * row is all ones, further batches change nothing and are skipped.
+ * C: DEVICE, n x ld, caller-owned, must outlive the state; it is complete
+ * once the context's stream reaches the work an insert enqueued (tn_sync).
+ * Event arrays: HOST, read during the call only.  stats (HOST, may be NULL)
+ * describe the batch.  Errors: TN_E_ARG (bad sizes, flags, ld, or a state
+ * of another context), TN_E_RANGE, TN_E_ORDER (times within the batch, or
+ * against those applied); nothing is enqueued when a check fails. */
+typedef struct tn_online tn_online;
+tn_status tn_online_create(tn_ctx *ctx, uint32_t n, uint32_t flags,
+                           uint64_t *C, int64_t ld, tn_online **out);
+tn_status tn_online_insert(tn_ctx *ctx, tn_online *online, int64_t m,
+                           const uint32_t *src, const uint32_t *dst,
+                           const int64_t *t, int64_t chunk_events,
+                           tn_stream_stats *stats);
+/* Waits for the context's stream and frees the state (not C).  NULL is
+ * ignored. */
+void tn_online_destroy(tn_online *online);
 
 /* Component sizes (Sec. 3.1, Eq. 1): out_sizes[u] = ones in row u (the
  * maximum out-component size of u), in_sizes[w] = ones in column w (the

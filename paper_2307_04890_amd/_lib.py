@@ -14,6 +14,7 @@ STATUS = {
 }
 DIRECTED = 1
 TIES_SEQUENTIAL = 2
+FORWARD = 4
 KERNELS = {1: "identity", 2: "rowor", 3: "out_sizes", 4: "in_sizes", 5: "batch",
            6: "hash", 7: "recombine", 8: "mlp_forward", 9: "mlp_backward", 10: "mlp_adam",
            11: "aux"}
@@ -87,6 +88,9 @@ SIGNATURES = {
     "tn_schedule_op_arrays": (_i32, [_P, _PP, _PP]),
     "tn_plan_execute": (_i32, [_P, _P, _P, _i64, _u32]),
     "tn_set_saturation": (_i32, [_P, ctypes.c_int]),
+    "tn_online_create": (_i32, [_P, _u32, _u32, _P, _i64, _PP]),
+    "tn_online_insert": (_i32, [_P, _P, _i64, _P, _P, _P, _i64, ctypes.POINTER(StreamStats)]),
+    "tn_online_destroy": (None, [_P]),
     "tn_plan_last_traffic": (_i32, [_P, _P]),
     "tn_build_component_matrix": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _P, _i64]),
     "tn_build_component_matrix_streamed": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _P, _i64,

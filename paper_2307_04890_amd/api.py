@@ -8,9 +8,11 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import DIRECTED, KERNELS, TIES_SEQUENTIAL, PlanStats, StreamStats, TNError, check, lib
+from ._lib import (DIRECTED, FORWARD, KERNELS, TIES_SEQUENTIAL, PlanStats, StreamStats, TNError,
+                   check, lib)
 
-__all__ = ["Context", "Plan", "build_component_matrix_streamed", "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+__all__ = ["Context", "Plan", "Online", "FORWARD", "build_component_matrix_streamed",
+           "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
 
@@ -185,6 +187,41 @@ def build_component_matrix_streamed(n: int, src, dst, t, flags: int = 0,
                                                  C.stride(0), int(chunk_events),
                                                  ctypes.byref(st)))
     return C, st.as_dict()
+
+
+class Online:
+    """A live component matrix that takes batches of events (tn_online_*).
+    With FORWARD in flags the batches come in time order and rows are
+    in-components; otherwise they come in reverse time order and rows are
+    out-components."""
+
+    def __init__(self, n: int, flags: int = 0, C: torch.Tensor | None = None,
+                 ctx: Context | None = None):
+        self.ctx = ctx or get_context()
+        self.n = int(n)
+        self.C = C if C is not None else alloc_matrix(self.n, device=self.ctx.device)
+        h = ctypes.c_void_p()
+        check(lib.tn_online_create(self.ctx.bind_stream(), self.n, int(flags), _dp(self.C),
+                                   self.C.stride(0), ctypes.byref(h)))
+        self.h = h
+
+    def insert(self, src, dst, t, chunk_events: int = 0) -> dict:
+        src, dst, t = _events(src, dst, t)
+        st = StreamStats()
+        check(lib.tn_online_insert(self.ctx.bind_stream(), self.h, src.shape[0], _hp(src),
+                                   _hp(dst), _hp(t), int(chunk_events), ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tn_online_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def component_sizes(C: torch.Tensor, n: int, out: bool = True, inn: bool = True,

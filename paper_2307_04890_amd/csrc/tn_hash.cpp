@@ -27,6 +27,7 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *s
     for (size_t i = 0; i < (size_t)H * 3 * order; ++i)
         if (coeffs[i] >= kP61) return fail(TN_E_ARG, "hash coefficients must be < 2^61 - 1");
     if (m < 0 || (m > 0 && (!src || !dst || !t))) return fail(TN_E_ARG, "bad event arrays");
+    if (flags & TN_FORWARD) return fail(TN_E_ARG, "hashing takes no TN_FORWARD");
     for (int64_t e = 0; e < m; ++e) {
         if (src[e] >= n || dst[e] >= n) return fail(TN_E_RANGE, "event " + std::to_string(e) + " has a node id >= n");
         if (e > 0 && t[e] < t[e - 1]) return fail(TN_E_ORDER, "event " + std::to_string(e) + " is earlier than its predecessor");
@@ -79,7 +80,8 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     if (!coeffs || !bucket || !count || !P) return fail(TN_E_ARG, "null coefficient or output array");
     if (ldK < (int64_t)((K + 63) / 64)) return fail(TN_E_ARG, "ldK must be >= ceil(K/64)");
     if (chunk_events < 0) return fail(TN_E_ARG, "chunk_events must be >= 0");
-    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL)) return fail(TN_E_ARG, "unknown flag bits");
+    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL))
+        return fail(TN_E_ARG, "unknown flag bits (hashing takes TN_DIRECTED | TN_TIES_SEQUENTIAL)");
     for (size_t i = 0; i < (size_t)H * 3 * order; ++i)
         if (coeffs[i] >= kP61) return fail(TN_E_ARG, "hash coefficients must be < 2^61 - 1");
     if (m < 0 || (m > 0 && (!src || !dst || !t))) return fail(TN_E_ARG, "bad event arrays");

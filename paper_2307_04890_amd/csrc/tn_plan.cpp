@@ -381,7 +381,7 @@ tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
     if (n == 0) { err = "n must be > 0"; return TN_E_ARG; }
     if (m < 0) { err = "m must be >= 0"; return TN_E_ARG; }
     if (m > 0 && (!src || !dst || !t)) { err = "null event array"; return TN_E_ARG; }
-    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL)) { err = "unknown flag bits"; return TN_E_ARG; }
+    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL | TN_FORWARD)) { err = "unknown flag bits"; return TN_E_ARG; }
     if (n > kNodeMask) { err = "n must be < 2^31"; return TN_E_UNSUPPORTED; }
     if (m >= (int64_t)0xffffffffLL) { err = "m must be < 2^32 - 1"; return TN_E_UNSUPPORTED; }
     const uint32_t id_limit = map ? n_src : n;
@@ -406,7 +406,23 @@ tn_status plan_events(uint32_t n, int64_t m, const uint32_t *src,
     out.n = n;
     out.m = m;
     out.flags = flags;
+    // Reverse time: time steps from the last, an event (u, v) brings v's row
+    // into u's.  Forward time (Algorithm 1 as printed): time steps from the
+    // first, and (u, v) brings u's row into v's, i.e. the reverse-time rule
+    // applied to (v, u).
+    const bool forward = flags & TN_FORWARD;
     auto walk = [&](Planner &pl) {
+        if (forward) {
+            int64_t a = 0;
+            while (a < m) {
+                int64_t b = a + 1;
+                if (!seq)
+                    while (b < m && t[b] == t[a]) ++b;
+                pl.group(dst, src, map, a, b);
+                a = b;
+            }
+            return;
+        }
         int64_t b = m;
         while (b > 0) {
             int64_t a = b - 1;

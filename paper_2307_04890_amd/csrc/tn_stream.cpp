@@ -1,17 +1,25 @@
-// Streamed one-shot build of the exact component matrix.
+// Streamed builds of the component matrix: the one-shot call and online
+// insertion.
 //
-// The reverse-time recurrence (Sec. 3.4) consumes the event list from its
-// end.  The list is cut into chunks of whole time steps; chunk 0 holds the
-// latest events.  Each chunk is planned on its own (levels start at 1; its
-// compound scratch rows live inside it), so host threads plan several chunks
-// at once, while the device runs the chunks strictly in order on the same
-// matrix.  Rows only gain bits in reverse time, so once every row of a
-// column slice is all ones nothing earlier in time can change that slice:
-// the row-OR kernel carries each slice's saturation bits from one chunk to
-// the next, a slice that is full returns at once, and the host stops
-// planning and launching as soon as every slice is full.  A chunk launched
-// after the last slice saturated only checks a flag, so the host polls the
-// device's done counter without ever waiting for it.
+// Algorithm 1 is a stream (Sec. 3.1): reverse time consumes the event list
+// from its end (Sec. 3.4), forward time from its start.  A matrix that
+// receives a stream keeps a device state (StreamState): the matrix itself,
+// each column slice's saturation bits and full-row count, and a ring of
+// launch buffers.  Events arrive in chunks of whole time steps.  Each chunk
+// is planned on its own (levels start at 1; compound scratch rows live inside
+// it), so host threads plan several chunks at once, while the device applies
+// them strictly in stream order.  Rows only gain bits, so once every row of
+// a column slice is all ones no further event can change that slice: the
+// row-OR kernel carries each slice's saturation state from one launch to the
+// next, a full slice returns at once, and the host stops planning and
+// launching once every slice is full.  A chunk launched after the last slice
+// saturated only checks a flag, so the host polls the device's done counter
+// without ever waiting for it.
+//
+// The one-shot build is one state fed the whole list.  Online insertion
+// (Sec. 3.5: new events and new nodes join a live matrix) keeps the state
+// between calls; a node enters with its first event, its identity row being
+// in place from the start.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -52,6 +60,21 @@ struct Slot {
 constexpr int kRing = 4;
 
 }  // namespace
+
+// Device state of one matrix that receives a stream chunk by chunk.
+struct StreamState {
+    uint32_t n = 0, flags = 0;
+    uint64_t *C = nullptr;
+    int64_t ld = 0;
+    uint32_t sw = 0, slices = 0;
+    uint32_t *persist = nullptr;  // per-slice state, then the done counter
+    unsigned int *done_count = nullptr;
+    Slot ring[kRing];
+    int64_t launches = 0;  // launches so far (ring position)
+    bool all_done = false;
+    bool has_time = false;
+    int64_t edge_t = 0;  // latest (forward) or earliest (reverse) time applied
+};
 
 // Validates every event (ids < n, non-decreasing t) on several threads and
 // reports the first offending event, as the single-threaded check would.
@@ -103,44 +126,30 @@ void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, bool sequential,
     }
 }
 
-tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
-                         const uint32_t *dst, const int64_t *t, uint32_t flags, uint64_t *C,
-                         int64_t ld, int64_t chunk_events, tn_stream_stats *stats) {
-    const auto t0 = std::chrono::steady_clock::now();
-    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
-    if (!C) return fail(TN_E_ARG, "C is NULL");
-    if (n == 0) return fail(TN_E_ARG, "n must be > 0");
-    if (m < 0) return fail(TN_E_ARG, "m must be >= 0");
-    if (m > 0 && (!src || !dst || !t)) return fail(TN_E_ARG, "null event array");
-    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL)) return fail(TN_E_ARG, "unknown flag bits");
-    if (n > kNodeMask) return fail(TN_E_UNSUPPORTED, "n must be < 2^31");
-    if (m >= (int64_t)0xffffffffLL) return fail(TN_E_UNSUPPORTED, "m must be < 2^32 - 1");
-    if (chunk_events < 0) return fail(TN_E_ARG, "chunk_events must be >= 0");
-    const int64_t nwords = (n + 63) / 64;
-    if (ld < nwords) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
-    {
-        std::string err;
-        tn_status st = validate_events(n, m, src, dst, t, err);
-        if (st != TN_OK) return fail(st, err);
-    }
-    const bool seq = flags & TN_TIES_SEQUENTIAL;
-    if (chunk_events == 0) chunk_events = std::max<int64_t>(1 << 18, (m + 63) / 64);
-    // chunk boundaries from the end of the list, on time-step boundaries
-    std::vector<std::pair<int64_t, int64_t>> bounds;
-    stream_chunks(m, t, chunk_events, seq, bounds);
-    std::vector<std::unique_ptr<Chunk>> chunks;
-    for (const auto &ab : bounds) {
-        auto c = std::make_unique<Chunk>();
-        c->a = ab.first;
-        c->b = ab.second;
-        chunks.push_back(std::move(c));
-    }
-    const int64_t nch = (int64_t)chunks.size();
+namespace {
 
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
-    const uint32_t sw = default_slice_words(n, ld);
-    const uint32_t slices = rowor_workgroups(n, sw);
+void state_release(tn_ctx *ctx, StreamState &s) {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (Slot &r : s.ring) {
+        if (r.dev) (void)hipFree(r.dev);
+        if (r.pinned) (void)hipHostFree(r.pinned);
+        if (r.done_host) (void)hipHostFree(r.done_host);
+        if (r.ev) (void)hipEventDestroy(r.ev);
+        r = Slot();
+    }
+    if (s.persist) (void)hipFree(s.persist);
+    s.persist = nullptr;
+}
+
+// Allocates the state of an n-row matrix C and writes C <- I.
+tn_status state_init(tn_ctx *ctx, StreamState &s, uint32_t n, uint32_t flags, uint64_t *C,
+                     int64_t ld) {
+    s.n = n;
+    s.flags = flags;
+    s.C = C;
+    s.ld = ld;
+    s.sw = default_slice_words(n, ld);
+    s.slices = rowor_workgroups(n, s.sw);
     hipError_t e;
     if (!ctx->traffic) {
         e = hipMalloc((void **)&ctx->traffic, 2 * sizeof(unsigned long long));
@@ -149,47 +158,70 @@ tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
             return fail(TN_E_NOMEM, "traffic counter allocation failed");
         }
     }
-    // persisted slice state, then the done counter
-    const size_t pwords = rowor_persist_words(n, sw);
-    uint32_t *persist = nullptr;
-    e = hipMalloc((void **)&persist, sizeof(uint32_t) * (pwords + 1));
-    if (e != hipSuccess) return fail(TN_E_NOMEM, "slice state allocation failed");
-    unsigned int *done_count = persist + pwords;
-    Slot ring[kRing];
-    auto release = [&]() {
-        (void)hipStreamSynchronize(ctx->stream);
-        for (Slot &s : ring) {
-            if (s.dev) (void)hipFree(s.dev);
-            if (s.pinned) (void)hipHostFree(s.pinned);
-            if (s.done_host) (void)hipHostFree(s.done_host);
-            if (s.ev) (void)hipEventDestroy(s.ev);
-        }
-        (void)hipFree(persist);
-    };
-    for (Slot &s : ring) {
-        e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&s.done_host, sizeof(unsigned int), 0);
+    const size_t pwords = rowor_persist_words(n, s.sw);
+    e = hipMalloc((void **)&s.persist, sizeof(uint32_t) * (pwords + 1));
+    if (e != hipSuccess) {
+        s.persist = nullptr;
+        return fail(TN_E_NOMEM, "slice state allocation failed");
+    }
+    s.done_count = s.persist + pwords;
+    for (Slot &r : s.ring) {
+        e = hipEventCreateWithFlags(&r.ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&r.done_host, sizeof(unsigned int), 0);
         if (e != hipSuccess) {
-            release();
+            state_release(ctx, s);
             return hip_fail(e, "launch ring set-up");
         }
-        *s.done_host = 0;
+        *r.done_host = 0;
     }
-    e = launch_fill_u32(persist, pwords + 1, 0u, ctx->stream);
+    e = launch_fill_u32(s.persist, pwords + 1, 0u, ctx->stream);
     if (e == hipSuccess) {
         ProfScope ps(ctx, TN_K_IDENTITY);
         e = launch_identity(C, n, ld, ctx->traffic, ctx->stream);
     }
     if (e != hipSuccess) {
-        release();
+        state_release(ctx, s);
         return hip_fail(e, "identity kernel launch");
     }
+    return TN_OK;
+}
+
+// Applies events [0, m) (already validated) to the state in its direction:
+// chunks planned on host threads, launched in stream order.  Returns once
+// every chunk is launched (or the matrix is saturated); the launches may
+// still run.
+tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *src,
+                      const uint32_t *dst, const int64_t *t, int64_t chunk_events,
+                      tn_stream_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool seq = s.flags & TN_TIES_SEQUENTIAL;
+    const bool forward = s.flags & TN_FORWARD;
+    const int64_t nwords = (s.n + 63) / 64;
+    if (chunk_events == 0) chunk_events = std::max<int64_t>(1 << 18, (m + 63) / 64);
+    std::vector<std::pair<int64_t, int64_t>> bounds;
+    stream_chunks(m, t, chunk_events, seq, bounds);
+    if (forward) std::reverse(bounds.begin(), bounds.end());  // from the start
+    std::vector<std::unique_ptr<Chunk>> chunks;
+    for (const auto &ab : bounds) {
+        auto c = std::make_unique<Chunk>();
+        c->a = ab.first;
+        c->b = ab.second;
+        chunks.push_back(std::move(c));
+    }
+    const int64_t nch = (int64_t)chunks.size();
+    // a completed launch may already report every slice full
+    auto poll = [&]() {
+        for (Slot &r : s.ring)
+            if (r.used && hipEventQuery(r.ev) == hipSuccess && *r.done_host == s.slices)
+                s.all_done = true;
+    };
+    poll();
 
     // planning workers: chunks in order, at most `window` ahead of the launches
     std::mutex mu;
     std::condition_variable cv;
     std::atomic<int64_t> next{0};
-    std::atomic<bool> stop{false};
+    std::atomic<bool> stop{s.all_done};
     int64_t consumed = 0;
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int64_t nth = std::max<int64_t>(1, std::min<int64_t>(std::min<unsigned>(hw, 16u), nch));
@@ -204,8 +236,8 @@ tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
             }
             Chunk &ch = *chunks[c];
             if (!stop.load()) {
-                ch.st = plan_events(n, ch.b - ch.a, src + ch.a, dst + ch.a, t + ch.a, flags, ch.hs,
-                                    ch.err, nullptr, 0, kFormOps);
+                ch.st = plan_events(s.n, ch.b - ch.a, src + ch.a, dst + ch.a, t + ch.a, s.flags,
+                                    ch.hs, ch.err, nullptr, 0, kFormOps);
                 if (ch.st == TN_OK) ops_pack(ch.hs, ch.image);
             }
             {
@@ -216,22 +248,13 @@ tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         }
     };
     std::vector<std::thread> pool;
-    for (int64_t k = 0; k < nth; ++k) pool.emplace_back(worker);
-    auto finish = [&](tn_status st) {
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            stop = true;
-        }
-        cv.notify_all();
-        for (auto &th : pool) th.join();
-        release();
-        return st;
-    };
+    if (!s.all_done)
+        for (int64_t k = 0; k < nth; ++k) pool.emplace_back(worker);
 
-    int64_t launched = 0, planned_events = 0, run_events = 0, levels = 0;
-    bool all_done = false;
+    int64_t launched = 0, run_events = 0, levels = 0;
     tn_status st = TN_OK;
-    for (int64_t c = 0; c < nch && !all_done; ++c) {
+    hipError_t e;
+    for (int64_t c = 0; c < nch && !s.all_done; ++c) {
         Chunk &ch = *chunks[c];
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -241,68 +264,65 @@ tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
             st = fail(ch.st, ch.err);
             break;
         }
-        // a completed earlier launch may already report every slice full
-        for (int k = 0; k < kRing; ++k)
-            if (ring[k].used && hipEventQuery(ring[k].ev) == hipSuccess &&
-                *ring[k].done_host == slices)
-                all_done = true;
-        if (all_done) break;
-        Slot &s = ring[c % kRing];
-        if (s.used) {
-            e = hipEventSynchronize(s.ev);
+        poll();
+        if (s.all_done) break;
+        Slot &r = s.ring[s.launches % kRing];
+        if (r.used) {
+            e = hipEventSynchronize(r.ev);
             if (e != hipSuccess) {
                 st = hip_fail(e, "hipEventSynchronize");
                 break;
             }
-            if (*s.done_host == slices) {
-                all_done = true;
+            if (*r.done_host == s.slices) {
+                s.all_done = true;
                 break;
             }
         }
         const size_t bytes = ch.image.size();
-        if (bytes > s.dev_bytes) {
-            if (s.dev) (void)hipFree(s.dev);
-            s.dev = nullptr;
-            s.dev_bytes = 0;
-            e = hipMalloc(&s.dev, bytes);
+        if (bytes > r.dev_bytes) {
+            if (r.dev) (void)hipFree(r.dev);
+            r.dev = nullptr;
+            r.dev_bytes = 0;
+            e = hipMalloc(&r.dev, bytes);
             if (e != hipSuccess) {
                 st = fail(TN_E_NOMEM, "chunk schedule allocation failed");
                 break;
             }
-            s.dev_bytes = bytes;
+            r.dev_bytes = bytes;
         }
-        if (bytes > s.pinned_bytes) {
-            if (s.pinned) (void)hipHostFree(s.pinned);
-            s.pinned = nullptr;
-            s.pinned_bytes = 0;
-            e = hipHostMalloc(&s.pinned, bytes, 0);
+        if (bytes > r.pinned_bytes) {
+            if (r.pinned) (void)hipHostFree(r.pinned);
+            r.pinned = nullptr;
+            r.pinned_bytes = 0;
+            e = hipHostMalloc(&r.pinned, bytes, 0);
             if (e != hipSuccess) {
                 st = fail(TN_E_NOMEM, "chunk staging allocation failed");
                 break;
             }
-            s.pinned_bytes = bytes;
+            r.pinned_bytes = bytes;
         }
-        std::memcpy(s.pinned, ch.image.data(), bytes);
-        const size_t need = sizeof(uint64_t) * ((size_t)slices * kRoworSinkWords +
+        std::memcpy(r.pinned, ch.image.data(), bytes);
+        const size_t need = sizeof(uint64_t) * ((size_t)s.slices * kRoworSinkWords +
                                                 (size_t)ch.hs.scratch_rows * (size_t)nwords);
         st = ensure_scratch(ctx, need);
         if (st != TN_OK) break;
-        e = hipMemcpyAsync(s.dev, s.pinned, bytes, hipMemcpyHostToDevice, ctx->stream);
+        e = hipMemcpyAsync(r.dev, r.pinned, bytes, hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess) {
             ProfScope ps(ctx, TN_K_ROWOR);
-            e = launch_rowor_global(ops_view(ch.hs, s.dev), n, C, ld, sw, (uint64_t *)ctx->scratch,
-                                    ch.hs.scratch_rows, ctx->traffic, ctx->saturation, persist,
-                                    done_count, ctx->stream);
+            e = launch_rowor_global(ops_view(ch.hs, r.dev), s.n, s.C, s.ld, s.sw,
+                                    (uint64_t *)ctx->scratch, ch.hs.scratch_rows, ctx->traffic,
+                                    ctx->saturation, s.persist, s.done_count, ctx->stream);
         }
         if (e == hipSuccess)
-            e = hipMemcpyAsync(s.done_host, done_count, sizeof(unsigned int),
+            e = hipMemcpyAsync(r.done_host, s.done_count, sizeof(unsigned int),
                                hipMemcpyDeviceToHost, ctx->stream);
-        if (e == hipSuccess) e = hipEventRecord(s.ev, ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(r.ev, ctx->stream);
         if (e != hipSuccess) {
             st = hip_fail(e, "chunk launch");
             break;
         }
-        s.used = true;
+        r.used = true;
+        ++s.launches;
         ++launched;
         run_events += ch.b - ch.a;
         levels += ch.hs.Lops;
@@ -315,30 +335,86 @@ tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         }
         cv.notify_all();
     }
-    for (int64_t c = 0; c < nch; ++c)
-        if (chunks[c]->ready && chunks[c]->st == TN_OK) planned_events += chunks[c]->b - chunks[c]->a;
-    if (st == TN_OK) {
-        e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        stop = true;
     }
-    if (st == TN_OK && !all_done)
-        for (Slot &s : ring)
-            if (s.used && *s.done_host == slices) all_done = true;
+    cv.notify_all();
+    for (auto &th : pool) th.join();
     if (stats) {
         stats->chunks = nch;
         stats->chunks_run = launched;
         stats->events_run = run_events;
         stats->levels_run = levels;
-        stats->saturated = all_done ? 1 : 0;
-        stats->slice_words = sw;
+        stats->saturated = s.all_done ? 1 : 0;
+        stats->slice_words = (int32_t)s.sw;
         stats->seconds =
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    (void)planned_events;
-    return finish(st);
+    return st;
+}
+
+tn_status check_common(tn_ctx *ctx, uint32_t n, uint32_t flags, const uint64_t *C, int64_t ld) {
+    if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
+    if (!C) return fail(TN_E_ARG, "C is NULL");
+    if (n == 0) return fail(TN_E_ARG, "n must be > 0");
+    if (flags & ~(uint32_t)(TN_DIRECTED | TN_TIES_SEQUENTIAL | TN_FORWARD))
+        return fail(TN_E_ARG, "unknown flag bits");
+    if (n > kNodeMask) return fail(TN_E_UNSUPPORTED, "n must be < 2^31");
+    if (ld < (int64_t)((n + 63) / 64)) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
+    return TN_OK;
+}
+
+tn_status check_events(int64_t m, const uint32_t *src, const uint32_t *dst, const int64_t *t,
+                       int64_t chunk_events) {
+    if (m < 0) return fail(TN_E_ARG, "m must be >= 0");
+    if (m > 0 && (!src || !dst || !t)) return fail(TN_E_ARG, "null event array");
+    if (m >= (int64_t)0xffffffffLL) return fail(TN_E_UNSUPPORTED, "m must be < 2^32 - 1");
+    if (chunk_events < 0) return fail(TN_E_ARG, "chunk_events must be >= 0");
+    return TN_OK;
+}
+
+}  // namespace
+
+tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
+                         const uint32_t *dst, const int64_t *t, uint32_t flags, uint64_t *C,
+                         int64_t ld, int64_t chunk_events, tn_stream_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    tn_status st = check_common(ctx, n, flags, C, ld);
+    if (st == TN_OK) st = check_events(m, src, dst, t, chunk_events);
+    if (st != TN_OK) return st;
+    {
+        std::string err;
+        st = validate_events(n, m, src, dst, t, err);
+        if (st != TN_OK) return fail(st, err);
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    StreamState s;
+    st = state_init(ctx, s, n, flags, C, ld);
+    if (st != TN_OK) return st;
+    st = state_apply(ctx, s, m, src, dst, t, chunk_events, stats);
+    if (st == TN_OK) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (st == TN_OK && stats) {
+        // launches that completed after the last poll may have saturated it
+        for (const Slot &r : s.ring)
+            if (r.used && *r.done_host == s.slices) stats->saturated = 1;
+        stats->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    state_release(ctx, s);
+    return st;
 }
 
 }  // namespace tn
+
+struct tn_online {
+    tn_ctx *ctx = nullptr;
+    tn::StreamState s;
+};
 
 extern "C" {
 
@@ -348,6 +424,70 @@ tn_status tn_build_component_matrix_streamed(tn_ctx *ctx, uint32_t n, int64_t m,
                                              int64_t ld, int64_t chunk_events,
                                              tn_stream_stats *stats) {
     return tn::build_streamed(ctx, n, m, src, dst, t, flags, C, ld, chunk_events, stats);
+}
+
+tn_status tn_online_create(tn_ctx *ctx, uint32_t n, uint32_t flags, uint64_t *C, int64_t ld,
+                           tn_online **out) {
+    using namespace tn;
+    if (!out) return fail(TN_E_ARG, "out is NULL");
+    *out = nullptr;
+    tn_status st = check_common(ctx, n, flags, C, ld);
+    if (st != TN_OK) return st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    tn_online *o = new (std::nothrow) tn_online();
+    if (!o) return fail(TN_E_NOMEM, "online state allocation failed");
+    o->ctx = ctx;
+    st = state_init(ctx, o->s, n, flags, C, ld);
+    if (st != TN_OK) {
+        delete o;
+        return st;
+    }
+    *out = o;
+    return TN_OK;
+}
+
+tn_status tn_online_insert(tn_ctx *ctx, tn_online *o, int64_t m, const uint32_t *src,
+                           const uint32_t *dst, const int64_t *t, int64_t chunk_events,
+                           tn_stream_stats *stats) {
+    using namespace tn;
+    if (!ctx || !o) return fail(TN_E_ARG, "ctx or online state is NULL");
+    if (o->ctx != ctx) return fail(TN_E_ARG, "online state belongs to another context");
+    tn_status st = check_events(m, src, dst, t, chunk_events);
+    if (st != TN_OK) return st;
+    StreamState &s = o->s;
+    {
+        std::string err;
+        st = validate_events(s.n, m, src, dst, t, err);
+        if (st != TN_OK) return fail(st, err);
+    }
+    if (stats) *stats = tn_stream_stats{};
+    if (m == 0) return TN_OK;
+    // events of one time step must arrive in one call (they form one
+    // snapshot), so a call continues strictly after what is applied
+    const bool forward = s.flags & TN_FORWARD, seq = s.flags & TN_TIES_SEQUENTIAL;
+    if (s.has_time) {
+        const bool ok = forward ? (seq ? t[0] >= s.edge_t : t[0] > s.edge_t)
+                                : (seq ? t[m - 1] <= s.edge_t : t[m - 1] < s.edge_t);
+        if (!ok)
+            return fail(TN_E_ORDER, forward ? "inserted events are not later than those applied"
+                                            : "inserted events are not earlier than those applied");
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    st = state_apply(ctx, s, m, src, dst, t, chunk_events, stats);
+    if (st == TN_OK) {
+        s.has_time = true;
+        s.edge_t = forward ? t[m - 1] : t[0];
+    }
+    return st;
+}
+
+void tn_online_destroy(tn_online *o) {
+    if (!o) return;
+    tn::DeviceGuard g(o->ctx->device);
+    tn::state_release(o->ctx, o->s);
+    delete o;
 }
 
 }  // extern "C"

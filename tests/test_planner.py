@@ -101,10 +101,13 @@ def check_disjoint(n, sch):
 
 
 @pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.TIES_SEQUENTIAL,
-                                   tn.DIRECTED | tn.TIES_SEQUENTIAL])
+                                   tn.DIRECTED | tn.TIES_SEQUENTIAL, tn.FORWARD,
+                                   tn.FORWARD | tn.DIRECTED,
+                                   tn.FORWARD | tn.DIRECTED | tn.TIES_SEQUENTIAL])
 def test_schedule_replay_matches_oracle(flags):
     directed = bool(flags & tn.DIRECTED)
     seq = bool(flags & tn.TIES_SEQUENTIAL)
+    fwd = bool(flags & tn.FORWARD)
     for case in range(80):
         n = 2 + (case * 7) % 150
         m = (case * 13) % 400
@@ -114,7 +117,8 @@ def test_schedule_replay_matches_oracle(flags):
         check_disjoint(n, sch)
         check_ops_independent(sch)
         got = simulate(n, sch)
-        want = oracle.reverse_matrix(n, s, d, t, directed=directed, sequential=seq)
+        ref = oracle.forward_matrix if fwd else oracle.reverse_matrix
+        want = ref(n, s, d, t, directed=directed, sequential=seq)
         assert (got == want).all(), case
         assert (simulate_ops(n, sch) == want).all(), case
 
@@ -180,6 +184,16 @@ def test_planner_rejects_bad_input():
     with pytest.raises(tn.TNError) as e:
         tn.host_schedule(4, [0], [1], [0], flags=8)
     assert e.value.code == -1
+
+
+def test_forward_schedule_is_the_transpose():
+    # Algorithm 1 in time order gives the transpose of the reverse-time
+    # matrix, here through the planner's own schedules
+    n = 120
+    s, d, t = T.random_tiny(n, 900, 60, seed=77)
+    f = simulate_ops(n, tn.host_schedule(n, s, d, t, tn.FORWARD))
+    r = simulate_ops(n, tn.host_schedule(n, s, d, t))
+    assert (oracle.to_dense(f, n) == oracle.to_dense(r, n).T).all()
 
 
 def test_wide_levels_are_split_and_big_compound_items_fold():
