@@ -20,6 +20,10 @@ Other modes (each prints its own single JSON line):
                    m = 10^6) and evaluated on 4 held-out networks
                    (n = 100,000, m = 10^7) against the exact sizes, beside the
                    fusion estimate and the smallest lifted size.
+  --mode sweep     the paper's synthetic experiment: ER G(n, 2/n) with a
+                   Poisson process per link, n from 100 to 10^4 and m from
+                   10^4 to 10^7, exact against hashed (H = 5, n_s = 0.3 n):
+                   Earth-Mover distance, relative time and memory.
 
 Each line carries the roofline of the mode's dominant kernel, timed with HIP
 events on the stream it runs on, and the CPU oracle timed on a bounded
@@ -523,6 +527,77 @@ def run_combiner(args):
     return r
 
 
+def run_sweep(args):
+    """The paper's synthetic experiment (Sec. 3.5 setting, Sec. 4.4 criteria):
+    ER G(n, 2/n) with a Poisson process on each link; for each (n, m), the
+    exact out-component size distribution against the hashed one (H = 5
+    hashes to n_s = 0.3 n super-nodes): Earth-Mover distance, relative time
+    and relative memory.  Both sides run end to end from host events."""
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+    from paper_2307_04890_amd.evaluate import emd_1d, relative_memory
+
+    ns = [100, 200, 500, 1000, 2000, 5000, 10000]
+    ms = [m for m in (10**4, 10**5, 10**6, 10**7, 10**8) if m <= args.sweep_max_m]
+    H = 5
+    rows = []
+    tot_events = tot_exact = 0.0
+
+    def best_of(fn, reps=2):
+        ts, out = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return min(ts), out
+
+    for i, n in enumerate(ns):
+        for j, m in enumerate(ms):
+            s, d, t = T.er_poisson(n, m, 100 * m, seed=100 * i + j)
+            K = max(1, int(round(0.3 * n)))
+            A = T.hash_coefficients(H, seed=7000 + 100 * i + j)
+
+            def exact():
+                C, st = tn.build_component_matrix_streamed(n, s, d, t)
+                out, _ = tn.component_sizes(C, n, inn=False)
+                return out, st
+
+            def hashed():
+                b, c, P, st = tn.hash_build_proxies(n, s, d, t, A, K)
+                est, _ = tn.recombine(P, b, c, n, lifted=False)
+                return est, st
+
+            te, (out, est_st) = best_of(exact)
+            th, (est, hst) = best_of(hashed)
+            o = out.cpu().numpy().astype(np.float64)
+            e = est.cpu().numpy().astype(np.float64)
+            emd = emd_1d(o, e)
+            rows.append({"n": n, "m": m, "K": K, "exact_s": te, "hashed_s": th,
+                         "relative_time": th / te,
+                         "relative_memory": relative_memory(n, K, H),
+                         "emd": emd, "emd_over_n": emd / n,
+                         "mean_exact": float(o.mean()), "mean_estimate": float(e.mean()),
+                         "exact_chunks_run": est_st["chunks_run"], "chunks": est_st["chunks"],
+                         "hashed_chunks_run": hst["chunks_run"]})
+            tot_events += m
+            tot_exact += te
+            log(f"[bench] sweep n={n} m={m}: exact {te * 1e3:.1f} ms, hashed {th * 1e3:.1f} ms, "
+                f"EMD {emd:.2f} ({emd / n:.4f} n)")
+    config = {"workload": "er_poisson_sweep", "n": ns, "m": ms, "H": H, "n_s": "0.3 n",
+              "T": "100 m", "graph": "G(n, 2/n)", "parallelism": "single-gpu"}
+    r = base_result(args, tot_events / tot_exact, "events/s", len(rows), 1e3 * tot_exact / len(rows),
+                    config)
+    r["value_note"] = ("exact path end to end from host events (streamed build + out-sizes), "
+                       "summed over the sweep")
+    r["sweep"] = rows
+    return r
+
+
 # ---------------------------------------------------------------------------
 # rocprofv3 summaries (run on the CSV files a profiled bench run wrote)
 def _read_csv(path):
@@ -599,7 +674,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="exact", choices=["exact", "hashed", "batched", "combiner"])
+    ap.add_argument("--mode", default="exact",
+                    choices=["exact", "hashed", "batched", "combiner", "sweep"])
+    ap.add_argument("--sweep-max-m", type=float, default=1e7,
+                    help="largest event count of the ER + Poisson sweep")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--slice-words", type=int, default=0)
     ap.add_argument("--hashes", type=int, default=16)
@@ -621,7 +699,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     run = {"exact": run_exact, "hashed": run_hashed, "batched": run_batched,
-           "combiner": run_combiner}[args.mode]
+           "combiner": run_combiner, "sweep": run_sweep}[args.mode]
     print(json.dumps(run(args)), flush=True)
 
 

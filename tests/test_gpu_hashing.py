@@ -148,3 +148,21 @@ def test_streamed_proxies_at_the_scaled_hashed_workload():
     for j in (0, 9):
         assert (host(P[j]) == oracle.reverse_matrix(K, wb[j][s], wb[j][d], t)).all(), j
     assert st["saturated"] == 1 and st["events_run"] < m
+
+
+def test_paper_setting_er_poisson_exact_and_hashed():
+    # G(n, 2/n) with a Poisson process per link, n_s = 0.3 n, H = 5
+    n, m, H = 300, 20_000, 5
+    K = 90
+    s, d, t = T.er_poisson(n, m, 100 * m, seed=11)
+    C = tn.build_component_matrix(n, s, d, t)
+    want = oracle.reverse_matrix(n, s, d, t)
+    assert (host(C) == want).all()
+    A = T.hash_coefficients(H, seed=12)
+    bucket, count, P, _ = tn.hash_build_proxies(n, s, d, t, A, K)
+    wb = oracle.hash_nodes(n, A, K)
+    WP = oracle.proxies(K, s, d, t, wb)
+    assert (host(P) == WP).all()
+    est, lifted = tn.recombine(P, bucket, count, n)
+    we, wl = oracle.recombine(n, WP, wb)
+    assert (est.cpu().numpy() == we).all() and (lifted.cpu().numpy() == wl).all()
