@@ -15,6 +15,8 @@ Contents
 * ``si.py``: deterministic SI simulation from every node (Sec. 1), the brute
   force that pins the matrix.
 * ``mlp.py``: float64 forward / backward / Adam of the learned combiner.
+* ``hll.py``: the HyperLogLog variant of the stream (Sec. 3.4): registers,
+  register-wise max per time step, and the estimator.
 
 Every matrix routine returns ``uint64`` arrays with node ``w`` at bit
 ``w & 63`` of word ``w >> 6``.

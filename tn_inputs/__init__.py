@@ -24,7 +24,7 @@ __all__ = [
     "rng", "sort_events", "uniform_pairs", "activity_driven", "er_poisson",
     "activities", "hash_coefficients", "MERSENNE61", "mlp_init", "MLP_SIZES",
     "mlp_param_count", "NetSpec", "batched_suite", "WORKLOADS", "make_workload",
-    "static_graph_rounds", "chronological_path", "random_tiny",
+    "static_graph_rounds", "chronological_path", "random_tiny", "hll_node_hashes",
 ]
 
 MERSENNE61 = (1 << 61) - 1
@@ -163,6 +163,15 @@ def chronological_path(k: int):
     """Events (i, i+1) at time i for i < k on k+1 nodes."""
     src = np.arange(k, dtype=np.uint32)
     return src, src + np.uint32(1), np.arange(k, dtype=np.int64)
+
+
+def hll_node_hashes(n: int, seed: int) -> np.ndarray:
+    """One uniform 64-bit hash value per node, the element hashes of the
+    HyperLogLog structures (drawn here, passed to both sides)."""
+    g = rng(seed)
+    hi = g.integers(0, 2**32, size=n, dtype=np.uint64)
+    lo = g.integers(0, 2**32, size=n, dtype=np.uint64)
+    return (hi << np.uint64(32)) | lo
 
 
 def hash_coefficients(H: int, seed: int, order: int = 4) -> np.ndarray:
