@@ -275,6 +275,30 @@ tn_status tn_online_insert(tn_ctx *ctx, tn_online *online, int64_t m,
  * ignored. */
 void tn_online_destroy(tn_online *online);
 
+/* HyperLogLog variant of the stream (Sec. 3.4, last paragraph; HLL in
+ * Sec. 2.2): every node starts with the HLL structure of {node} and each
+ * time step merges the structures its events join (register-wise maximum,
+ * the same level schedule and snapshot ties as the matrix), so row u ends as
+ * the HLL structure of u's out-component (in-component with TN_FORWARD) in
+ * s = 2^log2s one-byte registers instead of n bits.  Registers follow
+ * Flajolet et al. (2007): the top log2s bits of an element's 64-bit hash pick
+ * the register, which keeps the largest 1-based position of the leftmost 1
+ * in the remaining bits (64 - log2s + 1 for all zeros).  est[u] is the HLL
+ * estimate alpha_s s^2 / sum_j 2^-M[j], or s ln(s / V) when that is at most
+ * 5s/2 and V > 0 registers are zero (alpha_16 = 0.673, alpha_32 = 0.697,
+ * alpha_64 = 0.709, else 0.7213 / (1 + 1.079 / s)).
+ * node_hash: DEVICE uint64[n], one uniform hash per node (an input: the
+ * library draws no random numbers).  M: DEVICE n x s uint8, row-major,
+ * written entirely.  est: DEVICE float64[n] or NULL.  log2s in [4, 16].
+ * tn_hll_execute runs on a plan's schedule (asynchronous); tn_hll_build
+ * plans, runs and waits.  Errors: TN_E_ARG, plus those of tn_plan_create. */
+tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
+                         const uint64_t *node_hash, uint8_t *M, double *est);
+tn_status tn_hll_build(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
+                       const uint32_t *dst, const int64_t *t, uint32_t flags,
+                       uint32_t log2s, const uint64_t *node_hash, uint8_t *M,
+                       double *est);
+
 /* Component sizes (Sec. 3.1, Eq. 1): out_sizes[u] = ones in row u (the
  * maximum out-component size of u), in_sizes[w] = ones in column w (the
  * in-component size of w).  C: DEVICE n x ld.  out_sizes, in_sizes: DEVICE

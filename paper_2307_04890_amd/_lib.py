@@ -88,6 +88,8 @@ SIGNATURES = {
     "tn_schedule_op_arrays": (_i32, [_P, _PP, _PP]),
     "tn_plan_execute": (_i32, [_P, _P, _P, _i64, _u32]),
     "tn_set_saturation": (_i32, [_P, ctypes.c_int]),
+    "tn_hll_execute": (_i32, [_P, _P, _u32, _P, _P, _P]),
+    "tn_hll_build": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _u32, _P, _P, _P]),
     "tn_online_create": (_i32, [_P, _u32, _u32, _P, _i64, _PP]),
     "tn_online_insert": (_i32, [_P, _P, _i64, _P, _P, _P, _i64, ctypes.POINTER(StreamStats)]),
     "tn_online_destroy": (None, [_P]),

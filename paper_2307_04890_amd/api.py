@@ -11,7 +11,7 @@ import torch
 from ._lib import (DIRECTED, FORWARD, KERNELS, TIES_SEQUENTIAL, PlanStats, StreamStats, TNError,
                    check, lib)
 
-__all__ = ["Context", "Plan", "Online", "FORWARD", "build_component_matrix_streamed",
+__all__ = ["Context", "Plan", "Online", "FORWARD", "hll_build", "build_component_matrix_streamed",
            "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
@@ -139,6 +139,19 @@ class Plan:
         check(lib.tn_plan_get_stats(self.h, ctypes.byref(s)))
         return s.as_dict()
 
+    def hll(self, node_hash, log2s: int):
+        """The HyperLogLog stream on this plan's schedule (tn_hll_execute):
+        (registers (n, 2^log2s) uint8, estimates (n,) float64)."""
+        dev = f"cuda:{self.ctx.device}"
+        h = torch.as_tensor(np.ascontiguousarray(node_hash, dtype=np.uint64).view(np.int64)).to(dev)
+        if h.shape != (self.n,):
+            raise ValueError("node_hash must hold one value per node")
+        M = torch.empty((self.n, 1 << log2s), dtype=torch.uint8, device=dev)
+        est = torch.empty(self.n, dtype=torch.float64, device=dev)
+        check(lib.tn_hll_execute(self.ctx.bind_stream(), self.h, int(log2s), _dp(h), _dp(M),
+                                 _dp(est)))
+        return M, est
+
     def execute(self, C: torch.Tensor | None = None, slice_words: int = 0) -> torch.Tensor:
         if C is None:
             C = alloc_matrix(self.n, device=self.ctx.device)
@@ -187,6 +200,23 @@ def build_component_matrix_streamed(n: int, src, dst, t, flags: int = 0,
                                                  C.stride(0), int(chunk_events),
                                                  ctypes.byref(st)))
     return C, st.as_dict()
+
+
+def hll_build(n: int, src, dst, t, node_hash, log2s: int, flags: int = 0,
+              ctx: Context | None = None):
+    """HyperLogLog stream (tn_hll_build): returns (registers (n, 2^log2s)
+    uint8, estimates (n,) float64) on the device."""
+    ctx = ctx or get_context()
+    src, dst, t = _events(src, dst, t)
+    dev = f"cuda:{ctx.device}"
+    h = torch.as_tensor(np.ascontiguousarray(node_hash, dtype=np.uint64).view(np.int64)).to(dev)
+    if h.shape != (n,):
+        raise ValueError("node_hash must hold one value per node")
+    M = torch.empty((n, 1 << log2s), dtype=torch.uint8, device=dev)
+    est = torch.empty(n, dtype=torch.float64, device=dev)
+    check(lib.tn_hll_build(ctx.bind_stream(), int(n), src.shape[0], _hp(src), _hp(dst), _hp(t),
+                           int(flags), int(log2s), _dp(h), _dp(M), _dp(est)))
+    return M, est
 
 
 class Online:

@@ -339,6 +339,69 @@ tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m, const ui
     return tn::build_streamed(ctx, n, m, src, dst, t, flags, C, ld, 0, nullptr);
 }
 
+tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
+                         const uint64_t *node_hash, uint8_t *M, double *est) {
+    if (!ctx || !plan) return fail(TN_E_ARG, "ctx or plan is NULL");
+    if (!node_hash || !M) return fail(TN_E_ARG, "node_hash or M is NULL");
+    if (log2s < 4 || log2s > 16) return fail(TN_E_ARG, "log2s must be in [4, 16]");
+    if (plan->device != ctx->device) return fail(TN_E_ARG, "plan lives on another device");
+    const uint32_t n = plan->stats.n;
+    const uint32_t nwords = (1u << log2s) / 8;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    {
+        const size_t words = (size_t)tn::rowmax_workgroups(nwords) * tn::kRoworSinkWords +
+                             (size_t)plan->scratch_rows * (size_t)nwords;
+        tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * words);
+        if (st != TN_OK) return st;
+    }
+    hipError_t e;
+    if (!ctx->traffic) {
+        e = hipMalloc((void **)&ctx->traffic, 2 * sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            ctx->traffic = nullptr;
+            return fail(TN_E_NOMEM, "traffic counter allocation failed");
+        }
+    }
+    {
+        tn::ProfScope ps(ctx, TN_K_AUX);
+        e = tn::launch_fill_u32((uint32_t *)ctx->traffic, 4, 0u, ctx->stream);
+        if (e == hipSuccess) e = tn::launch_hll_init(n, log2s, node_hash, M, ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "HLL init launch");
+    {
+        tn::ProfScope ps(ctx, TN_K_ROWOR);
+        e = tn::launch_rowmax_global(plan->view, n, nwords, (uint64_t *)M, nwords,
+                                     (uint64_t *)ctx->scratch, plan->scratch_rows, ctx->traffic,
+                                     ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "HLL stream launch");
+    if (est) {
+        tn::ProfScope ps(ctx, TN_K_AUX);
+        e = tn::launch_hll_estimate(n, log2s, M, est, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "HLL estimate launch");
+    }
+    return TN_OK;
+}
+
+tn_status tn_hll_build(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
+                       const uint32_t *dst, const int64_t *t, uint32_t flags, uint32_t log2s,
+                       const uint64_t *node_hash, uint8_t *M, double *est) {
+    if (!node_hash || !M) return fail(TN_E_ARG, "node_hash or M is NULL");
+    if (log2s < 4 || log2s > 16) return fail(TN_E_ARG, "log2s must be in [4, 16]");
+    tn_plan *p = nullptr;
+    tn_status st = tn_plan_create(ctx, n, m, src, dst, t, flags, &p);
+    if (st != TN_OK) return st;
+    st = tn_hll_execute(ctx, p, log2s, node_hash, M, est);
+    if (st == TN_OK) {
+        DeviceGuard g(ctx->device);
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    tn_plan_destroy(p);
+    return st;
+}
+
 tn_status tn_component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C, int64_t ld,
                              int32_t *out_sizes, int32_t *in_sizes) {
     if (!ctx) return fail(TN_E_ARG, "ctx is NULL");

@@ -1,0 +1,94 @@
+// HyperLogLog structures of the reverse-time stream (Sec. 3.4, with the HLL
+// of Sec. 2.2): every node holds s = 2^b one-byte registers, the structure
+// of the set {node} at first; the stream merges structures with the
+// register-wise maximum (launch_rowmax_global, the row-OR kernel's level
+// loop on rows of s bytes); the estimate of each row follows Flajolet,
+// Fusy, Gandouet and Meunier (2007): alpha_s s^2 / sum_j 2^-M[j], and
+// s ln(s / V) when that is at most 5s/2 with V > 0 zero registers.
+// Element hashes are inputs, one uniform 64-bit value per node.
+#include <hip/hip_runtime.h>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+namespace {
+
+// Row u = the registers of {u}: register j (the top b bits of the hash)
+// holds rho, the 1-based position of the leftmost 1 in the other 64 - b
+// bits (64 - b + 1 when they are all zero).  One thread per word.
+__global__ void __launch_bounds__(256)
+k_hll_init(uint32_t n, uint32_t b, const uint64_t *__restrict__ node_hash, uint64_t *__restrict__ M) {
+    const uint32_t nwords = (1u << b) / 8;
+    const size_t total = (size_t)n * nwords;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t u = (uint32_t)(i / nwords), w = (uint32_t)(i % nwords);
+        const uint64_t x = node_hash[u];
+        const uint32_t j = (uint32_t)(x >> (64 - b));
+        const uint64_t tail = x & ((~0ull) >> b);
+        const uint32_t rho = tail ? (uint32_t)__clzll((long long)tail) - b + 1 : 64 - b + 1;
+        M[i] = (j >> 3) == w ? (uint64_t)rho << (8 * (j & 7u)) : 0ull;
+    }
+}
+
+double __device__ hll_alpha(uint32_t s) {
+    if (s == 16) return 0.673;
+    if (s == 32) return 0.697;
+    if (s == 64) return 0.709;
+    return 0.7213 / (1.0 + 1.079 / (double)s);
+}
+
+// One wavefront per node: the lanes sum 2^-M[j] and count zero registers,
+// then lane 0 forms the estimate (double precision).
+__global__ void __launch_bounds__(256)
+k_hll_estimate(uint32_t n, uint32_t b, const uint8_t *__restrict__ M, double *__restrict__ est) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t s = 1u << b;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t u = wave; u < n; u += nwave) {
+        const uint8_t *row = M + (size_t)u * s;
+        double z = 0.0;
+        uint32_t zeros = 0;
+        for (uint32_t j = lane; j < s; j += 64) {
+            const uint32_t r = row[j];
+            z += ldexp(1.0, -(int)r);
+            zeros += r == 0;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            z += __shfl_xor(z, off, 64);
+            zeros += __shfl_xor(zeros, off, 64);
+        }
+        if (lane == 0) {
+            const double sd = (double)s;
+            double e = hll_alpha(s) * sd * sd / z;
+            if (e <= 2.5 * sd && zeros > 0) e = sd * log(sd / (double)zeros);
+            est[u] = e;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_hll_init(uint32_t n, uint32_t log2s, const uint64_t *node_hash, uint8_t *M,
+                           hipStream_t st) {
+    const size_t total = (size_t)n * ((1u << log2s) / 8);
+    uint32_t blocks = (uint32_t)std::min<size_t>((total + 255) / 256, 65536);
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_hll_init, dim3(blocks), dim3(256), 0, st, n, log2s, node_hash,
+                       (uint64_t *)M);
+    return hipGetLastError();
+}
+
+hipError_t launch_hll_estimate(uint32_t n, uint32_t log2s, const uint8_t *M, double *est,
+                               hipStream_t st) {
+    uint32_t blocks = (n + 3) / 4;
+    if (blocks > 16384u) blocks = 16384u;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_hll_estimate, dim3(blocks), dim3(256), 0, st, n, log2s, M, est);
+    return hipGetLastError();
+}
+
+}  // namespace tn

@@ -217,6 +217,19 @@ tn_status validate_events(uint32_t n, int64_t m, const uint32_t *src, const uint
 // about `chunk` events and of whole time steps unless `sequential`
 void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, bool sequential,
                    std::vector<std::pair<int64_t, int64_t>> &out);
+// The row-OR kernel with rows merged by byte-wise maximum (HyperLogLog
+// registers below 128, nwords = 2, 4, 8, ... words per row of M, ld >=
+// nwords); scratch as for launch_rowor_global with rowmax_workgroups sinks.
+hipError_t launch_rowmax_global(const DevOps &s, uint32_t rows, uint32_t nwords, uint64_t *M,
+                                int64_t ld, uint64_t *scratch, uint32_t scratch_rows,
+                                unsigned long long *traffic, hipStream_t st);
+uint32_t rowmax_workgroups(uint32_t nwords);
+// HyperLogLog kernels (tn_hll.hip): every node's registers for its own hash,
+// and the size estimates
+hipError_t launch_hll_init(uint32_t n, uint32_t log2s, const uint64_t *node_hash, uint8_t *M,
+                           hipStream_t st);
+hipError_t launch_hll_estimate(uint32_t n, uint32_t log2s, const uint8_t *M, double *est,
+                               hipStream_t st);
 // streamed one-shot build (tn_stream.cpp)
 tn_status build_streamed(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
                          const uint32_t *dst, const int64_t *t, uint32_t flags, uint64_t *C,

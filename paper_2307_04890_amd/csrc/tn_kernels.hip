@@ -110,9 +110,20 @@ __device__ __forceinline__ bool sat_get(const OpArgs &A, uint32_t id) {
     return (A.sat[i >> 5] >> (i & 31u)) & 1u;
 }
 
+// Byte-wise maximum of two words whose bytes are all below 128 (HyperLogLog
+// registers, Sec. 3.4): (x | 0x80..) - y keeps each byte's borrow inside the
+// byte, and that byte's top bit then says whether x >= y.
+__device__ __forceinline__ uint64_t max_bytes7(uint64_t x, uint64_t y) {
+    constexpr uint64_t H = 0x8080808080808080ull;
+    const uint64_t ge = ((x | H) - y) & H;
+    const uint64_t mask = (ge >> 7) * 0xFFull;
+    return (x & mask) | (y & ~mask);
+}
+
 // Plain path: ops [base, n) of the current frame, UC per lane group, every
-// op loading and storing its rows.
-template <int UC>
+// op loading and storing its rows; MAX8 merges rows by byte-wise maximum
+// instead of OR.
+template <int UC, bool MAX8 = false>
 __device__ __forceinline__ void apply_frame(OpArgs &A, const op4 *frame, uint32_t base,
                                             uint32_t n) {
     op4 o[UC];
@@ -129,7 +140,7 @@ __device__ __forceinline__ void apply_frame(OpArgs &A, const op4 *frame, uint32_
 #pragma unroll
     for (int k = 0; k < UC; ++k) {
         const bool v = base + A.grp + k * A.ngrp < n;
-        const uint64_t r = x[k] | y[k];
+        const uint64_t r = MAX8 ? max_bytes7(x[k], y[k]) : (x[k] | y[k]);
         *op_addr(A, o[k].z, v) = r;
         *op_addr(A, o[k].w, v) = r;
         A.stored += ((v && A.wok && o[k].z != kNoRow) ? 1u : 0u) +
@@ -251,7 +262,7 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
 // CHUNK: one launch per chunk of a streamed build, with the slice state in
 // `persist` (a separate instantiation, so traces and counters keep the two
 // kinds of launch apart).
-template <int SW, int UC, bool SAT, bool CHUNK>
+template <int SW, int UC, bool SAT, bool CHUNK, bool MAX8 = false>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
                uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
@@ -387,11 +398,11 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
             uint32_t *work = worklist[SAT ? cw : 0];
             run_work<SW>(A, frame[cf], work, classify(A, frame[cf], lo, hi, work));
         } else {
-            apply_frame<UC>(A, frame[cf], 0, cnt);
+            apply_frame<UC, MAX8>(A, frame[cf], 0, cnt);
             if (WIDE) {
                 const uint32_t chunk = A.ngrp * UC;
                 for (uint32_t base = chunk; base < cnt; base += chunk)
-                    apply_frame<UC>(A, frame[cf], base, cnt);
+                    apply_frame<UC, MAX8>(A, frame[cf], base, cnt);
             }
         }
         __syncthreads();
@@ -508,6 +519,40 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
 }
 
 }  // namespace
+
+hipError_t launch_rowmax_global(const DevOps &s, uint32_t rows, uint32_t nwords, uint64_t *M,
+                                int64_t ld, uint64_t *scratch, uint32_t scratch_rows,
+                                unsigned long long *traffic, hipStream_t st) {
+    (void)scratch_rows;
+    if (s.L == 0) return hipSuccess;
+    const uint32_t sw = nwords < 8 ? nwords : 8;
+    const uint32_t slices = (nwords + sw - 1) / sw;
+    switch (sw) {
+        case 2:
+            hipLaunchKernelGGL((k_rowor_global<2, 3, false, false, true>), dim3(slices), dim3(1024),
+                               0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
+                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_rowor_global<4, 5, false, false, true>), dim3(slices), dim3(1024),
+                               0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
+                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_rowor_global<8, 10, false, false, true>), dim3(slices),
+                               dim3(1024), 0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
+                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+uint32_t rowmax_workgroups(uint32_t nwords) {
+    const uint32_t sw = nwords < 8 ? nwords : 8;
+    return (nwords + sw - 1) / sw;
+}
 
 uint32_t default_slice_words(uint32_t n, int64_t ld) {
     (void)ld;

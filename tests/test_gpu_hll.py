@@ -1,0 +1,65 @@
+"""GPU parity of the HyperLogLog stream (Sec. 3.4): registers bit-exact
+against the HLL oracle and, at a larger size, against the registers of the
+exact out-components the GPU matrix gives; estimates to fp64 rounding."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tn_inputs as T
+from oracle import hll
+
+pytestmark = pytest.mark.gpu
+
+tn = pytest.importorskip("paper_2307_04890_amd")
+
+
+@pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.TIES_SEQUENTIAL, tn.FORWARD,
+                                   tn.FORWARD | tn.DIRECTED])
+def test_registers_and_estimates_match_the_oracle(flags):
+    for case, (n, m, Tm, b) in enumerate([(60, 300, 40, 4), (200, 1500, 300, 6), (500, 4000, 900, 8),
+                                          (1000, 3000, 2000, 5), (7, 0, 1, 7)]):
+        s, d, t = T.random_tiny(n, max(m, 1), Tm, seed=700 + case)
+        s, d, t = s[:m], d[:m], t[:m]
+        h = T.hll_node_hashes(n, seed=70 + case)
+        M, est = tn.hll_build(n, s, d, t, h, b, flags=flags)
+        want = hll.stream_registers(n, s, d, t, h, b, directed=bool(flags & tn.DIRECTED),
+                                    sequential=bool(flags & tn.TIES_SEQUENTIAL),
+                                    forward=bool(flags & tn.FORWARD))
+        got = M.cpu().numpy()
+        assert (got == want).all(), case
+        we = hll.estimate(want)
+        assert np.allclose(est.cpu().numpy(), we, rtol=1e-12, atol=0), case
+
+
+def test_union_property_at_scale_against_the_exact_matrix():
+    n, m, b = 20_000, 200_000, 8
+    s, d, t = T.activity_driven(n, m, 40_000, seed=17)
+    h = T.hll_node_hashes(n, seed=18)
+    p = tn.Plan(n, s, d, t)
+    M, est = p.hll(h, b)
+    C = p.execute()
+    torch.cuda.synchronize()
+    got = M.cpu().numpy()
+    rows = C.cpu().numpy().view(np.uint64)
+    out, _ = tn.component_sizes(C, n, inn=False)
+    sizes = out.cpu().numpy()
+    for u in T.rng(3).choice(n, 60, replace=False):
+        members = np.nonzero(oracle.to_dense(rows[u:u + 1], n)[0])[0]
+        assert (got[u] == hll.registers_of_set(h[members], b)).all(), u
+    # the estimator's accuracy: standard error about 1.04 / sqrt(256) = 6.5 %
+    e = est.cpu().numpy()
+    big = sizes > 1000
+    assert big.sum() > 100
+    rel = e[big] / sizes[big] - 1
+    assert abs(rel.mean()) < 0.03 and rel.std() < 0.1
+    p.close()
+
+
+def test_hll_errors():
+    with pytest.raises(tn.TNError) as e:
+        tn.hll_build(10, [0], [1], [0], T.hll_node_hashes(10, 1), 3)
+    assert e.value.code == -1
+    with pytest.raises(tn.TNError) as e:
+        tn.hll_build(10, [0], [10], [0], T.hll_node_hashes(10, 1), 6)
+    assert e.value.code == -2
