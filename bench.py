@@ -20,6 +20,9 @@ Other modes (each prints its own single JSON line):
                    m = 10^6) and evaluated on 4 held-out networks
                    (n = 100,000, m = 10^7) against the exact sizes, beside the
                    fusion estimate and the smallest lifted size.
+  --mode hll       the HyperLogLog stream at n = 10^6, m = 10^8 (2^b one-byte
+                   registers per node instead of n bits), with its accuracy
+                   against the exact sizes at n = 10^5, m = 10^7.
   --mode sweep     the paper's synthetic experiment: ER G(n, 2/n) with a
                    Poisson process per link, n from 100 to 10^4 and m from
                    10^4 to 10^7, exact against hashed (H = 5, n_s = 0.3 n):
@@ -598,6 +601,72 @@ def run_sweep(args):
     return r
 
 
+def run_hll(args):
+    """HyperLogLog stream (Sec. 3.4) at the n = 10^6, m = 10^8 workload, where
+    the exact matrix would take 125 GB: registers of 2^b bytes per node,
+    resident plan; accuracy against the exact sizes at n = 10^5, m = 10^7."""
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+
+    b = args.hll_log2s
+    workload = args.workload or "activity_n1M_m100M"
+    spec = T.WORKLOADS[workload]
+    n = spec["n"]
+    log(f"[bench] generating {workload}")
+    s, d, t = T.make_workload(workload)
+    m = int(s.shape[0])
+    h = T.hll_node_hashes(n, seed=11)
+    ctx = tn.get_context()
+    t0 = time.perf_counter()
+    plan = tn.Plan(n, s, d, t)
+    plan_wall = time.perf_counter() - t0
+    st = plan.stats
+    log(f"[bench] plan: {st['op_levels']} op levels, {st['ops']} ops, {plan_wall:.1f} s")
+    elapsed, kms, _ = timed(ctx, lambda: plan.hll(h, b), args.steps, args.warmup)
+    M, est = plan.hll(h, b)
+    torch.cuda.synchronize()
+    e = est.cpu().numpy()
+    stream_ms = kms["rowor"]
+    ld_w, st_w = ctx.last_traffic()
+    moved = 8.0 * (ld_w + st_w) + 16.0 * st["ops"]
+    config = {"workload": workload, "n": n, "m": m, "T": spec["T"], "generator": spec["kind"],
+              "seed": spec["seed"], "registers": 1 << b, "flags": "undirected,strict-ties",
+              "parallelism": "single-gpu"}
+    r = base_result(args, m * args.steps / elapsed, "events/s", args.steps,
+                    1e3 * elapsed / args.steps, config)
+    r["value_note"] = "resident plan: register init + HLL stream + estimates per step"
+    r["roofline"] = {"bound": "hbm", "achieved": moved / (stream_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": moved / (stream_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rowor_global (byte-max rows)", "algorithmic_bytes": moved,
+                     "bytes_note": "register words the kernel loaded and stored, plus the "
+                                   "schedule once", "avg_launch_ms": stream_ms,
+                     "levels": st["op_levels"],
+                     "us_per_level": 1e3 * stream_ms / max(1, st["op_levels"])}
+    r["kernels_ms"] = kms
+    r["hll"] = {"registers_bytes": n * (1 << b), "exact_matrix_bytes": n * ((n + 63) // 64) * 8,
+                "plan_wall_s": plan_wall, "mean_estimate": float(e.mean()),
+                "estimate_quantiles": [float(q) for q in np.percentile(e, [1, 50, 99])]}
+    plan.close()
+    # accuracy against exact sizes on the 10^5-node workload
+    s2, d2, t2 = T.make_workload("activity_n100000_m10M")
+    n2 = 100_000
+    h2 = T.hll_node_hashes(n2, seed=12)
+    _, est2 = tn.hll_build(n2, s2, d2, t2, h2, b)
+    C2, _ = tn.build_component_matrix_streamed(n2, s2, d2, t2)
+    out2, _ = tn.component_sizes(C2, n2, inn=False)
+    ex = out2.cpu().numpy().astype(np.float64)
+    rel = est2.cpu().numpy() / ex - 1.0
+    r["hll"]["accuracy_n100000_m10M"] = {
+        "mean_relative_error": float(np.mean(np.abs(rel))), "bias": float(np.mean(rel)),
+        "std": float(np.std(rel)), "expected_std": 1.04 / np.sqrt(1 << b),
+        "mean_exact": float(ex.mean())}
+    return r
+
+
 # ---------------------------------------------------------------------------
 # rocprofv3 summaries (run on the CSV files a profiled bench run wrote)
 def _read_csv(path):
@@ -675,7 +744,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="exact",
-                    choices=["exact", "hashed", "batched", "combiner", "sweep"])
+                    choices=["exact", "hashed", "batched", "combiner", "sweep", "hll"])
+    ap.add_argument("--hll-log2s", type=int, default=8,
+                    help="log2 of the HyperLogLog registers per node (--mode hll)")
     ap.add_argument("--sweep-max-m", type=float, default=1e7,
                     help="largest event count of the ER + Poisson sweep")
     ap.add_argument("--workload", default=None)
@@ -699,7 +770,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     run = {"exact": run_exact, "hashed": run_hashed, "batched": run_batched,
-           "combiner": run_combiner, "sweep": run_sweep}[args.mode]
+           "combiner": run_combiner, "sweep": run_sweep, "hll": run_hll}[args.mode]
     print(json.dumps(run(args)), flush=True)
 
 

@@ -520,14 +520,25 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
 
 }  // namespace
 
+// Register rows are short (2^b bytes), so the level loop is bound by the
+// instructions each lane issues per level, not by bytes: one word per lane
+// (two for rows past 32 words) measured fastest (2x over 8 words at 256
+// registers), one workgroup per word column.
+static uint32_t rowmax_slice_words(uint32_t nwords) { return nwords <= 32 ? 1u : 2u; }
+
 hipError_t launch_rowmax_global(const DevOps &s, uint32_t rows, uint32_t nwords, uint64_t *M,
                                 int64_t ld, uint64_t *scratch, uint32_t scratch_rows,
                                 unsigned long long *traffic, hipStream_t st) {
     (void)scratch_rows;
     if (s.L == 0) return hipSuccess;
-    const uint32_t sw = nwords < 8 ? nwords : 8;
+    const uint32_t sw = rowmax_slice_words(nwords);
     const uint32_t slices = (nwords + sw - 1) / sw;
     switch (sw) {
+        case 1:
+            hipLaunchKernelGGL((k_rowor_global<1, 2, false, false, true>), dim3(slices), dim3(1024),
+                               0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
+                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+            break;
         case 2:
             hipLaunchKernelGGL((k_rowor_global<2, 3, false, false, true>), dim3(slices), dim3(1024),
                                0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
@@ -550,7 +561,7 @@ hipError_t launch_rowmax_global(const DevOps &s, uint32_t rows, uint32_t nwords,
 }
 
 uint32_t rowmax_workgroups(uint32_t nwords) {
-    const uint32_t sw = nwords < 8 ? nwords : 8;
+    const uint32_t sw = rowmax_slice_words(nwords);
     return (nwords + sw - 1) / sw;
 }
 
