@@ -63,7 +63,7 @@ def kernel_source_hash(files) -> str:
 
 
 KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h"),
-                  "batch": ("tn_batch.hip", "tn_batch.h", "tn_internal.h"),
+                  "batch": ("tn_batch.hip", "tn_batch.h", "tn_batch.cpp", "tn_internal.h"),
                   "recombine": ("tn_hash.hip", "tn_hash.h")}
 
 
@@ -356,6 +356,7 @@ def run_batched(args):
     b.execute(Cs)  # tunes and captures
     torch.cuda.synchronize()
     tune_wall = time.perf_counter() - t0
+    _, tiles, lds_tiles = b.stats()  # of the tuned shape
     elapsed, kms, _ = timed(ctx, lambda: b.execute(Cs), args.steps, args.warmup)
     batch_ms = kms["batch"]
     # the plain one-network kernel, network by network, on the same matrices
@@ -375,14 +376,18 @@ def run_batched(args):
               "flags": "undirected,strict-ties", "parallelism": "single-gpu"}
     r = base_result(args, m_total / (batch_ms * 1e-3), "events/s", args.steps,
                     1e3 * elapsed / args.steps, config)
-    r["roofline"] = {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS,
+    # the tuned shape decides where the rows live: LDS-resident slices, or
+    # global-memory tiles whose rows stream through L2 and HBM
+    lds_bound = 2 * lds_tiles >= tiles
+    peak = LDS_PEAK_GBS if lds_bound else HBM_PEAK_GBS
+    r["roofline"] = {"bound": "lds" if lds_bound else "hbm", "achieved": achieved, "peak": peak,
+                     "unit": "GB/s", "frac": achieved / peak,
                      "traffic": load_traffic("batch", config["workload"]),
                      "kernel": "k_batch_persistent", "algorithmic_bytes": dense,
                      "hbm_equivalent_frac": achieved / HBM_PEAK_GBS, "avg_launch_ms": batch_ms}
     r["batched"] = {"graph_launch_ms": batch_ms, "plain_network_by_network_ms": plain_ms,
                     "speedup_vs_plain": plain_ms / batch_ms, "tiles": tiles,
-                    "lds_tiles": lds_tiles, "host_plan_wall_s": plan_wall,
+                    "lds_tiles": lds_tiles, "shape": b.shape(), "host_plan_wall_s": plan_wall,
                     "autotune_and_capture_s": tune_wall}
     for p in plans:
         p.close()
@@ -704,7 +709,10 @@ def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, la
     return out
 
 
-def summarize_trace(stats_csv, command, top=12):
+def summarize_trace(stats_csv, command, top=12, trace_csv=None, match=None, last=0):
+    """Per-kernel stats of a --kernel-trace --stats run; with trace_csv, match
+    and last, also the mean duration of the last `last` dispatches of the
+    kernel whose name contains `match` (the timed ones, after autotuning)."""
     rows = _read_csv(stats_csv)
     lines = [f"command: {command}", "",
              f"{'calls':>6} {'avg ms':>10} {'total ms':>10} {'%':>6}  kernel"]
@@ -712,6 +720,14 @@ def summarize_trace(stats_csv, command, top=12):
         lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:10.3f} "
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}  "
                      f"{r['Name'][:110]}")
+    if trace_csv and match and last:
+        ds = [(int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+              for r in _read_csv(trace_csv) if match in r["Kernel_Name"]]
+        ds.sort()
+        tail = [d for _, d in ds[-last:]]
+        lines += ["", f"last {len(tail)} dispatches of {match} (the timed launches): "
+                      f"mean {sum(tail) / max(len(tail), 1) / 1e6:.3f} ms, each "
+                      + ", ".join(f"{d / 1e6:.3f}" for d in tail) + " ms"]
     return "\n".join(lines) + "\n"
 
 
@@ -722,6 +738,7 @@ def main():
         sp.add_argument("--fetch")
         sp.add_argument("--write")
         sp.add_argument("--stats")
+        sp.add_argument("--trace")
         sp.add_argument("--kernel", default="rowor")
         sp.add_argument("--workload", default="activity_n100000_m10M")
         sp.add_argument("--command", required=True)
@@ -737,7 +754,8 @@ def main():
                 json.dump(rec, f, indent=1)
         else:
             with open(a.out, "w") as f:
-                f.write(summarize_trace(a.stats, a.command))
+                f.write(summarize_trace(a.stats, a.command, trace_csv=a.trace, match=a.match,
+                                        last=a.last))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -330,6 +330,13 @@ tn_status tn_batch_execute(tn_ctx *ctx, tn_batch *batch, uint64_t *const *C,
 tn_status tn_batch_get_stats(const tn_batch *batch, tn_plan_stats *stats,
                              int64_t *tiles, int64_t *lds_tiles);
 
+/* The launch shape the batch runs with (the tuned one once it has been
+ * executed): shape[0] threads per workgroup, [1] dynamic LDS bytes per
+ * workgroup, [2] workgroups resident per compute unit, [3] grid size,
+ * [4] slice halvings below the widest slice that fits, [5] slice width of
+ * global-memory tiles in words.  shape: HOST int64[6].  Errors: TN_E_ARG. */
+tn_status tn_batch_get_shape(const tn_batch *batch, int64_t *shape);
+
 void tn_batch_destroy(tn_batch *batch);
 
 /* One call: batch create, execute, destroy. */

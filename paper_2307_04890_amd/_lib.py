@@ -101,6 +101,7 @@ SIGNATURES = {
     "tn_batch_create": (_i32, [_P, _i32, _P, _P, _P, _P, _P, _u32, _PP]),
     "tn_batch_execute": (_i32, [_P, _P, _P, _P]),
     "tn_batch_get_stats": (_i32, [_P, _P, _P, _P]),
+    "tn_batch_get_shape": (_i32, [_P, _P]),
     "tn_batch_destroy": (None, [_P]),
     "tn_build_component_matrix_batched": (_i32, [_P, _i32, _P, _P, _P, _P, _P, _u32, _P, _P]),
     "tn_hash_build_proxies": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _u32, _u32, _P, _i32,

@@ -332,6 +332,13 @@ class Batch:
         check(lib.tn_batch_get_stats(self.h, st, ctypes.byref(tiles), ctypes.byref(lds)))
         return [s.as_dict() for s in st], int(tiles.value), int(lds.value)
 
+    def shape(self) -> dict:
+        """The launch shape (the tuned one after the first execute())."""
+        v = (ctypes.c_int64 * 6)()
+        check(lib.tn_batch_get_shape(self.h, v))
+        keys = ("threads", "lds_bytes", "per_cu", "grid", "halvings", "global_width")
+        return dict(zip(keys, (int(x) for x in v)))
+
     def alloc(self):
         return [alloc_matrix(n, device=self.ctx.device) for n in self.ns]
 

@@ -9,6 +9,19 @@
 
 #include "tn_batch.h"
 
+namespace tn {
+// Launch shape of a batch: slice halvings, threads per workgroup, LDS bytes
+// a workgroup may take (a smaller budget fits more workgroups on a compute
+// unit and sends the widest networks to global-memory tiles) and the slice
+// width of global-memory tiles, in words.
+struct BatchShape {
+    int policy = 0;
+    uint32_t threads = 1024;
+    uint32_t lds = 163840;  // all of a compute unit's LDS on gfx950
+    uint32_t gwidth = 8;
+};
+}  // namespace tn
+
 struct tn_batch {
     int device = 0;
     int32_t B = 0;
@@ -20,10 +33,10 @@ struct tn_batch {
     void *dev_sched = nullptr;   // every schedule, one allocation
     // shapes
     std::vector<uint32_t> lw, mode;
-    uint32_t threads = 1024;
+    tn::BatchShape shape;
     uint32_t grid = 0;
     size_t dyn_lds = 0;
-    int policy = 0;
+    int per_cu = 0;
     // device metadata
     void *dev_meta = nullptr;
     size_t meta_bytes = 0;
@@ -55,8 +68,6 @@ namespace tn {
 
 namespace {
 
-constexpr size_t kLdsLimit = 163840;  // bytes of LDS per workgroup on gfx950
-
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 uint32_t pow2_ceil(uint32_t x) {
@@ -71,12 +82,14 @@ uint32_t ilog2(uint32_t x) {
     return l;
 }
 
-size_t lds_budget() { return kLdsLimit - batch_static_lds() - 256; }
+// dynamic LDS bytes left of a workgroup budget
+size_t lds_budget(size_t limit) { return limit - batch_static_lds() - 256; }
 
 // Widest power-of-two slice (<= 64 words) whose rows plus compound scratch
 // (plus the saturation bitmap when `sat`) fit in LDS; 0 if none does.
-uint32_t lds_fit_words(uint32_t n, int64_t max_gat, uint32_t nwords, bool sat) {
-    const size_t budget = lds_budget() - (sat ? sat_bitmap_bytes(n) : 0);
+uint32_t lds_fit_words(uint32_t n, int64_t max_gat, uint32_t nwords, bool sat, size_t limit) {
+    if (lds_budget(limit) < (sat ? sat_bitmap_bytes(n) : 0)) return 0;
+    const size_t budget = lds_budget(limit) - (sat ? sat_bitmap_bytes(n) : 0);
     uint32_t w = std::min<uint32_t>(64, pow2_ceil(nwords));
     for (; w >= 1; w >>= 1)
         if ((size_t)(n + (size_t)max_gat) * w * 8 <= budget) return w;
@@ -94,12 +107,13 @@ void free_meta(tn_batch *b) {
 // Chooses tile shapes for `policy` (0: widest slice that fits, k: k halvings
 // for more, smaller tiles), builds the LPT-ordered per-XCD queues and
 // uploads the descriptors.
-tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
+tn_status apply_shape(tn_ctx *ctx, tn_batch *b, const BatchShape &shape) {
     hipError_t se = hipStreamSynchronize(ctx->stream);
     if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
     free_meta(b);
-    b->policy = policy;
-    b->threads = threads;
+    b->shape = shape;
+    const int policy = shape.policy;
+    const uint32_t threads = shape.threads;
     b->sat = ctx->saturation;
     const int32_t B = b->B;
     b->lw.assign(B, 0);
@@ -117,8 +131,8 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
         const uint32_t nw = b->nwords[i];
         const size_t bm = sat_bitmap_bytes(b->n[i]);
         // the bitmap must fit beside the LDS tile, or alone for a global tile
-        sat_on[i] = b->sat && bm <= lds_budget();
-        uint32_t w = lds_fit_words(b->n[i], b->max_gat[i], nw, sat_on[i]);
+        sat_on[i] = b->sat && bm <= lds_budget(shape.lds);
+        uint32_t w = lds_fit_words(b->n[i], b->max_gat[i], nw, sat_on[i], shape.lds);
         if (b->streamed && !b->force_lw.empty()) {
             // the chunk keeps the stream's slices: LDS if that width fits
             const uint32_t fw = 1u << b->force_lw[i];
@@ -126,7 +140,7 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
             w = fw;
         } else if (w == 0) {
             b->mode[i] = kTileGlobal;
-            w = std::min<uint32_t>(8, pow2_ceil(nw));
+            w = std::min<uint32_t>(shape.gwidth, pow2_ceil(nw));
         }
         if (b->mode[i] == kTileGlobal && b->max_gat[i] > 0) {
             gscr_off[i] = gscr_words;
@@ -169,6 +183,7 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, int policy, uint32_t threads) {
     hipError_t e = batch_occupancy((int)threads, dyn, &per_cu);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     if (per_cu < 1) return fail(TN_E_UNSUPPORTED, "batch kernel does not fit on a compute unit");
+    b->per_cu = per_cu;
     const size_t ntiles = b->h_tiles.size();
     b->grid = (uint32_t)std::max<size_t>(1, std::min<size_t>((size_t)ctx->num_cus * per_cu, ntiles));
     // metadata allocation: nets, tiles, qptr, counters, global scratch
@@ -234,7 +249,7 @@ tn_status bind_outputs(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64
 }
 
 hipError_t launch_direct(tn_batch *b, hipStream_t st) {
-    return launch_batch(b->d_nets, b->d_tiles, b->d_qptr, b->d_counters, b->grid, b->threads,
+    return launch_batch(b->d_nets, b->d_tiles, b->d_qptr, b->d_counters, b->grid, b->shape.threads,
                         b->dyn_lds, b->done_count, st);
 }
 
@@ -266,25 +281,22 @@ tn_status capture_graph(tn_batch *b) {
 
 // Times every candidate shape on the device and keeps the fastest.
 tn_status autotune(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64_t *ld) {
-    struct Cand {
-        int policy;
-        uint32_t threads;
-    };
-    std::vector<Cand> cands;
-    for (int p = 0; p <= 2; ++p)
-        for (uint32_t th : {256u, 512u, 1024u}) cands.push_back({p, th});
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(TN_E_HIP, "event creation failed");
     float best_ms = 1e30f;
-    Cand best = cands[0];
+    bool found = false;
+    BatchShape best;
     tn_status st = TN_OK;
-    for (const Cand &c : cands) {
-        st = apply_shape(ctx, b, c.policy, c.threads);
-        if (st == TN_E_UNSUPPORTED) continue;
-        if (st != TN_OK) break;
+    auto trial = [&](const BatchShape &c) -> bool {
+        st = apply_shape(ctx, b, c);
+        if (st == TN_E_UNSUPPORTED) {
+            st = TN_OK;
+            return true;
+        }
+        if (st != TN_OK) return false;
         st = bind_outputs(ctx, b, C, ld);
-        if (st != TN_OK) break;
+        if (st != TN_OK) return false;
         hipError_t e = hipEventRecord(e0, ctx->stream);
         if (e == hipSuccess) e = launch_direct(b, ctx->stream);
         if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
@@ -293,17 +305,32 @@ tn_status autotune(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64_t *
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (e != hipSuccess) {
             st = hip_fail(e, "autotune launch");
-            break;
+            return false;
         }
         if (ms < best_ms) {
             best_ms = ms;
             best = c;
+            found = true;
         }
+        return true;
+    };
+    // stage 1: LDS budget per workgroup x threads, widest slices; stage 2:
+    // slice halvings and global tile width around the winner
+    bool ok = true;
+    for (uint32_t lds : {163840u, 81920u, 40960u, 20480u, 10240u})
+        for (uint32_t th : {256u, 512u, 1024u})
+            if (ok) ok = trial(BatchShape{0, th, lds, 8});
+    if (ok && found) {
+        const BatchShape s1 = best;
+        for (int p = 0; p <= 2; ++p)
+            for (uint32_t gw : {8u, 16u, 32u})
+                if (ok && (p != 0 || gw != 8)) ok = trial(BatchShape{p, s1.threads, s1.lds, gw});
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st != TN_OK && st != TN_E_UNSUPPORTED) return st;
-    st = apply_shape(ctx, b, best.policy, best.threads);
+    if (!ok) return st;
+    if (!found) return fail(TN_E_UNSUPPORTED, "no batch shape fits on a compute unit");
+    st = apply_shape(ctx, b, best);
     if (st != TN_OK) return st;
     b->tuned = true;
     return TN_OK;
@@ -384,7 +411,7 @@ tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t 
         if (stream->lw) b->force_lw.assign(stream->lw, stream->lw + B);
         if (stream->persist) b->persist.assign(stream->persist, stream->persist + B);
     }
-    tn_status st = apply_shape(ctx, b, 0, 1024);
+    tn_status st = apply_shape(ctx, b, BatchShape{});
     if (st != TN_OK) {
         free_meta(b);
         (void)hipFree(b->dev_sched);
@@ -412,7 +439,7 @@ tn_status batch_execute(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int6
         if (st != TN_OK) return st;
     } else if (b->sat != ctx->saturation) {
         // the context's saturation setting changed: rebuild the shape
-        st = apply_shape(ctx, b, b->policy, b->threads);
+        st = apply_shape(ctx, b, b->shape);
         if (st != TN_OK) return st;
     }
     st = bind_outputs(ctx, b, C, ld);
@@ -475,6 +502,17 @@ tn_status tn_batch_get_stats(const tn_batch *b, tn_plan_stats *stats, int64_t *t
         for (int32_t i = 0; i < b->B; ++i) stats[i] = b->stats[i];
     if (tiles) *tiles = (int64_t)b->h_tiles.size();
     if (lds_tiles) *lds_tiles = b->lds_tiles;
+    return TN_OK;
+}
+
+tn_status tn_batch_get_shape(const tn_batch *batch, int64_t *shape) {
+    if (!batch || !shape) return tn::fail(TN_E_ARG, "batch or shape is NULL");
+    shape[0] = batch->shape.threads;
+    shape[1] = (int64_t)batch->dyn_lds;
+    shape[2] = batch->per_cu;
+    shape[3] = batch->grid;
+    shape[4] = batch->shape.policy;
+    shape[5] = batch->shape.gwidth;
     return TN_OK;
 }
 

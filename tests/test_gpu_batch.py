@@ -123,3 +123,57 @@ def test_saturating_networks_with_and_without_skipping():
     finally:
         ctx.saturation(True)
         b.close()
+
+
+def test_dense_unsaturated_networks():
+    # dense activity-driven networks in which nodes active only late in time
+    # keep small out-components: tiles never saturate, although most of
+    # their items have full operands and full destinations
+    nets = []
+    for i, (n, m, Tm) in enumerate([(3000, 36_000, 3_600), (6000, 72_000, 7_200),
+                                    (1200, 14_400, 1_440), (4000, 40_000, 4_000)]):
+        s, d, t = T.activity_driven(n, m, Tm, seed=910 + i)
+        nets.append((n, s, d, t))
+    want = [oracle.reverse_matrix(n, s, d, t) for n, s, d, t in nets]
+    assert all(oracle.sizes(w, n)[0].min() < n for w, (n, _, _, _) in zip(want, nets))
+    ctx = tn.get_context()
+    b = tn.Batch(nets)
+    try:
+        for sat in (True, False):
+            ctx.saturation(sat)
+            Cs = b.execute()
+            for (n, _, _, _), C, w in zip(nets, Cs, want):
+                assert (host(C)[:, :oracle.words(n)] == w).all(), (sat, n)
+        for flags in (tn.DIRECTED, tn.FORWARD):
+            Cs = tn.build_component_matrix_batched(nets[:2], flags=flags)
+            for (n, s, d, t), C in zip(nets[:2], Cs):
+                ref = oracle.forward_matrix if flags == tn.FORWARD else oracle.reverse_matrix
+                assert (host(C)[:, :oracle.words(n)] ==
+                        ref(n, s, d, t, directed=bool(flags & tn.DIRECTED))).all()
+    finally:
+        ctx.saturation(True)
+        b.close()
+
+
+def test_star_steps_wide_and_narrow_gathers():
+    # one star per time step: the hub's compound item gathers from up to
+    # 1 + max_k rows (records with more than three sources read the rest from
+    # the source list), partners gather from two rows, self-loops from one;
+    # an LDS tile, a dense saturating one and a global-memory tile
+    nets = []
+    for i, (n, steps, k) in enumerate([(300, 3000, 9), (2000, 20000, 12), (30000, 4000, 6)]):
+        s, d, t = T.star_steps(n, steps, k, seed=950 + i)
+        nets.append((n, s, d, t))
+    sizes = set()
+    for n, s, d, t in nets:
+        sizes |= set(np.diff(tn.host_schedule(n, s, d, t)["gat_ptr"]).tolist())
+    assert min(sizes) <= 2 and max(sizes) >= 8
+    ctx = tn.get_context()
+    try:
+        for sat in (True, False):
+            ctx.saturation(sat)
+            for flags in (0, tn.DIRECTED):
+                Cs = tn.build_component_matrix_batched(nets, flags=flags)
+                check(nets, Cs, directed=bool(flags & tn.DIRECTED))
+    finally:
+        ctx.saturation(True)

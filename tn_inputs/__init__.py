@@ -25,6 +25,7 @@ __all__ = [
     "activities", "hash_coefficients", "MERSENNE61", "mlp_init", "MLP_SIZES",
     "mlp_param_count", "NetSpec", "batched_suite", "WORKLOADS", "make_workload",
     "static_graph_rounds", "chronological_path", "random_tiny", "hll_node_hashes",
+    "star_steps",
 ]
 
 MERSENNE61 = (1 << 61) - 1
@@ -157,6 +158,26 @@ def static_graph_rounds(n: int, n_links: int, rounds: int, seed: int):
     dst = np.tile(b, rounds).astype(np.uint32)
     t = np.repeat(np.arange(rounds, dtype=np.int64), n_links)
     return (a.astype(np.uint32), b.astype(np.uint32)), sort_events(src, dst, t)
+
+
+def star_steps(n: int, steps: int, max_k: int, seed: int):
+    """One star per time step: a random hub with 1..max_k distinct random
+    partners (a partner equal to the hub makes a self-loop event), so time
+    steps touch hubs with every number of partners up to max_k."""
+    g = rng(seed)
+    src, dst, t = [], [], []
+    for step in range(steps):
+        hub = int(g.integers(0, n))
+        k = int(g.integers(1, max_k + 1))
+        partners = g.choice(n, size=min(k, n), replace=False)
+        for p in partners:
+            if g.random() < 0.5:
+                src.append(hub); dst.append(int(p))
+            else:
+                src.append(int(p)); dst.append(hub)
+            t.append(step)
+    return sort_events(np.asarray(src, dtype=np.uint32), np.asarray(dst, dtype=np.uint32),
+                       np.asarray(t, dtype=np.int64))
 
 
 def chronological_path(k: int):
