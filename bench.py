@@ -132,11 +132,28 @@ def cpu_baseline_exact(n, s, d, t, budget_s: float):
     oracle.reverse_matrix(n, s, d, t, w0=0, nw=k)
     dt = time.perf_counter() - t0
     full_equiv = dt * nwords / k
-    return {"value": s.shape[0] / full_equiv, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"reverse-time recurrence on word columns [0,{k}) of {nwords} "
-                      f"({100.0 * k / nwords:.1f}% of the matrix), all {s.shape[0]} events; "
-                      f"{dt:.2f} s single-threaded, scaled to the full width",
-            "seconds": dt, "host_nproc": os.cpu_count()}
+    rec = {"value": s.shape[0] / full_equiv, "unit": "events/s", "cores": 1, "kind": "oracle",
+           "sample": f"reverse-time recurrence on word columns [0,{k}) of {nwords} "
+                     f"({100.0 * k / nwords:.1f}% of the matrix), all {s.shape[0]} events; "
+                     f"{dt:.2f} s single-threaded, scaled to the full width",
+           "seconds": dt, "host_nproc": os.cpu_count()}
+    # the same oracle on every host core: word columns are independent, so
+    # each thread runs it on its own column range (the calls release the GIL)
+    import concurrent.futures as cf
+    threads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16"))))
+    ka = min(nwords, k * threads)
+    cuts = [ka * i // threads for i in range(threads + 1)]
+    parts = [(cuts[i], cuts[i + 1] - cuts[i]) for i in range(threads) if cuts[i + 1] > cuts[i]]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(len(parts)) as ex:
+        list(ex.map(lambda p: oracle.reverse_matrix(n, s, d, t, w0=p[0], nw=p[1]), parts))
+    dta = time.perf_counter() - t0
+    rec["all_cores"] = {"value": s.shape[0] / (dta * nwords / ka), "unit": "events/s",
+                        "cores": len(parts), "kind": "oracle",
+                        "sample": f"word columns [0,{ka}) of {nwords} split over {len(parts)} "
+                                  f"threads; {dta:.2f} s wall, scaled to the full width",
+                        "seconds": dta}
+    return rec
 
 
 def run_exact(args):
@@ -190,7 +207,8 @@ def run_exact(args):
                     1e3 * elapsed / args.steps, config)
     r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("rowor", workload),
-                     "kernel": "k_rowor_global", "algorithmic_bytes": alg,
+                     "kernel": "k_rowor_global (zero-phase launch + the remaining levels)",
+                     "algorithmic_bytes": alg,
                      "avg_launch_ms": kms["rowor"], "moved_bytes": moved,
                      "moved_achieved": moved_gbs, "moved_frac": moved_gbs / HBM_PEAK_GBS,
                      "levels": st["op_levels"],
@@ -204,6 +222,8 @@ def run_exact(args):
     # the whole job from host events: streamed one-shot build (planning on
     # host threads overlapped with the device, stop at saturation) + sizes
     plan.close()
+    if args.no_end_to_end:
+        return r
     ee = []
     for rep in range(3):
         torch.cuda.synchronize()
@@ -681,12 +701,12 @@ def _read_csv(path):
 
 
 def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, last=0,
-                  match=None):
+                  match=None, per_launch=1):
     """HBM bytes per launch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB per
     dispatch, one --pmc run each), each scaled by what the same counter read
     for the plain device copy of calib_mib MiB in the same run.  last > 0
     keeps only the kernel's last `last` dispatches (the timed ones, after
-    autotuning)."""
+    autotuning); a launch is `per_launch` consecutive dispatches."""
     match = match or {"rowor": "k_rowor_global", "batch": "k_batch_persistent",
                       "recombine": "k_recombine_est"}[kernel]
     out = {"kernel": match, "workload": workload, "command": command,
@@ -702,17 +722,21 @@ def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, la
         if last:
             vals = vals[-last:]
         factor = known_kib / calib
+        launches = max(len(vals) / per_launch, 1)
         out[name] = {"kib_per_dispatch": vals, "calibration_kib": calib, "factor": factor,
-                     "bytes_per_launch": 1024.0 * factor * sum(vals) / max(len(vals), 1)}
+                     "dispatches_per_launch": per_launch,
+                     "bytes_per_launch": 1024.0 * factor * sum(vals) / launches}
     out["hbm_bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + \
         out["WRITE_SIZE"]["bytes_per_launch"]
     return out
 
 
-def summarize_trace(stats_csv, command, top=12, trace_csv=None, match=None, last=0):
+def summarize_trace(stats_csv, command, top=12, trace_csv=None, match=None, last=0,
+                    per_launch=1):
     """Per-kernel stats of a --kernel-trace --stats run; with trace_csv, match
     and last, also the mean duration of the last `last` dispatches of the
-    kernel whose name contains `match` (the timed ones, after autotuning)."""
+    kernel whose name contains `match` (the timed ones, after autotuning),
+    summed over each launch of `per_launch` consecutive dispatches."""
     rows = _read_csv(stats_csv)
     lines = [f"command: {command}", "",
              f"{'calls':>6} {'avg ms':>10} {'total ms':>10} {'%':>6}  kernel"]
@@ -725,9 +749,14 @@ def summarize_trace(stats_csv, command, top=12, trace_csv=None, match=None, last
               for r in _read_csv(trace_csv) if match in r["Kernel_Name"]]
         ds.sort()
         tail = [d for _, d in ds[-last:]]
-        lines += ["", f"last {len(tail)} dispatches of {match} (the timed launches): "
-                      f"mean {sum(tail) / max(len(tail), 1) / 1e6:.3f} ms, each "
-                      + ", ".join(f"{d / 1e6:.3f}" for d in tail) + " ms"]
+        k = max(1, per_launch)
+        groups = [sum(tail[i:i + k]) for i in range(0, len(tail) - k + 1, k)]
+        what = f"launches of {k} dispatches" if k > 1 else "dispatches"
+        lines += ["", f"last {len(groups)} {what} of {match} (the timed launches): "
+                      f"mean {sum(groups) / max(len(groups), 1) / 1e6:.3f} ms, each "
+                      + ", ".join(f"{d / 1e6:.3f}" for d in groups) + " ms"]
+        if k > 1:
+            lines.append("  dispatch durations: " + ", ".join(f"{d / 1e6:.3f}" for d in tail) + " ms")
     return "\n".join(lines) + "\n"
 
 
@@ -745,17 +774,18 @@ def main():
         sp.add_argument("--calib-mib", type=int, default=1024)
         sp.add_argument("--last", type=int, default=0)
         sp.add_argument("--match", default=None, help="kernel name substring")
+        sp.add_argument("--per-launch", type=int, default=1)
         sp.add_argument("--out", required=True)
         a = sp.parse_args(sys.argv[2:])
         if what == "--summarize-pmc":
             rec = summarize_pmc(a.fetch, a.write, a.kernel, a.workload, a.command, a.calib_mib,
-                                a.last, a.match)
+                                a.last, a.match, a.per_launch)
             with open(a.out, "w") as f:
                 json.dump(rec, f, indent=1)
         else:
             with open(a.out, "w") as f:
                 f.write(summarize_trace(a.stats, a.command, trace_csv=a.trace, match=a.match,
-                                        last=a.last))
+                                        last=a.last, per_launch=a.per_launch))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -769,6 +799,9 @@ def main():
                     help="largest event count of the ER + Poisson sweep")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--slice-words", type=int, default=0)
+    ap.add_argument("--no-end-to-end", action="store_true",
+                    help="exact mode: skip the streamed end-to-end runs (for profiles of the "
+                         "resident plan alone)")
     ap.add_argument("--hashes", type=int, default=16)
     ap.add_argument("--buckets", type=int, default=4096)
     ap.add_argument("--networks", type=int, default=256)

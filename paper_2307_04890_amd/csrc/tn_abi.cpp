@@ -164,6 +164,7 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
     }
     p->view = tn::ops_view(hs, p->dev);
     p->scratch_rows = hs.scratch_rows;
+    p->zero_levels = tn::zero_phase_levels(hs, n);
     tn::fill_stats(hs, p->stats);
     *out = p;
     return TN_OK;
@@ -281,13 +282,17 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         return fail(TN_E_ARG, "slice_words must be a power of two <= 64");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    // per-workgroup sink words, then the compound scratch rows, then (for a
+    // zero phase) the slice state the two launches share and its done counter
+    const size_t sink_rows_words = (size_t)tn::rowor_workgroups(n, slice_words) * tn::kRoworSinkWords +
+                                   (size_t)plan->scratch_rows * (size_t)nwords;
+    const bool zero_phase = ctx->saturation && plan->zero_levels > 0;
+    const size_t pwords = zero_phase ? tn::rowor_persist_words(n, slice_words) + 1 : 0;
     {
-        // per-workgroup sink words, then the compound scratch rows
-        const size_t words = (size_t)tn::rowor_workgroups(n, slice_words) * tn::kRoworSinkWords +
-                             (size_t)plan->scratch_rows * (size_t)nwords;
-        tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * words);
+        tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * sink_rows_words + 4 * pwords);
         if (st != TN_OK) return st;
     }
+    uint32_t *persist = zero_phase ? (uint32_t *)((uint64_t *)ctx->scratch + sink_rows_words) : nullptr;
     hipError_t e;
     if (!ctx->traffic) {
         e = hipMalloc((void **)&ctx->traffic, 2 * sizeof(unsigned long long));
@@ -299,13 +304,16 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     {
         tn::ProfScope ps(ctx, TN_K_IDENTITY);
         e = tn::launch_identity(C, n, ld, ctx->traffic, ctx->stream);
+        if (e == hipSuccess && persist)
+            e = tn::launch_fill_u32(persist, pwords, 0u, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "identity kernel launch");
     {
         tn::ProfScope ps(ctx, TN_K_ROWOR);
         e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
-                                    plan->scratch_rows, ctx->traffic, ctx->saturation,
-                                    nullptr, nullptr, ctx->stream);
+                                    plan->scratch_rows, ctx->traffic, ctx->saturation, persist,
+                                    persist ? persist + pwords - 1 : nullptr,
+                                    zero_phase ? plan->zero_levels : 0u, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "row-OR kernel launch");
     return TN_OK;

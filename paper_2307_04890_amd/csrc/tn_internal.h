@@ -145,6 +145,7 @@ struct tn_plan {
     size_t dev_bytes = 0;
     tn::DevOps view{};
     uint32_t scratch_rows = 0;
+    uint32_t zero_levels = 0;  // levels of the zero phase (tn::zero_phase_levels)
     tn_plan_stats stats{};
 };
 
@@ -194,7 +195,11 @@ constexpr size_t kRoworSatLds = 163840 - 40960;
 // The kernel adds the row words it loaded to traffic[0] and stored to
 // traffic[1] (device counters, zeroed by the caller).  With saturation, and
 // when a bit per row and scratch row fits kRoworSatLds, it skips the loads
-// and stores that saturated rows make redundant.  persist (nullable, only
+// and stores that saturated rows make redundant; when two such bitmaps fit,
+// also those that rows still all zero in a slice make redundant: with
+// persist, the first zero_levels levels run as a launch of their own that
+// tracks zero rows too (zero_phase_levels gives the number for a schedule
+// that starts from the identity, 0 turns the phase off).  persist (nullable, only
 // used with saturation): rowor_persist_words(n, slice_words) uint32 of
 // per-slice state carried between launches over consecutive chunks of one
 // stream, zero before the first; a slice that becomes all full sets its
@@ -204,10 +209,19 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
                                uint32_t slice_words, uint64_t *scratch,
                                uint32_t scratch_rows, unsigned long long *traffic,
                                bool saturation, uint32_t *persist, unsigned int *done_count,
-                               hipStream_t st);
-// uint32 words of persisted state: per slice, done + count + ceil(n/32) bits
+                               uint32_t zero_levels, hipStream_t st);
+// Levels of the zero phase of a schedule applied to the identity: those
+// before the level at which the ops so far reach n (about one op per row),
+// by when few row slices are still all zero.
+inline uint32_t zero_phase_levels(const HostSchedule &hs, uint32_t n) {
+    uint32_t l = 0;
+    while (l < hs.Lops && hs.lvl_op[l] < n) ++l;
+    return l;
+}
+// uint32 words of persisted state: per slice, done + count + ceil(n/32)
+// full-row bits + ceil(n/32) non-zero-row bits
 inline size_t rowor_persist_words(uint32_t n, uint32_t slice_words) {
-    return (size_t)rowor_workgroups(n, slice_words) * (((size_t)n + 31) / 32 + 2);
+    return (size_t)rowor_workgroups(n, slice_words) * (2 * (((size_t)n + 31) / 32) + 2);
 }
 // ids < n and non-decreasing t for every event, checked on several host
 // threads; the message names the first offending event (tn_stream.cpp)

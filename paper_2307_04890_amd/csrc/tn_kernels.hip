@@ -85,6 +85,12 @@ struct OpArgs {
     uint64_t fullw;     // this lane's word when its row slice is full (0 past the last word)
     uint64_t gmask;     // ballot bits of this lane's group
     int32_t *nfull;           // this level's change of the full real-row count
+    int32_t dfull, dzero;     // this lane's part of those changes, added once per wave
+    // zero bits (word-range skipping): same indexing as the saturation bits,
+    // bit set = the row is all zero in this slice
+    uint32_t *zb;
+    int32_t *nzero;           // this level's change of the zero real-row count
+    bool zon;                 // some real row is still zero (uniform per level)
     uint32_t loaded, stored;  // row words this lane moved
     bool lead;                // first lane of its group
 };
@@ -108,6 +114,20 @@ __device__ __forceinline__ uint32_t sat_index(const OpArgs &A, uint32_t id) {
 __device__ __forceinline__ bool sat_get(const OpArgs &A, uint32_t id) {
     const uint32_t i = sat_index(A, id);
     return (A.sat[i >> 5] >> (i & 31u)) & 1u;
+}
+
+__device__ __forceinline__ bool zero_get(const OpArgs &A, uint32_t id) {
+    const uint32_t i = sat_index(A, id);
+    return (A.zb[i >> 5] >> (i & 31u)) & 1u;
+}
+
+// A real row leaves the zero set once and never returns (rows only gain
+// bits); a scratch row is zero or not after each store into it.
+__device__ __forceinline__ void zero_set(OpArgs &A, uint32_t id, bool zero) {
+    const uint32_t i = sat_index(A, id);
+    if (zero) atomicOr(&A.zb[i >> 5], 1u << (i & 31u));
+    else atomicAnd(&A.zb[i >> 5], ~(1u << (i & 31u)));
+    if (!(id & kScratchBit)) A.dzero += zero ? 1 : -1;
 }
 
 // Byte-wise maximum of two words whose bytes are all below 128 (HyperLogLog
@@ -155,21 +175,50 @@ __device__ __forceinline__ void apply_frame(OpArgs &A, const op4 *frame, uint32_
 constexpr uint32_t kComputeWaves = (1024 - kLoaderThreads) / 64;
 constexpr uint32_t kWaveShare = (kOpsLevelCap + kComputeWaves - 1) / kComputeWaves;
 constexpr uint32_t kWorkSkip = 1u << 16, kWorkF1 = 1u << 17, kWorkF2 = 1u << 18;
+// zero flags: the result is zero (no loads), an operand is zero (no load
+// of it), a destination is zero
+constexpr uint32_t kWorkZero = 1u << 19, kWorkZX = 1u << 20, kWorkZY = 1u << 21;
+constexpr uint32_t kWorkZ1 = 1u << 22, kWorkZ2 = 1u << 23;
 
 // Flips the bit of a row whose state changed; a real row also moves this
-// level's count of full real rows.
-__device__ __forceinline__ void sat_set(const OpArgs &A, uint32_t id, bool full) {
+// level's count of full real rows: at once, or with AGG kept per lane and
+// added once per wave (level_counts).
+template <bool AGG>
+__device__ __forceinline__ void sat_set(OpArgs &A, uint32_t id, bool full) {
     const uint32_t i = sat_index(A, id);
     if (full) atomicOr(&A.sat[i >> 5], 1u << (i & 31u));
     else atomicAnd(&A.sat[i >> 5], ~(1u << (i & 31u)));
-    if (!(id & kScratchBit)) atomicAdd(A.nfull, full ? 1 : -1);
+    if (!(id & kScratchBit)) {
+        if (AGG) A.dfull += full ? 1 : -1;
+        else atomicAdd(A.nfull, full ? 1 : -1);
+    }
+}
+
+// Adds the wave's changes of the full and zero real-row counts to this
+// level's LDS counters: one atomic per wave and counter, not one per row (a
+// single LDS address serializes its atomics, and in the zero phase most
+// rows change state within a few hundred levels).  Skipped by waves with
+// nothing to add.
+__device__ __forceinline__ void level_counts(OpArgs &A) {
+    if (__ballot(A.dfull != 0 || A.dzero != 0) == 0) return;
+    int32_t f = A.dfull, z = A.dzero;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        f += __shfl_xor(f, off);
+        z += __shfl_xor(z, off);
+    }
+    if ((threadIdx.x & 63u) == 0) {
+        if (f) atomicAdd(A.nfull, f);
+        if (z) atomicAdd(A.nzero, z);
+    }
+    A.dfull = A.dzero = 0;
 }
 
 // The wave's nwork items (wave-uniform), one per lane group at a time.
 // Batching several items' loads per lane before their stores measured
 // slower: in the phase where most ops still need rows, the time goes to
 // random row-segment traffic, not to serialized round trips.
-template <int SW>
+template <int SW, bool ZERO>
 __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint32_t *work,
                                          uint32_t nwork) {
     constexpr uint32_t G = 64 / SW;  // lane groups per wave
@@ -178,30 +227,50 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
         const uint32_t j = j0 + g;
         const uint32_t e = work[min(j, kWaveShare - 1)];
         const op4 o = frame[e & (kOpsLevelCap - 1)];
-        const bool v = j < nwork, skip = e & kWorkSkip, ld = v && !skip;
-        const uint64_t x = *op_addr(A, o.x, ld);
-        const uint64_t y = *op_addr(A, o.y, ld);
-        A.loaded += (ld && A.wok) ? 2u : 0u;
-        const uint64_t r = skip ? A.fullw : (x | y);
+        const bool v = j < nwork, skip = e & kWorkSkip;
+        // an operand known zero in this slice is not loaded
+        const bool ldx = v && !skip && !(ZERO && (e & (kWorkZero | kWorkZX)));
+        const bool ldy = v && !skip && !(ZERO && (e & (kWorkZero | kWorkZY)));
+        const uint64_t x = *op_addr(A, o.x, ldx);
+        const uint64_t y = *op_addr(A, o.y, ldy);
+        A.loaded += ((ldx && A.wok) ? 1u : 0u) + ((ldy && A.wok) ? 1u : 0u);
+        const uint64_t r = skip ? A.fullw : ((ldx ? x : 0ull) | (ldy ? y : 0ull));
         // the group's SW lanes agree on whether the whole row slice is full
         const uint64_t ball = __ballot(r == A.fullw || !A.wok);
         const bool full = (ball & A.gmask) == A.gmask;
+        bool zero = false;
+        if (ZERO && A.zon) {
+            const uint64_t zb = __ballot(r == 0ull || !A.wok);
+            zero = (zb & A.gmask) == A.gmask;
+        }
         const bool f1 = e & kWorkF1, f2 = e & kWorkF2;
-        const bool s1 = v && o.z != kNoRow && !(full && f1);
-        const bool s2 = v && o.w != kNoRow && !(full && f2);
+        const bool z1 = ZERO && (e & kWorkZ1), z2 = ZERO && (e & kWorkZ2);
+        // a full result into a full row, or a zero result into a zero row,
+        // changes nothing
+        const bool s1 = v && o.z != kNoRow && !(full && f1) && !(zero && z1);
+        const bool s2 = v && o.w != kNoRow && !(full && f2) && !(zero && z2);
         *op_addr(A, o.z, s1) = r;
         *op_addr(A, o.w, s2) = r;
         A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
         // one lane per group refreshes the destinations' bits
         if (v && A.lead) {
-            if (o.z != kNoRow && f1 != full) sat_set(A, o.z, full);
-            if (o.w != kNoRow && f2 != full) sat_set(A, o.w, full);
+            if (o.z != kNoRow && f1 != full) sat_set<ZERO>(A, o.z, full);
+            if (o.w != kNoRow && f2 != full) sat_set<ZERO>(A, o.w, full);
+            if (ZERO && A.zon) {
+                if (o.z != kNoRow && z1 != zero) zero_set(A, o.z, zero);
+                if (o.w != kNoRow && z2 != zero) zero_set(A, o.w, zero);
+            }
         }
     }
 }
 
 // Classify ops [lo, hi) of the frame (hi - lo <= kWaveShare) into this
 // wave's work list; returns the list length (wave-uniform).
+// With ZERO and while some real row is zero, an op whose operands are both
+// zero has a zero result; it still needs a store only into a destination not
+// known to be zero (a scratch row: a real destination is contained in the
+// result, so it is zero too).
+template <bool ZERO>
 __device__ __forceinline__ uint32_t classify(const OpArgs &A, const op4 *frame, uint32_t lo,
                                              uint32_t hi, uint32_t *work) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -213,13 +282,25 @@ __device__ __forceinline__ uint32_t classify(const OpArgs &A, const op4 *frame, 
         const bool skip = sat_get(A, o.x) || sat_get(A, o.y);
         const bool f1 = o.z != kNoRow && sat_get(A, o.z);
         const bool f2 = o.w != kNoRow && sat_get(A, o.w);
-        const bool need = v && (!skip || (o.z != kNoRow && !f1) || (o.w != kNoRow && !f2));
+        bool zx = false, zy = false, z1 = false, z2 = false;
+        if (ZERO && A.zon) {
+            zx = zero_get(A, o.x);
+            zy = zero_get(A, o.y);
+            z1 = o.z != kNoRow && zero_get(A, o.z);
+            z2 = o.w != kNoRow && zero_get(A, o.w);
+        }
+        const bool zres = !skip && zx && zy;
+        const bool need =
+            v && (skip ? ((o.z != kNoRow && !f1) || (o.w != kNoRow && !f2))
+                       : (!zres || (o.z != kNoRow && !z1) || (o.w != kNoRow && !z2)));
         const uint64_t m = __ballot(need);
         const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         if (need)
             work[nwork + pos] = i | (skip ? kWorkSkip : 0u) | (f1 ? kWorkF1 : 0u) |
-                                (f2 ? kWorkF2 : 0u);
+                                (f2 ? kWorkF2 : 0u) | (zres ? kWorkZero : 0u) |
+                                (zx ? kWorkZX : 0u) | (zy ? kWorkZY : 0u) |
+                                (z1 ? kWorkZ1 : 0u) | (z2 ? kWorkZ2 : 0u);
         nwork += (uint32_t)__popcll(m);
     }
     return nwork;
@@ -262,7 +343,7 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
 // CHUNK: one launch per chunk of a streamed build, with the slice state in
 // `persist` (a separate instantiation, so traces and counters keep the two
 // kinds of launch apart).
-template <int SW, int UC, bool SAT, bool CHUNK, bool MAX8 = false>
+template <int SW, int UC, bool SAT, bool CHUNK, bool MAX8 = false, bool ZERO = false>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
                uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
@@ -275,6 +356,10 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     // level l adds into slot l % 3, every wave reads it after the barrier
     // that ends level l, and slot (l + 1) % 3 is cleared during level l
     __shared__ int32_t fdelta[3];
+    // the same for the zero real-row count (ZERO), and its start value
+    __shared__ int32_t zdelta[3];
+    __shared__ int32_t zcount0;
+    // dynamic: the saturation bitmap, then (ZERO) the zero bitmap
     extern __shared__ uint32_t satbits[];
     const uint32_t L = s.L;
     if (L == 0 || s.nops == 0) return;
@@ -311,25 +396,67 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     // slice {done, full-row count, real-row bits}, carried from the launch
     // of the previous chunk; a slice already done returns at once.  Scratch
     // rows never outlive a time step, so their bits start at zero.
+    //
+    // ZERO keeps a second bitmap of rows that are all zero in the slice: at
+    // the start every real row except those of the slice's own nodes (the
+    // identity), minus the rows an earlier chunk made non-zero (persisted
+    // complemented, so that a cleared state means a fresh identity).
+    // Scratch rows start unknown.
     const uint32_t c0 = slice * SW * 64u;
     const bool single = c0 + 1 == n;
     const uint32_t rwords = sbase / 32;  // words of real-row bits
-    uint32_t *pst = (SAT && CHUNK) ? persist + (size_t)slice * (rwords + 2) : nullptr;
+    const uint32_t swords = (sbits + 31) / 32;
+    // persisted per slice: done, full count, full bits, non-zero bits (all
+    // ones, i.e. unknown, after a launch without ZERO)
+    const size_t pslice = 2 * (size_t)rwords + 2;
+    uint32_t *pst = (SAT && CHUNK) ? persist + (size_t)slice * pslice : nullptr;
+    uint32_t *zbits = satbits + swords;
     int32_t nfull = single ? 1 : 0;
+    int32_t nzero = 0;
     if (SAT) {
         if (pst) {
             if (pst[0]) return;
             nfull = (int32_t)pst[1];
             if (single && !((pst[2 + (c0 >> 5)] >> (c0 & 31u)) & 1u)) ++nfull;
         }
-        for (uint32_t i = tid; i < (sbits + 31) / 32; i += blockDim.x) {
+        if (ZERO && tid == 0) zcount0 = 0;
+        __syncthreads();
+        const uint32_t c1 = min(n, c0 + SW * 64u);  // the slice's own nodes: [c0, c1)
+        for (uint32_t i = tid; i < swords; i += blockDim.x) {
             uint32_t v = (pst && i < rwords) ? pst[2 + i] : 0u;
             if (single && i == (c0 >> 5)) v |= 1u << (c0 & 31u);
             satbits[i] = v;
+            if (ZERO) {
+                uint32_t z = 0u;
+                if (i < rwords) {
+                    const uint32_t r0 = 32 * i;
+                    // rows < n, minus the identity rows, minus persisted non-zero rows
+                    z = r0 + 32 <= n ? ~0u : (r0 < n ? (1u << (n - r0)) - 1u : 0u);
+                    const uint32_t a = max(r0, c0), b = min(r0 + 32, c1);
+                    if (a < b) {
+                        const uint32_t len = b - a;
+                        z &= ~((len == 32 ? ~0u : ((1u << len) - 1u)) << (a - r0));
+                    }
+                    if (pst) z &= ~pst[2 + rwords + i];
+                    if (z) atomicAdd(&zcount0, (int32_t)__popc(z));
+                }
+                zbits[i] = z;
+            }
         }
-        if (tid < 3) fdelta[tid] = 0;
+        if (tid < 3) {
+            fdelta[tid] = 0;
+            zdelta[tid] = 0;
+        }
+        if (ZERO) {
+            __syncthreads();
+            nzero = zcount0;
+        }
     }
     A.nfull = fdelta;
+    A.dfull = A.dzero = 0;
+    A.zb = zbits;
+    A.nzero = zdelta;
+    A.zon = false;
     // all waves add the same deltas at the same barriers, so they agree
     auto done = [&](uint32_t l) -> bool {
         if (!SAT) return false;
@@ -392,11 +519,20 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
         if (SAT) {
             A.nfull = &fdelta[l % 3];
             if (ctid == 0) fdelta[(l + 1) % 3] = 0;
+            if (ZERO) {
+                // the zero count settles like the full count: every compute
+                // wave adds the same delta after the same barrier
+                if (l > 0) nzero += zdelta[(l - 1) % 3];
+                A.nzero = &zdelta[l % 3];
+                if (ctid == 0) zdelta[(l + 1) % 3] = 0;
+                A.zon = nzero > 0;
+            }
             const uint32_t cw = ctid >> 6;
             const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
             const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
             uint32_t *work = worklist[SAT ? cw : 0];
-            run_work<SW>(A, frame[cf], work, classify(A, frame[cf], lo, hi, work));
+            run_work<SW, ZERO>(A, frame[cf], work, classify<ZERO>(A, frame[cf], lo, hi, work));
+            if (ZERO) level_counts(A);
         } else {
             apply_frame<UC, MAX8>(A, frame[cf], 0, cnt);
             if (WIDE) {
@@ -412,7 +548,10 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     if (pst) {
         // the last level's delta settled at the loop's final barrier
         if (!stopped) nfull += fdelta[(L - 1) % 3];
-        for (uint32_t i = ctid; i < rwords; i += blockDim.x - kLoaderThreads) pst[2 + i] = satbits[i];
+        for (uint32_t i = ctid; i < rwords; i += blockDim.x - kLoaderThreads) {
+            pst[2 + i] = satbits[i];
+            pst[2 + rwords + i] = ZERO ? ~zbits[i] : ~0u;
+        }
         if (ctid == 0) {
             pst[1] = (uint32_t)nfull;
             if (nfull == (int32_t)n) {
@@ -497,18 +636,40 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
 template <int SW, int UC>
 hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, uint64_t *scratch,
                          uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
-                         uint32_t *persist, unsigned int *done_count, hipStream_t st) {
+                         uint32_t *persist, unsigned int *done_count, uint32_t zero_levels,
+                         hipStream_t st) {
     const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
     const uint32_t sbase = (n + 31u) & ~31u;
     const uint64_t sbits = (uint64_t)sbase + scratch_rows + 1;
     const size_t lds = (size_t)((sbits + 31) / 32) * 4;
     if (saturation && lds <= kRoworSatLds) {
+        DevOps rest = s;
+        // zero phase: the first levels, while most row slices are still all
+        // zero, in a launch of its own that also keeps the zero bitmap; the
+        // slice state carries over to the launch of the remaining levels,
+        // which keeps only the full-row bits (the zero phase's per-level work
+        // would cost more than it saves there)
+        if (zero_levels > 0 && persist && 2 * lds <= kRoworSatLds) {
+            DevOps head = s;
+            head.L = min(zero_levels, s.L);
+            auto kz = k_rowor_global<SW, UC, true, true, false, true>;
+            hipError_t e = hipFuncSetAttribute((const void *)kz,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)(2 * lds));
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kz, dim3(slices), dim3(1024), 2 * lds, st, C, ld, n, nwords, head,
+                               scratch, sbase, (uint32_t)sbits, traffic, persist, done_count);
+            e = hipGetLastError();
+            if (e != hipSuccess || head.L == s.L) return e;
+            rest.L = s.L - head.L;
+            rest.lvl = s.lvl + head.L;
+        }
         auto k = persist ? k_rowor_global<SW, UC, true, true> : k_rowor_global<SW, UC, true, false>;
         hipError_t e = hipFuncSetAttribute((const void *)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, n, nwords, s, scratch,
+        hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, n, nwords, rest, scratch,
                            sbase, (uint32_t)sbits, traffic, persist, done_count);
     } else {
         hipLaunchKernelGGL((k_rowor_global<SW, UC, false, false>), dim3(slices), dim3(1024), 0,
@@ -602,17 +763,17 @@ uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words) {
 hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                                uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
                                unsigned long long *traffic, bool saturation, uint32_t *persist,
-                               unsigned int *done_count, hipStream_t st) {
+                               unsigned int *done_count, uint32_t zero_levels, hipStream_t st) {
     if (s.L == 0) return hipSuccess;
     switch (slice_words) {
         // UC: ops per lane group and level, so that (896 / SW) * UC >= 1024
-        case 1: return rowor_variant<1, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
-        case 2: return rowor_variant<2, 3>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
-        case 4: return rowor_variant<4, 5>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
-        case 8: return rowor_variant<8, 10>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
-        case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
-        case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
-        case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, st);
+        case 1: return rowor_variant<1, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        case 2: return rowor_variant<2, 3>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        case 4: return rowor_variant<4, 5>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        case 8: return rowor_variant<8, 10>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -309,9 +309,11 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
         e = hipMemcpyAsync(r.dev, r.pinned, bytes, hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess) {
             ProfScope ps(ctx, TN_K_ROWOR);
+            // the stream's first launch starts from the identity: zero phase
+            const uint32_t zl = s.launches == 0 ? zero_phase_levels(ch.hs, s.n) : 0u;
             e = launch_rowor_global(ops_view(ch.hs, r.dev), s.n, s.C, s.ld, s.sw,
                                     (uint64_t *)ctx->scratch, ch.hs.scratch_rows, ctx->traffic,
-                                    ctx->saturation, s.persist, s.done_count, ctx->stream);
+                                    ctx->saturation, s.persist, s.done_count, zl, ctx->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(r.done_host, s.done_count, sizeof(unsigned int),

@@ -235,6 +235,24 @@ def test_saturation_skips_keep_the_matrix(sw):
         assert ld < ld0 and st < st0, case  # these networks saturate
 
 
+@pytest.mark.parametrize("sw", [1, 4])
+def test_zero_skips_keep_the_matrix(sw):
+    # sparse networks: most row slices stay all zero for many levels; not
+    # loading zero operands and not storing zero results into zero rows must
+    # not change any bit, and must move fewer words than the full-row rule
+    # alone
+    import satmodel
+    for case, (n, m, Tm) in enumerate([(700, 600, 300), (1000, 3000, 2000), (260, 400, 50)]):
+        s, d, t = T.random_tiny(n, m, Tm, seed=8400 + case)
+        sch = tn.host_schedule(n, s, d, t)
+        want = oracle.reverse_matrix(n, s, d, t)
+        got, ld, st = satmodel.replay(n, sch, sw)
+        assert (got == want).all(), case
+        got1, ld1, st1 = satmodel.replay(n, sch, sw, zero=False)
+        assert (got1 == want).all(), case
+        assert ld < ld1 and st <= st1, case
+
+
 def test_saturation_model_stops_full_slices():
     # a slice whose rows are all full stops: no traffic after that level,
     # same matrix; n = 64 k + 1 gives a last slice of one column whose only
