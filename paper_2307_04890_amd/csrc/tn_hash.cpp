@@ -213,7 +213,6 @@ tn_status tn_recombine(tn_ctx *ctx, uint32_t n, uint32_t H, uint32_t K, const ui
     if (K > 65536) return fail(TN_E_UNSUPPORTED, "K must be <= 65536");
     if (ldK < (int64_t)((K + 63) / 64)) return fail(TN_E_ARG, "ldK must be >= ceil(K/64)");
     if (!P || !bucket || !count || !est) return fail(TN_E_ARG, "null device array");
-    if (recombine_group(K) == 0) return fail(TN_E_UNSUPPORTED, "K too large for the LDS tables");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
     const uint32_t nq = (n + 63) / 64;

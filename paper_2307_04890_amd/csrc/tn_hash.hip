@@ -215,11 +215,13 @@ k_split_full(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bu
 }
 
 // est[u] += sum over the chunks q of this launch of popcount(AND_j Lt[q][j][h_j(u)]).
-// A workgroup owns kUPT nodes u per thread and a range of chunks; the tables
-// of G hashes of one chunk are staged in LDS at a time, and the AND of a
-// chunk is carried in registers across the hash groups.
+// A workgroup owns kUPT nodes u per thread and a range of chunks; with LDS,
+// the tables of G hashes of one chunk are staged in LDS at a time (K words
+// each), else (tables too large for LDS) they are read where they are, in
+// L2; the AND of a chunk is carried in registers across the hash groups.
 constexpr int kUPT = 8;
 constexpr int kQB = 4;
+template <bool LDS>
 __global__ void __launch_bounds__(512)
 k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *__restrict__ bucket,
                 const uint64_t *__restrict__ Lt, uint32_t q_begin, uint32_t q_end, uint32_t q0,
@@ -262,14 +264,18 @@ k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *
             for (int a = 0; a < kQB; ++a) {
                 if (a >= (int)nqb) break;
                 const uint64_t *src = Lt + ((size_t)(qb + a - q0) * H + j0) * K;
-                __syncthreads();
-                for (uint32_t i = tid; i < g * K; i += blockDim.x) tab[i] = src[i];
-                __syncthreads();
+                const uint64_t *tb = src;
+                if (LDS) {
+                    __syncthreads();
+                    for (uint32_t i = tid; i < g * K; i += blockDim.x) tab[i] = src[i];
+                    __syncthreads();
+                    tb = tab;
+                }
 #pragma unroll
                 for (int k = 0; k < kUPT; ++k)
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj)
-                        if (jj < (int)g) acc[a][k] &= tab[(size_t)jj * K + b[k][jj]];
+                        if (jj < (int)g) acc[a][k] &= tb[(size_t)jj * K + b[k][jj]];
             }
         }
 #pragma unroll
@@ -341,6 +347,8 @@ hipError_t launch_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, 
     return hipGetLastError();
 }
 
+// Hashes whose chunk tables fit in LDS together (at most 4); 0 when one
+// table does not fit, and the tables are read from global memory.
 uint32_t recombine_group(uint32_t K) {
     const size_t budget = 160 * 1024;
     size_t g = budget / ((size_t)K * 8);
@@ -366,9 +374,12 @@ hipError_t launch_split_full(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, co
 hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32_t *bucket,
                                 const uint64_t *Lt, uint32_t q0, uint32_t nq, const uint32_t *list,
                                 uint32_t nlist, int32_t *est, hipStream_t st) {
-    const uint32_t G = recombine_group(K);
-    const size_t lds = (size_t)G * K * 8;
-    hipError_t e = hipFuncSetAttribute((const void *)k_recombine_est,
+    const uint32_t GL = recombine_group(K);
+    const bool in_lds = GL > 0;
+    const uint32_t G = in_lds ? GL : 4u;
+    const size_t lds = in_lds ? (size_t)G * K * 8 : 0;
+    auto kern = in_lds ? k_recombine_est<true> : k_recombine_est<false>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const uint32_t threads = 512;
@@ -382,8 +393,8 @@ hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32
         const uint32_t qb = q0 + s * per;
         const uint32_t qe = min(q0 + nq, qb + per);
         if (qb >= qe) break;
-        hipLaunchKernelGGL(k_recombine_est, dim3(utiles), dim3(threads), lds, st, n, H, K, G, bucket,
-                           Lt, qb, qe, q0, list, nlist, est);
+        hipLaunchKernelGGL(kern, dim3(utiles), dim3(threads), lds, st, n, H, K, G, bucket, Lt, qb,
+                           qe, q0, list, nlist, est);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

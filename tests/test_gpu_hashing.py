@@ -33,7 +33,9 @@ def run_hashed(n, s, d, t, H, K, seed, flags=0):
 @pytest.mark.parametrize("n,m,H,K,mixed", [(300, 900, 3, 40, False), (2000, 8000, 4, 64, False),
                                            (5000, 30000, 5, 1500, False),
                                            (3000, 12000, 2, 4096, False), (2000, 300, 2, 64, True),
-                                           (3000, 250, 2, 40, True)])
+                                           (3000, 250, 2, 40, True),
+                                           # tables too large for LDS: read from global memory
+                                           (1500, 3000, 2, 32768, False)])
 def test_hash_proxies_and_recombine_match_oracle(n, m, H, K, mixed):
     Tm = m if mixed else m // 3
     s, d, t = T.uniform_pairs(n, m, Tm, seed=n + K)
