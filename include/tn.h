@@ -219,7 +219,10 @@ tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m,
 
 /* Streamed one-shot build (Sec. 3.4: the reverse-time recurrence consumes
  * the event list from its end).  The list is cut into chunks of about
- * chunk_events events on time-step boundaries (0 = max(2^18, m/64)); host
+ * chunk_events events on time-step boundaries; 0 selects chunks of
+ * max(2^18, m/64) events after a first chunk of a quarter of that (at least
+ * 2^14) that doubles up to it, so that a stream that saturates early plans
+ * little before its first launch; host
  * threads plan chunks concurrently while the device applies them in
  * reverse-time order to C.  Rows only gain bits, so once every row is all
  * ones within a column slice nothing earlier in time can change it: such
@@ -374,7 +377,9 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m,
  * in tn_hash_compress; P: DEVICE, H consecutive K x ldK uint64 matrices
  * (proxy j at P + j*K*ldK), written entirely.  The event list is cut into
  * chunks of whole time steps from its end (chunk_events as in
- * tn_build_component_matrix_streamed); each chunk's H mapped sub-streams are
+ * tn_build_component_matrix_streamed, except that the default first chunk
+ * is a sixteenth of the others: proxies of few super-nodes saturate within
+ * few events); each chunk's H mapped sub-streams are
  * planned on host threads and applied in one batched launch that resumes
  * from the proxies.  Once every tile of every proxy is all ones the earlier
  * chunks are skipped.  The proxies equal those of tn_hash_compress +

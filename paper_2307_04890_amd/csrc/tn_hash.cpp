@@ -109,9 +109,11 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
                        ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "bucket download");
-    if (chunk_events == 0) chunk_events = std::max<int64_t>(1 << 18, (m + 63) / 64);
+    int64_t first = 0;
+    // proxies of K << n super-nodes saturate within few events: start small
+    default_chunks(m, chunk_events, first, 16);
     std::vector<std::pair<int64_t, int64_t>> bounds;
-    stream_chunks(m, t, chunk_events, flags & TN_TIES_SEQUENTIAL, bounds);
+    stream_chunks(m, t, chunk_events, first, flags & TN_TIES_SEQUENTIAL, false, bounds);
     if (bounds.empty()) bounds.emplace_back(0, 0);  // no events: identity proxies
     std::vector<uint32_t> ns(H, K);
     std::vector<const uint32_t *> maps(H);

@@ -210,12 +210,13 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
                                uint32_t scratch_rows, unsigned long long *traffic,
                                bool saturation, uint32_t *persist, unsigned int *done_count,
                                uint32_t zero_levels, hipStream_t st);
-// Levels of the zero phase of a schedule applied to the identity: those
-// before the level at which the ops so far reach n (about one op per row),
-// by when few row slices are still all zero.
-inline uint32_t zero_phase_levels(const HostSchedule &hs, uint32_t n) {
+// Levels of the zero phase of a schedule: those before the level at which
+// its ops reach `budget`.  Applied to the identity the budget is n (about
+// one op per row), by when few row slices are still all zero; a streamed
+// build spends it over its first chunks.
+inline uint32_t zero_phase_levels(const HostSchedule &hs, int64_t budget) {
     uint32_t l = 0;
-    while (l < hs.Lops && hs.lvl_op[l] < n) ++l;
+    while (l < hs.Lops && (int64_t)hs.lvl_op[l] < budget) ++l;
     return l;
 }
 // uint32 words of persisted state: per slice, done + count + ceil(n/32)
@@ -227,10 +228,18 @@ inline size_t rowor_persist_words(uint32_t n, uint32_t slice_words) {
 // threads; the message names the first offending event (tn_stream.cpp)
 tn_status validate_events(uint32_t n, int64_t m, const uint32_t *src, const uint32_t *dst,
                           const int64_t *t, std::string &err);
-// chunks of a time-ordered list taken from its end: [a, b) pairs, each of
-// about `chunk` events and of whole time steps unless `sequential`
-void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, bool sequential,
-                   std::vector<std::pair<int64_t, int64_t>> &out);
+// chunks of a time-ordered list in the order they are applied: taken from
+// its end (reverse time) or, with forward, from its start; each of about
+// `chunk` events and of whole time steps unless `sequential`.  With
+// first > 0 the first chunk has about `first` events and each next one
+// twice as many as the one before, up to `chunk` (tn_stream.cpp).
+void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, int64_t first, bool sequential,
+                   bool forward, std::vector<std::pair<int64_t, int64_t>> &out);
+// chunk == 0 (the default): chunk = max(2^18, m/64) events, and a first
+// chunk of max(2^14, chunk/shrink) that doubles up to it, so that a stream
+// that saturates early plans and runs little; an explicit chunk is kept
+// fixed (first = 0)
+void default_chunks(int64_t m, int64_t &chunk, int64_t &first, int shrink);
 // The row-OR kernel with rows merged by byte-wise maximum (HyperLogLog
 // registers below 128, nwords = 2, 4, 8, ... words per row of M, ld >=
 // nwords); scratch as for launch_rowor_global with rowmax_workgroups sinks.

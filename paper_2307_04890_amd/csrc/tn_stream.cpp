@@ -71,6 +71,11 @@ struct StreamState {
     unsigned int *done_count = nullptr;
     Slot ring[kRing];
     int64_t launches = 0;  // launches so far (ring position)
+    // zero phase: while every launch so far ran all its levels in it, the
+    // persisted non-zero-row bits are exact and the next chunk may go on
+    // with it, until the ops applied reach n
+    bool zero_open = true;
+    int64_t zero_ops = 0;
     bool all_done = false;
     bool has_time = false;
     int64_t edge_t = 0;  // latest (forward) or earliest (reverse) time applied
@@ -114,15 +119,37 @@ tn_status validate_events(uint32_t n, int64_t m, const uint32_t *src, const uint
     return TN_OK;
 }
 
-void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, bool sequential,
-                   std::vector<std::pair<int64_t, int64_t>> &out) {
+void stream_chunks(int64_t m, const int64_t *t, int64_t chunk, int64_t first, bool sequential,
+                   bool forward, std::vector<std::pair<int64_t, int64_t>> &out) {
     out.clear();
-    for (int64_t b = m; b > 0;) {
-        int64_t a = std::max<int64_t>(0, b - chunk);
-        if (!sequential)
-            while (a > 0 && t[a - 1] == t[a]) --a;
-        out.emplace_back(a, b);
-        b = a;
+    int64_t size = first > 0 ? std::min(first, chunk) : chunk;
+    auto grow = [&]() { size = std::min(chunk, 2 * size); };
+    if (!forward) {
+        for (int64_t b = m; b > 0;) {
+            int64_t a = std::max<int64_t>(0, b - size);
+            if (!sequential)
+                while (a > 0 && t[a - 1] == t[a]) --a;
+            out.emplace_back(a, b);
+            b = a;
+            grow();
+        }
+    } else {
+        for (int64_t a = 0; a < m;) {
+            int64_t b = std::min<int64_t>(m, a + size);
+            if (!sequential)
+                while (b < m && t[b] == t[b - 1]) ++b;
+            out.emplace_back(a, b);
+            a = b;
+            grow();
+        }
+    }
+}
+
+void default_chunks(int64_t m, int64_t &chunk, int64_t &first, int shrink) {
+    first = 0;
+    if (chunk == 0) {
+        chunk = std::max<int64_t>(1 << 18, (m + 63) / 64);
+        first = std::max<int64_t>(1 << 14, chunk / shrink);
     }
 }
 
@@ -197,10 +224,12 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
     const bool seq = s.flags & TN_TIES_SEQUENTIAL;
     const bool forward = s.flags & TN_FORWARD;
     const int64_t nwords = (s.n + 63) / 64;
-    if (chunk_events == 0) chunk_events = std::max<int64_t>(1 << 18, (m + 63) / 64);
+    int64_t first = 0;
+    // the device time of the matrix stream dominates and planning runs ahead
+    // of it, so its first chunk is only a quarter of the others
+    default_chunks(m, chunk_events, first, 4);
     std::vector<std::pair<int64_t, int64_t>> bounds;
-    stream_chunks(m, t, chunk_events, seq, bounds);
-    if (forward) std::reverse(bounds.begin(), bounds.end());  // from the start
+    stream_chunks(m, t, chunk_events, first, seq, forward, bounds);
     std::vector<std::unique_ptr<Chunk>> chunks;
     for (const auto &ab : bounds) {
         auto c = std::make_unique<Chunk>();
@@ -309,8 +338,12 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
         e = hipMemcpyAsync(r.dev, r.pinned, bytes, hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess) {
             ProfScope ps(ctx, TN_K_ROWOR);
-            // the stream's first launch starts from the identity: zero phase
-            const uint32_t zl = s.launches == 0 ? zero_phase_levels(ch.hs, s.n) : 0u;
+            uint32_t zl = 0;
+            if (s.zero_open) {
+                zl = zero_phase_levels(ch.hs, (int64_t)s.n - s.zero_ops);
+                if (zl < ch.hs.Lops) s.zero_open = false;
+                s.zero_ops += (int64_t)ch.hs.ops.size() / 4;
+            }
             e = launch_rowor_global(ops_view(ch.hs, r.dev), s.n, s.C, s.ld, s.sw,
                                     (uint64_t *)ctx->scratch, ch.hs.scratch_rows, ctx->traffic,
                                     ctx->saturation, s.persist, s.done_count, zl, ctx->stream);

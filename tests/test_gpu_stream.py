@@ -77,3 +77,22 @@ def test_streamed_errors_enqueue_nothing():
     assert e.value.code == -1
     torch.cuda.synchronize()
     assert (C.cpu() == 0).all()
+
+
+@pytest.mark.parametrize("flags", [0, tn.FORWARD, tn.TIES_SEQUENTIAL | tn.FORWARD])
+def test_default_chunks_grow_from_the_first_applied_end(flags):
+    # chunk_events = 0: a first chunk of 2^16 events (a quarter of 2^18)
+    # doubling up to 2^18, cut from the end in reverse time and from the
+    # start forward: 64k + the rest of 180k events = 2 chunks
+    n, m = 1500, 180_000
+    s, d, t = T.uniform_pairs(n, m, 60_000, seed=31)
+    ref = oracle.forward_matrix if flags & tn.FORWARD else oracle.reverse_matrix
+    want = ref(n, s, d, t, sequential=bool(flags & tn.TIES_SEQUENTIAL))
+    ctx = tn.get_context()
+    try:
+        ctx.saturation(False)  # every chunk runs
+        C, st = tn.build_component_matrix_streamed(n, s, d, t, flags)
+    finally:
+        ctx.saturation(True)
+    assert (host(C) == want).all()
+    assert st["chunks"] == 2 and st["chunks_run"] == 2 and st["events_run"] == m
