@@ -9,9 +9,12 @@
 // then from the other XCDs' queues) until every queue is empty.
 //
 // A tile whose n x w slice (plus the scratch rows of its widest compound
-// level) fits in LDS is built entirely in LDS: identity, every level, then a
-// single write-back of the slice.  Larger tiles run the same level loop on
-// the matrix in global memory.
+// level) fits the launch's LDS budget per workgroup is built entirely in
+// LDS: identity, every level, then a single write-back of the slice.  Larger
+// tiles run the same level loop on the matrix in global memory.  The host
+// tunes the budget: levels are short, so a tile's time is mostly its levels'
+// barrier and memory round trips, and a smaller budget lets several
+// workgroups share a compute unit and hide each other's waits.
 //
 // Saturation (Sec. 3.4: rows only gain bits in reverse time).  A tile keeps
 // one LDS bit per row meaning "this row is all ones in the slice": an item
