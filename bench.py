@@ -658,36 +658,55 @@ def run_hll(args):
     h = T.hll_node_hashes(n, seed=11)
     ctx = tn.get_context()
     t0 = time.perf_counter()
-    plan = tn.Plan(n, s, d, t)
+    plan = tn.Plan(n, s, d, t, tn.HLL)
     plan_wall = time.perf_counter() - t0
     st = plan.stats
-    log(f"[bench] plan: {st['op_levels']} op levels, {st['ops']} ops, {plan_wall:.1f} s")
+    log(f"[bench] plan: {st['levels']} levels, {st['pairs']} pairs, {st['gathers']} gathers, "
+        f"{plan_wall:.1f} s")
     elapsed, kms, _ = timed(ctx, lambda: plan.hll(h, b), args.steps, args.warmup)
     M, est = plan.hll(h, b)
     torch.cuda.synchronize()
     e = est.cpu().numpy()
     stream_ms = kms["rowor"]
-    ld_w, st_w = ctx.last_traffic()
-    moved = 8.0 * (ld_w + st_w) + 16.0 * st["ops"]
+    # row transfers of the level stream: an undirected pair reads and writes
+    # two rows, a one-way pair reads two and writes one, a gather reads its
+    # sources and writes, reads and writes its scratch row and target
+    row = float(1 << b)
+    sym = st["pairs"] - st["directed_pairs"]
+    moved = row * (4.0 * sym + 3.0 * st["directed_pairs"] + st["gather_sources"] +
+                   3.0 * st["gathers"]) + st["device_bytes"]
     config = {"workload": workload, "n": n, "m": m, "T": spec["T"], "generator": spec["kind"],
               "seed": spec["seed"], "registers": 1 << b, "flags": "undirected,strict-ties",
               "parallelism": "single-gpu"}
     r = base_result(args, m * args.steps / elapsed, "events/s", args.steps,
                     1e3 * elapsed / args.steps, config)
-    r["value_note"] = "resident plan: register init + HLL stream + estimates per step"
+    r["value_note"] = "resident TN_HLL plan: register init + HLL stream + estimates per step"
     r["roofline"] = {"bound": "hbm", "achieved": moved / (stream_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": moved / (stream_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rowor_global (byte-max rows)", "algorithmic_bytes": moved,
-                     "bytes_note": "register words the kernel loaded and stored, plus the "
-                                   "schedule once", "avg_launch_ms": stream_ms,
-                     "levels": st["op_levels"],
-                     "us_per_level": 1e3 * stream_ms / max(1, st["op_levels"])}
+                     "kernel": "k_hll_level + k_hll_gathers_write (one launch per level)",
+                     "algorithmic_bytes": moved,
+                     "bytes_note": "register rows the level stream must read and write, plus "
+                                   "the schedule once", "avg_launch_ms": stream_ms,
+                     "levels": st["levels"],
+                     "us_per_level": 1e3 * stream_ms / max(1, st["levels"])}
     r["kernels_ms"] = kms
     r["hll"] = {"registers_bytes": n * (1 << b), "exact_matrix_bytes": n * ((n + 63) // 64) * 8,
                 "plan_wall_s": plan_wall, "mean_estimate": float(e.mean()),
                 "estimate_quantiles": [float(q) for q in np.percentile(e, [1, 50, 99])]}
     plan.close()
+    # the same stream as the row-OR kernel's level loop on an ops plan (one
+    # workgroup per register word column), for comparison
+    t0 = time.perf_counter()
+    oplan = tn.Plan(n, s, d, t)
+    oplan_wall = time.perf_counter() - t0
+    _, okms, _ = timed(ctx, lambda: oplan.hll(h, b), 1, 1)
+    M2, _ = oplan.hll(h, b)
+    assert torch.equal(M, M2), "the two register streams differ"
+    r["hll"]["ops_plan"] = {"stream_ms": okms["rowor"], "op_levels": oplan.stats["op_levels"],
+                            "plan_wall_s": oplan_wall}
+    oplan.close()
+    del M2
     # accuracy against exact sizes on the 10^5-node workload
     s2, d2, t2 = T.make_workload("activity_n100000_m10M")
     n2 = 100_000

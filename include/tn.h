@@ -64,11 +64,15 @@ enum {
                                 (the non-mutual sharing of the footnote in Sec. 3) */
     TN_TIES_SEQUENTIAL = 2u, /* list order is strict time order: Algorithm 1 read
                                 literally, events at one time step chain          */
-    TN_FORWARD = 4u          /* Algorithm 1 in time order (Sec. 3.1): row x of the
+    TN_FORWARD = 4u,         /* Algorithm 1 in time order (Sec. 3.1): row x of the
                                 result is x's in-component (the nodes that can
                                 reach x) instead of its out-component; the result
                                 is the transpose of the reverse-time one
                                 (Sec. 3.4).  Not valid for hashing.            */
+    TN_HLL = 8u              /* tn_plan_create only: plan for tn_hll_execute
+                                (the time-step schedule its register stream
+                                runs level by level); tn_plan_execute rejects
+                                such a plan                                    */
 };
 
 typedef struct tn_ctx tn_ctx;     /* device, stream, scratch, autotune cache   */
@@ -127,7 +131,8 @@ int32_t tn_profile_take(tn_ctx *ctx, int32_t *ids, float *ms, int32_t cap);
  * levels hold at most 1024 ops.  The schedule is copied to the device
  * (synchronously) and kept in the plan.
  * src, dst, t: HOST, m entries.  flags: TN_DIRECTED | TN_TIES_SEQUENTIAL |
- * TN_FORWARD (the stream then runs in time order).
+ * TN_FORWARD (the stream then runs in time order) | TN_HLL (a plan of pair
+ * and compound items by level, for tn_hll_execute only).
  * Errors: TN_E_ARG (n == 0, null arrays with m > 0, bad flags),
  * TN_E_RANGE, TN_E_ORDER, TN_E_UNSUPPORTED (m >= 2^32 or n >= 2^31). */
 tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m,
@@ -293,8 +298,12 @@ void tn_online_destroy(tn_online *online);
  * node_hash: DEVICE uint64[n], one uniform hash per node (an input: the
  * library draws no random numbers).  M: DEVICE n x s uint8, row-major,
  * written entirely.  est: DEVICE float64[n] or NULL.  log2s in [4, 16].
- * tn_hll_execute runs on a plan's schedule (asynchronous); tn_hll_build
- * plans, runs and waits.  Errors: TN_E_ARG, plus those of tn_plan_create. */
+ * tn_hll_execute runs on a plan's schedule (asynchronous): on a TN_HLL
+ * plan one launch per level (two for a level with compound items) spreads
+ * the level's items over the whole device, one group of lanes per item and
+ * row; on another plan the row-OR kernel's level loop runs with byte-wise
+ * maximum, one workgroup per word column.  tn_hll_build plans (TN_HLL), runs
+ * and waits.  Errors: TN_E_ARG, plus those of tn_plan_create. */
 tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
                          const uint64_t *node_hash, uint8_t *M, double *est);
 tn_status tn_hll_build(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,

@@ -15,6 +15,7 @@ STATUS = {
 DIRECTED = 1
 TIES_SEQUENTIAL = 2
 FORWARD = 4
+HLL = 8  # tn_plan_create: a plan for the HyperLogLog stream only
 KERNELS = {1: "identity", 2: "rowor", 3: "out_sizes", 4: "in_sizes", 5: "batch",
            6: "hash", 7: "recombine", 8: "mlp_forward", 9: "mlp_backward", 10: "mlp_adam",
            11: "aux"}

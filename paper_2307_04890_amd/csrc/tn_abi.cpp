@@ -1,6 +1,7 @@
 // C ABI: context, plans, validation and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -140,15 +141,19 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
     *out = nullptr;
     tn::HostSchedule hs;
     std::string err;
-    tn_status st = tn::plan_events(n, m, src, dst, t, flags, hs, err, nullptr, 0, tn::kFormOps);
+    const bool hll = flags & TN_HLL;
+    tn_status st = tn::plan_events(n, m, src, dst, t, flags & ~(uint32_t)TN_HLL, hs, err, nullptr,
+                                   0, hll ? tn::kFormGather : tn::kFormOps);
     if (st != TN_OK) return fail(st, err);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
     tn_plan *p = new (std::nothrow) tn_plan();
     if (!p) return fail(TN_E_NOMEM, "plan allocation failed");
     p->device = ctx->device;
+    p->hll = hll;
     std::vector<unsigned char> img;
-    tn::ops_pack(hs, img);
+    if (hll) tn::schedule_pack(hs, img);
+    else tn::ops_pack(hs, img);
     p->dev_bytes = img.size();
     hipError_t e = hipMalloc(&p->dev, p->dev_bytes);
     if (e != hipSuccess) {
@@ -162,10 +167,16 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         delete p;
         return hip_fail(e, "schedule upload");
     }
-    p->view = tn::ops_view(hs, p->dev);
-    p->scratch_rows = hs.scratch_rows;
-    p->zero_levels = tn::zero_phase_levels(hs, n);
     tn::fill_stats(hs, p->stats);
+    if (hll) {
+        p->gview = tn::schedule_view(hs, p->dev);
+        p->lvl_pair = std::move(hs.lvl_pair);
+        p->lvl_gat = std::move(hs.lvl_gat);
+    } else {
+        p->view = tn::ops_view(hs, p->dev);
+        p->scratch_rows = hs.scratch_rows;
+        p->zero_levels = tn::zero_phase_levels(hs, n);
+    }
     *out = p;
     return TN_OK;
 }
@@ -277,6 +288,7 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     const int64_t nwords = (n + 63) / 64;
     if (ld < nwords) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
     if (plan->device != ctx->device) return fail(TN_E_ARG, "plan lives on another device");
+    if (plan->hll) return fail(TN_E_ARG, "a TN_HLL plan runs only tn_hll_execute");
     if (slice_words == 0) slice_words = tn::default_slice_words(n, ld);
     if (slice_words > 64 || (slice_words & (slice_words - 1)))
         return fail(TN_E_ARG, "slice_words must be a power of two <= 64");
@@ -358,8 +370,12 @@ tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
     {
-        const size_t words = (size_t)tn::rowmax_workgroups(nwords) * tn::kRoworSinkWords +
-                             (size_t)plan->scratch_rows * (size_t)nwords;
+        // TN_HLL plans: one scratch row per gather of the widest level;
+        // others: per-workgroup sink words, then the compound scratch rows
+        const size_t words =
+            plan->hll ? (size_t)std::max<uint32_t>(plan->gview.max_gat, 1) * nwords
+                      : (size_t)tn::rowmax_workgroups(nwords) * tn::kRoworSinkWords +
+                            (size_t)plan->scratch_rows * (size_t)nwords;
         tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * words);
         if (st != TN_OK) return st;
     }
@@ -379,9 +395,14 @@ tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
     if (e != hipSuccess) return hip_fail(e, "HLL init launch");
     {
         tn::ProfScope ps(ctx, TN_K_ROWOR);
-        e = tn::launch_rowmax_global(plan->view, n, nwords, (uint64_t *)M, nwords,
-                                     (uint64_t *)ctx->scratch, plan->scratch_rows, ctx->traffic,
-                                     ctx->stream);
+        if (plan->hll)
+            e = tn::launch_hll_levels(plan->gview, plan->lvl_pair.data(), plan->lvl_gat.data(),
+                                      nwords, (uint64_t *)M, (uint64_t *)ctx->scratch,
+                                      ctx->stream);
+        else
+            e = tn::launch_rowmax_global(plan->view, n, nwords, (uint64_t *)M, nwords,
+                                         (uint64_t *)ctx->scratch, plan->scratch_rows,
+                                         ctx->traffic, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "HLL stream launch");
     if (est) {
@@ -398,7 +419,7 @@ tn_status tn_hll_build(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
     if (!node_hash || !M) return fail(TN_E_ARG, "node_hash or M is NULL");
     if (log2s < 4 || log2s > 16) return fail(TN_E_ARG, "log2s must be in [4, 16]");
     tn_plan *p = nullptr;
-    tn_status st = tn_plan_create(ctx, n, m, src, dst, t, flags, &p);
+    tn_status st = tn_plan_create(ctx, n, m, src, dst, t, flags | TN_HLL, &p);
     if (st != TN_OK) return st;
     st = tn_hll_execute(ctx, p, log2s, node_hash, M, est);
     if (st == TN_OK) {

@@ -2,12 +2,14 @@
 // of Sec. 2.2): every node holds s = 2^b one-byte registers, the structure
 // of the set {node} at first; the stream merges structures with the
 // register-wise maximum (launch_rowmax_global, the row-OR kernel's level
-// loop on rows of s bytes); the estimate of each row follows Flajolet,
+// loop on rows of s bytes, or launch_hll_levels below, one launch per level
+// of a TN_HLL plan); the estimate of each row follows Flajolet,
 // Fusy, Gandouet and Meunier (2007): alpha_s s^2 / sum_j 2^-M[j], and
 // s ln(s / V) when that is at most 5s/2 with V > 0 zero registers.
 // Element hashes are inputs, one uniform 64-bit value per node.
 #include <hip/hip_runtime.h>
 
+#include "tn_device.h"
 #include "tn_internal.h"
 
 namespace tn {
@@ -29,6 +31,58 @@ k_hll_init(uint32_t n, uint32_t b, const uint64_t *__restrict__ node_hash, uint6
         const uint64_t tail = x & ((~0ull) >> b);
         const uint32_t rho = tail ? (uint32_t)__clzll((long long)tail) - b + 1 : 64 - b + 1;
         M[i] = (j >> 3) == w ? (uint64_t)rho << (8 * (j & 7u)) : 0ull;
+    }
+}
+
+// One level of the register stream of a TN_HLL plan.  Items [0, np) are
+// the level's pairs: both rows (one for a one-way pair) become their
+// register-wise maximum, in place (the items of a level touch disjoint
+// rows).  Items [np, np + ng) are its gathers: the maximum over the source
+// rows goes to scratch row i - np, since gathers of one compound item read
+// each other's rows (their targets are written by k_hll_gathers_write).  A
+// group of G lanes takes an item; lane k takes words k, k + G, ... of its
+// rows, so each row access is one contiguous segment.
+__global__ void __launch_bounds__(256)
+k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *__restrict__ pairs,
+            uint32_t np, const uint32_t *__restrict__ gat_ptr,
+            const uint32_t *__restrict__ gat_src, uint32_t ng, uint64_t *__restrict__ scr) {
+    const uint32_t lane = threadIdx.x % G;
+    const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+    for (uint32_t i = blockIdx.x * (blockDim.x / G) + threadIdx.x / G; i < np + ng; i += ngroups) {
+        if (i < np) {
+            const uint2 it = pairs[i];
+            const uint32_t v = it.y & kNodeMask;
+            const bool dir = it.y & kDirBit;
+            uint64_t *ru = M + (size_t)it.x * nwords;
+            uint64_t *rv = M + (size_t)v * nwords;
+            for (uint32_t w = lane; w < nwords; w += G) {
+                const uint64_t r = max_bytes7(ru[w], rv[w]);
+                ru[w] = r;
+                if (!dir) rv[w] = r;
+            }
+        } else {
+            const uint32_t g = i - np;
+            const uint32_t s0 = gat_ptr[g], s1 = gat_ptr[g + 1];
+            uint64_t *dst = scr + (size_t)g * nwords;
+            for (uint32_t w = lane; w < nwords; w += G) {
+                uint64_t acc = 0;  // registers are never negative
+                for (uint32_t q = s0; q < s1; ++q)
+                    acc = max_bytes7(acc, M[(size_t)gat_src[q] * nwords + w]);
+                dst[w] = acc;
+            }
+        }
+    }
+}
+
+// The level's gathers write their targets from scratch.
+__global__ void __launch_bounds__(256)
+k_hll_gathers_write(uint64_t *__restrict__ M, uint32_t nwords, const uint32_t *__restrict__ gat_tgt,
+                    uint32_t ng, const uint64_t *__restrict__ scr) {
+    const size_t total = (size_t)ng * nwords;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t g = (uint32_t)(i / nwords), w = (uint32_t)(i % nwords);
+        M[(size_t)gat_tgt[g] * nwords + w] = scr[i];
     }
 }
 
@@ -80,6 +134,31 @@ hipError_t launch_hll_init(uint32_t n, uint32_t log2s, const uint64_t *node_hash
     hipLaunchKernelGGL(k_hll_init, dim3(blocks), dim3(256), 0, st, n, log2s, node_hash,
                        (uint64_t *)M);
     return hipGetLastError();
+}
+
+hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
+                             const uint32_t *lvl_gat, uint32_t nwords, uint64_t *M,
+                             uint64_t *scratch, hipStream_t st) {
+    const uint32_t G = nwords < 64 ? nwords : 64;  // nwords is a power of two >= 2
+    for (uint32_t l = 0; l < s.L; ++l) {
+        const uint32_t p0 = lvl_pair[l], np = lvl_pair[l + 1] - p0;
+        const uint32_t g0 = lvl_gat[l], ng = lvl_gat[l + 1] - g0;
+        if (np + ng == 0) continue;
+        const size_t threads = (size_t)(np + ng) * G;
+        const uint32_t blocks = (uint32_t)std::min<size_t>((threads + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_hll_level, dim3(blocks), dim3(256), 0, st, M, nwords, G,
+                           s.pairs + p0, np, s.gat_ptr + g0, s.gat_src, ng, scratch);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (ng == 0) continue;
+        const size_t words = (size_t)ng * nwords;
+        const uint32_t wb = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_hll_gathers_write, dim3(wb), dim3(256), 0, st, M, nwords,
+                           s.gat_tgt + g0, ng, scratch);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_hll_estimate(uint32_t n, uint32_t log2s, const uint8_t *M, double *est,

@@ -146,6 +146,11 @@ struct tn_plan {
     tn::DevOps view{};
     uint32_t scratch_rows = 0;
     uint32_t zero_levels = 0;  // levels of the zero phase (tn::zero_phase_levels)
+    // TN_HLL plans: the time-step schedule (pairs and gathers by level) on
+    // the device, its level boundaries on the host, instead of the ops
+    bool hll = false;
+    tn::DevSchedule gview{};
+    std::vector<uint32_t> lvl_pair, lvl_gat;
     tn_plan_stats stats{};
 };
 
@@ -251,6 +256,12 @@ uint32_t rowmax_workgroups(uint32_t nwords);
 // and the size estimates
 hipError_t launch_hll_init(uint32_t n, uint32_t log2s, const uint64_t *node_hash, uint8_t *M,
                            hipStream_t st);
+// The register stream of a TN_HLL plan: one launch per level (pairs, and
+// compound items' reads into scratch), then one writing the compound items'
+// rows; scratch: s.max_gat rows of nwords words.
+hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
+                             const uint32_t *lvl_gat, uint32_t nwords, uint64_t *M,
+                             uint64_t *scratch, hipStream_t st);
 hipError_t launch_hll_estimate(uint32_t n, uint32_t log2s, const uint8_t *M, double *est,
                                hipStream_t st);
 // streamed one-shot build (tn_stream.cpp)

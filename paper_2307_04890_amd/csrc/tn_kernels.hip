@@ -9,6 +9,7 @@
 // touch the same word.
 #include <hip/hip_runtime.h>
 
+#include "tn_device.h"
 #include "tn_internal.h"
 
 namespace tn {
@@ -128,16 +129,6 @@ __device__ __forceinline__ void zero_set(OpArgs &A, uint32_t id, bool zero) {
     if (zero) atomicOr(&A.zb[i >> 5], 1u << (i & 31u));
     else atomicAnd(&A.zb[i >> 5], ~(1u << (i & 31u)));
     if (!(id & kScratchBit)) A.dzero += zero ? 1 : -1;
-}
-
-// Byte-wise maximum of two words whose bytes are all below 128 (HyperLogLog
-// registers, Sec. 3.4): (x | 0x80..) - y keeps each byte's borrow inside the
-// byte, and that byte's top bit then says whether x >= y.
-__device__ __forceinline__ uint64_t max_bytes7(uint64_t x, uint64_t y) {
-    constexpr uint64_t H = 0x8080808080808080ull;
-    const uint64_t ge = ((x | H) - y) & H;
-    const uint64_t mask = (ge >> 7) * 0xFFull;
-    return (x & mask) | (y & ~mask);
 }
 
 // Plain path: ops [base, n) of the current frame, UC per lane group, every

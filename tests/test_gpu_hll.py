@@ -17,19 +17,42 @@ tn = pytest.importorskip("paper_2307_04890_amd")
 @pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.TIES_SEQUENTIAL, tn.FORWARD,
                                    tn.FORWARD | tn.DIRECTED])
 def test_registers_and_estimates_match_the_oracle(flags):
-    for case, (n, m, Tm, b) in enumerate([(60, 300, 40, 4), (200, 1500, 300, 6), (500, 4000, 900, 8),
-                                          (1000, 3000, 2000, 5), (7, 0, 1, 7)]):
-        s, d, t = T.random_tiny(n, max(m, 1), Tm, seed=700 + case)
-        s, d, t = s[:m], d[:m], t[:m]
+    # both register streams: one launch per level of a TN_HLL plan
+    # (hll_build), and the row-OR kernel's level loop on an ops plan
+    cases = [(60, 300, 40, 4), (200, 1500, 300, 6), (500, 4000, 900, 8), (1000, 3000, 2000, 5),
+             (7, 0, 1, 7), (300, 2000, 500, 10)]
+    for case, (n, m, Tm, b) in enumerate(cases + [(400, None, 600, 6), (150, None, 400, 8)]):
+        if m is None:  # star time steps: compound items of up to 10 nodes
+            s, d, t = T.star_steps(n, Tm, 9, seed=720 + case)
+            m = s.shape[0]
+        else:
+            s, d, t = T.random_tiny(n, max(m, 1), Tm, seed=700 + case)
+            s, d, t = s[:m], d[:m], t[:m]
         h = T.hll_node_hashes(n, seed=70 + case)
-        M, est = tn.hll_build(n, s, d, t, h, b, flags=flags)
         want = hll.stream_registers(n, s, d, t, h, b, directed=bool(flags & tn.DIRECTED),
                                     sequential=bool(flags & tn.TIES_SEQUENTIAL),
                                     forward=bool(flags & tn.FORWARD))
-        got = M.cpu().numpy()
-        assert (got == want).all(), case
         we = hll.estimate(want)
+        M, est = tn.hll_build(n, s, d, t, h, b, flags=flags)
+        assert (M.cpu().numpy() == want).all(), case
         assert np.allclose(est.cpu().numpy(), we, rtol=1e-12, atol=0), case
+        p = tn.Plan(n, s, d, t, flags)
+        M2, est2 = p.hll(h, b)
+        assert (M2.cpu().numpy() == want).all(), case
+        assert np.allclose(est2.cpu().numpy(), we, rtol=1e-12, atol=0), case
+        p.close()
+
+
+def test_hll_plan_runs_the_register_stream_only():
+    s, d, t = T.random_tiny(100, 500, 200, seed=5)
+    p = tn.Plan(100, s, d, t, tn.HLL)
+    M, _ = p.hll(T.hll_node_hashes(100, seed=6), 6)
+    torch.cuda.synchronize()
+    assert M.shape == (100, 64)
+    with pytest.raises(tn.TNError) as e:
+        p.execute()
+    assert e.value.code == -1
+    p.close()
 
 
 def test_union_property_at_scale_against_the_exact_matrix():
