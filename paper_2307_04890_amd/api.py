@@ -139,15 +139,25 @@ class Plan:
         check(lib.tn_plan_get_stats(self.h, ctypes.byref(s)))
         return s.as_dict()
 
-    def hll(self, node_hash, log2s: int):
+    def hll(self, node_hash, log2s: int, M: torch.Tensor | None = None,
+            est: torch.Tensor | None = None):
         """The HyperLogLog stream on this plan's schedule (tn_hll_execute):
-        (registers (n, 2^log2s) uint8, estimates (n,) float64)."""
+        (registers (n, 2^log2s) uint8, estimates (n,) float64), into M and
+        est when given (a TN_HLL plan replays its captured level launches
+        while M stays the same)."""
         dev = f"cuda:{self.ctx.device}"
         h = torch.as_tensor(np.ascontiguousarray(node_hash, dtype=np.uint64).view(np.int64)).to(dev)
         if h.shape != (self.n,):
             raise ValueError("node_hash must hold one value per node")
-        M = torch.empty((self.n, 1 << log2s), dtype=torch.uint8, device=dev)
-        est = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if M is None:
+            M = torch.empty((self.n, 1 << log2s), dtype=torch.uint8, device=dev)
+        if est is None:
+            est = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if (M.dtype != torch.uint8 or tuple(M.shape) != (self.n, 1 << log2s)
+                or not M.is_contiguous() or M.device != torch.device(dev)):
+            raise ValueError("M must be a contiguous uint8 (n, 2^log2s) tensor on the plan's device")
+        if est.dtype != torch.float64 or tuple(est.shape) != (self.n,) or est.device != torch.device(dev):
+            raise ValueError("est must be a float64 (n,) tensor on the plan's device")
         check(lib.tn_hll_execute(self.ctx.bind_stream(), self.h, int(log2s), _dp(h), _dp(M),
                                  _dp(est)))
         return M, est

@@ -276,6 +276,7 @@ tn_status tn_plan_get_stats(const tn_plan *plan, tn_plan_stats *out) {
 void tn_plan_destroy(tn_plan *plan) {
     if (!plan) return;
     DeviceGuard g(plan->device);
+    if (plan->hll_exec) (void)hipGraphExecDestroy(plan->hll_exec);
     if (plan->dev) (void)hipFree(plan->dev);
     delete plan;
 }
@@ -359,6 +360,53 @@ tn_status tn_build_component_matrix(tn_ctx *ctx, uint32_t n, int64_t m, const ui
     return tn::build_streamed(ctx, n, m, src, dst, t, flags, C, ld, 0, nullptr);
 }
 
+}  // extern "C"
+
+namespace {
+// The level launches of a TN_HLL plan as a HIP graph (captured on a stream
+// of its own, then launched on the context's): one launch per level costs
+// the host more than the device, and a graph replays them back to back.
+// Captured again when the rows, the scratch or the row width change.
+tn_status hll_graph(tn_ctx *ctx, const tn_plan *plan, uint32_t nwords, uint8_t *M) {
+    if (plan->gview.L == 0) return TN_OK;
+    if (plan->hll_exec && plan->hll_M == M && plan->hll_scr == ctx->scratch &&
+        plan->hll_nwords == nwords)
+        return TN_OK;
+    if (plan->hll_exec) {
+        // a queued replay may still run the old graph
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        (void)hipGraphExecDestroy(plan->hll_exec);
+        plan->hll_exec = nullptr;
+    }
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = tn::launch_hll_levels(plan->gview, plan->lvl_pair.data(),
+                                              plan->lvl_gat.data(), nwords, (uint64_t *)M,
+                                              (uint64_t *)ctx->scratch, cs);
+        e = hipStreamEndCapture(cs, &g);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->hll_exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        plan->hll_exec = nullptr;
+        return hip_fail(e, "HLL level graph");
+    }
+    plan->hll_M = M;
+    plan->hll_scr = ctx->scratch;
+    plan->hll_nwords = nwords;
+    return TN_OK;
+}
+}  // namespace
+
+extern "C" {
+
 tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
                          const uint64_t *node_hash, uint8_t *M, double *est) {
     if (!ctx || !plan) return fail(TN_E_ARG, "ctx or plan is NULL");
@@ -394,15 +442,18 @@ tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
     }
     if (e != hipSuccess) return hip_fail(e, "HLL init launch");
     {
-        tn::ProfScope ps(ctx, TN_K_ROWOR);
-        if (plan->hll)
-            e = tn::launch_hll_levels(plan->gview, plan->lvl_pair.data(), plan->lvl_gat.data(),
-                                      nwords, (uint64_t *)M, (uint64_t *)ctx->scratch,
-                                      ctx->stream);
-        else
+        if (plan->hll) {
+            std::lock_guard<std::mutex> lk(plan->hll_mu);
+            tn_status st = hll_graph(ctx, plan, nwords, M);
+            if (st != TN_OK) return st;
+            tn::ProfScope ps(ctx, TN_K_ROWOR);
+            e = plan->hll_exec ? hipGraphLaunch(plan->hll_exec, ctx->stream) : hipSuccess;
+        } else {
+            tn::ProfScope ps(ctx, TN_K_ROWOR);
             e = tn::launch_rowmax_global(plan->view, n, nwords, (uint64_t *)M, nwords,
                                          (uint64_t *)ctx->scratch, plan->scratch_rows,
                                          ctx->traffic, ctx->stream);
+        }
     }
     if (e != hipSuccess) return hip_fail(e, "HLL stream launch");
     if (est) {

@@ -37,19 +37,43 @@ k_hll_init(uint32_t n, uint32_t b, const uint64_t *__restrict__ node_hash, uint6
 // One level of the register stream of a TN_HLL plan.  Items [0, np) are
 // the level's pairs: both rows (one for a one-way pair) become their
 // register-wise maximum, in place (the items of a level touch disjoint
-// rows).  Items [np, np + ng) are its gathers: the maximum over the source
-// rows goes to scratch row i - np, since gathers of one compound item read
-// each other's rows (their targets are written by k_hll_gathers_write).  A
-// group of G lanes takes an item; lane k takes words k, k + G, ... of its
+// rows).  The level's gathers read each other's rows (those of one compound
+// item), so every source is read before any target is written:
+//  - inline (a narrow level): one group takes all ng gathers, item np; each
+//    lane writes the maxima of its own words to scratch rows, then copies
+//    them to the targets, so no other lane ever reads what it writes;
+//  - else items [np, np + ng) are the gathers, each writing scratch row
+//    i - np, and k_hll_gathers_write copies them in a launch of its own.
+// A group of G lanes takes an item; lane k takes words k, k + G, ... of its
 // rows, so each row access is one contiguous segment.
+__device__ __forceinline__ void hll_gather_read(const uint64_t *__restrict__ M, uint32_t nwords,
+                                                uint32_t lane, uint32_t G, uint32_t s0, uint32_t s1,
+                                                const uint32_t *__restrict__ gat_src,
+                                                uint64_t *__restrict__ dst) {
+    for (uint32_t w = lane; w < nwords; w += G) {
+        uint64_t acc = 0;  // registers are never negative
+        for (uint32_t q = s0; q < s1; ++q) acc = max_bytes7(acc, M[(size_t)gat_src[q] * nwords + w]);
+        dst[w] = acc;
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *__restrict__ pairs,
             uint32_t np, const uint32_t *__restrict__ gat_ptr,
-            const uint32_t *__restrict__ gat_src, uint32_t ng, uint64_t *__restrict__ scr) {
+            const uint32_t *__restrict__ gat_src, const uint32_t *__restrict__ gat_tgt,
+            uint32_t ng, uint32_t inline_gathers, uint64_t *__restrict__ scr) {
     const uint32_t lane = threadIdx.x % G;
     const uint32_t ngroups = gridDim.x * (blockDim.x / G);
-    for (uint32_t i = blockIdx.x * (blockDim.x / G) + threadIdx.x / G; i < np + ng; i += ngroups) {
-        if (i < np) {
+    const uint32_t items = np + (inline_gathers ? (ng > 0 ? 1u : 0u) : ng);
+    for (uint32_t i = blockIdx.x * (blockDim.x / G) + threadIdx.x / G; i < items; i += ngroups) {
+        if (i >= np && inline_gathers) {
+            for (uint32_t g = 0; g < ng; ++g)
+                hll_gather_read(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
+                                scr + (size_t)g * nwords);
+            for (uint32_t g = 0; g < ng; ++g)
+                for (uint32_t w = lane; w < nwords; w += G)
+                    M[(size_t)gat_tgt[g] * nwords + w] = scr[(size_t)g * nwords + w];
+        } else if (i < np) {
             const uint2 it = pairs[i];
             const uint32_t v = it.y & kNodeMask;
             const bool dir = it.y & kDirBit;
@@ -62,17 +86,14 @@ k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *
             }
         } else {
             const uint32_t g = i - np;
-            const uint32_t s0 = gat_ptr[g], s1 = gat_ptr[g + 1];
-            uint64_t *dst = scr + (size_t)g * nwords;
-            for (uint32_t w = lane; w < nwords; w += G) {
-                uint64_t acc = 0;  // registers are never negative
-                for (uint32_t q = s0; q < s1; ++q)
-                    acc = max_bytes7(acc, M[(size_t)gat_src[q] * nwords + w]);
-                dst[w] = acc;
-            }
+            hll_gather_read(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
+                            scr + (size_t)g * nwords);
         }
     }
 }
+
+// Gathers of a level handled in one group of its launch, at most.
+constexpr uint32_t kHllInlineGathers = 4;
 
 // The level's gathers write their targets from scratch.
 __global__ void __launch_bounds__(256)
@@ -144,13 +165,17 @@ hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
         const uint32_t p0 = lvl_pair[l], np = lvl_pair[l + 1] - p0;
         const uint32_t g0 = lvl_gat[l], ng = lvl_gat[l + 1] - g0;
         if (np + ng == 0) continue;
-        const size_t threads = (size_t)(np + ng) * G;
+        // a few gathers run in one group of the level's launch; many are
+        // spread over groups, then written by a second launch
+        const uint32_t inl = ng <= kHllInlineGathers ? 1u : 0u;
+        const size_t threads = (size_t)(np + (inl ? (ng > 0 ? 1u : 0u) : ng)) * G;
         const uint32_t blocks = (uint32_t)std::min<size_t>((threads + 255) / 256, 4096);
         hipLaunchKernelGGL(k_hll_level, dim3(blocks), dim3(256), 0, st, M, nwords, G,
-                           s.pairs + p0, np, s.gat_ptr + g0, s.gat_src, ng, scratch);
+                           s.pairs + p0, np, s.gat_ptr + g0, s.gat_src, s.gat_tgt + g0, ng, inl,
+                           scratch);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (ng == 0) continue;
+        if (ng == 0 || inl) continue;
         const size_t words = (size_t)ng * nwords;
         const uint32_t wb = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
         hipLaunchKernelGGL(k_hll_gathers_write, dim3(wb), dim3(256), 0, st, M, nwords,

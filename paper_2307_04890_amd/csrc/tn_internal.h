@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -151,6 +152,13 @@ struct tn_plan {
     bool hll = false;
     tn::DevSchedule gview{};
     std::vector<uint32_t> lvl_pair, lvl_gat;
+    // ... and their level launches captured in a HIP graph, for the register
+    // rows, scratch and row width they were captured with (replaced when one
+    // changes; the mutex keeps concurrent calls on one plan apart)
+    mutable std::mutex hll_mu;
+    mutable hipGraphExec_t hll_exec = nullptr;
+    mutable const void *hll_M = nullptr, *hll_scr = nullptr;
+    mutable uint32_t hll_nwords = 0;
     tn_plan_stats stats{};
 };
 

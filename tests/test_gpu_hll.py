@@ -86,3 +86,29 @@ def test_hll_errors():
     with pytest.raises(tn.TNError) as e:
         tn.hll_build(10, [0], [10], [0], T.hll_node_hashes(10, 1), 6)
     assert e.value.code == -2
+
+
+def test_hll_plan_graph_replays_with_other_work_between():
+    # the level launches of a TN_HLL plan are captured once per output and
+    # replayed: every replay, with eager work and other plans' launches
+    # between, must give the oracle's registers
+    n, b = 600, 7
+    s, d, t = T.random_tiny(n, 5000, 1200, seed=41)
+    p = tn.Plan(n, s, d, t, tn.HLL)
+    M = torch.empty((n, 1 << b), dtype=torch.uint8, device="cuda")
+    est = torch.empty(n, dtype=torch.float64, device="cuda")
+    other = tn.Plan(3000, *T.uniform_pairs(3000, 20000, 3000, seed=42))
+    for rep in range(4):
+        h = T.hll_node_hashes(n, seed=400 + rep)
+        want = hll.stream_registers(n, s, d, t, h, b)
+        out = M if rep < 3 else torch.empty_like(M)  # a new output is captured anew
+        p.hll(h, b, M=out, est=est)
+        got = out.cpu().numpy()
+        assert (got == want).all(), rep
+        assert np.allclose(est.cpu().numpy(), hll.estimate(want), rtol=1e-12, atol=0), rep
+        junk = torch.randn(1 << 20, device="cuda")
+        (junk * 2).sum().item()
+        other.execute()  # other launches on the stream (and the context scratch)
+        torch.cuda.synchronize()
+    p.close()
+    other.close()
