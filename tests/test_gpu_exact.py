@@ -219,3 +219,23 @@ def test_full_size_streamed_build_stops_early(c2):
     C, st = tn.build_component_matrix_streamed(100_000, c2["s"], c2["d"], c2["t"])
     assert torch.equal(C, c2["C"])
     assert st["saturated"] == 1 and st["events_run"] < 10_000_000
+
+
+def test_node_relabeling_gives_the_relabeled_matrix():
+    # a race check: a random relabeling of the nodes changes every row
+    # address and the order of the items inside each level, so any result
+    # that depended on item order or on unsynchronized row traffic would
+    # differ; the plan, the streamed build and the batched kernel must all
+    # give C'[pi(u)][pi(w)] = C[u][w]
+    n = 1500
+    s, d, t = T.activity_driven(n, 40_000, 2_000, seed=77)
+    pi = T.rng(78).permutation(n).astype(np.uint32)
+    want = oracle.to_dense(oracle.reverse_matrix(n, s, d, t), n)
+    ps, pd = pi[s], pi[d]
+    p = tn.Plan(n, ps, pd, t)
+    outs = [p.execute(), tn.build_component_matrix_streamed(n, ps, pd, t, chunk_events=3000)[0]]
+    outs += tn.build_component_matrix_batched([(n, ps, pd, t), (n, s, d, t)])[:1]
+    for k, C in enumerate(outs):
+        D = oracle.to_dense(host(C)[:, :oracle.words(n)], n)
+        assert (D[np.ix_(pi, pi)] == want).all(), k
+    p.close()
