@@ -339,20 +339,24 @@ tn_status autotune(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64_t *
 }  // namespace
 
 // Plans B networks on host threads and uploads their schedules.
-tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t *m,
-                       const uint32_t *const *src, const uint32_t *const *dst,
-                       const int64_t *const *t, uint32_t flags, tn_batch **out,
-                       const uint32_t *const *maps, uint32_t n_src, const BatchStream *stream) {
-    if (!ctx || !out) return fail(TN_E_ARG, "ctx or out is NULL");
-    *out = nullptr;
-    if (B <= 0) return fail(TN_E_ARG, "B must be > 0");
-    if (!n || !m || !src || !dst || !t) return fail(TN_E_ARG, "null batch array");
-    std::vector<HostSchedule> hs(B);
+tn_status plan_batch(int32_t B, const uint32_t *n, const int64_t *m, const uint32_t *const *src,
+                     const uint32_t *const *dst, const int64_t *const *t, uint32_t flags,
+                     std::vector<HostSchedule> &hs, std::string &err,
+                     const uint32_t *const *maps, uint32_t n_src, unsigned threads) {
+    if (B <= 0) {
+        err = "B must be > 0";
+        return TN_E_ARG;
+    }
+    if (!n || !m || !src || !dst || !t) {
+        err = "null batch array";
+        return TN_E_ARG;
+    }
+    hs.assign(B, HostSchedule());
     std::vector<tn_status> sts(B, TN_OK);
     std::vector<std::string> errs(B);
     std::atomic<int32_t> next{0};
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const unsigned nth = std::min<unsigned>(hw, (unsigned)B);
+    const unsigned nth = std::min<unsigned>(threads ? threads : hw, (unsigned)B);
     auto worker = [&]() {
         for (;;) {
             const int32_t i = next.fetch_add(1);
@@ -366,7 +370,32 @@ tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t 
     worker();
     for (auto &th : pool) th.join();
     for (int32_t i = 0; i < B; ++i)
-        if (sts[i] != TN_OK) return fail(sts[i], "network " + std::to_string(i) + ": " + errs[i]);
+        if (sts[i] != TN_OK) {
+            err = "network " + std::to_string(i) + ": " + errs[i];
+            return sts[i];
+        }
+    return TN_OK;
+}
+
+tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t *m,
+                       const uint32_t *const *src, const uint32_t *const *dst,
+                       const int64_t *const *t, uint32_t flags, tn_batch **out,
+                       const uint32_t *const *maps, uint32_t n_src, const BatchStream *stream) {
+    if (!ctx || !out) return fail(TN_E_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    std::vector<HostSchedule> hs;
+    std::string err;
+    tn_status st = plan_batch(B, n, m, src, dst, t, flags, hs, err, maps, n_src, 0);
+    if (st != TN_OK) return fail(st, err);
+    return batch_from_plans(ctx, B, n, flags, hs, out, stream);
+}
+
+tn_status batch_from_plans(tn_ctx *ctx, int32_t B, const uint32_t *n, uint32_t flags,
+                           std::vector<HostSchedule> &hs, tn_batch **out,
+                           const BatchStream *stream) {
+    if (!ctx || !out) return fail(TN_E_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    if (B <= 0 || (int32_t)hs.size() != B) return fail(TN_E_ARG, "one schedule per network");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
     tn_batch *b = new (std::nothrow) tn_batch();

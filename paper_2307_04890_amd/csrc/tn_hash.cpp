@@ -1,6 +1,11 @@
 // C ABI of network hashing (Sec. 4.1) and fusion (Sec. 4.2).
 #include <algorithm>
 #include <chrono>
+#include <atomic>
+#include <condition_variable>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "tn_batch.h"
@@ -134,19 +139,79 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     e = hipHostMalloc((void **)&done_host, sizeof(unsigned int), 0);
     if (e != hipSuccess) return hip_fail(e, "pinned counter");
     *done_host = 0;
-    for (size_t c = 0; c < bounds.size() && st == TN_OK; ++c) {
+    // Chunk 0 is planned here on every host thread: its latency comes first,
+    // and proxies of few super-nodes often saturate within it.  Only if they
+    // do not, later chunks are planned by background threads, one chunk each
+    // (its H streams in turn), ahead of the launches by at most `window`
+    // chunks and about 2^26 mapped events, so that host planning overlaps
+    // the device.
+    const size_t nch = bounds.size();
+    struct Planned {
+        std::vector<HostSchedule> hs;
+        tn_status st = TN_OK;
+        std::string err;
+        bool ready = false;
+    };
+    std::vector<Planned> plans(nch);
+    std::mutex mu;
+    std::condition_variable cv;
+    std::atomic<size_t> next{1};
+    bool stop = false;    // under mu: no more chunks are wanted
+    size_t consumed = 0;  // under mu: chunks launched
+    auto plan_chunk = [&](size_t c, unsigned threads) {
         const int64_t a = bounds[c].first, mc = bounds[c].second - bounds[c].first;
         std::vector<int64_t> ms(H, mc);
         std::vector<const uint32_t *> ss(H, src ? src + a : nullptr), ds(H, dst ? dst + a : nullptr);
         std::vector<const int64_t *> ts(H, t ? t + a : nullptr);
+        std::vector<HostSchedule> hs;
+        std::string err;
+        const tn_status ps = plan_batch((int32_t)H, ns.data(), ms.data(), ss.data(), ds.data(),
+                                        ts.data(), flags, hs, err, maps.data(), n, threads);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            plans[c].hs = std::move(hs);
+            plans[c].st = ps;
+            plans[c].err = std::move(err);
+            plans[c].ready = true;
+        }
+        cv.notify_all();
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nth = std::min<size_t>(std::min<unsigned>(hw, 16u), nch - 1);
+    const size_t window = std::max<size_t>(
+        1, std::min<size_t>(nth, ((size_t)1 << 26) / std::max<size_t>(1, (size_t)H * chunk_events)));
+    auto worker = [&]() {
+        for (;;) {
+            const size_t c = next.fetch_add(1);
+            if (c >= nch) return;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop || c < consumed + window; });
+                if (stop) return;
+            }
+            plan_chunk(c, 1);
+        }
+    };
+    plan_chunk(0, 0);
+    std::vector<std::thread> pool;
+    for (size_t c = 0; c < nch && st == TN_OK; ++c) {
+        const int64_t mc = bounds[c].second - bounds[c].first;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return plans[c].ready; });
+        }
+        if (plans[c].st != TN_OK) {
+            st = fail(plans[c].st, plans[c].err);
+            break;
+        }
         BatchStream bs;
         bs.lw = c ? lw.data() : nullptr;
         bs.persist = c ? pst.data() : nullptr;
         bs.resume = c ? 1u : 0u;
         bs.done_count = done_dev;
         tn_batch *b = nullptr;
-        st = batch_create(ctx, (int32_t)H, ns.data(), ms.data(), ss.data(), ds.data(), ts.data(),
-                          flags, &b, maps.data(), n, &bs);
+        st = batch_from_plans(ctx, (int32_t)H, ns.data(), flags, plans[c].hs, &b, &bs);
+        plans[c].hs.clear();
         if (st != TN_OK) break;
         if (c == 0) {
             // slice state of every tile of every proxy, then the done counter
@@ -186,11 +251,24 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
         if (st != TN_OK) break;
         ++launched;
         run_events += mc;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            consumed = c + 1;
+        }
+        cv.notify_all();
         if (ctx->saturation && *done_host == tiles) {
             all_done = true;
             break;
         }
+        if (c == 0)
+            for (size_t k = 0; k < nth; ++k) pool.emplace_back(worker);
     }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        stop = true;
+    }
+    cv.notify_all();
+    for (auto &th : pool) th.join();
     (void)hipStreamSynchronize(ctx->stream);
     if (state) (void)hipFree(state);
     (void)hipHostFree(done_host);
