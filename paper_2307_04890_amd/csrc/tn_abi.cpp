@@ -290,6 +290,11 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     if (ld < nwords) return fail(TN_E_ARG, "ld must be >= ceil(n/64)");
     if (plan->device != ctx->device) return fail(TN_E_ARG, "plan lives on another device");
     if (plan->hll) return fail(TN_E_ARG, "a TN_HLL plan runs only tn_hll_execute");
+    // a small network with the slice width left to the library runs on one
+    // wavefront per word column, its column in LDS
+    const bool wave = slice_words == 0 && tn::default_slice_words(n, ld) == 1 &&
+                      tn::rowor_wave_pays(n, plan->scratch_rows, plan->stats.ops,
+                                          plan->stats.op_levels);
     if (slice_words == 0) slice_words = tn::default_slice_words(n, ld);
     if (slice_words > 64 || (slice_words & (slice_words - 1)))
         return fail(TN_E_ARG, "slice_words must be a power of two <= 64");
@@ -299,7 +304,7 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     // zero phase) the slice state the two launches share and its done counter
     const size_t sink_rows_words = (size_t)tn::rowor_workgroups(n, slice_words) * tn::kRoworSinkWords +
                                    (size_t)plan->scratch_rows * (size_t)nwords;
-    const bool zero_phase = ctx->saturation && plan->zero_levels > 0;
+    const bool zero_phase = !wave && ctx->saturation && plan->zero_levels > 0;
     const size_t pwords = zero_phase ? tn::rowor_persist_words(n, slice_words) + 1 : 0;
     {
         tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * sink_rows_words + 4 * pwords);
@@ -323,10 +328,15 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     if (e != hipSuccess) return hip_fail(e, "identity kernel launch");
     {
         tn::ProfScope ps(ctx, TN_K_ROWOR);
-        e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
-                                    plan->scratch_rows, ctx->traffic, ctx->saturation, persist,
-                                    persist ? persist + pwords - 1 : nullptr,
-                                    zero_phase ? plan->zero_levels : 0u, ctx->stream);
+        if (wave)
+            e = tn::launch_rowor_wave(plan->view, n, C, ld, plan->scratch_rows, ctx->traffic,
+                                      nullptr, nullptr, ctx->stream);
+        else
+            e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words,
+                                        (uint64_t *)ctx->scratch, plan->scratch_rows,
+                                        ctx->traffic, ctx->saturation, persist,
+                                        persist ? persist + pwords - 1 : nullptr,
+                                        zero_phase ? plan->zero_levels : 0u, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "row-OR kernel launch");
     return TN_OK;

@@ -223,6 +223,22 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
                                uint32_t scratch_rows, unsigned long long *traffic,
                                bool saturation, uint32_t *persist, unsigned int *done_count,
                                uint32_t zero_levels, hipStream_t st);
+// Small networks: the row-OR stream of one-word slices with the column in
+// LDS, one wavefront per word column and no barrier (k_rowor_wave), for n
+// real plus scratch rows in kRoworWaveLds bytes.  It loads and stores C
+// once and keeps persist (as launch_rowor_global's with one-word slices)
+// when given; traffic counts those loads and stores.
+constexpr size_t kRoworWaveLds = 64 * 1024;
+bool rowor_wave_fits(uint32_t n, uint32_t scratch_rows);
+// ... and whether it beats the workgroup kernel: its lanes take a level's
+// ops 64 at a time, so it wins while levels are short (timed: n = 100 and
+// 1000, about 11 and 97 ops per level, 3.9x and 1.7x faster; n = 3000,
+// 282 ops per level, 1.3x slower)
+constexpr int64_t kRoworWaveOpsPerLevel = 128;
+bool rowor_wave_pays(uint32_t n, uint32_t scratch_rows, int64_t ops, int64_t levels);
+hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
+                             uint32_t scratch_rows, unsigned long long *traffic,
+                             uint32_t *persist, unsigned int *done_count, hipStream_t st);
 // Levels of the zero phase of a schedule: those before the level at which
 // its ops reach `budget`.  Applied to the identity the budget is n (about
 // one op per row), by when few row slices are still all zero; a streamed

@@ -553,6 +553,91 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     }
 }
 
+// Small networks: one wavefront per word column keeps that column of every
+// row and scratch row in LDS and runs every level of the op schedule with
+// no barrier.  The ops of a level touch disjoint rows, and one wavefront's
+// LDS accesses complete in program order, so level l + 1 sees level l.
+// Ops and level starts are staged in LDS windows of kWaveWin entries, one
+// global round trip per window instead of one per level: here a level
+// costs a few LDS round trips, where the workgroup kernel pays a barrier
+// and a schedule load.  The column starts from C and is written back; with
+// persist, the slice state of the workgroup kernel's layout is written too
+// (done flag, full count, full-row bits, non-zero-row bits), so either
+// kernel can run the next chunk of a stream.
+constexpr uint32_t kWaveWin = 1024;
+__global__ void __launch_bounds__(64)
+k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
+             unsigned long long *__restrict__ traffic, uint32_t *__restrict__ persist,
+             unsigned int *__restrict__ done_count) {
+    extern __shared__ uint64_t rows[];  // n real rows, then the scratch rows
+    __shared__ op4 obuf[kWaveWin];
+    __shared__ uint32_t lbuf[kWaveWin];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t w = xcd_slice(blockIdx.x, gridDim.x);  // this wavefront's word column
+    const uint32_t rwords = (n + 31) / 32;
+    uint32_t *pst = persist ? persist + (size_t)w * (2 * (size_t)rwords + 2) : nullptr;
+    if (pst && pst[0]) return;  // the column is all ones already (uniform)
+    for (uint32_t r = lane; r < n; r += 64) rows[r] = C[(size_t)r * ld + w];
+    auto slot = [&](uint32_t id) { return (id & kScratchBit) ? n + (id & kNodeMask) : id; };
+    uint32_t lbase = 0xffffffffu, obase = 0xffffffffu;
+    // level start l from the staged window (reloaded when l leaves it)
+    auto level_start = [&](uint32_t l) -> uint32_t {
+        if (lbase == 0xffffffffu || l >= lbase + kWaveWin) {
+            lbase = l;
+            for (uint32_t i = lane; i < kWaveWin; i += 64) lbuf[i] = s.lvl[min(l + i, s.L)];
+        }
+        return lbuf[l - lbase];
+    };
+    const op4 *ops = reinterpret_cast<const op4 *>(s.ops);
+    uint32_t p0 = level_start(0);
+    for (uint32_t l = 0; l < s.L; ++l) {
+        const uint32_t p1 = level_start(l + 1);
+        for (uint32_t q0 = p0; q0 < p1; q0 += 64) {
+            if (obase == 0xffffffffu || q0 + 64 > obase + kWaveWin) {
+                obase = q0;
+                for (uint32_t i = lane; i < kWaveWin; i += 64) obuf[i] = ops[min(q0 + i, s.nops - 1)];
+            }
+            const uint32_t q = q0 + lane;
+            if (q < p1) {
+                const op4 o = obuf[q - obase];
+                const uint64_t r = rows[slot(o.x)] | rows[slot(o.y)];
+                if (o.z != kNoRow) rows[slot(o.z)] = r;
+                if (o.w != kNoRow) rows[slot(o.w)] = r;
+            }
+        }
+        p0 = p1;
+    }
+    for (uint32_t r = lane; r < n; r += 64) C[(size_t)r * ld + w] = rows[r];
+    if (traffic && lane == 0) {
+        atomicAdd(traffic, (unsigned long long)n);
+        atomicAdd(traffic + 1, (unsigned long long)n);
+    }
+    if (!pst) return;
+    const uint32_t tail = n & 63u;
+    const uint64_t fullw = (w + 1 < nwords || tail == 0) ? ~0ull : (1ull << tail) - 1ull;
+    int32_t nfull = 0;
+    for (uint32_t k = lane; k < rwords; k += 64) {
+        uint32_t fb = 0, nz = 0;
+        for (uint32_t b = 0; b < 32 && 32 * k + b < n; ++b) {
+            const uint64_t v = rows[32 * k + b];
+            fb |= (uint32_t)(v == fullw) << b;
+            nz |= (uint32_t)(v != 0) << b;
+        }
+        pst[2 + k] = fb;
+        pst[2 + rwords + k] = nz;
+        nfull += __popc(fb);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nfull += __shfl_xor(nfull, off);
+    if (lane == 0) {
+        pst[1] = (uint32_t)nfull;
+        if (nfull == (int32_t)n) {
+            pst[0] = 1u;
+            atomicAdd(done_count, 1u);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -749,6 +834,29 @@ hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, unsigned long lo
 uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words) {
     const uint32_t nwords = (n + 63) / 64;
     return (nwords + slice_words - 1) / slice_words;
+}
+
+bool rowor_wave_fits(uint32_t n, uint32_t scratch_rows) {
+    return ((size_t)n + scratch_rows + 1) * 8 <= kRoworWaveLds;
+}
+
+bool rowor_wave_pays(uint32_t n, uint32_t scratch_rows, int64_t ops, int64_t levels) {
+    return rowor_wave_fits(n, scratch_rows) && ops <= kRoworWaveOpsPerLevel * levels;
+}
+
+hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
+                             uint32_t scratch_rows, unsigned long long *traffic,
+                             uint32_t *persist, unsigned int *done_count, hipStream_t st) {
+    if (s.L == 0 || s.nops == 0) return hipSuccess;
+    if (!rowor_wave_fits(n, scratch_rows)) return hipErrorInvalidValue;
+    const uint32_t nwords = (n + 63) / 64;
+    const size_t lds = ((size_t)n + scratch_rows + 1) * 8;
+    hipError_t e = hipFuncSetAttribute((const void *)k_rowor_wave,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowor_wave, dim3(nwords), dim3(64), lds, st, C, ld, n, nwords, s, traffic,
+                       persist, done_count);
+    return hipGetLastError();
 }
 
 hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,

@@ -344,9 +344,19 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
                 if (zl < ch.hs.Lops) s.zero_open = false;
                 s.zero_ops += (int64_t)ch.hs.ops.size() / 4;
             }
-            e = launch_rowor_global(ops_view(ch.hs, r.dev), s.n, s.C, s.ld, s.sw,
-                                    (uint64_t *)ctx->scratch, ch.hs.scratch_rows, ctx->traffic,
-                                    ctx->saturation, s.persist, s.done_count, zl, ctx->stream);
+            if (s.sw == 1 && rowor_wave_pays(s.n, ch.hs.scratch_rows,
+                                             (int64_t)ch.hs.ops.size() / 4, ch.hs.Lops))
+                // a small network: one wavefront per word column; the slice
+                // state goes on only when saturated slices may stop
+                e = launch_rowor_wave(ops_view(ch.hs, r.dev), s.n, s.C, s.ld,
+                                      ch.hs.scratch_rows, ctx->traffic,
+                                      ctx->saturation ? s.persist : nullptr, s.done_count,
+                                      ctx->stream);
+            else
+                e = launch_rowor_global(ops_view(ch.hs, r.dev), s.n, s.C, s.ld, s.sw,
+                                        (uint64_t *)ctx->scratch, ch.hs.scratch_rows,
+                                        ctx->traffic, ctx->saturation, s.persist, s.done_count,
+                                        zl, ctx->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(r.done_host, s.done_count, sizeof(unsigned int),

@@ -239,3 +239,26 @@ def test_node_relabeling_gives_the_relabeled_matrix():
         D = oracle.to_dense(host(C)[:, :oracle.words(n)], n)
         assert (D[np.ix_(pi, pi)] == want).all(), k
     p.close()
+
+
+@pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.TIES_SEQUENTIAL, tn.FORWARD])
+def test_small_networks_on_one_wavefront_per_column(flags):
+    # small n with the slice width left to the library: one wavefront per
+    # word column runs every level with the column in LDS.  Long schedules
+    # (many op and level windows), compound-heavy star steps, a column count
+    # that is not a multiple of anything; against the oracle and against the
+    # workgroup kernel (an explicit slice width selects it)
+    cases = [T.er_poisson(100, 200_000, 20_000_000, seed=81), T.star_steps(700, 5000, 9, seed=82),
+             T.activity_driven(3000, 60_000, 30_000, seed=83)]
+    for k, (s, d, t) in enumerate(cases):
+        n = (100, 700, 3000)[k]
+        st = tn.host_schedule(n, s, d, t, flags)["stats"]
+        assert st["ops"] <= 128 * st["op_levels"], k  # short levels: the wavefront kernel
+        ref = oracle.forward_matrix if flags & tn.FORWARD else oracle.reverse_matrix
+        want = ref(n, s, d, t, directed=bool(flags & tn.DIRECTED),
+                   sequential=bool(flags & tn.TIES_SEQUENTIAL))
+        assert (gpu_matrix(n, s, d, t, flags) == want).all(), k
+        assert (gpu_matrix(n, s, d, t, flags, slice_words=1) == want).all(), k
+        C, st = tn.build_component_matrix_streamed(n, s, d, t, flags, chunk_events=7000)
+        assert (host(C)[:, :oracle.words(n)] == want).all(), k
+        assert st["chunks_run"] <= st["chunks"]
