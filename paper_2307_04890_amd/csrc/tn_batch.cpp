@@ -342,7 +342,7 @@ tn_status autotune(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64_t *
 tn_status plan_batch(int32_t B, const uint32_t *n, const int64_t *m, const uint32_t *const *src,
                      const uint32_t *const *dst, const int64_t *const *t, uint32_t flags,
                      std::vector<HostSchedule> &hs, std::string &err,
-                     const uint32_t *const *maps, uint32_t n_src, unsigned threads) {
+                     const uint32_t *const *maps, uint32_t n_src, unsigned threads, int forms) {
     if (B <= 0) {
         err = "B must be > 0";
         return TN_E_ARG;
@@ -362,7 +362,7 @@ tn_status plan_batch(int32_t B, const uint32_t *n, const int64_t *m, const uint3
             const int32_t i = next.fetch_add(1);
             if (i >= B) return;
             sts[i] = plan_events(n[i], m[i], src[i], dst[i], t[i], flags, hs[i], errs[i],
-                                 maps ? maps[i] : nullptr, n_src);
+                                 maps ? maps[i] : nullptr, n_src, forms);
         }
     };
     std::vector<std::thread> pool;
@@ -385,7 +385,7 @@ tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t 
     *out = nullptr;
     std::vector<HostSchedule> hs;
     std::string err;
-    tn_status st = plan_batch(B, n, m, src, dst, t, flags, hs, err, maps, n_src, 0);
+    tn_status st = plan_batch(B, n, m, src, dst, t, flags, hs, err, maps, n_src, 0, kFormGather);
     if (st != TN_OK) return fail(st, err);
     return batch_from_plans(ctx, B, n, flags, hs, out, stream);
 }

@@ -46,14 +46,15 @@ tn_status batch_create(tn_ctx *ctx, int32_t B, const uint32_t *n, const int64_t 
                        const uint32_t *const *maps = nullptr, uint32_t n_src = 0,
                        const BatchStream *stream = nullptr);
 // The two halves of batch_create.  plan_batch plans the B networks on the
-// host only (up to `threads` host threads, 0 = all), so it may run on any
-// thread; its error text goes to err.  batch_from_plans uploads them and
+// host only (up to `threads` host threads, 0 = all; `forms` as for
+// plan_events), so it may run on any thread; its error text goes to err.  batch_from_plans uploads them and
 // sets the launch shape (device work: the calling thread must own the
 // context's stream); it empties hs.
 tn_status plan_batch(int32_t B, const uint32_t *n, const int64_t *m, const uint32_t *const *src,
                      const uint32_t *const *dst, const int64_t *const *t, uint32_t flags,
                      std::vector<HostSchedule> &hs, std::string &err,
-                     const uint32_t *const *maps, uint32_t n_src, unsigned threads);
+                     const uint32_t *const *maps, uint32_t n_src, unsigned threads,
+                     int forms = kFormGather);
 tn_status batch_from_plans(tn_ctx *ctx, int32_t B, const uint32_t *n, uint32_t flags,
                            std::vector<HostSchedule> &hs, tn_batch **out,
                            const BatchStream *stream);

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <atomic>
 #include <condition_variable>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -64,6 +65,134 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *s
     return batch_create(ctx, (int32_t)H, ns.data(), ms.data(), ss.data(), ds.data(), ts.data(),
                         flags, proxies, maps.data(), n);
 }
+
+}  // extern "C"
+
+namespace tn {
+namespace {
+// Proxies of at most this many super-nodes run on one wavefront per column.
+constexpr uint32_t kWaveProxyK = 2048;
+
+// Host image of one chunk of small proxies, in pinned memory so that its
+// upload is one DMA: the H op schedules at 256-byte aligned offsets off[j],
+// then room for the H WaveNet records at off[H].  Images are packed by the
+// planner threads and recycled from chunk to chunk.
+struct WaveImage {
+    unsigned char *pin = nullptr;
+    size_t cap = 0;
+    size_t bytes = 0;
+    std::vector<size_t> off;
+    WaveImage() = default;
+    WaveImage(const WaveImage &) = delete;
+    WaveImage &operator=(const WaveImage &) = delete;
+    WaveImage(WaveImage &&o) noexcept { swap(o); }
+    WaveImage &operator=(WaveImage &&o) noexcept {
+        swap(o);
+        return *this;
+    }
+    ~WaveImage() { release(); }
+    void swap(WaveImage &o) noexcept {
+        std::swap(pin, o.pin);
+        std::swap(cap, o.cap);
+        std::swap(bytes, o.bytes);
+        off.swap(o.off);
+    }
+    void release() {
+        if (pin) (void)hipHostFree(pin);
+        pin = nullptr;
+        cap = 0;
+    }
+};
+
+tn_status wave_image_pack(const std::vector<HostSchedule> &hs, WaveImage &w) {
+    const uint32_t H = (uint32_t)hs.size();
+    w.off.assign(H + 1, 0);
+    for (uint32_t j = 0; j < H; ++j)
+        w.off[j + 1] = w.off[j] + ((ops_device_bytes(hs[j]) + 255) & ~(size_t)255);
+    w.bytes = w.off[H] + sizeof(WaveNet) * H;
+    if (w.bytes > w.cap) {
+        const size_t cap = std::max(w.bytes, w.cap + w.cap / 2);
+        w.release();
+        if (hipHostMalloc((void **)&w.pin, cap, 0) != hipSuccess) {
+            w.pin = nullptr;
+            return TN_E_NOMEM;
+        }
+        w.cap = cap;
+    }
+    for (uint32_t j = 0; j < H; ++j) {
+        const HostSchedule &s = hs[j];
+        unsigned char *b = w.pin + w.off[j];
+        std::memcpy(b, s.lvl_op.data(), 4 * s.lvl_op.size());
+        if (!s.ops.empty())
+            std::memcpy(b + ((4 * s.lvl_op.size() + 255) & ~(size_t)255), s.ops.data(),
+                        4 * s.ops.size());
+    }
+    return TN_OK;
+}
+
+// Device side of the upload: one buffer, grown as needed, kept across chunks.
+struct WaveBuf {
+    void *dev = nullptr;
+    size_t cap = 0;
+    ~WaveBuf() {
+        if (dev) (void)hipFree(dev);
+    }
+};
+
+// One chunk of small proxies: uploads the packed image, runs the H op
+// schedules on one wavefront per word column of each proxy (slice state per
+// column in state, col_words per proxy), reads the done count into
+// *done_host and waits.
+tn_status run_wave_chunk(tn_ctx *ctx, const std::vector<HostSchedule> &hs, WaveImage &img,
+                         uint32_t K, const std::vector<uint64_t *> &Cs, int64_t ldK,
+                         uint32_t *state, size_t col_words, unsigned int *done_dev,
+                         unsigned int *done_host, int64_t &levels, WaveBuf &buf) {
+    const uint32_t H = (uint32_t)hs.size();
+    uint32_t max_scr = 0;
+    for (uint32_t j = 0; j < H; ++j) {
+        max_scr = std::max(max_scr, hs[j].scratch_rows);
+        levels += hs[j].Lops;
+    }
+    hipError_t e = hipSuccess;
+    if (img.bytes > buf.cap) {
+        // the previous chunk's copy and launch are complete (it was waited for)
+        const size_t cap = std::max(img.bytes, buf.cap + buf.cap / 2);
+        if (buf.dev) (void)hipFree(buf.dev);
+        buf.dev = nullptr;
+        buf.cap = 0;
+        e = hipMalloc(&buf.dev, cap);
+        if (e != hipSuccess) {
+            buf.dev = nullptr;
+            return fail(TN_E_NOMEM, "proxy schedule allocation failed");
+        }
+        buf.cap = cap;
+    }
+    unsigned char *dev = (unsigned char *)buf.dev;
+    for (uint32_t j = 0; j < H; ++j) {
+        WaveNet net;
+        net.s = ops_view(hs[j], dev + img.off[j]);
+        net.C = Cs[j];
+        net.ld = ldK;
+        net.persist = ctx->saturation ? state + (size_t)j * col_words : nullptr;
+        std::memcpy(img.pin + img.off[H] + sizeof(WaveNet) * j, &net, sizeof(WaveNet));
+    }
+    e = hipMemcpyAsync(dev, img.pin, img.bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        ProfScope ps(ctx, TN_K_BATCH);
+        e = launch_rowor_wave_multi((const WaveNet *)(dev + img.off[H]), H, K, max_scr, nullptr,
+                                    done_dev, ctx->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(done_host, done_dev, sizeof(unsigned int), hipMemcpyDeviceToHost,
+                           ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "proxy chunk");
+    return TN_OK;
+}
+}  // namespace
+}  // namespace tn
+
+extern "C" {
 
 // Streamed build of the H proxies (Sec. 4.3: the hashed networks are
 // independent and built in parallel; Sec. 3.4: each is a reverse-time
@@ -128,9 +257,18 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
         maps[j] = hb.data() + (size_t)j * n;
         Cs[j] = P + (size_t)j * K * ldK;
     }
+    // Small proxies (K <= kWaveProxyK) run as op schedules on one wavefront
+    // per word column with the column in LDS (levels cost a few LDS round
+    // trips there, against a barrier and schedule loads in the batched
+    // kernel); larger ones as batched tiles.  One stream keeps one kind, as
+    // the two keep different slice states.
+    const bool wave = K <= kWaveProxyK && rowor_wave_fits(K, kOpsScratchRows);
+    const uint32_t kw = (K + 63) / 64;
+    const size_t wave_col = 2 * (size_t)((K + 31) / 32) + 2;  // slice state words per column
     std::vector<uint32_t> lw;
     std::vector<uint32_t *> pst(H, nullptr);
     uint32_t *state = nullptr;
+    WaveBuf wbuf;
     unsigned int *done_host = nullptr;
     unsigned int *done_dev = nullptr;
     uint64_t tiles = 0;
@@ -148,10 +286,12 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     const size_t nch = bounds.size();
     struct Planned {
         std::vector<HostSchedule> hs;
+        WaveImage img;  // small proxies: the packed schedules
         tn_status st = TN_OK;
         std::string err;
         bool ready = false;
     };
+    std::vector<WaveImage> spare;  // under mu: images of launched chunks
     std::vector<Planned> plans(nch);
     std::mutex mu;
     std::condition_variable cv;
@@ -166,12 +306,27 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
         std::vector<HostSchedule> hs;
         std::string err;
         const tn_status ps = plan_batch((int32_t)H, ns.data(), ms.data(), ss.data(), ds.data(),
-                                        ts.data(), flags, hs, err, maps.data(), n, threads);
+                                        ts.data(), flags, hs, err, maps.data(), n, threads,
+                                        wave ? kFormOps : kFormGather);
+        WaveImage img;
+        tn_status ws = TN_OK;
+        if (wave && ps == TN_OK) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!spare.empty()) {
+                    img = std::move(spare.back());
+                    spare.pop_back();
+                }
+            }
+            ws = wave_image_pack(hs, img);
+        }
         {
             std::lock_guard<std::mutex> lk(mu);
             plans[c].hs = std::move(hs);
-            plans[c].st = ps;
-            plans[c].err = std::move(err);
+            plans[c].img = std::move(img);
+            plans[c].st = ps == TN_OK ? ws : ps;
+            plans[c].err = ps == TN_OK && ws != TN_OK ? "pinned schedule image allocation failed"
+                                                      : std::move(err);
             plans[c].ready = true;
         }
         cv.notify_all();
@@ -181,6 +336,7 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     const size_t window = std::max<size_t>(
         1, std::min<size_t>(nth, ((size_t)1 << 26) / std::max<size_t>(1, (size_t)H * chunk_events)));
     auto worker = [&]() {
+        (void)hipSetDevice(ctx->device);  // for the pinned image allocations
         for (;;) {
             const size_t c = next.fetch_add(1);
             if (c >= nch) return;
@@ -203,6 +359,47 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
         if (plans[c].st != TN_OK) {
             st = fail(plans[c].st, plans[c].err);
             break;
+        }
+        if (wave) {
+            if (c == 0) {
+                // per-column slice state of every proxy, the done counter;
+                // the proxies start as the identity
+                const size_t words = (size_t)H * kw * wave_col;
+                e = hipMalloc((void **)&state, sizeof(uint32_t) * (words + 1));
+                if (e != hipSuccess) {
+                    state = nullptr;
+                    st = fail(TN_E_NOMEM, "slice state allocation failed");
+                    break;
+                }
+                done_dev = state + words;
+                tiles = (uint64_t)H * kw;
+                e = launch_fill_u32(state, words + 1, 0u, ctx->stream);
+                for (uint32_t j = 0; j < H && e == hipSuccess; ++j)
+                    e = launch_identity(Cs[j], K, ldK, nullptr, ctx->stream);
+                if (e != hipSuccess) {
+                    st = hip_fail(e, "proxy initialisation");
+                    break;
+                }
+            }
+            st = run_wave_chunk(ctx, plans[c].hs, plans[c].img, K, Cs, ldK, state, wave_col * kw,
+                                done_dev, done_host, levels, wbuf);
+            plans[c].hs.clear();
+            if (st != TN_OK) break;
+            ++launched;
+            run_events += mc;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                consumed = c + 1;
+                spare.push_back(std::move(plans[c].img));
+            }
+            cv.notify_all();
+            if (ctx->saturation && *done_host == tiles) {
+                all_done = true;
+                break;
+            }
+            if (c == 0)
+                for (size_t k = 0; k < nth; ++k) pool.emplace_back(worker);
+            continue;
         }
         BatchStream bs;
         bs.lw = c ? lw.data() : nullptr;
@@ -278,7 +475,7 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
         stats->events_run = run_events;
         stats->levels_run = levels;
         stats->saturated = all_done ? 1 : 0;
-        stats->slice_words = lw.empty() ? 0 : (int32_t)(1u << lw[0]);
+        stats->slice_words = wave ? 1 : (lw.empty() ? 0 : (int32_t)(1u << lw[0]));
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return st;

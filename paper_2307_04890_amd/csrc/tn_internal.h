@@ -236,6 +236,20 @@ bool rowor_wave_fits(uint32_t n, uint32_t scratch_rows);
 // 282 ops per level, 1.3x slower)
 constexpr int64_t kRoworWaveOpsPerLevel = 128;
 bool rowor_wave_pays(uint32_t n, uint32_t scratch_rows, int64_t ops, int64_t levels);
+// One network of a multi-network wavefront launch (the hashed proxies): its
+// op schedule, its matrix (n rows of ld words) and its per-column state
+// (nullable; the layout of launch_rowor_global's with one-word slices).
+struct WaveNet {
+    DevOps s;
+    uint64_t *C;
+    int64_t ld;
+    uint32_t *persist;
+};
+// count networks of n nodes each, one wavefront per word column of each;
+// nets: DEVICE array; scratch rows up to max_scratch_rows in every network.
+hipError_t launch_rowor_wave_multi(const WaveNet *nets, uint32_t count, uint32_t n,
+                                   uint32_t max_scratch_rows, unsigned long long *traffic,
+                                   unsigned int *done_count, hipStream_t st);
 hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                              uint32_t scratch_rows, unsigned long long *traffic,
                              uint32_t *persist, unsigned int *done_count, hipStream_t st);

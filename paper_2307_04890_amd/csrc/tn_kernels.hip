@@ -565,18 +565,16 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
 // (done flag, full count, full-row bits, non-zero-row bits), so either
 // kernel can run the next chunk of a stream.
 constexpr uint32_t kWaveWin = 1024;
-__global__ void __launch_bounds__(64)
-k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
-             unsigned long long *__restrict__ traffic, uint32_t *__restrict__ persist,
-             unsigned int *__restrict__ done_count) {
-    extern __shared__ uint64_t rows[];  // n real rows, then the scratch rows
-    __shared__ op4 obuf[kWaveWin];
-    __shared__ uint32_t lbuf[kWaveWin];
+// One word column w of one network; rows: LDS of n real plus scratch rows.
+__device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords,
+                                  const DevOps &s, uint32_t w, uint64_t *rows, op4 *obuf,
+                                  uint32_t *lbuf, unsigned long long *__restrict__ traffic,
+                                  uint32_t *__restrict__ persist, unsigned int *__restrict__ done_count) {
     const uint32_t lane = threadIdx.x;
-    const uint32_t w = xcd_slice(blockIdx.x, gridDim.x);  // this wavefront's word column
     const uint32_t rwords = (n + 31) / 32;
     uint32_t *pst = persist ? persist + (size_t)w * (2 * (size_t)rwords + 2) : nullptr;
-    if (pst && pst[0]) return;  // the column is all ones already (uniform)
+    if (s.L == 0 || s.nops == 0) return;  // nothing to apply: C is left as it is
+    if (pst && pst[0]) return;            // the column is all ones already (uniform)
     for (uint32_t r = lane; r < n; r += 64) rows[r] = C[(size_t)r * ld + w];
     auto slot = [&](uint32_t id) { return (id & kScratchBit) ? n + (id & kNodeMask) : id; };
     uint32_t lbase = 0xffffffffu, obase = 0xffffffffu;
@@ -636,6 +634,31 @@ k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, 
             atomicAdd(done_count, 1u);
         }
     }
+}
+
+__global__ void __launch_bounds__(64)
+k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
+             unsigned long long *__restrict__ traffic, uint32_t *__restrict__ persist,
+             unsigned int *__restrict__ done_count) {
+    extern __shared__ uint64_t rows[];  // n real rows, then the scratch rows
+    __shared__ op4 obuf[kWaveWin];
+    __shared__ uint32_t lbuf[kWaveWin];
+    rowor_wave_column(C, ld, n, nwords, s, xcd_slice(blockIdx.x, gridDim.x), rows, obuf, lbuf,
+                      traffic, persist, done_count);
+}
+
+// Many networks of n nodes each (the hashed proxies): wavefront b runs word
+// column b % nwords of network b / nwords.
+__global__ void __launch_bounds__(64)
+k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords,
+                   unsigned long long *__restrict__ traffic, unsigned int *__restrict__ done_count) {
+    extern __shared__ uint64_t rows[];
+    __shared__ op4 obuf[kWaveWin];
+    __shared__ uint32_t lbuf[kWaveWin];
+    const uint32_t b = xcd_slice(blockIdx.x, gridDim.x);
+    const WaveNet &net = nets[b / nwords];
+    rowor_wave_column(net.C, net.ld, n, nwords, net.s, b % nwords, rows, obuf, lbuf, traffic,
+                      net.persist, done_count);
 }
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
@@ -856,6 +879,21 @@ hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t l
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rowor_wave, dim3(nwords), dim3(64), lds, st, C, ld, n, nwords, s, traffic,
                        persist, done_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowor_wave_multi(const WaveNet *nets, uint32_t count, uint32_t n,
+                                   uint32_t max_scratch_rows, unsigned long long *traffic,
+                                   unsigned int *done_count, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    if (!rowor_wave_fits(n, max_scratch_rows)) return hipErrorInvalidValue;
+    const uint32_t nwords = (n + 63) / 64;
+    const size_t lds = ((size_t)n + max_scratch_rows + 1) * 8;
+    hipError_t e = hipFuncSetAttribute((const void *)k_rowor_wave_multi,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowor_wave_multi, dim3(count * nwords), dim3(64), lds, st, nets, n, nwords,
+                       traffic, done_count);
     return hipGetLastError();
 }
 
