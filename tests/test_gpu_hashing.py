@@ -141,6 +141,32 @@ def test_streamed_proxies_equal_the_batched_proxies(flags):
             assert st["saturated"] == 1 and st["chunks_run"] < st["chunks"]
 
 
+def test_streamed_proxies_on_both_sides_of_the_wavefront_limit():
+    # proxies of at most 2048 super-nodes run one wavefront per word column,
+    # larger ones as batched tiles: both, over several chunks, with and
+    # without saturation tracking, and with a padded row stride
+    n, m, H = 9000, 40000, 3
+    s, d, t = T.activity_driven(n, m, 4000, seed=77)
+    ctx = tn.get_context()
+    try:
+        for K in (2047, 2048, 2049):
+            A = T.hash_coefficients(H, seed=K)
+            wb = oracle.hash_nodes(n, A, K)
+            WP = oracle.proxies(K, s, d, t, wb)
+            for sat in (True, False):
+                ctx.saturation(sat)
+                ld = oracle.words(K) + (1 if sat else 0)
+                P = torch.full((H, K, ld), -1, dtype=torch.int64, device="cuda")
+                _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, chunk_events=7000, P=P)
+                got = host(P)
+                assert (got[:, :, :oracle.words(K)] == WP).all(), (K, sat)
+                if ld > oracle.words(K):
+                    assert (got[:, :, -1] == 0).all(), (K, sat)  # P is written entirely
+                assert st["chunks"] > 1 and st["slice_words"] >= 1
+    finally:
+        ctx.saturation(True)
+
+
 def test_streamed_proxies_at_the_scaled_hashed_workload():
     n, m, H, K = 200_000, 5_000_000, 16, 4096
     s, d, t = T.activity_driven(n, m, 500_000, seed=3)
