@@ -557,53 +557,115 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
 // row and scratch row in LDS and runs every level of the op schedule with
 // no barrier.  The ops of a level touch disjoint rows, and one wavefront's
 // LDS accesses complete in program order, so level l + 1 sees level l.
-// Ops and level starts are staged in LDS windows of kWaveWin entries, one
-// global round trip per window instead of one per level: here a level
-// costs a few LDS round trips, where the workgroup kernel pays a barrier
-// and a schedule load.  The column starts from C and is written back; with
-// persist, the slice state of the workgroup kernel's layout is written too
-// (done flag, full count, full-row bits, non-zero-row bits), so either
-// kernel can run the next chunk of a stream.
-constexpr uint32_t kWaveWin = 1024;
+// The loop is software-pipelined so that a group of up to 64 ops of one
+// level costs one LDS round trip.  Ops and level starts each live in an LDS
+// ring of two windows; the window after those is loaded from HBM into
+// registers one window ahead of use.  The next group's ops and the start
+// of the level after next are read from LDS before the current group's row
+// reads, so the level loop never waits on HBM or on a second LDS trip.
+constexpr uint32_t kWaveWin = 512;
+constexpr uint32_t kWaveRing = 2 * kWaveWin;
+constexpr uint32_t kWavePre = kWaveWin / 64;  // entries per lane of a prefetched window
+
+// A ring of two windows of T in LDS fed from src[0 .. count) (the last
+// entry repeated past the end), with the window after them in registers.
+template <typename T>
+struct WaveRing {
+    T *ring;
+    const T *src;
+    uint32_t count, nwin, next;  // windows below next are (or were) in the ring
+    T pre[kWavePre];
+    __device__ void fetch(uint32_t win, uint32_t lane) {
+#pragma unroll
+        for (uint32_t k = 0; k < kWavePre; ++k) pre[k] = src[min(win * kWaveWin + 64 * k + lane, count - 1)];
+    }
+    __device__ void store(uint32_t win, uint32_t lane) {
+#pragma unroll
+        for (uint32_t k = 0; k < kWavePre; ++k) ring[(win * kWaveWin + 64 * k + lane) % kWaveRing] = pre[k];
+    }
+    __device__ void init(T *r, const T *s, uint32_t c, uint32_t lane) {
+        ring = r;
+        src = s;
+        count = c;
+        nwin = (c + kWaveWin - 1) / kWaveWin;
+        next = min(nwin, 2u);
+        for (uint32_t win = 0; win < next; ++win) {
+            fetch(win, lane);
+            store(win, lane);
+        }
+        if (next < nwin) fetch(next, lane);
+    }
+    // makes entries up to `last` readable; reads advance by less than a
+    // window at a time, so the ring slot refilled held a window no longer read
+    __device__ void need(uint32_t last, uint32_t lane) {
+        if (last / kWaveWin >= next && next < nwin) {
+            store(next, lane);
+            ++next;
+            if (next < nwin) fetch(next, lane);
+        }
+    }
+    __device__ T at(uint32_t i) const { return ring[i % kWaveRing]; }
+};
+
 // One word column w of one network; rows: LDS of n real plus scratch rows.
+// sink: 64 words of LDS, one per lane, that take the idle lanes' accesses.
 __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords,
-                                  const DevOps &s, uint32_t w, uint64_t *rows, op4 *obuf,
-                                  uint32_t *lbuf, unsigned long long *__restrict__ traffic,
+                                  const DevOps &s, uint32_t w, uint64_t *rows, uint64_t *sink, op4 *oring,
+                                  uint32_t *lring, unsigned long long *__restrict__ traffic,
                                   uint32_t *__restrict__ persist, unsigned int *__restrict__ done_count) {
     const uint32_t lane = threadIdx.x;
     const uint32_t rwords = (n + 31) / 32;
     uint32_t *pst = persist ? persist + (size_t)w * (2 * (size_t)rwords + 2) : nullptr;
     if (s.L == 0 || s.nops == 0) return;  // nothing to apply: C is left as it is
     if (pst && pst[0]) return;            // the column is all ones already (uniform)
-    for (uint32_t r = lane; r < n; r += 64) rows[r] = C[(size_t)r * ld + w];
+    const uint32_t L = s.L;
     auto slot = [&](uint32_t id) { return (id & kScratchBit) ? n + (id & kNodeMask) : id; };
-    uint32_t lbase = 0xffffffffu, obase = 0xffffffffu;
-    // level start l from the staged window (reloaded when l leaves it)
-    auto level_start = [&](uint32_t l) -> uint32_t {
-        if (lbase == 0xffffffffu || l >= lbase + kWaveWin) {
-            lbase = l;
-            for (uint32_t i = lane; i < kWaveWin; i += 64) lbuf[i] = s.lvl[min(l + i, s.L)];
-        }
-        return lbuf[l - lbase];
-    };
-    const op4 *ops = reinterpret_cast<const op4 *>(s.ops);
-    uint32_t p0 = level_start(0);
-    for (uint32_t l = 0; l < s.L; ++l) {
-        const uint32_t p1 = level_start(l + 1);
-        for (uint32_t q0 = p0; q0 < p1; q0 += 64) {
-            if (obase == 0xffffffffu || q0 + 64 > obase + kWaveWin) {
-                obase = q0;
-                for (uint32_t i = lane; i < kWaveWin; i += 64) obuf[i] = ops[min(q0 + i, s.nops - 1)];
+    WaveRing<op4> opr;
+    opr.init(oring, reinterpret_cast<const op4 *>(s.ops), s.nops, lane);
+    WaveRing<uint32_t> lvr;
+    lvr.init(lring, s.lvl, L + 1, lane);
+    auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+    for (uint32_t r = lane; r < n; r += 64) rows[r] = C[(size_t)r * ld + w];
+    // group: ops [q0, min(q0 + 64, p1)) of level l; p2 = start of level
+    // l + 2.  The loop starts on an empty level -1, so that every op and
+    // level start it uses was read inside it.
+    uint32_t l = 0xffffffffu, q0 = uni(lvr.at(0)), p1 = q0;
+    uint32_t p2 = uni(lvr.at(1));
+    uint32_t p3v = L >= 2 ? lvr.at(2) : s.nops;  // start of level l + 3 (lane-uniform VGPR)
+    op4 op = {0u, 0u, kNoRow, kNoRow};
+    for (;;) {
+        uint32_t nl = l, nq0, np1, np2 = p2;
+        if (q0 + 64 < p1) {
+            nq0 = q0 + 64;
+            np1 = p1;
+        } else {
+            nl = l + 1;
+            nq0 = p1;
+            np1 = p2;
+            np2 = uni(p3v);
+            if (nl + 3 <= L) {
+                lvr.need(nl + 3, lane);
+                p3v = lvr.at(nl + 3);
             }
-            const uint32_t q = q0 + lane;
-            if (q < p1) {
-                const op4 o = obuf[q - obase];
-                const uint64_t r = rows[slot(o.x)] | rows[slot(o.y)];
-                if (o.z != kNoRow) rows[slot(o.z)] = r;
-                if (o.w != kNoRow) rows[slot(o.w)] = r;
-            }
         }
-        p0 = p1;
+        const bool more = nl < L;
+        if (more && np1 > nq0) opr.need(min(nq0 + 64, np1) - 1, lane);
+        const op4 nop = opr.at(nq0 + lane);
+        {
+            // branch-free: idle lanes and absent targets use the lane's own
+            // sink word, so every group issues the same LDS operations
+            const bool act = q0 + lane < p1;
+            uint64_t *const own = sink + lane;
+            const uint64_t r = *(act ? rows + slot(op.x) : own) | *(act ? rows + slot(op.y) : own);
+            *(act && op.z != kNoRow ? rows + slot(op.z) : own) = r;
+            *(act && op.w != kNoRow ? rows + slot(op.w) : own) = r;
+        }
+        if (!more) break;
+        op = nop;
+        q0 = nq0;
+        p1 = np1;
+        p2 = np2;
+        l = nl;
     }
     for (uint32_t r = lane; r < n; r += 64) C[(size_t)r * ld + w] = rows[r];
     if (traffic && lane == 0) {
@@ -641,10 +703,11 @@ k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, 
              unsigned long long *__restrict__ traffic, uint32_t *__restrict__ persist,
              unsigned int *__restrict__ done_count) {
     extern __shared__ uint64_t rows[];  // n real rows, then the scratch rows
-    __shared__ op4 obuf[kWaveWin];
-    __shared__ uint32_t lbuf[kWaveWin];
-    rowor_wave_column(C, ld, n, nwords, s, xcd_slice(blockIdx.x, gridDim.x), rows, obuf, lbuf,
-                      traffic, persist, done_count);
+    __shared__ op4 oring[kWaveRing];
+    __shared__ uint32_t lring[kWaveRing];
+    __shared__ uint64_t sink[64];
+    rowor_wave_column(C, ld, n, nwords, s, xcd_slice(blockIdx.x, gridDim.x), rows, sink, oring,
+                      lring, traffic, persist, done_count);
 }
 
 // Many networks of n nodes each (the hashed proxies): wavefront b runs word
@@ -653,12 +716,13 @@ __global__ void __launch_bounds__(64)
 k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords,
                    unsigned long long *__restrict__ traffic, unsigned int *__restrict__ done_count) {
     extern __shared__ uint64_t rows[];
-    __shared__ op4 obuf[kWaveWin];
-    __shared__ uint32_t lbuf[kWaveWin];
+    __shared__ op4 oring[kWaveRing];
+    __shared__ uint32_t lring[kWaveRing];
     const uint32_t b = xcd_slice(blockIdx.x, gridDim.x);
     const WaveNet &net = nets[b / nwords];
-    rowor_wave_column(net.C, net.ld, n, nwords, net.s, b % nwords, rows, obuf, lbuf, traffic,
-                      net.persist, done_count);
+    __shared__ uint64_t sink[64];
+    rowor_wave_column(net.C, net.ld, n, nwords, net.s, b % nwords, rows, sink, oring, lring,
+                      traffic, net.persist, done_count);
 }
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
