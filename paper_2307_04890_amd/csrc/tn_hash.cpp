@@ -5,6 +5,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -70,17 +71,22 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *s
 
 namespace tn {
 namespace {
-// Proxies of at most this many super-nodes run on one wavefront per column.
-constexpr uint32_t kWaveProxyK = 2048;
+// Proxies of at most this many super-nodes run on one wavefront per column
+// (timed on ER networks with Poisson events, K = 2100 to 3900: 1.4x to 2.2x
+// faster than batched tiles; proxies that fill up within the first chunk
+// lose the tiles' early stop there, a fraction of a millisecond).
+constexpr uint32_t kWaveProxyK = 4096;
 
-// Host image of one chunk of small proxies, in pinned memory so that its
-// upload is one DMA: the H op schedules at 256-byte aligned offsets off[j],
-// then room for the H WaveNet records at off[H].  Images are packed by the
-// planner threads and recycled from chunk to chunk.
+// Host image of one chunk of small proxies: the H op schedules at 256-byte
+// aligned offsets off[j], then room for the H WaveNet records at off[H].
+// Images are packed by the planner threads and recycled from chunk to
+// chunk.  A long stream keeps them in pinned memory, so that an upload is
+// one DMA; with few chunks the pinning would cost more than it saves.
 struct WaveImage {
     unsigned char *pin = nullptr;
     size_t cap = 0;
     size_t bytes = 0;
+    bool pinned = false;
     std::vector<size_t> off;
     WaveImage() = default;
     WaveImage(const WaveImage &) = delete;
@@ -95,27 +101,35 @@ struct WaveImage {
         std::swap(pin, o.pin);
         std::swap(cap, o.cap);
         std::swap(bytes, o.bytes);
+        std::swap(pinned, o.pinned);
         off.swap(o.off);
     }
     void release() {
-        if (pin) (void)hipHostFree(pin);
+        if (pin && pinned) (void)hipHostFree(pin);
+        else delete[] pin;
         pin = nullptr;
         cap = 0;
     }
 };
 
-tn_status wave_image_pack(const std::vector<HostSchedule> &hs, WaveImage &w) {
+tn_status wave_image_pack(const std::vector<HostSchedule> &hs, WaveImage &w, bool pinned) {
     const uint32_t H = (uint32_t)hs.size();
     w.off.assign(H + 1, 0);
     for (uint32_t j = 0; j < H; ++j)
         w.off[j + 1] = w.off[j] + ((ops_device_bytes(hs[j]) + 255) & ~(size_t)255);
     w.bytes = w.off[H] + sizeof(WaveNet) * H;
-    if (w.bytes > w.cap) {
+    if (w.bytes > w.cap || w.pinned != pinned) {
         const size_t cap = std::max(w.bytes, w.cap + w.cap / 2);
         w.release();
-        if (hipHostMalloc((void **)&w.pin, cap, 0) != hipSuccess) {
-            w.pin = nullptr;
-            return TN_E_NOMEM;
+        w.pinned = pinned;
+        if (pinned) {
+            if (hipHostMalloc((void **)&w.pin, cap, 0) != hipSuccess) {
+                w.pin = nullptr;
+                return TN_E_NOMEM;
+            }
+        } else {
+            w.pin = new (std::nothrow) unsigned char[cap];
+            if (!w.pin) return TN_E_NOMEM;
         }
         w.cap = cap;
     }
@@ -279,25 +293,31 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     *done_host = 0;
     // Chunk 0 is planned here on every host thread: its latency comes first,
     // and proxies of few super-nodes often saturate within it.  Only if they
-    // do not, later chunks are planned by background threads, one chunk each
-    // (its H streams in turn), ahead of the launches by at most `window`
-    // chunks and about 2^26 mapped events, so that host planning overlaps
-    // the device.
+    // do not, later chunks are planned by background threads, one proxy of
+    // one chunk per task (so that few chunks still use every thread), ahead
+    // of the launches by at most `window` chunks and about 2^26 mapped
+    // events, so that host planning overlaps the device.
     const size_t nch = bounds.size();
     struct Planned {
         std::vector<HostSchedule> hs;
         WaveImage img;  // small proxies: the packed schedules
         tn_status st = TN_OK;
         std::string err;
+        uint32_t left = 0;  // under mu: proxies of the chunk still being planned
         bool ready = false;
     };
     std::vector<WaveImage> spare;  // under mu: images of launched chunks
     std::vector<Planned> plans(nch);
+    for (size_t c = 1; c < nch; ++c) {
+        plans[c].hs.assign(H, HostSchedule());
+        plans[c].left = H;
+    }
     std::mutex mu;
     std::condition_variable cv;
-    std::atomic<size_t> next{1};
+    std::atomic<size_t> next{H};  // background tasks: proxy j of chunk c is task c * H + j
     bool stop = false;    // under mu: no more chunks are wanted
     size_t consumed = 0;  // under mu: chunks launched
+    bool pin_images = false;  // set below, before the first chunk is planned
     auto plan_chunk = [&](size_t c, unsigned threads) {
         const int64_t a = bounds[c].first, mc = bounds[c].second - bounds[c].first;
         std::vector<int64_t> ms(H, mc);
@@ -318,34 +338,82 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
                     spare.pop_back();
                 }
             }
-            ws = wave_image_pack(hs, img);
+            ws = wave_image_pack(hs, img, pin_images);
         }
         {
             std::lock_guard<std::mutex> lk(mu);
             plans[c].hs = std::move(hs);
             plans[c].img = std::move(img);
             plans[c].st = ps == TN_OK ? ws : ps;
-            plans[c].err = ps == TN_OK && ws != TN_OK ? "pinned schedule image allocation failed"
+            plans[c].err = ps == TN_OK && ws != TN_OK ? "schedule image allocation failed"
                                                       : std::move(err);
             plans[c].ready = true;
         }
         cv.notify_all();
     };
+    // proxy j of chunk c >= 1, on a background thread; the last proxy of a
+    // chunk to finish packs the chunk's image
+    auto plan_one = [&](size_t c, uint32_t j) {
+        const int64_t a = bounds[c].first, mc = bounds[c].second - bounds[c].first;
+        HostSchedule h;
+        std::string err;
+        const tn_status ps = plan_events(K, mc, src ? src + a : nullptr, dst ? dst + a : nullptr,
+                                         t ? t + a : nullptr, flags, h, err, maps[j], n,
+                                         wave ? kFormOps : kFormGather);
+        bool last;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            plans[c].hs[j] = std::move(h);
+            if (ps != TN_OK && plans[c].st == TN_OK) {
+                plans[c].st = ps;
+                plans[c].err = "network " + std::to_string(j) + ": " + err;
+            }
+            last = --plans[c].left == 0;
+        }
+        if (!last) return;
+        // every other task of chunk c has finished: its schedules are ours
+        WaveImage img;
+        tn_status ws = TN_OK;
+        if (wave && plans[c].st == TN_OK) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!spare.empty()) {
+                    img = std::move(spare.back());
+                    spare.pop_back();
+                }
+            }
+            ws = wave_image_pack(plans[c].hs, img, pin_images);
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            plans[c].img = std::move(img);
+            if (ws != TN_OK && plans[c].st == TN_OK) {
+                plans[c].st = ws;
+                plans[c].err = "schedule image allocation failed";
+            }
+            plans[c].ready = true;
+        }
+        cv.notify_all();
+    };
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const size_t nth = std::min<size_t>(std::min<unsigned>(hw, 16u), nch - 1);
+    const size_t nth = std::min<size_t>(std::min<unsigned>(hw, 16u), (nch - 1) * H);
     const size_t window = std::max<size_t>(
         1, std::min<size_t>(nth, ((size_t)1 << 26) / std::max<size_t>(1, (size_t)H * chunk_events)));
+    // at most window + 1 images are live at once: pin them when each is
+    // reused a few times
+    pin_images = nch >= 4 * (window + 1);
     auto worker = [&]() {
         (void)hipSetDevice(ctx->device);  // for the pinned image allocations
         for (;;) {
-            const size_t c = next.fetch_add(1);
+            const size_t task = next.fetch_add(1);
+            const size_t c = task / H;
             if (c >= nch) return;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv.wait(lk, [&] { return stop || c < consumed + window; });
                 if (stop) return;
             }
-            plan_chunk(c, 1);
+            plan_one(c, (uint32_t)(task % H));
         }
     };
     plan_chunk(0, 0);

@@ -231,10 +231,10 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
 constexpr size_t kRoworWaveLds = 64 * 1024;
 bool rowor_wave_fits(uint32_t n, uint32_t scratch_rows);
 // ... and whether it beats the workgroup kernel: its lanes take a level's
-// ops 64 at a time, so it wins while levels are short (timed: n = 100 and
-// 1000, about 11 and 97 ops per level, 3.9x and 1.7x faster; n = 3000,
-// 282 ops per level, 1.3x slower)
-constexpr int64_t kRoworWaveOpsPerLevel = 128;
+// ops 64 at a time, one LDS round trip per 64, so it wins while levels are
+// short (timed on ER networks with Poisson events: 199 and 460 ops per
+// level, 2.2x and 1.25x faster; 736 ops per level, even)
+constexpr int64_t kRoworWaveOpsPerLevel = 640;
 bool rowor_wave_pays(uint32_t n, uint32_t scratch_rows, int64_t ops, int64_t levels);
 // One network of a multi-network wavefront launch (the hashed proxies): its
 // op schedule, its matrix (n rows of ld words) and its per-column state

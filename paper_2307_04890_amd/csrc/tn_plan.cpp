@@ -352,20 +352,30 @@ void finish_ops(Planner &p, HostSchedule &out) {
     for (uint32_t l = 1; l <= L; ++l)
         base[l + 1] = base[l] + std::max<uint32_t>(1, (cnt[l] + kOpsLevelCap - 1) / kOpsLevelCap);
     const uint32_t Lf = base[L + 1];
-    std::vector<uint32_t> fcnt(Lf, 0), rank((size_t)L + 1, 0), flev(P);
-    for (size_t i = 0; i < P; ++i) {
-        const uint32_t lv = p.olev[i];
-        flev[i] = base[lv] + rank[lv]++ / kOpsLevelCap;
-        fcnt[flev[i]]++;
-    }
     out.Lops = Lf;
     out.lvl_op.assign((size_t)Lf + 1, 0);
-    for (uint32_t l = 0; l < Lf; ++l) out.lvl_op[l + 1] = out.lvl_op[l] + fcnt[l];
     out.ops.resize(4 * P);
-    std::vector<uint32_t> pos(out.lvl_op.begin(), out.lvl_op.end() - 1);
-    for (size_t i = 0; i < P; ++i) {
-        const size_t q = pos[flev[i]]++;
-        std::memcpy(&out.ops[4 * q], &p.ops[i], sizeof(Planner::Op));
+    if (Lf == L) {
+        // no level is split (the usual case): one counting-sort pass
+        for (uint32_t l = 0; l < L; ++l) out.lvl_op[l + 1] = out.lvl_op[l] + cnt[l + 1];
+        std::vector<uint32_t> pos(out.lvl_op.begin(), out.lvl_op.end() - 1);
+        for (size_t i = 0; i < P; ++i) {
+            const size_t q = pos[p.olev[i] - 1]++;
+            std::memcpy(&out.ops[4 * q], &p.ops[i], sizeof(Planner::Op));
+        }
+    } else {
+        std::vector<uint32_t> fcnt(Lf, 0), rank((size_t)L + 1, 0), flev(P);
+        for (size_t i = 0; i < P; ++i) {
+            const uint32_t lv = p.olev[i];
+            flev[i] = base[lv] + rank[lv]++ / kOpsLevelCap;
+            fcnt[flev[i]]++;
+        }
+        for (uint32_t l = 0; l < Lf; ++l) out.lvl_op[l + 1] = out.lvl_op[l] + fcnt[l];
+        std::vector<uint32_t> pos(out.lvl_op.begin(), out.lvl_op.end() - 1);
+        for (size_t i = 0; i < P; ++i) {
+            const size_t q = pos[flev[i]]++;
+            std::memcpy(&out.ops[4 * q], &p.ops[i], sizeof(Planner::Op));
+        }
     }
     out.scratch_rows = p.S;
     out.op_levels_unsplit = L;

@@ -142,14 +142,14 @@ def test_streamed_proxies_equal_the_batched_proxies(flags):
 
 
 def test_streamed_proxies_on_both_sides_of_the_wavefront_limit():
-    # proxies of at most 2048 super-nodes run one wavefront per word column,
+    # proxies of at most 4096 super-nodes run one wavefront per word column,
     # larger ones as batched tiles: both, over several chunks, with and
     # without saturation tracking, and with a padded row stride
     n, m, H = 9000, 40000, 3
     s, d, t = T.activity_driven(n, m, 4000, seed=77)
     ctx = tn.get_context()
     try:
-        for K in (2047, 2048, 2049):
+        for K in (4095, 4096, 4097):
             A = T.hash_coefficients(H, seed=K)
             wb = oracle.hash_nodes(n, A, K)
             WP = oracle.proxies(K, s, d, t, wb)
