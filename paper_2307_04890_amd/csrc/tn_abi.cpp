@@ -330,7 +330,7 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         tn::ProfScope ps(ctx, TN_K_ROWOR);
         if (wave)
             e = tn::launch_rowor_wave(plan->view, n, C, ld, plan->scratch_rows, ctx->traffic,
-                                      nullptr, nullptr, ctx->stream);
+                                      ctx->saturation, nullptr, nullptr, ctx->stream);
         else
             e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words,
                                         (uint64_t *)ctx->scratch, plan->scratch_rows,

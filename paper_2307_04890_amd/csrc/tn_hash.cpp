@@ -194,7 +194,7 @@ tn_status run_wave_chunk(tn_ctx *ctx, const std::vector<HostSchedule> &hs, WaveI
     if (e == hipSuccess) {
         ProfScope ps(ctx, TN_K_BATCH);
         e = launch_rowor_wave_multi((const WaveNet *)(dev + img.off[H]), H, K, max_scr, nullptr,
-                                    done_dev, ctx->stream);
+                                    ctx->saturation, done_dev, ctx->stream);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(done_host, done_dev, sizeof(unsigned int), hipMemcpyDeviceToHost,

@@ -227,7 +227,8 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
 // LDS, one wavefront per word column and no barrier (k_rowor_wave), for n
 // real plus scratch rows in kRoworWaveLds bytes.  It loads and stores C
 // once and keeps persist (as launch_rowor_global's with one-word slices)
-// when given; traffic counts those loads and stores.
+// when given; traffic counts those loads and stores.  With saturation a
+// column stops once every real row of it is all ones.
 constexpr size_t kRoworWaveLds = 64 * 1024;
 bool rowor_wave_fits(uint32_t n, uint32_t scratch_rows);
 // ... and whether it beats the workgroup kernel: its lanes take a level's
@@ -249,9 +250,9 @@ struct WaveNet {
 // nets: DEVICE array; scratch rows up to max_scratch_rows in every network.
 hipError_t launch_rowor_wave_multi(const WaveNet *nets, uint32_t count, uint32_t n,
                                    uint32_t max_scratch_rows, unsigned long long *traffic,
-                                   unsigned int *done_count, hipStream_t st);
+                                   bool saturation, unsigned int *done_count, hipStream_t st);
 hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                             uint32_t scratch_rows, unsigned long long *traffic,
+                             uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
                              uint32_t *persist, unsigned int *done_count, hipStream_t st);
 // Levels of the zero phase of a schedule: those before the level at which
 // its ops reach `budget`.  Applied to the identity the budget is n (about

@@ -595,26 +595,36 @@ struct WaveRing {
         }
         if (next < nwin) fetch(next, lane);
     }
-    // makes entries up to `last` readable; reads advance by less than a
-    // window at a time, so the ring slot refilled held a window no longer read
-    __device__ void need(uint32_t last, uint32_t lane) {
+    // makes entries up to `last` readable (true when that took a new
+    // window); reads advance by less than a window at a time, so the ring
+    // slot refilled held a window no longer read
+    __device__ bool need(uint32_t last, uint32_t lane) {
         if (last / kWaveWin >= next && next < nwin) {
             store(next, lane);
             ++next;
             if (next < nwin) fetch(next, lane);
+            return true;
         }
+        return false;
     }
     __device__ T at(uint32_t i) const { return ring[i % kWaveRing]; }
 };
 
 // One word column w of one network; rows: LDS of n real plus scratch rows.
 // sink: 64 words of LDS, one per lane, that take the idle lanes' accesses.
+// With sat, the column stops once every real row is all ones: rows only
+// gain bits, so nothing later in the schedule can change it.  It is checked
+// whenever a new window of ops enters the ring (every kWaveWin ops, off the
+// per-group path), by a scan of the column in LDS that ends at the first
+// 64-row block holding a row not yet full.
 __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords,
                                   const DevOps &s, uint32_t w, uint64_t *rows, uint64_t *sink, op4 *oring,
-                                  uint32_t *lring, unsigned long long *__restrict__ traffic,
+                                  uint32_t *lring, unsigned long long *__restrict__ traffic, bool sat,
                                   uint32_t *__restrict__ persist, unsigned int *__restrict__ done_count) {
     const uint32_t lane = threadIdx.x;
     const uint32_t rwords = (n + 31) / 32;
+    const uint32_t tail = n & 63u;
+    const uint64_t fullw = (w + 1 < nwords || tail == 0) ? ~0ull : (1ull << tail) - 1ull;
     uint32_t *pst = persist ? persist + (size_t)w * (2 * (size_t)rwords + 2) : nullptr;
     if (s.L == 0 || s.nops == 0) return;  // nothing to apply: C is left as it is
     if (pst && pst[0]) return;            // the column is all ones already (uniform)
@@ -649,7 +659,16 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
             }
         }
         const bool more = nl < L;
-        if (more && np1 > nq0) opr.need(min(nq0 + 64, np1) - 1, lane);
+        bool stop = false;
+        if (more && np1 > nq0 && opr.need(min(nq0 + 64, np1) - 1, lane) && sat) {
+            // every group before this one has been applied; this one is
+            // applied all the same (it cannot change a full column), so
+            // that no path through the loop skips the group's waits
+            bool full = true;
+            for (uint32_t r0 = 0; r0 < n && full; r0 += 64)
+                full = __all(r0 + lane >= n || rows[r0 + lane] == fullw);
+            stop = full;
+        }
         const op4 nop = opr.at(nq0 + lane);
         {
             // branch-free: idle lanes and absent targets use the lane's own
@@ -657,10 +676,14 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
             const bool act = q0 + lane < p1;
             uint64_t *const own = sink + lane;
             const uint64_t r = *(act ? rows + slot(op.x) : own) | *(act ? rows + slot(op.y) : own);
+            // keeps the read of the next group's ops beside the row reads
+            // (the compiler would otherwise sink it past the saturation
+            // check, a second LDS round trip per group)
+            asm volatile("" : : "v"(nop.x), "v"(nop.y), "v"(nop.z), "v"(nop.w));
             *(act && op.z != kNoRow ? rows + slot(op.z) : own) = r;
             *(act && op.w != kNoRow ? rows + slot(op.w) : own) = r;
         }
-        if (!more) break;
+        if (!more || stop) break;
         op = nop;
         q0 = nq0;
         p1 = np1;
@@ -673,8 +696,6 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
         atomicAdd(traffic + 1, (unsigned long long)n);
     }
     if (!pst) return;
-    const uint32_t tail = n & 63u;
-    const uint64_t fullw = (w + 1 < nwords || tail == 0) ? ~0ull : (1ull << tail) - 1ull;
     int32_t nfull = 0;
     for (uint32_t k = lane; k < rwords; k += 64) {
         uint32_t fb = 0, nz = 0;
@@ -700,21 +721,22 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
 
 __global__ void __launch_bounds__(64)
 k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
-             unsigned long long *__restrict__ traffic, uint32_t *__restrict__ persist,
+             unsigned long long *__restrict__ traffic, bool sat, uint32_t *__restrict__ persist,
              unsigned int *__restrict__ done_count) {
     extern __shared__ uint64_t rows[];  // n real rows, then the scratch rows
     __shared__ op4 oring[kWaveRing];
     __shared__ uint32_t lring[kWaveRing];
     __shared__ uint64_t sink[64];
     rowor_wave_column(C, ld, n, nwords, s, xcd_slice(blockIdx.x, gridDim.x), rows, sink, oring,
-                      lring, traffic, persist, done_count);
+                      lring, traffic, sat, persist, done_count);
 }
 
 // Many networks of n nodes each (the hashed proxies): wavefront b runs word
 // column b % nwords of network b / nwords.
 __global__ void __launch_bounds__(64)
 k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords,
-                   unsigned long long *__restrict__ traffic, unsigned int *__restrict__ done_count) {
+                   unsigned long long *__restrict__ traffic, bool sat,
+                   unsigned int *__restrict__ done_count) {
     extern __shared__ uint64_t rows[];
     __shared__ op4 oring[kWaveRing];
     __shared__ uint32_t lring[kWaveRing];
@@ -722,7 +744,7 @@ k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords
     const WaveNet &net = nets[b / nwords];
     __shared__ uint64_t sink[64];
     rowor_wave_column(net.C, net.ld, n, nwords, net.s, b % nwords, rows, sink, oring, lring,
-                      traffic, net.persist, done_count);
+                      traffic, sat, net.persist, done_count);
 }
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
@@ -932,7 +954,7 @@ bool rowor_wave_pays(uint32_t n, uint32_t scratch_rows, int64_t ops, int64_t lev
 }
 
 hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                             uint32_t scratch_rows, unsigned long long *traffic,
+                             uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
                              uint32_t *persist, unsigned int *done_count, hipStream_t st) {
     if (s.L == 0 || s.nops == 0) return hipSuccess;
     if (!rowor_wave_fits(n, scratch_rows)) return hipErrorInvalidValue;
@@ -942,13 +964,13 @@ hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t l
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rowor_wave, dim3(nwords), dim3(64), lds, st, C, ld, n, nwords, s, traffic,
-                       persist, done_count);
+                       saturation, persist, done_count);
     return hipGetLastError();
 }
 
 hipError_t launch_rowor_wave_multi(const WaveNet *nets, uint32_t count, uint32_t n,
                                    uint32_t max_scratch_rows, unsigned long long *traffic,
-                                   unsigned int *done_count, hipStream_t st) {
+                                   bool saturation, unsigned int *done_count, hipStream_t st) {
     if (count == 0) return hipSuccess;
     if (!rowor_wave_fits(n, max_scratch_rows)) return hipErrorInvalidValue;
     const uint32_t nwords = (n + 63) / 64;
@@ -957,7 +979,7 @@ hipError_t launch_rowor_wave_multi(const WaveNet *nets, uint32_t count, uint32_t
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rowor_wave_multi, dim3(count * nwords), dim3(64), lds, st, nets, n, nwords,
-                       traffic, done_count);
+                       traffic, saturation, done_count);
     return hipGetLastError();
 }
 

@@ -349,7 +349,7 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
                 // a small network: one wavefront per word column; the slice
                 // state goes on only when saturated slices may stop
                 e = launch_rowor_wave(ops_view(ch.hs, r.dev), s.n, s.C, s.ld,
-                                      ch.hs.scratch_rows, ctx->traffic,
+                                      ch.hs.scratch_rows, ctx->traffic, ctx->saturation,
                                       ctx->saturation ? s.persist : nullptr, s.done_count,
                                       ctx->stream);
             else
