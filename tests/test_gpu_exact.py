@@ -262,3 +262,26 @@ def test_small_networks_on_one_wavefront_per_column(flags):
         C, st = tn.build_component_matrix_streamed(n, s, d, t, flags, chunk_events=7000)
         assert (host(C)[:, :oracle.words(n)] == want).all(), k
         assert st["chunks_run"] <= st["chunks"]
+
+
+def test_wavefront_kernel_stops_full_columns():
+    # networks whose rows all fill up long before their earliest events: the
+    # wavefront kernel stops a full column partway through the schedule (a
+    # ragged last column among them); with saturation on and off, resident
+    # and streamed, against the oracle
+    ctx = tn.get_context()
+    cases = [(129, 30_000, 3_000, 91), (700, 60_000, 6_000, 92), (2500, 120_000, 12_000, 93)]
+    try:
+        for n, m, Tm, seed in cases:
+            s, d, t = T.activity_driven(n, m, Tm, seed=seed)
+            want = oracle.reverse_matrix(n, s, d, t)
+            assert (oracle.sizes(want, n)[0] == n).all(), n  # every row fills up
+            st = tn.host_schedule(n, s, d, t)["stats"]
+            assert st["ops"] <= 640 * st["op_levels"] and st["ops"] > 4096, n
+            for sat in (True, False):
+                ctx.saturation(sat)
+                assert (gpu_matrix(n, s, d, t) == want).all(), (n, sat)
+                C, _ = tn.build_component_matrix_streamed(n, s, d, t, chunk_events=m // 5)
+                assert (host(C)[:, :oracle.words(n)] == want).all(), (n, sat)
+    finally:
+        ctx.saturation(True)
