@@ -59,6 +59,8 @@ struct Slot {
 
 constexpr int kRing = 4;
 
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 }  // namespace
 
 // Device state of one matrix that receives a stream chunk by chunk.
@@ -238,6 +240,15 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
         chunks.push_back(std::move(c));
     }
     const int64_t nch = (int64_t)chunks.size();
+    // Ring buffers are sized once for the largest chunk (its schedule image
+    // as the planner reserves it: m + m/4 ops), so that the stream does not
+    // reallocate as its chunks grow; a buffer that must grow all the same
+    // is freed only after the stream, as hipFree would wait for the device.
+    int64_t max_events = 0;
+    for (const auto &c : chunks) max_events = std::max(max_events, c->b - c->a);
+    const size_t reserve_ops = (size_t)max_events + (size_t)max_events / 4 + 4;
+    const size_t image_guess = align256(4 * (reserve_ops + 1)) + align256(16 * reserve_ops);
+    std::vector<void *> old_dev, old_pinned;
     // a completed launch may already report every slice full
     auto poll = [&]() {
         for (Slot &r : s.ring)
@@ -309,26 +320,30 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
         }
         const size_t bytes = ch.image.size();
         if (bytes > r.dev_bytes) {
-            if (r.dev) (void)hipFree(r.dev);
+            const size_t cap = std::max(std::max(bytes, image_guess), r.dev_bytes + r.dev_bytes / 2);
+            if (r.dev) old_dev.push_back(r.dev);
             r.dev = nullptr;
             r.dev_bytes = 0;
-            e = hipMalloc(&r.dev, bytes);
+            e = hipMalloc(&r.dev, cap);
             if (e != hipSuccess) {
+                r.dev = nullptr;
                 st = fail(TN_E_NOMEM, "chunk schedule allocation failed");
                 break;
             }
-            r.dev_bytes = bytes;
+            r.dev_bytes = cap;
         }
         if (bytes > r.pinned_bytes) {
-            if (r.pinned) (void)hipHostFree(r.pinned);
+            const size_t cap = std::max(std::max(bytes, image_guess), r.pinned_bytes + r.pinned_bytes / 2);
+            if (r.pinned) old_pinned.push_back(r.pinned);
             r.pinned = nullptr;
             r.pinned_bytes = 0;
-            e = hipHostMalloc(&r.pinned, bytes, 0);
+            e = hipHostMalloc(&r.pinned, cap, 0);
             if (e != hipSuccess) {
+                r.pinned = nullptr;
                 st = fail(TN_E_NOMEM, "chunk staging allocation failed");
                 break;
             }
-            r.pinned_bytes = bytes;
+            r.pinned_bytes = cap;
         }
         std::memcpy(r.pinned, ch.image.data(), bytes);
         const size_t need = sizeof(uint64_t) * ((size_t)s.slices * kRoworSinkWords +
@@ -386,6 +401,12 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
     }
     cv.notify_all();
     for (auto &th : pool) th.join();
+    if (!old_dev.empty() || !old_pinned.empty()) {
+        // launches may still read the buffers that were replaced
+        (void)hipStreamSynchronize(ctx->stream);
+        for (void *p : old_dev) (void)hipFree(p);
+        for (void *p : old_pinned) (void)hipHostFree(p);
+    }
     if (stats) {
         stats->chunks = nch;
         stats->chunks_run = launched;
