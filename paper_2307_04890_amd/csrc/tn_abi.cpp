@@ -51,6 +51,22 @@ tn_status ensure_scratch(tn_ctx *ctx, size_t bytes) {
     ctx->scratch_bytes = want;
     return TN_OK;
 }
+
+tn_status ensure_host_staging(tn_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->host_staging_bytes) return TN_OK;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (ctx->host_staging) (void)hipHostFree(ctx->host_staging);
+    ctx->host_staging = nullptr;
+    ctx->host_staging_bytes = 0;
+    e = hipHostMalloc(&ctx->host_staging, bytes, 0);
+    if (e != hipSuccess) {
+        ctx->host_staging = nullptr;
+        return fail(TN_E_NOMEM, "pinned staging allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    ctx->host_staging_bytes = bytes;
+    return TN_OK;
+}
 }  // namespace tn
 
 extern "C" {
@@ -97,6 +113,7 @@ void tn_destroy(tn_ctx *ctx) {
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->host_staging) (void)hipHostFree(ctx->host_staging);
     if (ctx->traffic) (void)hipFree(ctx->traffic);
     for (auto &r : ctx->recs) {
         (void)hipEventDestroy(r.a);

@@ -52,9 +52,12 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *s
                                 ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "hash kernel launch");
-    // the host planner needs the bucket map of every hash
-    std::vector<uint32_t> hb((size_t)H * n);
-    e = hipMemcpyAsync(hb.data(), bucket, sizeof(uint32_t) * hb.size(), hipMemcpyDeviceToHost,
+    // the host planner needs the bucket map of every hash: into the
+    // context's pinned staging (one DMA, no page faults on a fresh array)
+    st = ensure_host_staging(ctx, sizeof(uint32_t) * H * n);
+    if (st != TN_OK) return st;
+    const uint32_t *hb = (const uint32_t *)ctx->host_staging;
+    e = hipMemcpyAsync(ctx->host_staging, bucket, sizeof(uint32_t) * H * n, hipMemcpyDeviceToHost,
                        ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "bucket download");
@@ -62,7 +65,7 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *s
     std::vector<int64_t> ms(H, m);
     std::vector<const uint32_t *> ss(H, src), ds(H, dst), maps(H);
     std::vector<const int64_t *> ts(H, t);
-    for (uint32_t j = 0; j < H; ++j) maps[j] = hb.data() + (size_t)j * n;
+    for (uint32_t j = 0; j < H; ++j) maps[j] = hb + (size_t)j * n;
     return batch_create(ctx, (int32_t)H, ns.data(), ms.data(), ss.data(), ds.data(), ts.data(),
                         flags, proxies, maps.data(), n);
 }
@@ -252,8 +255,12 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
                                 ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "hash kernel launch");
-    std::vector<uint32_t> hb((size_t)H * n);
-    e = hipMemcpyAsync(hb.data(), bucket, sizeof(uint32_t) * hb.size(), hipMemcpyDeviceToHost,
+    // the bucket maps into the context's pinned staging (one DMA, no page
+    // faults on a fresh host array)
+    st = ensure_host_staging(ctx, sizeof(uint32_t) * H * n);
+    if (st != TN_OK) return st;
+    const uint32_t *hb = (const uint32_t *)ctx->host_staging;
+    e = hipMemcpyAsync(ctx->host_staging, bucket, sizeof(uint32_t) * H * n, hipMemcpyDeviceToHost,
                        ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "bucket download");
@@ -268,7 +275,7 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     std::vector<uint64_t *> Cs(H);
     std::vector<int64_t> lds(H, ldK);
     for (uint32_t j = 0; j < H; ++j) {
-        maps[j] = hb.data() + (size_t)j * n;
+        maps[j] = hb + (size_t)j * n;
         Cs[j] = P + (size_t)j * K * ldK;
     }
     // Small proxies (K <= kWaveProxyK) run as op schedules on one wavefront
@@ -338,7 +345,8 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
                     spare.pop_back();
                 }
             }
-            ws = wave_image_pack(hs, img, pin_images);
+            // chunk 0 is uploaded once and its latency comes first: never pinned
+            ws = wave_image_pack(hs, img, pin_images && c > 0);
         }
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -400,7 +408,8 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     const size_t window = std::max<size_t>(
         1, std::min<size_t>(nth, ((size_t)1 << 26) / std::max<size_t>(1, (size_t)H * chunk_events)));
     // at most window + 1 images are live at once: pin them when each is
-    // reused a few times
+    // reused a few times (chunk 0's never: pinning a fresh image costs
+    // more than one pageable upload, at K = 4096, H = 16 about 7 ms)
     pin_images = nch >= 4 * (window + 1);
     auto worker = [&]() {
         (void)hipSetDevice(ctx->device);  // for the pinned image allocations

@@ -126,6 +126,10 @@ struct tn_ctx {
     hipStream_t stream = nullptr;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // pinned host memory for device-to-host copies within one call (the
+    // bucket maps of the hashed builds), kept for the next call
+    void *host_staging = nullptr;
+    size_t host_staging_bytes = 0;
     // row words loaded / stored by the last tn_plan_execute (device)
     unsigned long long *traffic = nullptr;
     bool saturation = true;
@@ -191,6 +195,10 @@ struct ProfScope {
 
 // Grows the context scratch to at least `bytes`.
 tn_status ensure_scratch(tn_ctx *ctx, size_t bytes);
+// Grows the context's pinned host staging buffer to at least `bytes`
+// (waits for the context's stream first; the buffer serves one call at a
+// time, like the device scratch).
+tn_status ensure_host_staging(tn_ctx *ctx, size_t bytes);
 void fill_stats(const HostSchedule &hs, tn_plan_stats &s);
 
 // ---- kernel launchers (tn_kernels.hip) ---------------------------------
