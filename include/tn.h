@@ -22,7 +22,9 @@
  * - Memory: pointers documented HOST are ordinary host memory, borrowed for
  *   the duration of the call.  Pointers documented DEVICE are device memory
  *   on the context's device, owned by the caller and never freed by the
- *   library.  The context owns all scratch memory it allocates.
+ *   library.  The context owns all scratch memory it allocates (device
+ *   scratch, and pinned host staging for device-to-host copies); it serves
+ *   one call at a time.
  * - Ordering: device work is enqueued on the context's stream (tn_create /
  *   tn_set_stream) and is asynchronous unless stated otherwise;
  *   tn_sync() waits for it and reports a device-side error.
@@ -94,8 +96,8 @@ tn_status tn_set_stream(tn_ctx *ctx, void *stream);
 /* Waits for the context's stream; reports a device error as TN_E_HIP. */
 tn_status tn_sync(tn_ctx *ctx);
 
-/* Frees the context's scratch memory.  Plans and batches must be destroyed
- * first.  NULL is ignored. */
+/* Frees the context's scratch memory (device and pinned host).  Plans and
+ * batches must be destroyed first.  NULL is ignored. */
 void tn_destroy(tn_ctx *ctx);
 
 /* Kernel timing on the context's stream.  While enabled, every kernel the
@@ -389,10 +391,13 @@ tn_status tn_hash_compress(tn_ctx *ctx, uint32_t n, int64_t m,
  * tn_build_component_matrix_streamed, except that the default first chunk
  * is a sixteenth of the others: proxies of few super-nodes saturate within
  * few events); each chunk's H mapped sub-streams are
- * planned on host threads and applied in one batched launch that resumes
- * from the proxies.  Once every tile of every proxy is all ones the earlier
- * chunks are skipped.  The proxies equal those of tn_hash_compress +
- * tn_batch_execute.  stats (HOST, may be NULL) as for the streamed build.
+ * planned on host threads and applied in one launch that resumes from the
+ * proxies (K <= 4096: one wavefront per word column of every proxy, the
+ * column in LDS; larger K: batched tiles).  Once every column or tile of
+ * every proxy is all ones the earlier chunks are skipped.  The proxies
+ * equal those of tn_hash_compress + tn_batch_execute.  stats (HOST, may be
+ * NULL) as for the streamed build.  The bucket maps come down into pinned
+ * host memory that the context keeps for later calls (4*H*n bytes).
  * Errors as tn_hash_compress, plus TN_E_ARG for ldK < ceil(K/64). */
 tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m,
                                 const uint32_t *src, const uint32_t *dst,
