@@ -167,6 +167,22 @@ def test_streamed_proxies_on_both_sides_of_the_wavefront_limit():
         ctx.saturation(True)
 
 
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_streamed_small_proxies_edge_shapes(flags):
+    # the wavefront path at its smallest shapes: one super-node, one hash,
+    # a ragged second word column (K = 65), a single time step, many ties
+    cases = [(300, 2000, 1, 1, 50), (400, 3000, 1, 65, 3), (250, 1500, 4, 65, 1),
+             (600, 4000, 2, 127, 40)]
+    for n, m, H, K, Tm in cases:
+        s, d, t = T.random_tiny(n, m, Tm, seed=n + K + flags)
+        A = T.hash_coefficients(H, seed=K + 10 * flags)
+        _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, flags=flags, chunk_events=m // 3)
+        WP = oracle.proxies(K, s, d, t, oracle.hash_nodes(n, A, K), directed=bool(flags & 1),
+                            sequential=bool(flags & 2))
+        assert (host(P) == WP).all(), (n, H, K, flags)
+        assert st["slice_words"] == 1, (n, H, K)
+
+
 def test_streamed_proxies_at_the_scaled_hashed_workload():
     n, m, H, K = 200_000, 5_000_000, 16, 4096
     s, d, t = T.activity_driven(n, m, 500_000, seed=3)
