@@ -166,10 +166,13 @@ tn_status run_wave_chunk(tn_ctx *ctx, const std::vector<HostSchedule> &hs, WaveI
                          unsigned int *done_host, int64_t &levels, WaveBuf &buf) {
     const uint32_t H = (uint32_t)hs.size();
     uint32_t max_scr = 0;
+    int64_t ops = 0, lv = 0;
     for (uint32_t j = 0; j < H; ++j) {
         max_scr = std::max(max_scr, hs[j].scratch_rows);
-        levels += hs[j].Lops;
+        lv += hs[j].Lops;
+        ops += (int64_t)hs[j].ops.size() / 4;
     }
+    levels += lv;
     hipError_t e = hipSuccess;
     if (img.bytes > buf.cap) {
         // the previous chunk's copy and launch are complete (it was waited for)
@@ -196,8 +199,9 @@ tn_status run_wave_chunk(tn_ctx *ctx, const std::vector<HostSchedule> &hs, WaveI
     e = hipMemcpyAsync(dev, img.pin, img.bytes, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) {
         ProfScope ps(ctx, TN_K_BATCH);
-        e = launch_rowor_wave_multi((const WaveNet *)(dev + img.off[H]), H, K, max_scr, nullptr,
-                                    ctx->saturation, done_dev, ctx->stream);
+        e = launch_rowor_wave_multi((const WaveNet *)(dev + img.off[H]), H, K, max_scr,
+                                    rowor_wave_wide(ops, lv), nullptr, ctx->saturation, done_dev,
+                                    ctx->stream);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(done_host, done_dev, sizeof(unsigned int), hipMemcpyDeviceToHost,

@@ -256,9 +256,14 @@ struct WaveNet {
 };
 // count networks of n nodes each, one wavefront per word column of each;
 // nets: DEVICE array; scratch rows up to max_scratch_rows in every network.
+// Levels average more than this many ops: each lane takes two ops of a
+// level per LDS round trip (a group of 128) instead of one.
+constexpr int64_t kRoworWaveWideOps = 80;
+bool rowor_wave_wide(int64_t ops, int64_t levels);
 hipError_t launch_rowor_wave_multi(const WaveNet *nets, uint32_t count, uint32_t n,
-                                   uint32_t max_scratch_rows, unsigned long long *traffic,
-                                   bool saturation, unsigned int *done_count, hipStream_t st);
+                                   uint32_t max_scratch_rows, bool wide,
+                                   unsigned long long *traffic, bool saturation,
+                                   unsigned int *done_count, hipStream_t st);
 hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                              uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
                              uint32_t *persist, unsigned int *done_count, hipStream_t st);

@@ -617,6 +617,9 @@ struct WaveRing {
 // whenever a new window of ops enters the ring (every kWaveWin ops, off the
 // per-group path), by a scan of the column in LDS that ends at the first
 // 64-row block holding a row not yet full.
+// W: ops per lane and group; a group is up to 64 * W ops of one level, all
+// of whose row reads are issued together (ops of a level are independent).
+template <int W>
 __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords,
                                   const DevOps &s, uint32_t w, uint64_t *rows, uint64_t *sink, op4 *oring,
                                   uint32_t *lring, unsigned long long *__restrict__ traffic, bool sat,
@@ -636,17 +639,20 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
     lvr.init(lring, s.lvl, L + 1, lane);
     auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
     for (uint32_t r = lane; r < n; r += 64) rows[r] = C[(size_t)r * ld + w];
-    // group: ops [q0, min(q0 + 64, p1)) of level l; p2 = start of level
+    // group: ops [q0, min(q0 + 64 W, p1)) of level l; p2 = start of level
     // l + 2.  The loop starts on an empty level -1, so that every op and
     // level start it uses was read inside it.
+    constexpr uint32_t G = 64 * W;
     uint32_t l = 0xffffffffu, q0 = uni(lvr.at(0)), p1 = q0;
     uint32_t p2 = uni(lvr.at(1));
     uint32_t p3v = L >= 2 ? lvr.at(2) : s.nops;  // start of level l + 3 (lane-uniform VGPR)
-    op4 op = {0u, 0u, kNoRow, kNoRow};
+    op4 op[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) op[k] = op4{0u, 0u, kNoRow, kNoRow};
     for (;;) {
         uint32_t nl = l, nq0, np1, np2 = p2;
-        if (q0 + 64 < p1) {
-            nq0 = q0 + 64;
+        if (q0 + G < p1) {
+            nq0 = q0 + G;
             np1 = p1;
         } else {
             nl = l + 1;
@@ -660,7 +666,7 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
         }
         const bool more = nl < L;
         bool stop = false;
-        if (more && np1 > nq0 && opr.need(min(nq0 + 64, np1) - 1, lane) && sat) {
+        if (more && np1 > nq0 && opr.need(min(nq0 + G, np1) - 1, lane) && sat) {
             // every group before this one has been applied; this one is
             // applied all the same (it cannot change a full column), so
             // that no path through the loop skips the group's waits
@@ -669,22 +675,35 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
                 full = __all(r0 + lane >= n || rows[r0 + lane] == fullw);
             stop = full;
         }
-        const op4 nop = opr.at(nq0 + lane);
+        op4 nop[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) nop[k] = opr.at(nq0 + lane + 64 * k);
         {
             // branch-free: idle lanes and absent targets use the lane's own
             // sink word, so every group issues the same LDS operations
-            const bool act = q0 + lane < p1;
             uint64_t *const own = sink + lane;
-            const uint64_t r = *(act ? rows + slot(op.x) : own) | *(act ? rows + slot(op.y) : own);
+            bool act[W];
+            uint64_t r[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                act[k] = q0 + lane + 64 * k < p1;
+                r[k] = *(act[k] ? rows + slot(op[k].x) : own) | *(act[k] ? rows + slot(op[k].y) : own);
+            }
             // keeps the read of the next group's ops beside the row reads
             // (the compiler would otherwise sink it past the saturation
             // check, a second LDS round trip per group)
-            asm volatile("" : : "v"(nop.x), "v"(nop.y), "v"(nop.z), "v"(nop.w));
-            *(act && op.z != kNoRow ? rows + slot(op.z) : own) = r;
-            *(act && op.w != kNoRow ? rows + slot(op.w) : own) = r;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                asm volatile("" : : "v"(nop[k].x), "v"(nop[k].y), "v"(nop[k].z), "v"(nop[k].w));
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                *(act[k] && op[k].z != kNoRow ? rows + slot(op[k].z) : own) = r[k];
+                *(act[k] && op[k].w != kNoRow ? rows + slot(op[k].w) : own) = r[k];
+            }
         }
         if (!more || stop) break;
-        op = nop;
+#pragma unroll
+        for (int k = 0; k < W; ++k) op[k] = nop[k];
         q0 = nq0;
         p1 = np1;
         p2 = np2;
@@ -719,6 +738,7 @@ __device__ void rowor_wave_column(uint64_t *__restrict__ C, int64_t ld, uint32_t
     }
 }
 
+template <int W>
 __global__ void __launch_bounds__(64)
 k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
              unsigned long long *__restrict__ traffic, bool sat, uint32_t *__restrict__ persist,
@@ -727,12 +747,13 @@ k_rowor_wave(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, 
     __shared__ op4 oring[kWaveRing];
     __shared__ uint32_t lring[kWaveRing];
     __shared__ uint64_t sink[64];
-    rowor_wave_column(C, ld, n, nwords, s, xcd_slice(blockIdx.x, gridDim.x), rows, sink, oring,
-                      lring, traffic, sat, persist, done_count);
+    rowor_wave_column<W>(C, ld, n, nwords, s, xcd_slice(blockIdx.x, gridDim.x), rows, sink, oring,
+                         lring, traffic, sat, persist, done_count);
 }
 
 // Many networks of n nodes each (the hashed proxies): wavefront b runs word
 // column b % nwords of network b / nwords.
+template <int W>
 __global__ void __launch_bounds__(64)
 k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords,
                    unsigned long long *__restrict__ traffic, bool sat,
@@ -743,8 +764,8 @@ k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords
     const uint32_t b = xcd_slice(blockIdx.x, gridDim.x);
     const WaveNet &net = nets[b / nwords];
     __shared__ uint64_t sink[64];
-    rowor_wave_column(net.C, net.ld, n, nwords, net.s, b % nwords, rows, sink, oring, lring,
-                      traffic, sat, net.persist, done_count);
+    rowor_wave_column<W>(net.C, net.ld, n, nwords, net.s, b % nwords, rows, sink, oring, lring,
+                         traffic, sat, net.persist, done_count);
 }
 
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
@@ -960,28 +981,40 @@ hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t l
     if (!rowor_wave_fits(n, scratch_rows)) return hipErrorInvalidValue;
     const uint32_t nwords = (n + 63) / 64;
     const size_t lds = ((size_t)n + scratch_rows + 1) * 8;
-    hipError_t e = hipFuncSetAttribute((const void *)k_rowor_wave,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool wide = rowor_wave_wide(s.nops, s.L);
+    const void *fn = wide ? (const void *)k_rowor_wave<2> : (const void *)k_rowor_wave<1>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rowor_wave, dim3(nwords), dim3(64), lds, st, C, ld, n, nwords, s, traffic,
-                       saturation, persist, done_count);
+    if (wide)
+        hipLaunchKernelGGL(k_rowor_wave<2>, dim3(nwords), dim3(64), lds, st, C, ld, n, nwords, s,
+                           traffic, saturation, persist, done_count);
+    else
+        hipLaunchKernelGGL(k_rowor_wave<1>, dim3(nwords), dim3(64), lds, st, C, ld, n, nwords, s,
+                           traffic, saturation, persist, done_count);
     return hipGetLastError();
 }
 
 hipError_t launch_rowor_wave_multi(const WaveNet *nets, uint32_t count, uint32_t n,
-                                   uint32_t max_scratch_rows, unsigned long long *traffic,
-                                   bool saturation, unsigned int *done_count, hipStream_t st) {
+                                   uint32_t max_scratch_rows, bool wide,
+                                   unsigned long long *traffic, bool saturation,
+                                   unsigned int *done_count, hipStream_t st) {
     if (count == 0) return hipSuccess;
     if (!rowor_wave_fits(n, max_scratch_rows)) return hipErrorInvalidValue;
     const uint32_t nwords = (n + 63) / 64;
     const size_t lds = ((size_t)n + max_scratch_rows + 1) * 8;
-    hipError_t e = hipFuncSetAttribute((const void *)k_rowor_wave_multi,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fn = wide ? (const void *)k_rowor_wave_multi<2> : (const void *)k_rowor_wave_multi<1>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rowor_wave_multi, dim3(count * nwords), dim3(64), lds, st, nets, n, nwords,
-                       traffic, saturation, done_count);
+    if (wide)
+        hipLaunchKernelGGL(k_rowor_wave_multi<2>, dim3(count * nwords), dim3(64), lds, st, nets, n,
+                           nwords, traffic, saturation, done_count);
+    else
+        hipLaunchKernelGGL(k_rowor_wave_multi<1>, dim3(count * nwords), dim3(64), lds, st, nets, n,
+                           nwords, traffic, saturation, done_count);
     return hipGetLastError();
 }
+
+bool rowor_wave_wide(int64_t ops, int64_t levels) { return ops > kRoworWaveWideOps * levels; }
 
 hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                                uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
