@@ -62,7 +62,7 @@ def kernel_source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h"),
+KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h", "tn_device.h"),
                   "batch": ("tn_batch.hip", "tn_batch.h", "tn_batch.cpp", "tn_internal.h"),
                   "recombine": ("tn_hash.hip", "tn_hash.h")}
 

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "tn_internal.h"
+#include "tn_wave.h"
 
 namespace {
 thread_local std::string g_err;

@@ -1,4 +1,5 @@
-// Device helpers shared by the kernels that merge HyperLogLog registers.
+// Device helpers shared by the row-OR kernels and those that merge
+// HyperLogLog registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,6 +7,19 @@
 #include <cstdint>
 
 namespace tn {
+
+// One op {a, b, d1, d2} as a native 4-lane vector.
+typedef uint32_t op4 __attribute__((ext_vector_type(4)));
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip; map the
+// workgroup index so that each XCD receives a contiguous range of slices
+// (adjacent slices share cache lines of the same rows).
+__device__ __forceinline__ uint32_t xcd_slice(uint32_t b, uint32_t nb) {
+    const uint32_t x = b & 7u, k = b >> 3;
+    const uint32_t q = nb >> 3, r = nb & 7u;
+    return x * q + min(x, r) + k;
+}
+
 
 // Byte-wise maximum of two words whose bytes are all below 128 (HyperLogLog
 // registers, Sec. 3.4): (x | 0x80..) - y keeps each byte's borrow inside the

@@ -12,6 +12,7 @@
 
 #include "tn_batch.h"
 #include "tn_hash.h"
+#include "tn_wave.h"
 
 namespace {
 constexpr uint64_t kP61 = (1ull << 61) - 1;

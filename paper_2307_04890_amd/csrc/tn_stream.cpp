@@ -30,6 +30,7 @@
 #include <thread>
 
 #include "tn_internal.h"
+#include "tn_wave.h"
 
 namespace tn {
 
