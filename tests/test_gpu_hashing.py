@@ -183,6 +183,26 @@ def test_streamed_small_proxies_edge_shapes(flags):
         assert st["slice_words"] == 1, (n, H, K)
 
 
+def test_streamed_proxies_of_few_super_nodes():
+    # ER networks with Poisson events at the paper's n_s = 0.3 n and H = 5,
+    # tiny proxies (fewer super-nodes than a word, or exactly one word) over
+    # several chunks, with saturation on and off; the rare
+    # simultaneous events make a few compound steps in every chunk
+    ctx = tn.get_context()
+    try:
+        for n, K, m in [(60, 18, 20_000), (150, 45, 60_000), (210, 63, 90_000), (220, 64, 90_000)]:
+            s, d, t = T.er_poisson(n, m, 100 * m, seed=n)
+            A = T.hash_coefficients(5, seed=K)
+            WP = oracle.proxies(K, s, d, t, oracle.hash_nodes(n, A, K))
+            for sat in (True, False):
+                ctx.saturation(sat)
+                _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, chunk_events=m // 4)
+                assert (host(P) == WP).all(), (n, K, sat)
+                assert st["chunks_run"] >= 1
+    finally:
+        ctx.saturation(True)
+
+
 def test_streamed_proxies_at_the_scaled_hashed_workload():
     n, m, H, K = 200_000, 5_000_000, 16, 4096
     s, d, t = T.activity_driven(n, m, 500_000, seed=3)
