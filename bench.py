@@ -27,6 +27,10 @@ Other modes (each prints its own single JSON line):
                    Poisson process per link, n from 100 to 10^4 and m from
                    10^4 to 10^7, exact against hashed (H = 5, n_s = 0.3 n):
                    Earth-Mover distance, relative time and memory.
+  --mode online    forward time with online insertion: the n = 10^5,
+                   m = 10^7 events in time order, in batches, into a live
+                   matrix of in-components, against the resident forward
+                   plan (bit for bit).
 
 Each line carries the roofline of the mode's dominant kernel, timed with HIP
 events on the stream it runs on, and the CPU oracle timed on a bounded
@@ -121,19 +125,21 @@ def timed(ctx, fn, steps, warmup):
 
 
 # ---------------------------------------------------------------------------
-def cpu_baseline_exact(n, s, d, t, budget_s: float):
+def cpu_baseline_exact(n, s, d, t, budget_s: float, forward: bool = False):
     import oracle
+    recurrence = oracle.forward_matrix if forward else oracle.reverse_matrix
+    what = "forward-time" if forward else "reverse-time"
     nwords = (n + 63) // 64
     t0 = time.perf_counter()
-    oracle.reverse_matrix(n, s, d, t, w0=0, nw=min(16, nwords))
+    recurrence(n, s, d, t, w0=0, nw=min(16, nwords))
     probe = time.perf_counter() - t0
     k = min(nwords, max(16, int(16 * budget_s / max(probe, 1e-3))))
     t0 = time.perf_counter()
-    oracle.reverse_matrix(n, s, d, t, w0=0, nw=k)
+    recurrence(n, s, d, t, w0=0, nw=k)
     dt = time.perf_counter() - t0
     full_equiv = dt * nwords / k
     rec = {"value": s.shape[0] / full_equiv, "unit": "events/s", "cores": 1, "kind": "oracle",
-           "sample": f"reverse-time recurrence on word columns [0,{k}) of {nwords} "
+           "sample": f"{what} recurrence on word columns [0,{k}) of {nwords} "
                      f"({100.0 * k / nwords:.1f}% of the matrix), all {s.shape[0]} events; "
                      f"{dt:.2f} s single-threaded, scaled to the full width",
            "seconds": dt, "host_nproc": os.cpu_count()}
@@ -146,7 +152,7 @@ def cpu_baseline_exact(n, s, d, t, budget_s: float):
     parts = [(cuts[i], cuts[i + 1] - cuts[i]) for i in range(threads) if cuts[i + 1] > cuts[i]]
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(len(parts)) as ex:
-        list(ex.map(lambda p: oracle.reverse_matrix(n, s, d, t, w0=p[0], nw=p[1]), parts))
+        list(ex.map(lambda p: recurrence(n, s, d, t, w0=p[0], nw=p[1]), parts))
     dta = time.perf_counter() - t0
     rec["all_cores"] = {"value": s.shape[0] / (dta * nwords / ka), "unit": "events/s",
                         "cores": len(parts), "kind": "oracle",
@@ -241,6 +247,82 @@ def run_exact(args):
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
         r["cpu_baseline"] = cpu_baseline_exact(n, s, d, t, args.cpu_budget)
+    return r
+
+
+def run_online(args):
+    """Forward-time streaming with online insertion (Sec. 3.5): the events of
+    the 10^5-node workload arrive in time order, in batches, into a live
+    matrix whose rows are in-components; against the resident forward plan
+    (Algorithm 1 as printed, Sec. 3.1), bit for bit."""
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+
+    workload = args.workload or "activity_n100000_m10M"
+    spec = T.WORKLOADS[workload]
+    n = spec["n"]
+    log(f"[bench] generating {workload}")
+    s, d, t = T.make_workload(workload)
+    m = int(s.shape[0])
+    ctx = tn.get_context()
+    log("[bench] forward plan on the host")
+    t0 = time.perf_counter()
+    plan = tn.Plan(n, s, d, t, flags=tn.FORWARD)
+    plan_wall = time.perf_counter() - t0
+    st = plan.stats
+    C = tn.api.alloc_matrix(n)
+    elapsed, kms, _ = timed(ctx, lambda: plan.execute(C), args.steps, args.warmup)
+    alg = algorithmic_bytes(st, n)
+    achieved = alg / (kms["rowor"] * 1e-3) / 1e9
+    plan.close()
+    # batch boundaries at the first event of a time step (a batch starts
+    # strictly after the last time step applied)
+    B = max(1, args.online_batches)
+    cuts = [0] + [int(np.searchsorted(t, t[m * k // B], side="left")) for k in range(1, B)] + [m]
+    cuts = sorted(set(cuts))
+    C2 = tn.api.alloc_matrix(n)
+    runs = []
+    for rep in range(2):
+        on = tn.Online(n, flags=tn.FORWARD, C=C2)
+        lat, stats = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            t1 = time.perf_counter()
+            stats.append(on.insert(s[a:b], d[a:b], t[a:b]))
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t1)
+        total = time.perf_counter() - t0
+        on.close()
+        runs.append((total, lat, stats))
+    assert torch.equal(C2, C), "online insertion differs from the forward plan"
+    total, lat, stats = min(runs, key=lambda x: x[0])
+    config = {"workload": workload + "_forward_online", "n": n, "m": m, "T": spec["T"],
+              "generator": spec["kind"], "seed": spec["seed"], "batches": len(cuts) - 1,
+              "flags": "forward,undirected,strict-ties", "parallelism": "single-gpu"}
+    r = base_result(args, m / total, "events/s", len(cuts) - 1, 1e3 * total / (len(cuts) - 1),
+                    config)
+    r["value_note"] = ("online insertion end to end from host events: every batch planned on "
+                       "host threads and applied to the live matrix (one step = one batch)")
+    r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rowor_global on the resident forward plan",
+                     "algorithmic_bytes": alg, "avg_launch_ms": kms["rowor"],
+                     "levels": st["op_levels"],
+                     "us_per_level": 1e3 * kms["rowor"] / max(1, st["op_levels"])}
+    r["kernels_ms"] = kms
+    r["forward_plan"] = {"events_per_s": m * args.steps / elapsed, "levels": st["levels"],
+                         "op_levels": st["op_levels"], "ops": st["ops"],
+                         "host_seconds": st["host_seconds"], "wall_seconds": plan_wall}
+    r["online"] = {"seconds": total, "seconds_all": [x[0] for x in runs],
+                   "batch_latency_ms": [1e3 * x for x in lat],
+                   "batches": [{k: v for k, v in x.items() if k != "seconds"} for x in stats]}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a column sample")
+        r["cpu_baseline"] = cpu_baseline_exact(n, s, d, t, args.cpu_budget, forward=True)
     return r
 
 
@@ -826,7 +908,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="exact",
-                    choices=["exact", "hashed", "batched", "combiner", "sweep", "hll"])
+                    choices=["exact", "hashed", "batched", "combiner", "sweep", "hll", "online"])
+    ap.add_argument("--online-batches", type=int, default=10,
+                    help="event batches of the online mode")
     ap.add_argument("--hll-log2s", type=int, default=8,
                     help="log2 of the HyperLogLog registers per node (--mode hll)")
     ap.add_argument("--sweep-max-m", type=float, default=1e7,
@@ -855,7 +939,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     run = {"exact": run_exact, "hashed": run_hashed, "batched": run_batched,
-           "combiner": run_combiner, "sweep": run_sweep, "hll": run_hll}[args.mode]
+           "combiner": run_combiner, "sweep": run_sweep, "hll": run_hll,
+           "online": run_online}[args.mode]
     print(json.dumps(run(args)), flush=True)
 
 
