@@ -141,7 +141,8 @@ def test_streamed_proxies_equal_the_batched_proxies(flags):
             assert st["saturated"] == 1 and st["chunks_run"] < st["chunks"]
 
 
-def test_streamed_proxies_on_both_sides_of_the_wavefront_limit():
+@pytest.mark.parametrize("flags", [0, 3])
+def test_streamed_proxies_on_both_sides_of_the_wavefront_limit(flags):
     # proxies of at most 4096 super-nodes run one wavefront per word column,
     # larger ones as batched tiles: both, over several chunks, with and
     # without saturation tracking, and with a padded row stride
@@ -152,12 +153,13 @@ def test_streamed_proxies_on_both_sides_of_the_wavefront_limit():
         for K in (4095, 4096, 4097):
             A = T.hash_coefficients(H, seed=K)
             wb = oracle.hash_nodes(n, A, K)
-            WP = oracle.proxies(K, s, d, t, wb)
+            WP = oracle.proxies(K, s, d, t, wb, directed=bool(flags & 1), sequential=bool(flags & 2))
             for sat in (True, False):
                 ctx.saturation(sat)
                 ld = oracle.words(K) + (1 if sat else 0)
                 P = torch.full((H, K, ld), -1, dtype=torch.int64, device="cuda")
-                _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, chunk_events=7000, P=P)
+                _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, flags=flags,
+                                                    chunk_events=7000, P=P)
                 got = host(P)
                 assert (got[:, :, :oracle.words(K)] == WP).all(), (K, sat)
                 if ld > oracle.words(K):
