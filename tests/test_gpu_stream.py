@@ -96,3 +96,48 @@ def test_default_chunks_grow_from_the_first_applied_end(flags):
         ctx.saturation(True)
     assert (host(C) == want).all()
     assert st["chunks"] == 2 and st["chunks_run"] == 2 and st["events_run"] == m
+
+
+def _matchings_then_singles(n, steps, singles, seed, wide_first):
+    # `steps` time steps of a random perfect matching (n / 2 simultaneous,
+    # node-disjoint events: levels of about 1000 ops, the workgroup kernel)
+    # and `singles` time steps of one event each along a path (one op per
+    # level, the wavefront kernel), in either order along time
+    g = T.rng(seed)
+    wide = []
+    for _ in range(steps):
+        p = g.permutation(n).astype(np.uint32)
+        wide.append((p[0::2], p[1::2]))
+    start = int(g.integers(0, n))
+    one = [(np.array([(start + k) % n], dtype=np.uint32),
+            np.array([(start + k + 1) % n], dtype=np.uint32)) for k in range(singles)]
+    parts = wide + one if wide_first else one + wide
+    s = np.concatenate([a for a, _ in parts])
+    d = np.concatenate([b for _, b in parts])
+    t = np.concatenate([np.full(a.shape[0], k, dtype=np.int64) for k, (a, _) in enumerate(parts)])
+    return s, d, t
+
+
+@pytest.mark.parametrize("wide_first", [True, False])
+def test_stream_switches_kernels_between_chunks(wide_first):
+    # chunks of short levels run on one wavefront per word column, chunks of
+    # wide levels on the workgroup kernel; each hands its per-column slice
+    # state to the other
+    n = 6000
+    s, d, t = _matchings_then_singles(n, 6, 4000, seed=61 + wide_first, wide_first=wide_first)
+    for a, b in ((0, 3000), (t.shape[0] - 3000, t.shape[0])):
+        st = tn.host_schedule(n, s[a:b], d[a:b], t[a:b])["stats"]
+        wide = t[a] < 6 if wide_first else t[a] >= 4000
+        assert (st["ops"] > 640 * st["op_levels"]) == wide, (a, st["ops"], st["op_levels"])
+    want = oracle.reverse_matrix(n, s, d, t)
+    ctx = tn.get_context()
+    try:
+        for sat in (True, False):
+            ctx.saturation(sat)
+            C, st = tn.build_component_matrix_streamed(n, s, d, t, chunk_events=3000)
+            assert (host(C) == want).all(), (wide_first, sat)
+            assert st["slice_words"] == 1 and st["chunks"] >= 4
+            if not sat:
+                assert st["chunks_run"] == st["chunks"]
+    finally:
+        ctx.saturation(True)
