@@ -91,6 +91,7 @@ struct WaveImage {
     size_t cap = 0;
     size_t bytes = 0;
     bool pinned = false;
+    bool flat = false;  // the flat schedule format (k_rowor_wave_flat)
     std::vector<size_t> off;
     WaveImage() = default;
     WaveImage(const WaveImage &) = delete;
@@ -106,6 +107,7 @@ struct WaveImage {
         std::swap(cap, o.cap);
         std::swap(bytes, o.bytes);
         std::swap(pinned, o.pinned);
+        std::swap(flat, o.flat);
         off.swap(o.off);
     }
     void release() {
@@ -116,11 +118,24 @@ struct WaveImage {
     }
 };
 
-tn_status wave_image_pack(const std::vector<HostSchedule> &hs, WaveImage &w, bool pinned) {
+// Short levels (at most 80 ops on average) take the flat format: each op's
+// rows as LDS byte offsets of a column of K real rows then the scratch rows,
+// and a level-end bit, so that the kernel needs no level starts.
+tn_status wave_image_pack(const std::vector<HostSchedule> &hs, uint32_t K, WaveImage &w,
+                          bool pinned) {
     const uint32_t H = (uint32_t)hs.size();
+    int64_t ops = 0, lv = 0;
+    for (uint32_t j = 0; j < H; ++j) {
+        ops += (int64_t)hs[j].ops.size() / 4;
+        lv += hs[j].Lops;
+    }
+    w.flat = !rowor_wave_wide(ops, lv);
     w.off.assign(H + 1, 0);
-    for (uint32_t j = 0; j < H; ++j)
-        w.off[j + 1] = w.off[j] + ((ops_device_bytes(hs[j]) + 255) & ~(size_t)255);
+    for (uint32_t j = 0; j < H; ++j) {
+        const size_t bytes = w.flat ? std::max<size_t>(256, hs[j].ops.size() * 4)
+                                    : ops_device_bytes(hs[j]);
+        w.off[j + 1] = w.off[j] + ((bytes + 255) & ~(size_t)255);
+    }
     w.bytes = w.off[H] + sizeof(WaveNet) * H;
     if (w.bytes > w.cap || w.pinned != pinned) {
         const size_t cap = std::max(w.bytes, w.cap + w.cap / 2);
@@ -137,13 +152,30 @@ tn_status wave_image_pack(const std::vector<HostSchedule> &hs, WaveImage &w, boo
         }
         w.cap = cap;
     }
+    auto byte_off = [K](uint32_t id) -> uint32_t {
+        return 8u * ((id & kScratchBit) ? K + (id & kNodeMask) : id);
+    };
     for (uint32_t j = 0; j < H; ++j) {
         const HostSchedule &s = hs[j];
         unsigned char *b = w.pin + w.off[j];
-        std::memcpy(b, s.lvl_op.data(), 4 * s.lvl_op.size());
-        if (!s.ops.empty())
-            std::memcpy(b + ((4 * s.lvl_op.size() + 255) & ~(size_t)255), s.ops.data(),
-                        4 * s.ops.size());
+        if (!w.flat) {
+            std::memcpy(b, s.lvl_op.data(), 4 * s.lvl_op.size());
+            if (!s.ops.empty())
+                std::memcpy(b + ((4 * s.lvl_op.size() + 255) & ~(size_t)255), s.ops.data(),
+                            4 * s.ops.size());
+            continue;
+        }
+        uint32_t *o = reinterpret_cast<uint32_t *>(b);
+        for (uint32_t l = 0; l < s.Lops; ++l) {
+            const uint32_t q1 = s.lvl_op[l + 1];
+            for (uint32_t q = s.lvl_op[l]; q < q1; ++q) {
+                const uint32_t *src = &s.ops[4 * (size_t)q];
+                o[4 * (size_t)q] = byte_off(src[0]) | (q + 1 == q1 ? kFlatEnd : 0u);
+                o[4 * (size_t)q + 1] = byte_off(src[1]);
+                o[4 * (size_t)q + 2] = src[2] == kNoRow ? kFlatNone : byte_off(src[2]);
+                o[4 * (size_t)q + 3] = src[3] == kNoRow ? kFlatNone : byte_off(src[3]);
+            }
+        }
     }
     return TN_OK;
 }
@@ -191,7 +223,12 @@ tn_status run_wave_chunk(tn_ctx *ctx, const std::vector<HostSchedule> &hs, WaveI
     unsigned char *dev = (unsigned char *)buf.dev;
     for (uint32_t j = 0; j < H; ++j) {
         WaveNet net;
-        net.s = ops_view(hs[j], dev + img.off[j]);
+        if (img.flat) {
+            net.s = DevOps{hs[j].Lops, (uint32_t)(hs[j].ops.size() / 4), nullptr,
+                           reinterpret_cast<const uint4 *>(dev + img.off[j])};
+        } else {
+            net.s = ops_view(hs[j], dev + img.off[j]);
+        }
         net.C = Cs[j];
         net.ld = ldK;
         net.persist = ctx->saturation ? state + (size_t)j * col_words : nullptr;
@@ -200,9 +237,13 @@ tn_status run_wave_chunk(tn_ctx *ctx, const std::vector<HostSchedule> &hs, WaveI
     e = hipMemcpyAsync(dev, img.pin, img.bytes, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) {
         ProfScope ps(ctx, TN_K_BATCH);
-        e = launch_rowor_wave_multi((const WaveNet *)(dev + img.off[H]), H, K, max_scr,
-                                    rowor_wave_wide(ops, lv), nullptr, ctx->saturation, done_dev,
-                                    ctx->stream);
+        if (img.flat)
+            e = launch_rowor_wave_flat((const WaveNet *)(dev + img.off[H]), H, K, max_scr,
+                                       ctx->saturation, done_dev, ctx->stream);
+        else
+            e = launch_rowor_wave_multi((const WaveNet *)(dev + img.off[H]), H, K, max_scr,
+                                        rowor_wave_wide(ops, lv), nullptr, ctx->saturation,
+                                        done_dev, ctx->stream);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(done_host, done_dev, sizeof(unsigned int), hipMemcpyDeviceToHost,
@@ -351,7 +392,7 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
                 }
             }
             // chunk 0 is uploaded once and its latency comes first: never pinned
-            ws = wave_image_pack(hs, img, pin_images && c > 0);
+            ws = wave_image_pack(hs, K, img, pin_images && c > 0);
         }
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -395,7 +436,7 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
                     spare.pop_back();
                 }
             }
-            ws = wave_image_pack(plans[c].hs, img, pin_images);
+            ws = wave_image_pack(plans[c].hs, K, img, pin_images);
         }
         {
             std::lock_guard<std::mutex> lk(mu);

@@ -45,4 +45,16 @@ hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t l
                              uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
                              uint32_t *persist, unsigned int *done_count, hipStream_t st);
 
+// Flat schedules of many networks (k_rowor_wave_flat): ops in level order
+// as {a, b, d1, d2} LDS byte offsets of the rows in a column (n real rows,
+// then the scratch rows; kFlatNone for no second target), with kFlatEnd set
+// in a on the last op of each level.  The DevOps of a WaveNet then holds
+// only ops and nops.
+constexpr uint32_t kFlatEnd = 0x80000000u;
+constexpr uint32_t kFlatOffMask = 0x7fffffffu;
+constexpr uint32_t kFlatNone = 0xffffffffu;
+hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t n,
+                                  uint32_t max_scratch_rows, bool saturation,
+                                  unsigned int *done_count, hipStream_t st);
+
 }  // namespace tn

@@ -225,7 +225,111 @@ k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords
                          traffic, sat, net.persist, done_count);
 }
 
+// The same stream from a flat schedule (many networks of n nodes, one
+// wavefront per word column): ops in level order, their rows as LDS byte
+// offsets of the column (kFlatNone: no second target) and bit 31 of the
+// first offset set on the last op of every level.  A group is up to 64 ops
+// of one level; the next group's ops are read ahead, and one ballot of
+// their level-end bits gives its size, so the loop keeps no level starts.
+__global__ void __launch_bounds__(64)
+k_rowor_wave_flat(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords, bool sat,
+                  unsigned int *__restrict__ done_count) {
+    extern __shared__ uint64_t rows[];
+    __shared__ op4 oring[kWaveRing];
+    __shared__ uint64_t sink[64];
+    const uint32_t b = xcd_slice(blockIdx.x, gridDim.x);
+    const WaveNet &net = nets[b / nwords];
+    const uint32_t w = b % nwords;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t rwords = (n + 31) / 32;
+    const uint32_t tail = n & 63u;
+    const uint64_t fullw = (w + 1 < nwords || tail == 0) ? ~0ull : (1ull << tail) - 1ull;
+    uint32_t *pst = net.persist ? net.persist + (size_t)w * (2 * (size_t)rwords + 2) : nullptr;
+    const uint32_t nops = net.s.nops;
+    if (nops == 0) return;       // nothing to apply: C is left as it is
+    if (pst && pst[0]) return;   // the column is all ones already (uniform)
+    uint64_t *const C = net.C;
+    const int64_t ld = net.ld;
+    for (uint32_t r = lane; r < n; r += 64) rows[r] = C[(size_t)r * ld + w];
+    WaveRing<op4> opr;
+    opr.init(oring, reinterpret_cast<const op4 *>(net.s.ops), nops, lane);
+    unsigned char *const base = reinterpret_cast<unsigned char *>(rows);
+    uint64_t *const own = sink + lane;
+    auto row = [&](uint32_t off) { return reinterpret_cast<uint64_t *>(base + (off & kFlatOffMask)); };
+    auto group = [&](const op4 &o, uint32_t q) -> uint32_t {
+        const uint64_t ends = __ballot(q + lane < nops && (o.x >> 31));
+        const uint32_t g = ends ? (uint32_t)__ffsll((unsigned long long)ends) : 64u;
+        return min(g, nops - q);
+    };
+    uint32_t q = 0;
+    op4 op = opr.at(lane);
+    uint32_t size = group(op, 0);
+    for (;;) {
+        const uint32_t nq = q + size;
+        const bool more = nq < nops;
+        bool stop = false;
+        if (more && opr.need(min(nq + 64, nops) - 1, lane) && sat) {
+            // every group before this one has been applied; this one is
+            // applied all the same (it cannot change a full column)
+            bool full = true;
+            for (uint32_t r0 = 0; r0 < n && full; r0 += 64)
+                full = __all(r0 + lane >= n || rows[r0 + lane] == fullw);
+            stop = full;
+        }
+        const op4 nop = opr.at(nq + lane);
+        {
+            const bool act = lane < size;
+            const uint64_t r = *(act ? row(op.x) : own) | *(act ? row(op.y) : own);
+            asm volatile("" : : "v"(nop.x), "v"(nop.y), "v"(nop.z), "v"(nop.w));
+            *(act && op.z != kFlatNone ? row(op.z) : own) = r;
+            *(act && op.w != kFlatNone ? row(op.w) : own) = r;
+        }
+        if (!more || stop) break;
+        size = group(nop, nq);
+        op = nop;
+        q = nq;
+    }
+    for (uint32_t r = lane; r < n; r += 64) C[(size_t)r * ld + w] = rows[r];
+    if (!pst) return;
+    int32_t nfull = 0;
+    for (uint32_t k = lane; k < rwords; k += 64) {
+        uint32_t fb = 0, nz = 0;
+        for (uint32_t bb = 0; bb < 32 && 32 * k + bb < n; ++bb) {
+            const uint64_t v = rows[32 * k + bb];
+            fb |= (uint32_t)(v == fullw) << bb;
+            nz |= (uint32_t)(v != 0) << bb;
+        }
+        pst[2 + k] = fb;
+        pst[2 + rwords + k] = nz;
+        nfull += __popc(fb);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nfull += __shfl_xor(nfull, off);
+    if (lane == 0) {
+        pst[1] = (uint32_t)nfull;
+        if (nfull == (int32_t)n) {
+            pst[0] = 1u;
+            atomicAdd(done_count, 1u);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t n,
+                                  uint32_t max_scratch_rows, bool saturation,
+                                  unsigned int *done_count, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    if (!rowor_wave_fits(n, max_scratch_rows)) return hipErrorInvalidValue;
+    const uint32_t nwords = (n + 63) / 64;
+    const size_t lds = ((size_t)n + max_scratch_rows + 1) * 8;
+    hipError_t e = hipFuncSetAttribute((const void *)k_rowor_wave_flat,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowor_wave_flat, dim3(count * nwords), dim3(64), lds, st, nets, n, nwords,
+                       saturation, done_count);
+    return hipGetLastError();
+}
 
 bool rowor_wave_fits(uint32_t n, uint32_t scratch_rows) {
     return ((size_t)n + scratch_rows + 1) * 8 <= kRoworWaveLds;
