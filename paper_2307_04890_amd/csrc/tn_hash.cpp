@@ -132,8 +132,7 @@ tn_status wave_image_pack(const std::vector<HostSchedule> &hs, uint32_t K, WaveI
     w.flat = !rowor_wave_wide(ops, lv);
     w.off.assign(H + 1, 0);
     for (uint32_t j = 0; j < H; ++j) {
-        const size_t bytes = w.flat ? std::max<size_t>(256, hs[j].ops.size() * 4)
-                                    : ops_device_bytes(hs[j]);
+        const size_t bytes = w.flat ? flat_ops_bytes(hs[j]) : ops_device_bytes(hs[j]);
         w.off[j + 1] = w.off[j] + ((bytes + 255) & ~(size_t)255);
     }
     w.bytes = w.off[H] + sizeof(WaveNet) * H;
@@ -152,9 +151,6 @@ tn_status wave_image_pack(const std::vector<HostSchedule> &hs, uint32_t K, WaveI
         }
         w.cap = cap;
     }
-    auto byte_off = [K](uint32_t id) -> uint32_t {
-        return 8u * ((id & kScratchBit) ? K + (id & kNodeMask) : id);
-    };
     for (uint32_t j = 0; j < H; ++j) {
         const HostSchedule &s = hs[j];
         unsigned char *b = w.pin + w.off[j];
@@ -165,17 +161,7 @@ tn_status wave_image_pack(const std::vector<HostSchedule> &hs, uint32_t K, WaveI
                             4 * s.ops.size());
             continue;
         }
-        uint32_t *o = reinterpret_cast<uint32_t *>(b);
-        for (uint32_t l = 0; l < s.Lops; ++l) {
-            const uint32_t q1 = s.lvl_op[l + 1];
-            for (uint32_t q = s.lvl_op[l]; q < q1; ++q) {
-                const uint32_t *src = &s.ops[4 * (size_t)q];
-                o[4 * (size_t)q] = byte_off(src[0]) | (q + 1 == q1 ? kFlatEnd : 0u);
-                o[4 * (size_t)q + 1] = byte_off(src[1]);
-                o[4 * (size_t)q + 2] = src[2] == kNoRow ? kFlatNone : byte_off(src[2]);
-                o[4 * (size_t)q + 3] = src[3] == kNoRow ? kFlatNone : byte_off(src[3]);
-            }
-        }
+        flat_ops_pack(s, K, reinterpret_cast<uint32_t *>(b));
     }
     return TN_OK;
 }

@@ -40,6 +40,7 @@ struct Chunk {
     int64_t a = 0, b = 0;  // events [a, b)
     HostSchedule hs;
     std::vector<unsigned char> image;
+    bool flat = false;  // the flat form, then room for one WaveNet (k_rowor_wave_flat)
     std::string err;
     tn_status st = TN_OK;
     bool ready = false;
@@ -279,7 +280,20 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
             if (!stop.load()) {
                 ch.st = plan_events(s.n, ch.b - ch.a, src + ch.a, dst + ch.a, t + ch.a, s.flags,
                                     ch.hs, ch.err, nullptr, 0, kFormOps);
-                if (ch.st == TN_OK) ops_pack(ch.hs, ch.image);
+                if (ch.st == TN_OK) {
+                    // a chunk of short levels on the wavefront kernel takes
+                    // the flat form (no level starts in the kernel's loop)
+                    const int64_t nops = (int64_t)ch.hs.ops.size() / 4;
+                    ch.flat = s.sw == 1 && rowor_wave_pays(s.n, ch.hs.scratch_rows, nops,
+                                                           ch.hs.Lops) &&
+                              !rowor_wave_wide(nops, ch.hs.Lops);
+                    if (ch.flat) {
+                        ch.image.assign(align256(flat_ops_bytes(ch.hs)) + sizeof(WaveNet), 0);
+                        flat_ops_pack(ch.hs, s.n, reinterpret_cast<uint32_t *>(ch.image.data()));
+                    } else {
+                        ops_pack(ch.hs, ch.image);
+                    }
+                }
             }
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -347,6 +361,16 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
             r.pinned_bytes = cap;
         }
         std::memcpy(r.pinned, ch.image.data(), bytes);
+        const size_t net_off = bytes - sizeof(WaveNet);  // flat: where the WaveNet goes
+        if (ch.flat) {
+            WaveNet net;
+            net.s = DevOps{ch.hs.Lops, (uint32_t)(ch.hs.ops.size() / 4), nullptr,
+                           reinterpret_cast<const uint4 *>(r.dev)};
+            net.C = s.C;
+            net.ld = s.ld;
+            net.persist = ctx->saturation ? s.persist : nullptr;
+            std::memcpy((unsigned char *)r.pinned + net_off, &net, sizeof(WaveNet));
+        }
         const size_t need = sizeof(uint64_t) * ((size_t)s.slices * kRoworSinkWords +
                                                 (size_t)ch.hs.scratch_rows * (size_t)nwords);
         st = ensure_scratch(ctx, need);
@@ -360,8 +384,12 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
                 if (zl < ch.hs.Lops) s.zero_open = false;
                 s.zero_ops += (int64_t)ch.hs.ops.size() / 4;
             }
-            if (s.sw == 1 && rowor_wave_pays(s.n, ch.hs.scratch_rows,
-                                             (int64_t)ch.hs.ops.size() / 4, ch.hs.Lops))
+            if (ch.flat)
+                e = launch_rowor_wave_flat(
+                    reinterpret_cast<const WaveNet *>((unsigned char *)r.dev + net_off), 1, s.n,
+                    ch.hs.scratch_rows, ctx->saturation, s.done_count, ctx->stream);
+            else if (s.sw == 1 && rowor_wave_pays(s.n, ch.hs.scratch_rows,
+                                                  (int64_t)ch.hs.ops.size() / 4, ch.hs.Lops))
                 // a small network: one wavefront per word column; the slice
                 // state goes on only when saturated slices may stop
                 e = launch_rowor_wave(ops_view(ch.hs, r.dev), s.n, s.C, s.ld,

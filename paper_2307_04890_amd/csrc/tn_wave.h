@@ -53,6 +53,10 @@ hipError_t launch_rowor_wave(const DevOps &s, uint32_t n, uint64_t *C, int64_t l
 constexpr uint32_t kFlatEnd = 0x80000000u;
 constexpr uint32_t kFlatOffMask = 0x7fffffffu;
 constexpr uint32_t kFlatNone = 0xffffffffu;
+// Writes the flat form of schedule s of a network of n nodes to out
+// (4 uint32 per op, flat_ops_bytes(s) bytes).
+size_t flat_ops_bytes(const HostSchedule &s);
+void flat_ops_pack(const HostSchedule &s, uint32_t n, uint32_t *out);
 hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t n,
                                   uint32_t max_scratch_rows, bool saturation,
                                   unsigned int *done_count, hipStream_t st);

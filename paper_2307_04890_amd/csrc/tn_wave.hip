@@ -3,6 +3,8 @@
 // reverse time, Sec. 3.4; each word column evolves on its own).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tn_device.h"
 #include "tn_wave.h"
 
@@ -315,6 +317,25 @@ k_rowor_wave_flat(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords,
 }
 
 }  // namespace
+
+size_t flat_ops_bytes(const HostSchedule &s) { return std::max<size_t>(256, 4 * s.ops.size()); }
+
+void flat_ops_pack(const HostSchedule &s, uint32_t n, uint32_t *out) {
+    auto byte_off = [n](uint32_t id) -> uint32_t {
+        return 8u * ((id & kScratchBit) ? n + (id & kNodeMask) : id);
+    };
+    for (uint32_t l = 0; l < s.Lops; ++l) {
+        const uint32_t q1 = s.lvl_op[l + 1];
+        for (uint32_t q = s.lvl_op[l]; q < q1; ++q) {
+            const uint32_t *src = &s.ops[4 * (size_t)q];
+            uint32_t *o = out + 4 * (size_t)q;
+            o[0] = byte_off(src[0]) | (q + 1 == q1 ? kFlatEnd : 0u);
+            o[1] = byte_off(src[1]);
+            o[2] = src[2] == kNoRow ? kFlatNone : byte_off(src[2]);
+            o[3] = src[3] == kNoRow ? kFlatNone : byte_off(src[3]);
+        }
+    }
+}
 
 hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t n,
                                   uint32_t max_scratch_rows, bool saturation,
