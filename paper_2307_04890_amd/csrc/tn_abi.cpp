@@ -172,6 +172,15 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
     std::vector<unsigned char> img;
     if (hll) tn::schedule_pack(hs, img);
     else tn::ops_pack(hs, img);
+    // a small network with short levels also keeps its ops in the flat form
+    const int64_t nops = (int64_t)(hs.ops.size() / 4);
+    const bool flat = !hll && tn::rowor_wave_pays(n, hs.scratch_rows, nops, hs.Lops) &&
+                      !tn::rowor_wave_wide(nops, hs.Lops);
+    const size_t flat_off = (img.size() + 255) & ~(size_t)255;
+    if (flat) {
+        img.resize(flat_off + tn::flat_ops_bytes(hs), 0);
+        tn::flat_ops_pack(hs, n, (uint32_t *)(img.data() + flat_off));
+    }
     p->dev_bytes = img.size();
     hipError_t e = hipMalloc(&p->dev, p->dev_bytes);
     if (e != hipSuccess) {
@@ -192,6 +201,7 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         p->lvl_gat = std::move(hs.lvl_gat);
     } else {
         p->view = tn::ops_view(hs, p->dev);
+        if (flat) p->flat = (const uint32_t *)((unsigned char *)p->dev + flat_off);
         p->scratch_rows = hs.scratch_rows;
         p->zero_levels = tn::zero_phase_levels(hs, n);
     }
@@ -346,7 +356,11 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     if (e != hipSuccess) return hip_fail(e, "identity kernel launch");
     {
         tn::ProfScope ps(ctx, TN_K_ROWOR);
-        if (wave)
+        if (wave && plan->flat)
+            e = tn::launch_rowor_wave_flat1(plan->flat, plan->view.nops, n, C, ld,
+                                            plan->scratch_rows, ctx->traffic, ctx->saturation,
+                                            ctx->stream);
+        else if (wave)
             e = tn::launch_rowor_wave(plan->view, n, C, ld, plan->scratch_rows, ctx->traffic,
                                       ctx->saturation, nullptr, nullptr, ctx->stream);
         else

@@ -149,6 +149,9 @@ struct tn_plan {
     void *dev = nullptr;
     size_t dev_bytes = 0;
     tn::DevOps view{};
+    // the same ops in the flat form, for small networks whose levels are
+    // short (one wavefront per word column; null otherwise)
+    const uint32_t *flat = nullptr;
     uint32_t scratch_rows = 0;
     uint32_t zero_levels = 0;  // levels of the zero phase (tn::zero_phase_levels)
     // TN_HLL plans: the time-step schedule (pairs and gathers by level) on

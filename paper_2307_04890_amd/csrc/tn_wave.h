@@ -60,5 +60,10 @@ void flat_ops_pack(const HostSchedule &s, uint32_t n, uint32_t *out);
 hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t n,
                                   uint32_t max_scratch_rows, bool saturation,
                                   unsigned int *done_count, hipStream_t st);
+// One network (a resident plan): flat_ops a DEVICE array of nops flat ops;
+// C as for launch_rowor_wave, no per-column state; traffic nullable.
+hipError_t launch_rowor_wave_flat1(const uint32_t *flat_ops, uint32_t nops, uint32_t n,
+                                   uint64_t *C, int64_t ld, uint32_t scratch_rows,
+                                   unsigned long long *traffic, bool saturation, hipStream_t st);
 
 }  // namespace tn

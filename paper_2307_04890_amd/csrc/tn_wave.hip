@@ -233,15 +233,14 @@ k_rowor_wave_multi(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords
 // first offset set on the last op of every level.  A group is up to 64 ops
 // of one level; the next group's ops are read ahead, and one ballot of
 // their level-end bits gives its size, so the loop keeps no level starts.
-__global__ void __launch_bounds__(64)
-k_rowor_wave_flat(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords, bool sat,
-                  unsigned int *__restrict__ done_count) {
+// Word column w of one network with a flat schedule (one wavefront).
+__device__ __forceinline__ void
+rowor_wave_flat_column(const WaveNet &net, uint32_t w, uint32_t n, uint32_t nwords, bool sat,
+                       unsigned int *__restrict__ done_count,
+                       unsigned long long *__restrict__ traffic) {
     extern __shared__ uint64_t rows[];
     __shared__ op4 oring[kWaveRing];
     __shared__ uint64_t sink[64];
-    const uint32_t b = xcd_slice(blockIdx.x, gridDim.x);
-    const WaveNet &net = nets[b / nwords];
-    const uint32_t w = b % nwords;
     const uint32_t lane = threadIdx.x;
     const uint32_t rwords = (n + 31) / 32;
     const uint32_t tail = n & 63u;
@@ -292,6 +291,10 @@ k_rowor_wave_flat(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords,
         q = nq;
     }
     for (uint32_t r = lane; r < n; r += 64) C[(size_t)r * ld + w] = rows[r];
+    if (traffic && lane == 0) {
+        atomicAdd(traffic, (unsigned long long)n);
+        atomicAdd(traffic + 1, (unsigned long long)n);
+    }
     if (!pst) return;
     int32_t nfull = 0;
     for (uint32_t k = lane; k < rwords; k += 64) {
@@ -314,6 +317,22 @@ k_rowor_wave_flat(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords,
             atomicAdd(done_count, 1u);
         }
     }
+}
+
+// count networks (nets: device array), one block per (network, column)
+__global__ void __launch_bounds__(64)
+k_rowor_wave_flat(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords, bool sat,
+                  unsigned int *__restrict__ done_count) {
+    const uint32_t b = xcd_slice(blockIdx.x, gridDim.x);
+    rowor_wave_flat_column(nets[b / nwords], b % nwords, n, nwords, sat, done_count, nullptr);
+}
+
+// one network passed by value (a resident plan), one block per column
+__global__ void __launch_bounds__(64)
+k_rowor_wave_flat1(WaveNet net, uint32_t n, uint32_t nwords, bool sat,
+                   unsigned long long *__restrict__ traffic) {
+    rowor_wave_flat_column(net, xcd_slice(blockIdx.x, gridDim.x), n, nwords, sat, nullptr,
+                           traffic);
 }
 
 }  // namespace
@@ -349,6 +368,26 @@ hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rowor_wave_flat, dim3(count * nwords), dim3(64), lds, st, nets, n, nwords,
                        saturation, done_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowor_wave_flat1(const uint32_t *flat_ops, uint32_t nops, uint32_t n,
+                                   uint64_t *C, int64_t ld, uint32_t scratch_rows,
+                                   unsigned long long *traffic, bool saturation, hipStream_t st) {
+    if (nops == 0) return hipSuccess;
+    if (!rowor_wave_fits(n, scratch_rows)) return hipErrorInvalidValue;
+    const uint32_t nwords = (n + 63) / 64;
+    const size_t lds = ((size_t)n + scratch_rows + 1) * 8;
+    hipError_t e = hipFuncSetAttribute((const void *)k_rowor_wave_flat1,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    WaveNet net{};
+    net.s.nops = nops;
+    net.s.ops = reinterpret_cast<const uint4 *>(flat_ops);
+    net.C = C;
+    net.ld = ld;
+    hipLaunchKernelGGL(k_rowor_wave_flat1, dim3(nwords), dim3(64), lds, st, net, n, nwords,
+                       saturation, traffic);
     return hipGetLastError();
 }
 
