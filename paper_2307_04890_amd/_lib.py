@@ -126,7 +126,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is not built: the HIP library is required (run "
-            "__graft_entry__.build() or python -m paper_2307_04890_amd._build)")
+            "__graft_entry__.build() or python paper_2307_04890_amd/_build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
