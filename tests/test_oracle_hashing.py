@@ -152,3 +152,37 @@ def test_identity_hash_is_exact_and_single_bucket_is_everything():
     one = np.zeros((2, n), dtype=np.uint32)
     est1, _ = oracle.recombine(n, oracle.proxies(1, s, d, t, one), one)
     assert (est1 == n).all()
+
+
+def _hash_by_big_integers(A, u):
+    # Sec. 4.1 written out as plain polynomials: T_i(x) = A_i0 x^3 + A_i1 x^2 +
+    # A_i2 x + A_i3 mod (2^61 - 1), characters x0 = low 32 bits, x1 = high 32
+    # bits, x2 = x0 + x1, and the three table values XORed.
+    def T_(row, x):
+        return sum(int(row[l]) * x ** (3 - l) for l in range(4)) % P61
+    x0, x1 = u & 0xFFFFFFFF, u >> 32
+    return T_(A[0], x0) ^ T_(A[1], x1) ^ T_(A[2], x0 + x1)
+
+
+def test_hash_nodes_each_table_and_modulus_against_big_integers():
+    # every hash j must use its own table (stride of 3 x order entries) and the
+    # reduction mod K; shared or shifted tables would pass the statistics above
+    H, n = 5, 2500
+    A = T.hash_coefficients(H, seed=91)
+    assert len({A[j].tobytes() for j in range(H)}) == H
+    raw = [[_hash_by_big_integers(A[j], u) for u in range(n)] for j in range(H)]
+    for K in (1, 7, 1000, 4096, 65536):
+        b = oracle.hash_nodes(n, A, K)
+        want = np.array([[r % K for r in raw[j]] for j in range(H)], dtype=np.uint32)
+        assert (b == want).all(), K
+    # the tables really give different maps (a shared table would repeat rows)
+    b = oracle.hash_nodes(n, A, 4096)
+    for j in range(1, H):
+        assert (b[j] != b[0]).mean() > 0.9
+
+
+def test_hash_raw_against_big_integers_above_32_bits():
+    A = T.hash_coefficients(3, seed=92)
+    for j in range(3):
+        for u in (0, 5, (1 << 32) - 1, 1 << 32, (1 << 32) + 77, (5 << 32) + 3, (1 << 40) + 11):
+            assert oracle.hash_raw(A[j], u) == _hash_by_big_integers(A[j], u)

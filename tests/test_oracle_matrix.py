@@ -186,3 +186,59 @@ def test_rejects_bad_input():
         oracle.reverse_matrix(5, [0], [5], [0])
     with pytest.raises(ValueError):
         oracle.reverse_matrix(5, [0, 1], [1, 2], [3, 2])
+
+
+def _dense_by_unpackbits(M, n_cols):
+    # numpy's own bit unpacking, little-endian within each byte: column b is
+    # bit b & 63 of word b >> 6
+    bits = np.unpackbits(np.ascontiguousarray(M).view(np.uint8), axis=1, bitorder="little")
+    return bits[:, :n_cols].astype(np.int64)
+
+
+def test_col_counts_hand_placed_bits_at_word_edges():
+    # Sec. 3.1: the in-component size of w is the number of rows holding bit w.
+    # Bits at the first and last position of a word and in the next word catch
+    # a wrong bit order or word offset, which leave the column total unchanged.
+    nw = 3
+    M = np.zeros((4, nw), dtype=np.uint64)
+    placed = {0: [0, 63, 64, 130], 1: [63, 64, 191], 2: [64, 65, 130], 3: [1, 130]}
+    for row, cols in placed.items():
+        for b in cols:
+            M[row, b >> 6] |= np.uint64(1) << np.uint64(b & 63)
+    want = np.zeros(64 * nw, dtype=np.int64)
+    for cols in placed.values():
+        for b in cols:
+            want[b] += 1
+    assert (oracle.col_counts(M) == want).all()
+    assert (oracle.row_counts(M) == [len(placed[r]) for r in range(4)]).all()
+
+
+def test_col_and_row_counts_per_column_against_numpy_bits():
+    g = T.rng(71)
+    for n_rows, nw in ((1, 1), (37, 2), (200, 5)):
+        M = g.integers(0, 2 ** 63, size=(n_rows, nw), dtype=np.uint64)
+        M ^= g.integers(0, 2, size=(n_rows, nw), dtype=np.uint64) << np.uint64(63)
+        D = _dense_by_unpackbits(M, 64 * nw)
+        assert (oracle.col_counts(M) == D.sum(axis=0)).all()
+        assert (oracle.row_counts(M) == D.sum(axis=1)).all()
+
+
+def test_in_sizes_per_column_equal_forward_rows_and_si():
+    # Sec. 3.4: the reverse-time matrix is the transpose of forward Algorithm 1's,
+    # so column w's count (w's in-component) is row w's count of the forward
+    # matrix; SI brute force from every source gives the same per-column count.
+    for case, (n, m, Tm, directed) in enumerate([(150, 900, 60, False), (131, 700, 40, True),
+                                                 (65, 300, 20, False)]):
+        s, d, t = T.uniform_pairs(n, m, Tm, seed=80 + case)
+        C = oracle.reverse_matrix(n, s, d, t, directed=directed)
+        S = oracle.forward_matrix(n, s, d, t, directed=directed)
+        inn = oracle.col_counts(C, n)
+        assert (inn == oracle.row_counts(S)).all()
+        assert (inn == _dense_by_unpackbits(C, n).sum(axis=0)).all()
+        oc = si.out_components(n, s, d, t, directed=directed)
+        by_si = np.zeros(n, dtype=np.int64)
+        for comp in oc:
+            for w in comp:
+                by_si[w] += 1
+        assert (inn == by_si).all()
+        assert len(set(inn.tolist())) > 3  # the counts really differ by column
