@@ -225,7 +225,7 @@ tn_status run_wave_chunk(tn_ctx *ctx, const std::vector<HostSchedule> &hs, WaveI
         ProfScope ps(ctx, TN_K_BATCH);
         if (img.flat)
             e = launch_rowor_wave_flat((const WaveNet *)(dev + img.off[H]), H, K, max_scr,
-                                       ctx->saturation, done_dev, ctx->stream);
+                                       ctx->saturation, done_dev, nullptr, ctx->stream);
         else
             e = launch_rowor_wave_multi((const WaveNet *)(dev + img.off[H]), H, K, max_scr,
                                         rowor_wave_wide(ops, lv), nullptr, ctx->saturation,
@@ -314,8 +314,10 @@ tn_status tn_hash_build_proxies(tn_ctx *ctx, uint32_t n, int64_t m, const uint32
     // per word column with the column in LDS (levels cost a few LDS round
     // trips there, against a barrier and schedule loads in the batched
     // kernel); larger ones as batched tiles.  One stream keeps one kind, as
-    // the two keep different slice states.
-    const bool wave = K <= kWaveProxyK && rowor_wave_fits(K, kOpsScratchRows);
+    // the two keep different slice states, so the wavefront path is taken
+    // only when every chunk's schedule fits it: the op planner never needs
+    // more than max(default, K - 1) scratch rows for K nodes.
+    const bool wave = K <= kWaveProxyK && rowor_wave_fits(K, std::max(kOpsScratchRows, K - 1));
     const uint32_t kw = (K + 63) / 64;
     const size_t wave_col = 2 * (size_t)((K + 31) / 32) + 2;  // slice state words per column
     std::vector<uint32_t> lw;

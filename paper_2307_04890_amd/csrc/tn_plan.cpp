@@ -277,18 +277,39 @@ struct Planner {
 
     // Compound item as binary ops: each target folds its old row and its
     // partners' old rows into a scratch row (all folds read only old rows),
-    // then every target copies its scratch row back.
+    // then every target copies its scratch row back.  A compound of more
+    // targets than the default scratch folds its last target into its own
+    // row instead: emit() places those in-place ops after every other fold
+    // that reads the old row, and the partners' rows they read are only
+    // written by the copies back, which come later.  Such an item then needs
+    // targets - 1 scratch rows, so a network of K nodes never needs more
+    // than K - 1.
     void compound_ops(uint32_t n0, uint32_t n1, uint32_t e0, uint32_t e1) {
         partners(n0, n1, e0, e1);
         const uint32_t cn = n1 - n0;
-        grow_scratch(cn);
+        uint32_t targets = 0;
+        for (uint32_t c = 0; c < cn; ++c) {
+            const uint32_t x = lnode[comp_nodes[n0 + c]];
+            for (uint32_t q = nbr_ptr[c]; q < nbr_ptr[c + 1]; ++q)
+                if (nbr[q] != x) {
+                    ++targets;
+                    break;
+                }
+        }
+        if (targets == 0) return;
+        const bool in_place = targets > kOpsScratchRows;
+        grow_scratch(in_place ? targets - 1 : targets);
         tgt.clear();
         tscr.clear();
+        uint32_t seen = 0;
         for (uint32_t c = 0; c < cn; ++c) {
             const uint32_t b0 = nbr_ptr[c], b1 = nbr_ptr[c + 1];
-            if (b0 == b1) continue;  // no incoming information: row unchanged
             const uint32_t x = lnode[comp_nodes[n0 + c]];
-            const uint32_t tsc = (next_scratch++ % S) | kScratchBit;
+            bool has = false;
+            for (uint32_t q = b0; q < b1 && !has; ++q) has = nbr[q] != x;
+            if (!has) continue;  // no incoming information: row unchanged
+            const bool own = in_place && ++seen == targets;
+            const uint32_t tsc = own ? x : ((next_scratch++ % S) | kScratchBit);
             uint32_t acc = x;
             int64_t k = 0;
             for (uint32_t q = b0; q < b1; ++q) {
@@ -297,9 +318,9 @@ struct Planner {
                 acc = tsc;
                 ++k;
             }
-            if (k == 0) continue;
             ++n_targets;
             n_sources += k + 1;
+            if (own) continue;
             tgt.push_back(x);
             tscr.push_back(tsc);
         }

@@ -387,7 +387,8 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
             if (ch.flat)
                 e = launch_rowor_wave_flat(
                     reinterpret_cast<const WaveNet *>((unsigned char *)r.dev + net_off), 1, s.n,
-                    ch.hs.scratch_rows, ctx->saturation, s.done_count, ctx->stream);
+                    ch.hs.scratch_rows, ctx->saturation, s.done_count, ctx->traffic,
+                    ctx->stream);
             else if (s.sw == 1 && rowor_wave_pays(s.n, ch.hs.scratch_rows,
                                                   (int64_t)ch.hs.ops.size() / 4, ch.hs.Lops))
                 // a small network: one wavefront per word column; the slice

@@ -57,9 +57,12 @@ constexpr uint32_t kFlatNone = 0xffffffffu;
 // (4 uint32 per op, flat_ops_bytes(s) bytes).
 size_t flat_ops_bytes(const HostSchedule &s);
 void flat_ops_pack(const HostSchedule &s, uint32_t n, uint32_t *out);
+// traffic (nullable) counts the row words loaded and stored, as for
+// launch_rowor_wave.
 hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t n,
                                   uint32_t max_scratch_rows, bool saturation,
-                                  unsigned int *done_count, hipStream_t st);
+                                  unsigned int *done_count, unsigned long long *traffic,
+                                  hipStream_t st);
 // One network (a resident plan): flat_ops a DEVICE array of nops flat ops;
 // C as for launch_rowor_wave, no per-column state; traffic nullable.
 hipError_t launch_rowor_wave_flat1(const uint32_t *flat_ops, uint32_t nops, uint32_t n,

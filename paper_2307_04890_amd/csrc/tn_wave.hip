@@ -322,9 +322,10 @@ rowor_wave_flat_column(const WaveNet &net, uint32_t w, uint32_t n, uint32_t nwor
 // count networks (nets: device array), one block per (network, column)
 __global__ void __launch_bounds__(64)
 k_rowor_wave_flat(const WaveNet *__restrict__ nets, uint32_t n, uint32_t nwords, bool sat,
-                  unsigned int *__restrict__ done_count) {
+                  unsigned int *__restrict__ done_count,
+                  unsigned long long *__restrict__ traffic) {
     const uint32_t b = xcd_slice(blockIdx.x, gridDim.x);
-    rowor_wave_flat_column(nets[b / nwords], b % nwords, n, nwords, sat, done_count, nullptr);
+    rowor_wave_flat_column(nets[b / nwords], b % nwords, n, nwords, sat, done_count, traffic);
 }
 
 // one network passed by value (a resident plan), one block per column
@@ -358,7 +359,8 @@ void flat_ops_pack(const HostSchedule &s, uint32_t n, uint32_t *out) {
 
 hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t n,
                                   uint32_t max_scratch_rows, bool saturation,
-                                  unsigned int *done_count, hipStream_t st) {
+                                  unsigned int *done_count, unsigned long long *traffic,
+                                  hipStream_t st) {
     if (count == 0) return hipSuccess;
     if (!rowor_wave_fits(n, max_scratch_rows)) return hipErrorInvalidValue;
     const uint32_t nwords = (n + 63) / 64;
@@ -367,7 +369,7 @@ hipError_t launch_rowor_wave_flat(const WaveNet *nets, uint32_t count, uint32_t 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rowor_wave_flat, dim3(count * nwords), dim3(64), lds, st, nets, n, nwords,
-                       saturation, done_count);
+                       saturation, done_count, traffic);
     return hipGetLastError();
 }
 

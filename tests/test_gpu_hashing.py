@@ -232,3 +232,29 @@ def test_paper_setting_er_poisson_exact_and_hashed():
     est, lifted = tn.recombine(P, bucket, count, n)
     we, wl = oracle.recombine(n, WP, wb)
     assert (est.cpu().numpy() == we).all() and (lifted.cpu().numpy() == wl).all()
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_streamed_small_proxies_with_a_time_step_over_every_bucket(flags):
+    # one time step whose mapped events join nearly all of K = 4096
+    # super-nodes: a compound item of more than 1024 targets inside a chunk
+    # of the wavefront path (its last target folds in place, so the chunk's
+    # scratch rows still fit beside the K rows in LDS)
+    n, H, K = 20000, 2, 4096
+    g = T.rng(31)
+    s1, d1, t1 = T.uniform_pairs(n, 4000, 400, seed=32)
+    s2 = g.integers(0, n, 30000).astype(np.uint32)
+    d2 = ((s2.astype(np.int64) + 1 + g.integers(0, n - 1, 30000)) % n).astype(np.uint32)
+    t2 = np.full(30000, 400, dtype=np.int64)
+    s3, d3, t3 = T.uniform_pairs(n, 4000, 400, seed=33)
+    s = np.concatenate([s1, s2, s3])
+    d = np.concatenate([d1, d2, d3])
+    t = np.concatenate([t1, t2, t3 + 401])
+    A = T.hash_coefficients(H, seed=34)
+    wb = oracle.hash_nodes(n, A, K)
+    sch = tn.host_schedule(K, wb[0][s], wb[0][d], t, flags)
+    assert 1024 < sch["stats"]["scratch_rows"] <= K - 1
+    WP = oracle.proxies(K, s, d, t, wb, directed=bool(flags & 1))
+    _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, flags=flags, chunk_events=5000)
+    assert (host(P) == WP).all()
+    assert st["chunks"] > 2

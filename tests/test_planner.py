@@ -214,6 +214,29 @@ def test_wide_levels_are_split_and_big_compound_items_fold():
     assert (simulate_ops(n, sch) == oracle.reverse_matrix(n, s_, d_, t_)).all()
 
 
+@pytest.mark.parametrize("flags", [0, tn.DIRECTED])
+def test_compound_over_every_node_needs_fewer_scratch_rows_than_nodes(flags):
+    # one time step whose events join all K = 4096 nodes: a compound item of
+    # (nearly) every node as a target.  Its last target folds in place, so the
+    # schedule needs at most K - 1 scratch rows: K + scratch + 1 LDS words fit
+    # the one-wavefront kernel's 8192.
+    g = T.rng(14)
+    K = 4096
+    perm = g.permutation(K).astype(np.uint32)
+    s_ = np.concatenate([perm, g.integers(0, K, 6000).astype(np.uint32)])
+    d_ = np.concatenate([np.roll(perm, -1), g.integers(0, K, 6000).astype(np.uint32)])
+    t_ = np.zeros(s_.shape[0], dtype=np.int64)
+    s2, d2, t2 = T.uniform_pairs(K, 3000, 40, seed=15)
+    s_ = np.concatenate([s_, s2])
+    d_ = np.concatenate([d_, d2])
+    t_ = np.concatenate([t_, t2 + 1])
+    sch = tn.host_schedule(K, s_, d_, t_, flags)
+    check_ops_independent(sch)
+    assert 1024 < sch["stats"]["scratch_rows"] <= K - 1
+    want = oracle.reverse_matrix(K, s_, d_, t_, directed=bool(flags & tn.DIRECTED))
+    assert (simulate_ops(K, sch) == want).all()
+
+
 @pytest.mark.parametrize("sw", [1, 2, 8])
 def test_saturation_skips_keep_the_matrix(sw):
     # skipping the loads of saturated operands and the stores of full results
