@@ -557,7 +557,7 @@ def run_combiner(args):
         log(f"[bench] {tag}: {args.train_networks} training networks")
         X, Y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
         data_s = time.perf_counter() - t0
-        comb = cb.Combiner(T.mlp_init(1))
+        comb = cb.Combiner(seed=1)
         g = T.rng(2)
         orders = [g.permutation(X.shape[0]) for _ in range(args.epochs)]
         ctx.profile(True)
@@ -632,7 +632,7 @@ def run_combiner(args):
         from oracle import mlp as ref
         xs_ = np.zeros((4096, 16))
         ys_ = np.zeros(4096)
-        p = T.mlp_init(1).astype(np.float64)
+        p = ref.init(1).astype(np.float64)
         g = T.rng(3)
         xs_[:] = g.normal(size=xs_.shape)
         ys_[:] = g.normal(size=ys_.shape)

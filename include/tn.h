@@ -427,6 +427,16 @@ tn_status tn_recombine(tn_ctx *ctx, uint32_t n, uint32_t H, uint32_t K,
 /* Number of float parameters: per layer W (out x in, row-major) then b. */
 int32_t tn_mlp_param_count(void);
 
+/* Seeded initial parameters on the device: every weight of layer i is
+ * (2u - 1) * sqrt(6 / fan_in_i) (He-uniform), every bias 0.  For weight p
+ * of the packed vector, u is the top 24 bits of the p-th output of a
+ * SplitMix64 generator seeded with `seed` (Steele, Lea and Flood, 2014),
+ * times 2^-24; the product is formed in fp64 and rounded to float once.
+ * Equal seeds give bit-equal parameters on any device.  params: DEVICE
+ * float[tn_mlp_param_count()], caller-owned, overwritten; asynchronous on the
+ * context's stream.  Errors: TN_E_ARG for a NULL ctx or params. */
+tn_status tn_mlp_init(tn_ctx *ctx, uint64_t seed, float *params);
+
 /* Features x[u*H + j] = ln(lifted[j*n + u] / n) as float.  lifted: DEVICE
  * int32[H*n]; x: DEVICE float[n*H].  H must be 16. */
 tn_status tn_mlp_features(tn_ctx *ctx, uint32_t n, uint32_t H,

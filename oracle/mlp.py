@@ -14,6 +14,44 @@ import numpy as np
 SIZES = (16, 64, 64, 1)
 
 
+_M64 = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64(seed: int, count: int) -> list[int]:
+    """The first ``count`` outputs of SplitMix64 (Steele, Lea and Flood, 2014)
+    seeded with ``seed``: the state advances by the golden-ratio increment,
+    and each output is the state passed through the generator's mix
+    (xor-shift 30, multiply, xor-shift 27, multiply, xor-shift 31)."""
+    out, state = [], seed & _M64
+    for _ in range(count):
+        state = (state + _GAMMA) & _M64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def init(seed: int, sizes=SIZES) -> np.ndarray:
+    """Seeded initial parameters (float32): weights of layer i are
+    (2u - 1) * sqrt(6 / fan_in_i) (He-uniform), biases 0, where for entry p of
+    the packed vector u is the top 24 bits of SplitMix64 output p, over 2^24.
+    The product is formed in float64 and rounded to float32 once."""
+    total = sum(sizes[i] * sizes[i + 1] + sizes[i + 1] for i in range(len(sizes) - 1))
+    draws = splitmix64(seed, total)
+    p = np.zeros(total, dtype=np.float64)
+    o = 0
+    for i in range(len(sizes) - 1):
+        fi, fo = sizes[i], sizes[i + 1]
+        bound = np.sqrt(6.0 / fi)
+        for k in range(fo * fi):
+            u = (draws[o + k] >> 40) / float(1 << 24)
+            p[o + k] = (2.0 * u - 1.0) * bound
+        o += fo * fi + fo
+    return p.astype(np.float32)
+
+
 def unpack(p, sizes=SIZES):
     p = np.asarray(p, dtype=np.float64)
     layers, o = [], 0

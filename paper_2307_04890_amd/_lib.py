@@ -111,6 +111,7 @@ SIGNATURES = {
                                 _PP]),
     "tn_recombine": (_i32, [_P, _u32, _u32, _u32, _P, _i64, _P, _P, _P, _P]),
     "tn_mlp_param_count": (_i32, []),
+    "tn_mlp_init": (_i32, [_P, _u64, _P]),
     "tn_mlp_features": (_i32, [_P, _u32, _u32, _P, _P]),
     "tn_mlp_forward": (_i32, [_P, _P, _P, _i64, _P]),
     "tn_mlp_predict": (_i32, [_P, _P, _P, _i64, _u32, _P, _P]),

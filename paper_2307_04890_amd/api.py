@@ -12,7 +12,7 @@ from ._lib import (DIRECTED, FORWARD, KERNELS, TIES_SEQUENTIAL, PlanStats, Strea
                    check, lib)
 
 __all__ = ["Context", "Plan", "Online", "FORWARD", "hll_build", "build_component_matrix_streamed",
-           "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+           "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_init", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
 
@@ -459,6 +459,19 @@ def recombine(P: torch.Tensor, bucket: torch.Tensor, count: torch.Tensor, n: int
 
 
 MLP_PARAMS = 5313
+
+
+def mlp_init(seed: int, params: torch.Tensor | None = None,
+             ctx: Context | None = None) -> torch.Tensor:
+    """Seeded He-uniform initial parameters on the device (tn_mlp_init):
+    (MLP_PARAMS,) float32."""
+    ctx = ctx or get_context()
+    if params is None:
+        params = torch.empty(MLP_PARAMS, dtype=torch.float32, device=f"cuda:{ctx.device}")
+    if params.dtype != torch.float32 or params.numel() != MLP_PARAMS or not params.is_contiguous():
+        raise ValueError(f"params must be a contiguous float32 tensor of {MLP_PARAMS} values")
+    check(lib.tn_mlp_init(ctx.bind_stream(), int(seed) & ((1 << 64) - 1), _dp(params)))
+    return params
 
 
 def mlp_features(lifted: torch.Tensor, n: int, ctx: Context | None = None) -> torch.Tensor:

@@ -50,13 +50,19 @@ def exact_out_sizes_batched(nets, flags=0, ctx=None):
 class Combiner:
     """The trainable network: parameters and Adam moments live on the device."""
 
-    def __init__(self, init_params: np.ndarray, device: int | None = None):
+    def __init__(self, seed: int = 1, init_params: np.ndarray | None = None,
+                 device: int | None = None):
+        """Parameters from tn_mlp_init(seed) on the device, or copied from
+        ``init_params`` when given."""
         if device is None:
             device = torch.cuda.current_device()
-        p = np.ascontiguousarray(init_params, dtype=np.float32)
-        if p.shape != (api.MLP_PARAMS,):
-            raise ValueError(f"expected {api.MLP_PARAMS} parameters")
-        self.params = torch.from_numpy(p).to(f"cuda:{device}")
+        if init_params is None:
+            self.params = api.mlp_init(seed)
+        else:
+            p = np.ascontiguousarray(init_params, dtype=np.float32)
+            if p.shape != (api.MLP_PARAMS,):
+                raise ValueError(f"expected {api.MLP_PARAMS} parameters")
+            self.params = torch.from_numpy(p).to(f"cuda:{device}")
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.step = 0

@@ -7,6 +7,19 @@ extern "C" {
 
 int32_t tn_mlp_param_count(void) { return tn::mlp_param_count(); }
 
+tn_status tn_mlp_init(tn_ctx *ctx, uint64_t seed, float *params) {
+    using namespace tn;
+    if (!ctx || !params) return fail(TN_E_ARG, "null argument");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    hipError_t e;
+    {
+        ProfScope ps(ctx, TN_K_AUX);
+        e = launch_mlp_init(seed, params, ctx->stream);
+    }
+    return e == hipSuccess ? TN_OK : hip_fail(e, "init kernel launch");
+}
+
 tn_status tn_mlp_features(tn_ctx *ctx, uint32_t n, uint32_t H, const int32_t *lifted, float *x) {
     using namespace tn;
     if (!ctx || !lifted || !x) return fail(TN_E_ARG, "null argument");

@@ -10,6 +10,8 @@
 // W2 (64 x 64), b2 (64), W3 (1 x 64), b3 (1).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "tn_mlp.h"
 
 namespace tn {
@@ -191,6 +193,35 @@ k_mlp_features(uint32_t n, uint32_t H, const int32_t *__restrict__ lifted, float
     }
 }
 
+// Seeded initial parameters: He-uniform weights, zero biases.  Weight p of
+// the packed vector takes the p-th output of a SplitMix64 generator seeded
+// with `seed` (Steele, Lea and Flood, 2014): state seed + (p + 1) * gamma,
+// then the generator's output mix.  Each index is computed on its own, so
+// the result does not depend on the launch shape.  The top 24 bits give
+// u in [0, 1); the weight is (2u - 1) * bound in fp64, rounded to float once.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t p) {
+    uint64_t z = seed + (p + 1) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_init(uint64_t seed, double bound1, double bound2, double bound3, float *__restrict__ params) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kParams) return;
+    double bound;
+    if (p < oB1) bound = bound1;
+    else if (p >= oW2 && p < oB2) bound = bound2;
+    else if (p >= oW3 && p < oB3) bound = bound3;
+    else {
+        params[p] = 0.f;  // a bias
+        return;
+    }
+    const double u = (double)(splitmix64_at(seed, (uint64_t)p) >> 40) * 0x1p-24;
+    params[p] = (float)((2.0 * u - 1.0) * bound);
+}
+
 }  // namespace
 
 int mlp_param_count() { return kParams; }
@@ -227,6 +258,13 @@ hipError_t launch_mlp_adam(const float *partial, int nblk, float *params, float 
                            float *grad, hipStream_t st) {
     hipLaunchKernelGGL(k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, st, partial, nblk,
                        params, m, v, lr, c1, c2, loss_partial, loss, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(uint64_t seed, float *params, hipStream_t st) {
+    // sqrt(6 / fan_in) of each layer, rounded once on the host
+    hipLaunchKernelGGL(k_mlp_init, dim3((kParams + 255) / 256), dim3(256), 0, st, seed,
+                       std::sqrt(6.0 / kIn), std::sqrt(6.0 / kH), std::sqrt(6.0 / kH), params);
     return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ def test_combiner_gains_over_fusion_estimate():
     xs, ys, _, _, _ = dataset(train, H, K, 10)
     X = torch.cat(xs).contiguous()
     Y = torch.cat(ys).contiguous()
-    comb = cb.Combiner(T.mlp_init(1))
+    comb = cb.Combiner(seed=1)
     g = T.rng(2)
     losses = comb.fit(X, Y, [g.permutation(X.shape[0]) for _ in range(60)], batch=2048, lr=2e-3)
     assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:10])

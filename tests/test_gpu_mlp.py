@@ -94,3 +94,15 @@ def test_features_are_log_fractions():
     lifted = T.rng(11).integers(1, n + 1, size=(H, n)).astype(np.int32)
     x = tn.mlp_features(dev(lifted), n).cpu().numpy()
     assert np.allclose(x, np.log(lifted.T / n), rtol=1e-6, atol=1e-6)
+
+
+def test_device_init_matches_oracle_bit_for_bit():
+    # tn_mlp_init against the oracle's own SplitMix64 and He-uniform draw
+    for seed in (0, 1, 12345, (1 << 63) + 5):
+        got = tn.mlp_init(seed).cpu().numpy()
+        want = ref.init(seed)
+        assert got.dtype == np.float32 and (got.view(np.uint32) == want.view(np.uint32)).all(), seed
+    a = tn.mlp_init(7)
+    b = tn.mlp_init(7, params=torch.full((tn.MLP_PARAMS,), 3.0, device="cuda"))
+    assert torch.equal(a, b)
+    assert not torch.equal(a, tn.mlp_init(8))

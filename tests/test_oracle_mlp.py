@@ -1,5 +1,7 @@
 """Pins of the float64 learned-combiner reference: central finite differences,
 torch autograd and torch's Adam on the CPU (library routines)."""
+import os
+
 import numpy as np
 import torch
 
@@ -74,3 +76,31 @@ def test_first_adam_step_is_lr_times_sign():
     q, _, _ = mlp.adam_step(p, np.zeros_like(p), np.zeros_like(p), g, 1, lr=1e-3)
     big = np.abs(g) > 1e-4
     assert np.allclose((p - q)[big], 1e-3 * np.sign(g[big]), rtol=1e-3)
+
+
+def test_splitmix64_known_answer():
+    # the published first outputs of SplitMix64 for one seed (golden file)
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed1234567.txt")
+    lines = [ln.split("#", 1)[0].strip() for ln in open(path)]
+    lines = [ln for ln in lines if ln]
+    seed = int(lines[0].split()[1])
+    want = [int(v) for v in lines[1:]]
+    assert mlp.splitmix64(seed, len(want)) == want
+
+
+def test_init_bounds_biases_and_moments():
+    # He-uniform: weights of layer i uniform on (-sqrt(6/fan_in), sqrt(6/fan_in)),
+    # biases zero; mean 0 and variance bound^2 / 3 within sampling error
+    p = mlp.init(11).astype(np.float64)
+    for W, b in mlp.unpack(p):
+        bound = np.sqrt(6.0 / W.shape[1])
+        assert (np.abs(W) <= bound).all() and (b == 0).all()
+        k = W.size
+        assert abs(W.mean()) < 5 * bound / np.sqrt(3 * k)
+        var = W.var()
+        # variance of the sample variance of a uniform: (bound^4)(1/5 - 1/9) / k
+        assert abs(var - bound ** 2 / 3) < 5 * bound ** 2 * np.sqrt((1 / 5 - 1 / 9) / k)
+        # the draws fill the whole interval
+        assert W.min() < -0.9 * bound and W.max() > 0.9 * bound
+    assert (mlp.init(11) == mlp.init(11)).all()
+    assert (mlp.init(11) != mlp.init(12)).mean() > 0.9
