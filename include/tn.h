@@ -86,6 +86,14 @@ typedef struct tn_batch tn_batch; /* many networks' schedules, one launch      *
 /* Thread-local text of the last error (never NULL). */
 const char *tn_last_error(void);
 
+/* The row stride (in uint64 words) this library suggests for a bit matrix of
+ * n columns: ceil(n/64) rounded up to 16 words (one 128-byte line) once a
+ * row spans 16 words or more, so that every row starts on a line and the
+ * column slices of the row-OR kernels never straddle two lines; ceil(n/64)
+ * below that.  Any ld >= ceil(n/64) is accepted everywhere; this one is
+ * faster (the padding words are written as 0).  Host only. */
+int64_t tn_recommended_ld(uint32_t n);
+
 /* Creates a context on HIP device `device`, enqueuing on `stream` (a
  * hipStream_t; NULL = the null stream).  *out receives the context. */
 tn_status tn_create(int device, void *stream, tn_ctx **out);
@@ -187,6 +195,16 @@ tn_status tn_schedule_arrays(const tn_host_schedule *s, tn_plan_stats *stats,
  * one level read rows no op of that level writes. */
 tn_status tn_schedule_op_arrays(const tn_host_schedule *s,
                                 const uint32_t **lvl_op, const uint32_t **ops);
+/* The forwarded form of the binary-op schedule that the plain row-OR kernel
+ * runs (host only, for inspection and tests): levels of at most 768 ops,
+ * *levels of them, level l owning ops [lvl[l], lvl[l+1]), 4 uint32 each
+ * {a, b, d1, d2} as in the op form, except that an operand with bit 30 set
+ * is the result r of op (operand & 0x3ff) of level l - 1, and a
+ * destination with bit 30 set is not written to memory (level l + 1
+ * overwrites that row, reading it, if at all, through the same
+ * forwarding).  The arrays live until tn_schedule_destroy. */
+tn_status tn_schedule_fwd_arrays(tn_host_schedule *s, uint32_t *levels,
+                                 const uint32_t **lvl, const uint32_t **ops);
 void tn_schedule_destroy(tn_host_schedule *s);
 
 /* Destroys a plan (frees its device schedule).  NULL is ignored. */

@@ -86,6 +86,7 @@ SIGNATURES = {
     "tn_schedule_build": (_i32, [_u32, _i64, _P, _P, _P, _u32, _PP]),
     "tn_schedule_arrays": (_i32, [_P, ctypes.POINTER(PlanStats), _PP, _PP, _PP, _PP, _PP, _PP]),
     "tn_schedule_destroy": (None, [_P]),
+    "tn_schedule_fwd_arrays": (_i32, [_P, _P, _PP, _PP]),
     "tn_schedule_op_arrays": (_i32, [_P, _PP, _PP]),
     "tn_plan_execute": (_i32, [_P, _P, _P, _i64, _u32]),
     "tn_set_saturation": (_i32, [_P, ctypes.c_int]),
@@ -111,6 +112,7 @@ SIGNATURES = {
                                 _PP]),
     "tn_recombine": (_i32, [_P, _u32, _u32, _u32, _P, _i64, _P, _P, _P, _P]),
     "tn_mlp_param_count": (_i32, []),
+    "tn_recommended_ld": (_i64, [_u32]),
     "tn_mlp_init": (_i32, [_P, _u64, _P]),
     "tn_mlp_features": (_i32, [_P, _u32, _u32, _P, _P]),
     "tn_mlp_forward": (_i32, [_P, _P, _P, _i64, _P]),

@@ -113,10 +113,12 @@ def _events(src, dst, t):
 
 
 def alloc_matrix(n: int, ld: int | None = None, device: int | None = None, rows: int | None = None):
+    """An (n, ld) int64 device tensor for a bit matrix of n columns; ld
+    defaults to tn_recommended_ld(n) (rows on 128-byte lines)."""
     if device is None:
         device = torch.cuda.current_device()
     if ld is None:
-        ld = words(n)
+        ld = int(lib.tn_recommended_ld(int(n)))
     return torch.empty((n if rows is None else rows, ld), dtype=torch.int64,
                        device=f"cuda:{device}")
 
@@ -301,6 +303,12 @@ def host_schedule(n: int, src, dst, t, flags: int = 0) -> dict:
                    pairs=arr(ptrs[2], 2 * P).reshape(P, 2), gat_tgt=arr(ptrs[3], G),
                    gat_ptr=gat_ptr, gat_src=arr(ptrs[5], int(gat_ptr[-1]) if G else 0),
                    lvl_op=arr(optr[0], Lo + 1), ops=arr(optr[1], 4 * nops).reshape(nops, 4))
+        fl = ctypes.c_uint32()
+        fptr = [ctypes.c_void_p() for _ in range(2)]
+        check(lib.tn_schedule_fwd_arrays(h, ctypes.byref(fl), ctypes.byref(fptr[0]),
+                                         ctypes.byref(fptr[1])))
+        out["fwd_lvl"] = arr(fptr[0], fl.value + 1)
+        out["fwd_ops"] = arr(fptr[1], 4 * nops).reshape(nops, 4)
     finally:
         lib.tn_schedule_destroy(h)
     return out

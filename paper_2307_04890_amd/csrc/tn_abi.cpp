@@ -204,6 +204,8 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         if (flat) p->flat = (const uint32_t *)((unsigned char *)p->dev + flat_off);
         p->scratch_rows = hs.scratch_rows;
         p->zero_levels = tn::zero_phase_levels(hs, n);
+        p->host_lvl_op = std::move(hs.lvl_op);
+        p->host_ops = std::move(hs.ops);
     }
     *out = p;
     return TN_OK;
@@ -251,6 +253,7 @@ extern "C" {
 
 struct tn_host_schedule {
     tn::HostSchedule hs;
+    std::vector<uint32_t> flvl, fops;  // the forwarded op form, made on request
 };
 
 tn_status tn_schedule_build(uint32_t n, int64_t m, const uint32_t *src, const uint32_t *dst,
@@ -293,6 +296,17 @@ tn_status tn_schedule_op_arrays(const tn_host_schedule *s, const uint32_t **lvl_
     return TN_OK;
 }
 
+tn_status tn_schedule_fwd_arrays(tn_host_schedule *s, uint32_t *levels,
+                                 const uint32_t **lvl, const uint32_t **ops) {
+    if (!s || !levels) return fail(TN_E_ARG, "schedule or levels is NULL");
+    if (s->flvl.empty())
+        tn::fwd_schedule(s->hs.lvl_op, s->hs.ops, s->hs.n, s->hs.scratch_rows, s->flvl, s->fops);
+    *levels = (uint32_t)s->flvl.size() - 1;
+    if (lvl) *lvl = s->flvl.data();
+    if (ops) *ops = s->fops.data();
+    return TN_OK;
+}
+
 void tn_schedule_destroy(tn_host_schedule *s) { delete s; }
 
 tn_status tn_plan_get_stats(const tn_plan *plan, tn_plan_stats *out) {
@@ -305,9 +319,47 @@ void tn_plan_destroy(tn_plan *plan) {
     if (!plan) return;
     DeviceGuard g(plan->device);
     if (plan->hll_exec) (void)hipGraphExecDestroy(plan->hll_exec);
+    if (plan->fwd_dev) (void)hipFree(plan->fwd_dev);
     if (plan->dev) (void)hipFree(plan->dev);
     delete plan;
 }
+
+int64_t tn_recommended_ld(uint32_t n) {
+    const int64_t nwords = ((int64_t)n + 63) / 64;
+    return nwords >= 16 ? (nwords + 15) / 16 * 16 : nwords;
+}
+
+namespace {
+// The plan's forwarded schedule on the device, made on first use (waits for
+// the upload).
+tn_status plan_fwd(tn_ctx *ctx, const tn_plan *plan) {
+    std::lock_guard<std::mutex> lk(plan->fwd_mu);
+    if (plan->fwd_dev) return TN_OK;
+    std::vector<uint32_t> flvl, fops;
+    tn::fwd_schedule(plan->host_lvl_op, plan->host_ops, plan->stats.n, plan->scratch_rows, flvl,
+                     fops);
+    const size_t lb = (4 * flvl.size() + 255) & ~(size_t)255;
+    const size_t bytes = lb + 4 * std::max<size_t>(fops.size(), 4);
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(TN_E_NOMEM, "forwarded schedule allocation failed");
+    e = hipMemcpyAsync(d, flvl.data(), 4 * flvl.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess && !fops.empty())
+        e = hipMemcpyAsync((unsigned char *)d + lb, fops.data(), 4 * fops.size(),
+                           hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "forwarded schedule upload");
+    }
+    plan->fwd_view.L = (uint32_t)flvl.size() - 1;
+    plan->fwd_view.nops = (uint32_t)(fops.size() / 4);
+    plan->fwd_view.lvl = (const uint32_t *)d;
+    plan->fwd_view.ops = (const uint4 *)((unsigned char *)d + lb);
+    plan->fwd_dev = d;
+    return TN_OK;
+}
+}  // namespace
 
 tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t ld,
                           uint32_t slice_words) {
@@ -354,9 +406,20 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
             e = tn::launch_fill_u32(persist, pwords, 0u, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "identity kernel launch");
+    // the plain recurrence (saturation off, or no room for its bitmap) runs
+    // on the forwarded schedule where the slice width allows
+    const bool fwd = !wave && (!ctx->saturation || !tn::rowor_saturates(n, plan->scratch_rows)) &&
+                     tn::rowor_fwd_supported(n, slice_words) && plan->stats.ops > 0;
+    if (fwd) {
+        tn_status st = plan_fwd(ctx, plan);
+        if (st != TN_OK) return st;
+    }
     {
         tn::ProfScope ps(ctx, TN_K_ROWOR);
-        if (wave && plan->flat)
+        if (fwd)
+            e = tn::launch_rowor_fwd(plan->fwd_view, n, C, ld, slice_words,
+                                     (uint64_t *)ctx->scratch, ctx->traffic, ctx->stream);
+        else if (wave && plan->flat)
             e = tn::launch_rowor_wave_flat1(plan->flat, plan->view.nops, n, C, ld,
                                             plan->scratch_rows, ctx->traffic, ctx->saturation,
                                             ctx->stream);

@@ -58,6 +58,22 @@ struct HostSchedule {
     double host_seconds = 0.0;
 };
 
+// Forwarded op form, for the plain row-OR kernel that keeps each level's
+// results in LDS for the next level (launch_rowor_fwd).  Levels hold at most
+// kFwdLevelCap ops.  An operand with kFwdHot set is the result of op
+// (operand & kFwdSlotMask) of the level just before, read from LDS; any
+// other operand is a row id as in the op form (last written two or more
+// levels before).  A destination with kFwdNoStore set is not stored: the
+// next level overwrites that row (kNoRow carries the bit too).  Row and
+// scratch ids stay below 2^30.
+constexpr uint32_t kFwdLevelCap = 768;
+constexpr uint32_t kFwdHot = 0x40000000u;
+constexpr uint32_t kFwdNoStore = 0x40000000u;
+constexpr uint32_t kFwdSlotMask = 0x3ffu;
+void fwd_schedule(const std::vector<uint32_t> &lvl_op, const std::vector<uint32_t> &ops,
+                  uint32_t n, uint32_t scratch_rows, std::vector<uint32_t> &flvl,
+                  std::vector<uint32_t> &fops);
+
 // Device view of one schedule (all pointers into one allocation).
 struct DevSchedule {
     uint32_t n;
@@ -154,6 +170,12 @@ struct tn_plan {
     const uint32_t *flat = nullptr;
     uint32_t scratch_rows = 0;
     uint32_t zero_levels = 0;  // levels of the zero phase (tn::zero_phase_levels)
+    // the op schedule on the host, and its forwarded form on the device,
+    // made by the first execution of the plain recurrence (tn::fwd_schedule)
+    std::vector<uint32_t> host_lvl_op, host_ops;
+    mutable std::mutex fwd_mu;
+    mutable void *fwd_dev = nullptr;
+    mutable tn::DevOps fwd_view{};
     // TN_HLL plans: the time-step schedule (pairs and gathers by level) on
     // the device, its level boundaries on the host, instead of the ops
     bool hll = false;
@@ -234,6 +256,14 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
                                uint32_t scratch_rows, unsigned long long *traffic,
                                bool saturation, uint32_t *persist, unsigned int *done_count,
                                uint32_t zero_levels, hipStream_t st);
+// The plain recurrence (no saturation) on a forwarded op schedule
+// (fwd_schedule), one workgroup per slice of slice_words <= 8 words as in
+// launch_rowor_global, with the same scratch layout and traffic counters;
+// each level's results stay in LDS for the next level.
+bool rowor_fwd_supported(uint32_t n, uint32_t slice_words);
+hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
+                            uint32_t slice_words, uint64_t *scratch,
+                            unsigned long long *traffic, hipStream_t st);
 // Levels of the zero phase of a schedule: those before the level at which
 // its ops reach `budget`.  Applied to the identity the budget is n (about
 // one op per row), by when few row slices are still all zero; a streamed

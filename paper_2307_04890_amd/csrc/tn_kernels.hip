@@ -542,6 +542,159 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     }
 }
 
+// The plain recurrence with level-to-level forwarding (forwarded op form,
+// tn_internal.h).  Each op's result r also goes into this level's LDS
+// result frame, at the op's index; an operand that the level just before
+// wrote is read from there instead of memory, and a row that the next level
+// overwrites is not stored.  About half of all row reads and stores of an
+// activity-driven stream leave memory this way: almost every op reads one
+// row the level before wrote, and that row is rewritten right away.
+//
+// Cold operands (rows last written two or more levels before) do not
+// depend on the level just before, so their loads are issued one level
+// early: right after the barrier that starts level l, the compute waves
+// issue the cold loads of level l + 1, then run level l on the values that
+// arrived meanwhile.  The barrier waits for every wave's loads and stores,
+// so the stores of level l - 1 are in memory before any load of level l + 1
+// can read them.  Loader waves keep a ring of three op frames (the level
+// run, the level whose cold loads are in flight, the level being loaded);
+// results alternate between two LDS frames.
+constexpr uint32_t kFwdFrames = 3;
+
+template <int UC>
+struct ColdVals {
+    uint64_t x[UC], y[UC];
+};
+
+// The cold operands of the level in `frame` (forwarded ones read the sink).
+template <int SW, int UC>
+__device__ __forceinline__ void fwd_issue(OpArgs &A, const op4 *frame, uint32_t cnt,
+                                          ColdVals<UC> &c) {
+#pragma unroll
+    for (int k = 0; k < UC; ++k) {
+        const uint32_t j = A.grp + k * A.ngrp;
+        const op4 o = frame[min(j, kOpsLevelCap - 1)];
+        const bool v = j < cnt;
+        const bool hx = o.x & kFwdHot, hy = o.y & kFwdHot;
+        c.x[k] = *op_addr(A, o.x, v && !hx);
+        c.y[k] = *op_addr(A, o.y, v && !hy);
+        A.loaded += ((v && A.wok && !hx) ? 1u : 0u) + ((v && A.wok && !hy) ? 1u : 0u);
+    }
+}
+
+// Runs the level in `frame` with its cold values in c.
+template <int SW, int UC>
+__device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t cnt,
+                                          const ColdVals<UC> &c, const uint64_t *res_prev,
+                                          uint64_t *res_cur, uint32_t lig) {
+#pragma unroll
+    for (int k = 0; k < UC; ++k) {
+        const uint32_t j = A.grp + k * A.ngrp;
+        const op4 o = frame[min(j, kOpsLevelCap - 1)];
+        const bool v = j < cnt;
+        // a cold operand's low bits are a row id: its (unused) read is
+        // clamped into the frame
+        const uint64_t lx = res_prev[min(o.x & kFwdSlotMask, kFwdLevelCap) * SW + lig];
+        const uint64_t ly = res_prev[min(o.y & kFwdSlotMask, kFwdLevelCap) * SW + lig];
+        const uint64_t r = ((o.x & kFwdHot) ? lx : c.x[k]) | ((o.y & kFwdHot) ? ly : c.y[k]);
+        // slot kFwdLevelCap takes the writes of lanes with no op
+        res_cur[(v ? j : kFwdLevelCap) * SW + lig] = r;
+        // kNoRow has the no-store bit too: it is never stored
+        const bool s1 = v && !(o.z & kFwdNoStore);
+        const bool s2 = v && !(o.w & kFwdNoStore);
+        *op_addr(A, o.z, s1) = r;
+        *op_addr(A, o.w, s2) = r;
+        A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+    }
+}
+
+template <int SW, int UC>
+__global__ void __launch_bounds__(1024)
+k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
+            uint64_t *__restrict__ scratch, unsigned long long *__restrict__ traffic) {
+    static_assert(((1024 - kLoaderThreads) / SW) * UC >= kFwdLevelCap, "a level per pass");
+    __shared__ op4 frame[kFwdFrames][kOpsLevelCap];
+    __shared__ uint32_t fcount[kFwdFrames];
+    // dynamic: two result frames of kFwdLevelCap + 1 slots (the last one a
+    // sink) of SW words
+    extern __shared__ uint64_t results[];
+    constexpr uint32_t kFrameWords = (kFwdLevelCap + 1) * SW;
+    const uint32_t L = s.L;
+    if (L == 0 || s.nops == 0) return;
+    const uint32_t tid = threadIdx.x;
+    const bool loader = tid < kLoaderThreads;
+    const uint32_t ctid = tid - kLoaderThreads;
+    const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
+    OpArgs A;
+    A.C = C;
+    A.ldz = (size_t)ld;
+    A.nwords = nwords;
+    A.w = slice * SW + (ctid % SW);
+    A.wok = !loader && A.w < nwords;
+    A.grp = ctid / SW;
+    A.ngrp = (blockDim.x - kLoaderThreads) / SW;
+    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
+    A.rows = scratch + (size_t)gridDim.x * kRoworSinkWords;
+    A.loaded = A.stored = 0;
+    if (loader) {
+        // levels 0 and 1 before the first barrier; at the barrier that
+        // starts level l, frame (l + 2) % 3 receives level l + 2.  Starts
+        // and ops are fetched a level ahead into registers (hA, hB; the
+        // loop is unrolled by two so that they never change registers).
+        put_level(frame[0], fetch_ops(s, level_start(s, 0), tid), tid);
+        put_level(frame[1], fetch_ops(s, level_start(s, 1), tid), tid);
+        if (tid == 0) {
+            fcount[0] = level_start(s, 1) - level_start(s, 0);
+            fcount[1] = level_start(s, 2) - level_start(s, 1);
+        }
+        uint32_t p2 = level_start(s, 2), p3 = level_start(s, 3);
+        HeldOps hA = fetch_ops(s, p2, tid);
+        uint32_t p4 = level_start(s, 4);
+        HeldOps hB = fetch_ops(s, p3, tid);
+        // at level l: h holds the ops of level l + 2, p2..p4 the starts of
+        // levels l + 2 .. l + 4
+        auto feed = [&](uint32_t l, HeldOps &h) {
+            __syncthreads();
+            const uint32_t nf = (l + 2) % kFwdFrames;
+            put_level(frame[nf], h, tid);
+            if (tid == 0) fcount[nf] = p3 - p2;
+            const uint32_t q = p4;
+            p2 = p3;
+            p3 = q;
+            p4 = level_start(s, l + 5);
+            h = fetch_ops(s, q, tid);
+        };
+        for (uint32_t l = 0; l < L; l += 2) {
+            feed(l, hA);
+            if (l + 1 >= L) break;
+            feed(l + 1, hB);
+        }
+        return;
+    }
+    const uint32_t lig = ctid % SW;
+    ColdVals<UC> cA, cB;
+    // runs level l with cur holding its cold values, after issuing level
+    // l + 1's into nxt
+    auto period = [&](uint32_t l, ColdVals<UC> &cur, ColdVals<UC> &nxt) {
+        __syncthreads();
+        if (l == 0) fwd_issue<SW, UC>(A, frame[0], fcount[0], cur);
+        if (l + 1 < L) {
+            const uint32_t nf = (l + 1) % kFwdFrames;
+            fwd_issue<SW, UC>(A, frame[nf], fcount[nf], nxt);
+        }
+        const uint32_t cf = l % kFwdFrames;
+        fwd_apply<SW, UC>(A, frame[cf], fcount[cf], cur, results + (size_t)((l + 1) & 1u) * kFrameWords,
+                          results + (size_t)(l & 1u) * kFrameWords, lig);
+    };
+    for (uint32_t l = 0; l < L; l += 2) {
+        period(l, cA, cB);
+        if (l + 1 >= L) break;
+        period(l + 1, cB, cA);
+    }
+    count_add(traffic, A.loaded);
+    count_add(traffic + 1, A.stored);
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -754,6 +907,39 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
         case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
         case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
         case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int SW, int UC>
+hipError_t rowor_fwd_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
+                             uint64_t *scratch, unsigned long long *traffic, hipStream_t st) {
+    const uint32_t nwords = (n + 63) / 64;
+    const uint32_t slices = (nwords + SW - 1) / SW;
+    const size_t lds = sizeof(uint64_t) * 2 * (kFwdLevelCap + 1) * SW;
+    auto k = k_rowor_fwd<SW, UC>;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, nwords, s, scratch, traffic);
+    return hipGetLastError();
+}
+
+bool rowor_fwd_supported(uint32_t n, uint32_t slice_words) {
+    return slice_words <= 8 && n < (1u << 30);
+}
+
+hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
+                            uint32_t slice_words, uint64_t *scratch,
+                            unsigned long long *traffic, hipStream_t st) {
+    if (s.L == 0) return hipSuccess;
+    if (!rowor_fwd_supported(n, slice_words)) return hipErrorInvalidValue;
+    switch (slice_words) {
+        // UC: ops per lane group, so that (896 / SW) * UC >= kFwdLevelCap
+        case 1: return rowor_fwd_variant<1, 1>(s, n, C, ld, scratch, traffic, st);
+        case 2: return rowor_fwd_variant<2, 2>(s, n, C, ld, scratch, traffic, st);
+        case 4: return rowor_fwd_variant<4, 4>(s, n, C, ld, scratch, traffic, st);
+        case 8: return rowor_fwd_variant<8, 7>(s, n, C, ld, scratch, traffic, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -618,3 +618,69 @@ DevSchedule schedule_view(const HostSchedule &s, const void *dev_base) {
 }
 
 }  // namespace tn
+
+namespace tn {
+
+// The forwarded form of an op schedule (see tn_internal.h).  Levels wider
+// than kFwdLevelCap are cut into consecutive parts of near-equal size (the
+// ops of a level are independent, so any split keeps the result).  A forward
+// pass then rewrites every operand last written by the level just before
+// as that writer's index in it (kFwdHot); a backward pass flags every
+// destination whose row the next level overwrites (kFwdNoStore): that
+// level reads the row, if at all, from the forwarded copy, so memory never
+// needs the value.  Rows are keyed n + id for scratch rows.
+void fwd_schedule(const std::vector<uint32_t> &lvl_op, const std::vector<uint32_t> &ops,
+                  uint32_t n, uint32_t scratch_rows, std::vector<uint32_t> &flvl,
+                  std::vector<uint32_t> &fops) {
+    const uint32_t Lops = lvl_op.empty() ? 0 : (uint32_t)lvl_op.size() - 1;
+    flvl.clear();
+    flvl.push_back(0);
+    for (uint32_t l = 0; l < Lops; ++l) {
+        const uint32_t a = lvl_op[l], b = lvl_op[l + 1], k = b - a;
+        const uint32_t parts = (k + kFwdLevelCap - 1) / kFwdLevelCap;
+        for (uint32_t p = 1; p <= parts; ++p) flvl.push_back(a + (uint32_t)((uint64_t)k * p / parts));
+    }
+    const uint32_t L = (uint32_t)flvl.size() - 1;
+    fops.assign(ops.begin(), ops.end());
+    const size_t keys = (size_t)n + scratch_rows + 1;
+    auto key = [n](uint32_t id) -> size_t {
+        return (id & kScratchBit) ? (size_t)n + (id & kNodeMask) : (size_t)id;
+    };
+    // forward: the level and index of each row's last write
+    std::vector<uint32_t> wl(keys, 0xffffffffu), wj(keys, 0);
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t q0 = flvl[l], q1 = flvl[l + 1];
+        for (uint32_t q = q0; q < q1; ++q) {
+            uint32_t *o = &fops[4 * (size_t)q];
+            for (int i = 0; i < 2; ++i) {
+                const size_t k = key(ops[4 * (size_t)q + i]);
+                if (l > 0 && wl[k] == l - 1) o[i] = kFwdHot | wj[k];
+            }
+        }
+        for (uint32_t q = q0; q < q1; ++q)
+            for (int i = 2; i < 4; ++i) {
+                const uint32_t d = ops[4 * (size_t)q + i];
+                if (d == kNoRow) continue;
+                wl[key(d)] = l;
+                wj[key(d)] = q - q0;
+            }
+    }
+    // backward: the level of each row's next write
+    std::fill(wl.begin(), wl.end(), 0xffffffffu);
+    for (uint32_t l = L; l-- > 0;) {
+        const uint32_t q0 = flvl[l], q1 = flvl[l + 1];
+        for (uint32_t q = q0; q < q1; ++q)
+            for (int i = 2; i < 4; ++i) {
+                const uint32_t d = ops[4 * (size_t)q + i];
+                if (d == kNoRow) continue;
+                if (wl[key(d)] == l + 1) fops[4 * (size_t)q + i] = d | kFwdNoStore;
+            }
+        for (uint32_t q = q0; q < q1; ++q)
+            for (int i = 2; i < 4; ++i) {
+                const uint32_t d = ops[4 * (size_t)q + i];
+                if (d != kNoRow) wl[key(d)] = l;
+            }
+    }
+}
+
+}  // namespace tn

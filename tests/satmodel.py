@@ -81,3 +81,18 @@ def replay(n, sch, slice_words, saturation=True, zero=True):
             upd = alive & zon
             zflag[np.ix_(d, upd)] = zz[:, upd]
     return R[:n, :nw], loads, stores
+
+
+FWD = 0x40000000
+
+
+def fwd_traffic(n, sch):
+    """Row words the plain kernel loads and stores on the forwarded schedule:
+    operands without the forwarding bit are loaded, destinations without the
+    no-store bit are stored, each over every word of the row."""
+    nw = oracle.words(n)
+    fo = sch["fwd_ops"].astype(np.int64)
+    cold = int(((fo[:, :2] & FWD) == 0).sum())
+    dst = fo[:, 2:]
+    stored = int(((dst != NOROW) & ((dst & FWD) == 0)).sum())  # FWD is the no-store bit here
+    return cold * nw, stored * nw

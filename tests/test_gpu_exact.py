@@ -6,15 +6,11 @@ import torch
 
 import oracle
 import tn_inputs as T
+from gpu_util import host
 
 pytestmark = pytest.mark.gpu
 
 tn = pytest.importorskip("paper_2307_04890_amd")
-
-
-def host(C):
-    torch.cuda.synchronize()
-    return C.cpu().numpy().view(np.uint64)
 
 
 def gpu_matrix(n, s, d, t, flags=0, ld=None, slice_words=0):
@@ -146,7 +142,11 @@ def test_saturation_counts_match_host_model(flags):
                 for sw in (1, 4, 8, 64):
                     C = p.execute(slice_words=sw)
                     assert (host(C) == want).all(), (case, sat, sw)
-                    _, ld, st = satmodel.replay(n, sch, sw, saturation=sat)
+                    if not sat and sw <= 8:
+                        # the plain recurrence on the forwarded schedule
+                        ld, st = satmodel.fwd_traffic(n, sch)
+                    else:
+                        _, ld, st = satmodel.replay(n, sch, sw, saturation=sat)
                     assert ctx.last_traffic() == (ld, st), (case, sat, sw)
             p.close()
     finally:
@@ -209,9 +209,13 @@ def test_full_size_saturation_off_gives_same_matrix(c2):
     finally:
         ctx.saturation(True)
     assert torch.equal(C, c2["C"]) and torch.equal(C0, c2["C"])
-    st = c2["plan"].stats
+    # the plain recurrence runs on the forwarded schedule: about half the
+    # operands come from the level before through LDS
+    import satmodel
+    sch = tn.host_schedule(100_000, c2["s"], c2["d"], c2["t"])
+    assert (ld_off, st_off) == satmodel.fwd_traffic(100_000, sch)
     nw = oracle.words(100_000)
-    assert ld_off == 2 * st["ops"] * nw
+    assert ld_off < 2 * c2["plan"].stats["ops"] * nw
     assert ld_on < ld_off and st_on < st_off
 
 

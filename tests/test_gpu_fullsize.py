@@ -10,17 +10,13 @@ import torch
 
 import oracle
 import tn_inputs as T
+from gpu_util import host
 
 pytestmark = pytest.mark.gpu
 
 tn = pytest.importorskip("paper_2307_04890_amd")
 
 N = 100_000
-
-
-def host(C):
-    torch.cuda.synchronize()
-    return C.cpu().numpy().view(np.uint64)
 
 
 @pytest.fixture(scope="module")

@@ -7,15 +7,11 @@ import torch
 
 import oracle
 import tn_inputs as T
+from gpu_util import host
 
 pytestmark = pytest.mark.gpu
 
 tn = pytest.importorskip("paper_2307_04890_amd")
-
-
-def host(C):
-    torch.cuda.synchronize()
-    return C.cpu().numpy().view(np.uint64)
 
 
 def run_hashed(n, s, d, t, H, K, seed, flags=0):
@@ -161,9 +157,8 @@ def test_streamed_proxies_on_both_sides_of_the_wavefront_limit(flags):
                 _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, flags=flags,
                                                     chunk_events=7000, P=P)
                 got = host(P)
-                assert (got[:, :, :oracle.words(K)] == WP).all(), (K, sat)
-                if ld > oracle.words(K):
-                    assert (got[:, :, -1] == 0).all(), (K, sat)  # P is written entirely
+                # host() also checks that the padding word is written as 0
+                assert (got == WP).all(), (K, sat)
                 assert st["chunks"] > 1 and st["slice_words"] >= 1
     finally:
         ctx.saturation(True)
@@ -255,6 +250,6 @@ def test_streamed_small_proxies_with_a_time_step_over_every_bucket(flags):
     sch = tn.host_schedule(K, wb[0][s], wb[0][d], t, flags)
     assert 1024 < sch["stats"]["scratch_rows"] <= K - 1
     WP = oracle.proxies(K, s, d, t, wb, directed=bool(flags & 1))
-    _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, flags=flags, chunk_events=5000)
+    _, _, P, st = tn.hash_build_proxies(n, s, d, t, A, K, flags=flags, chunk_events=1500)
     assert (host(P) == WP).all()
     assert st["chunks"] > 2

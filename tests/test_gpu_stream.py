@@ -8,15 +8,11 @@ import torch
 
 import oracle
 import tn_inputs as T
+from gpu_util import host
 
 pytestmark = pytest.mark.gpu
 
 tn = pytest.importorskip("paper_2307_04890_amd")
-
-
-def host(C):
-    torch.cuda.synchronize()
-    return C.cpu().numpy().view(np.uint64)
 
 
 def flag_kw(flags):

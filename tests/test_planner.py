@@ -70,6 +70,44 @@ def simulate_ops(n, sch):
     return C
 
 
+FWD = 0x40000000
+
+
+def simulate_fwd(n, sch):
+    """Apply the forwarded op form level by level as the plain kernel does:
+    an operand with the forwarding bit is the result of that op of the level
+    before (kept aside, never read from the matrix); any other operand is
+    read from the matrix, which holds only the values actually stored; a
+    destination with the bit is not stored."""
+    nw = oracle.words(n)
+    C = oracle.from_dense(np.eye(n, dtype=bool)) if n else np.zeros((0, nw), np.uint64)
+    S = np.zeros((sch["stats"]["scratch_rows"] + 1, nw), dtype=np.uint64)
+    lv, ops = sch["fwd_lvl"], sch["fwd_ops"].astype(np.int64)
+    prev = np.zeros((0, nw), dtype=np.uint64)
+
+    def row(i):
+        return S[i & 0x7FFFFFFF] if i & SCR else C[i]
+
+    for l in range(len(lv) - 1):
+        O = ops[lv[l]:lv[l + 1]]
+        assert O.shape[0] <= 768
+        cur = np.empty((O.shape[0], nw), dtype=np.uint64)
+        for j, (a, b, d1, d2) in enumerate(O):
+            x = prev[a & 0x3FF] if (a & FWD) else row(a)
+            y = prev[b & 0x3FF] if (b & FWD) else row(b)
+            cur[j] = x | y
+        for j, (a, b, d1, d2) in enumerate(O):
+            for dd in (d1, d2):
+                if dd == NOROW or (dd & FWD):
+                    continue
+                if dd & SCR:
+                    S[dd & 0x7FFFFFFF] = cur[j]
+                else:
+                    C[dd] = cur[j]
+        prev = cur
+    return C
+
+
 def check_ops_independent(sch):
     lv, ops = sch["lvl_op"], sch["ops"].astype(np.int64)
     for l in range(sch["stats"]["op_levels"]):
@@ -235,6 +273,42 @@ def test_compound_over_every_node_needs_fewer_scratch_rows_than_nodes(flags):
     assert 1024 < sch["stats"]["scratch_rows"] <= K - 1
     want = oracle.reverse_matrix(K, s_, d_, t_, directed=bool(flags & tn.DIRECTED))
     assert (simulate_ops(K, sch) == want).all()
+
+
+@pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.TIES_SEQUENTIAL, tn.FORWARD])
+def test_forwarded_schedule_replay_matches_oracle(flags):
+    # the plain kernel's form: results of the level before come from LDS, and
+    # rows the next level overwrites are never stored; replayed with the
+    # matrix holding only stored values, it must still give the oracle's
+    # matrix (a wrongly skipped store or a stale read would show)
+    cases = [T.random_tiny(150, 900, 30, seed=61), T.activity_driven(400, 6000, 300, seed=62),
+             T.star_steps(300, 400, 12, seed=63), T.uniform_pairs(2000, 40000, 400, seed=66)]
+    for k, (s_, d_, t_) in enumerate(cases):
+        n = (150, 400, 300, 2000)[k]
+        sch = tn.host_schedule(n, s_, d_, t_, flags)
+        ref = oracle.forward_matrix if flags & tn.FORWARD else oracle.reverse_matrix
+        want = ref(n, s_, d_, t_, directed=bool(flags & tn.DIRECTED),
+                   sequential=bool(flags & tn.TIES_SEQUENTIAL))
+        assert (simulate_fwd(n, sch) == want).all(), k
+        fo = sch["fwd_ops"].astype(np.int64)
+        assert (fo[:, :2] & FWD).any() and ((fo[:, 2:] != NOROW) & (fo[:, 2:] & FWD != 0)).any()
+
+
+def test_forwarded_schedule_splits_wide_levels():
+    # one time step of 3000 events: levels of up to 1024 ops become parts of
+    # at most 768, and the replay still matches
+    g = T.rng(64)
+    n, m = 2000, 3000
+    s_ = g.integers(0, n, m).astype(np.uint32)
+    d_ = ((s_.astype(np.int64) + 1 + g.integers(0, n - 1, m)) % n).astype(np.uint32)
+    s2, d2, t2 = T.uniform_pairs(n, 20000, 5, seed=65)
+    s_, d_ = np.concatenate([s_, s2]), np.concatenate([d_, d2])
+    t_ = np.concatenate([np.zeros(m, dtype=np.int64), t2 + 1])
+    sch = tn.host_schedule(n, s_, d_, t_)
+    widths = np.diff(sch["fwd_lvl"])
+    assert widths.max() <= 768 and np.diff(sch["lvl_op"]).max() > 768
+    assert len(widths) > sch["stats"]["op_levels"]
+    assert (simulate_fwd(n, sch) == oracle.reverse_matrix(n, s_, d_, t_)).all()
 
 
 @pytest.mark.parametrize("sw", [1, 2, 8])
