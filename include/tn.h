@@ -488,6 +488,21 @@ tn_status tn_mlp_train_step(tn_ctx *ctx, float *params, float *adam_m,
                             const float *y, const int32_t *idx, int64_t N,
                             float lr, float *loss, float *grad);
 
+/* tn_mlp_train_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same step, bit for bit, with its partial gradients in a
+ * static device array of the library instead of the context's scratch.  The
+ * call allocates nothing.  N must be <= 16384 (TN_E_UNSUPPORTED otherwise;
+ * nothing is enqueued); the array takes 5.4 MB on each GPU the library runs
+ * on, held until the process ends, and is bound at tn_create.  Every call on
+ * a GPU shares that GPU's array, so calls that overlap on one GPU (several
+ * streams or threads) race; calls in stream order do not.  Arguments,
+ * ownership and the other errors as tn_mlp_train_step. */
+tn_status tn_mlp_train_step_noalloc(tn_ctx *ctx, float *params, float *adam_m,
+                                    float *adam_v, int64_t step, const float *x,
+                                    const float *y, const int32_t *idx, int64_t N,
+                                    float lr, float *loss, float *grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -118,6 +118,7 @@ SIGNATURES = {
     "tn_mlp_forward": (_i32, [_P, _P, _P, _i64, _P]),
     "tn_mlp_predict": (_i32, [_P, _P, _P, _i64, _u32, _P, _P]),
     "tn_mlp_train_step": (_i32, [_P, _P, _P, _P, _i64, _P, _P, _P, _i64, _f32, _P, _P]),
+    "tn_mlp_train_step_noalloc": (_i32, [_P, _P, _P, _P, _i64, _P, _P, _P, _i64, _f32, _P, _P]),
 }
 
 

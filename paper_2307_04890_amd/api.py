@@ -12,7 +12,7 @@ from ._lib import (DIRECTED, FORWARD, KERNELS, TIES_SEQUENTIAL, PlanStats, Strea
                    check, lib)
 
 __all__ = ["Context", "Plan", "Online", "FORWARD", "hll_build", "build_component_matrix_streamed",
-           "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_init", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
+           "hash_build_proxies", "Batch", "hash_compress", "recombine", "MLP_PARAMS", "mlp_init", "mlp_features", "mlp_forward", "mlp_predict", "mlp_train_step", "mlp_train_step_noalloc", "build_component_matrix_batched", "host_schedule", "DIRECTED", "TIES_SEQUENTIAL", "TNError", "words",
            "build_component_matrix", "component_sizes", "get_context"]
 
 
@@ -509,6 +509,19 @@ def mlp_train_step(params, adam_m, adam_v, step: int, x, y, idx=None, lr: float 
     check(lib.tn_mlp_train_step(ctx.bind_stream(), _dp(params), _dp(adam_m), _dp(adam_v),
                                 int(step), _dp(x), _dp(y), _dp(idx), N, float(lr), _dp(loss),
                                 _dp(grad)))
+    return loss, grad
+
+
+def mlp_train_step_noalloc(params, adam_m, adam_v, step: int, x, y, idx=None, lr: float = 1e-3,
+                           loss=None, grad=None, ctx: Context | None = None):
+    """tn_mlp_train_step_noalloc: the same Adam step with no device allocation
+    inside the call (at most 16384 samples); loss and grad, if given, are
+    caller-owned outputs.  Returns (loss, grad)."""
+    ctx = ctx or get_context()
+    N = x.shape[0] if idx is None else idx.shape[0]
+    check(lib.tn_mlp_train_step_noalloc(ctx.bind_stream(), _dp(params), _dp(adam_m), _dp(adam_v),
+                                        int(step), _dp(x), _dp(y), _dp(idx), N, float(lr),
+                                        _dp(loss), _dp(grad)))
     return loss, grad
 
 

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "tn_internal.h"
+#include "tn_mlp.h"
 #include "tn_wave.h"
 
 namespace {
@@ -90,6 +91,12 @@ tn_status tn_create(int device, void *stream, tn_ctx **out) {
         if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) !=
             hipSuccess)
             c->num_cus = 256;
+        // the static scratch of tn_mlp_train_step_noalloc on this device
+        e = g.ok ? tn::mlp_noalloc_bind(device) : hipErrorInvalidDevice;
+    }
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "binding the static training scratch");
     }
     *out = c;
     return TN_OK;

@@ -17,6 +17,9 @@ hipError_t launch_mlp_backward(const float *params, const float *x, const float 
 hipError_t launch_mlp_adam(const float *partial, int nblk, float *params, float *m, float *v,
                            float lr, float c1, float c2, const float *loss_partial, float *loss,
                            float *grad, hipStream_t st);
+// Binds the static training scratch of tn_mlp_train_step_noalloc on the
+// current device (hipGetSymbolAddress, once per device; tn_create calls it).
+hipError_t mlp_noalloc_bind(int device);
 hipError_t launch_mlp_init(uint64_t seed, float *params, hipStream_t st);
 hipError_t launch_mlp_features(uint32_t n, uint32_t H, const int32_t *lifted, float *x,
                                hipStream_t st);

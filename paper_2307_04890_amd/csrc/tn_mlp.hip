@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "tn_mlp.h"
 
@@ -278,3 +279,77 @@ hipError_t launch_mlp_features(uint32_t n, uint32_t H, const int32_t *lifted, fl
 }
 
 }  // namespace tn
+
+// ---- training step without allocation --------------------------------------
+//
+// The partial gradients and losses of one training step live in a file-scope
+// device array instead of the context's scratch, so that callers that cannot
+// allocate (code under HIP graph capture, serving loops) can train.  Each GPU
+// holds its own copy until the process ends.  In host code the array's name
+// is only a stand-in for the symbol: its device address is looked up once
+// per device (hipGetSymbolAddress, from tn_create) and only that address is
+// passed to kernels.  Every partial the Adam kernel reads is written first by
+// the backward kernel of the same call, so nothing needs clearing; calls that
+// overlap on one GPU share the array and race.
+namespace {
+constexpr int64_t kNoAllocMaxSamples = 16384;
+constexpr int kNoAllocBlocks = (int)(kNoAllocMaxSamples / 64);
+static __device__ __align__(256) float scratch[(size_t)kNoAllocBlocks * (5313 + 1)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+namespace tn {
+// Looks up the array's address on the current device (once per device).
+hipError_t mlp_noalloc_bind(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    float *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+}  // namespace tn
+
+extern "C" tn_status tn_mlp_train_step_noalloc(tn_ctx *ctx, float *params, float *adam_m,
+                                               float *adam_v, int64_t step, const float *x,
+                                               const float *y, const int32_t *idx, int64_t N,
+                                               float lr, float *loss, float *grad) {
+    using namespace tn;
+    if (!ctx || !params || !adam_m || !adam_v || !x || !y) return fail(TN_E_ARG, "null argument");
+    if (N <= 0) return fail(TN_E_ARG, "N must be > 0");
+    if (N > kNoAllocMaxSamples)
+        return fail(TN_E_UNSUPPORTED, "tn_mlp_train_step_noalloc takes at most 16384 samples per step");
+    if (step < 1) return fail(TN_E_ARG, "step is 1-based");
+    if (!(lr > 0.f)) return fail(TN_E_ARG, "lr must be > 0");
+    if (ctx->device < 0 || ctx->device >= kMaxDevices) return fail(TN_E_ARG, "device out of range");
+    float *partial;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        partial = g_scratch_ptr[ctx->device];
+    }
+    if (!partial) return fail(TN_E_HIP, "the static training scratch of this device is not bound");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    const int nblk = mlp_backward_blocks(N);
+    static_assert(kParams == 5313, "array size");
+    float *loss_partial = partial + (size_t)nblk * kParams;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)step)));
+    hipError_t e;
+    {
+        ProfScope ps(ctx, TN_K_MLP_BACKWARD);
+        e = launch_mlp_backward(params, x, y, idx, N, partial, loss_partial, ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "backward kernel launch");
+    {
+        ProfScope ps(ctx, TN_K_MLP_ADAM);
+        e = launch_mlp_adam(partial, nblk, params, adam_m, adam_v, lr, c1, c2, loss_partial, loss,
+                            grad, ctx->stream);
+    }
+    return e == hipSuccess ? TN_OK : hip_fail(e, "Adam kernel launch");
+}
+
