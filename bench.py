@@ -6,7 +6,11 @@ resident schedule of one network: C <- I, every level of reverse-time row
 ORs, then the out- and in-component sizes.  The workload is the
 activity-driven network with n = 100,000 nodes and m = 10,000,000 events
 (T = 10^6 ticks).  Events, schedule and matrix are in HBM when the timed
-region starts; host planning time is reported separately.
+region starts; host planning time is reported separately.  Beside the step:
+the plain recurrence on the same plan (saturation off; its launch gives the
+roofline), and the hashed block: the n = 10^6, m = 10^8 stream with H = 16
+end to end at K = 4096, all proxies at K = 65,536 in one launch, and fusion
+timed where it intersects (--no-hashed skips it).
 
 Other modes (each prints its own single JSON line):
   --mode hashed    n = 10^6, m = 10^8 activity-driven, H = 16 hashes to
@@ -27,6 +31,8 @@ Other modes (each prints its own single JSON line):
                    Poisson process per link, n from 100 to 10^4 and m from
                    10^4 to 10^7, exact against hashed (H = 5, n_s = 0.3 n):
                    Earth-Mover distance, relative time and memory.
+  --mode fusion    fusion alone, on 2*10^5 nodes whose proxy rows are mostly
+                   not full (the hashed block's fusion timing).
   --mode online    forward time with online insertion: the n = 10^5,
                    m = 10^7 events in time order, in batches, into a live
                    matrix of in-components, against the resident forward
@@ -67,6 +73,7 @@ def kernel_source_hash(files) -> str:
 
 
 KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h", "tn_device.h"),
+                  "rowor_plain": ("tn_kernels.hip", "tn_internal.h", "tn_device.h", "tn_plan.cpp"),
                   "batch": ("tn_batch.hip", "tn_batch.h", "tn_batch.cpp", "tn_internal.h"),
                   "recombine": ("tn_hash.hip", "tn_hash.h")}
 
@@ -198,27 +205,66 @@ def run_exact(args):
     elapsed, kms, _ = timed(ctx, step, args.steps, args.warmup)
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
     alg = algorithmic_bytes(st, n)
-    achieved = alg / (kms["rowor"] * 1e-3) / 1e9
-    # what the kernel actually had to move: its own counters of row words
-    # loaded and stored (saturated rows skipped), plus the schedule once
+    # what the saturating kernel actually had to move: its own counters of
+    # row words loaded and stored (saturated rows skipped), plus the schedule
     ld_w, st_w = ctx.last_traffic()
     moved = 8.0 * (ld_w + st_w) + 16.0 * st["ops"] + 4.0 * (st["op_levels"] + 1)
-    moved_gbs = moved / (kms["rowor"] * 1e-3) / 1e9
     o, i = out.cpu().numpy(), inn.cpu().numpy()
     assert o.sum() == i.sum(), "sum of out-sizes differs from sum of in-sizes"
+    # the plain leg: the same plan with saturation off, so that every op moves
+    # its rows (the forwarded kernel); its launches give the roofline
+    ctx.saturation(False)
+    try:
+        p_elapsed, pkms, pper = timed(ctx, lambda: plan.execute(C, slice_words=args.slice_words),
+                                      max(2, args.steps // 2), 1)
+        pld, pst = ctx.last_traffic()
+    finally:
+        ctx.saturation(True)
+    # (the tests compare whole matrices; here the sizes of both legs)
+    tn._lib.check(tn.lib.tn_component_sizes(ctx.bind_stream(), n, cp(C), C.stride(0), cp(out),
+                                            cp(inn)))
+    assert np.array_equal(out.cpu().numpy(), o) and np.array_equal(inn.cpu().numpy(), i), \
+        "plain recurrence differs from the saturating kernel"
+    plain_ms = pkms["rowor"]
+    achieved = alg / (plain_ms * 1e-3) / 1e9
+    plain_traffic = load_traffic("rowor_plain", workload)
+    sat_ms = kms["rowor"]
+    sat_traffic = load_traffic("rowor", workload)
     config = {"workload": workload, "n": n, "m": m, "T": spec["T"], "generator": spec["kind"],
-              "seed": spec["seed"], "flags": "undirected,strict-ties",
+              "seed": spec["seed"], "flags": "undirected,strict-ties", "ld_words": C.stride(0),
               "slice_words": args.slice_words or "auto", "parallelism": "single-gpu"}
     r = base_result(args, m * args.steps / elapsed, "events/s", args.steps,
                     1e3 * elapsed / args.steps, config)
+    r["value_note"] = ("one step = identity + the saturating row-OR kernel (rows that are all "
+                       "ones in a column slice are not moved again; the matrix is bit-identical "
+                       "to the plain recurrence) + out- and in-sizes")
     r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("rowor", workload),
-                     "kernel": "k_rowor_global (zero-phase launch + the remaining levels)",
-                     "algorithmic_bytes": alg,
-                     "avg_launch_ms": kms["rowor"], "moved_bytes": moved,
-                     "moved_achieved": moved_gbs, "moved_frac": moved_gbs / HBM_PEAK_GBS,
-                     "levels": st["op_levels"],
-                     "us_per_level": 1e3 * kms["rowor"] / max(1, st["op_levels"])}
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": plain_traffic,
+                     "kernel": "k_rowor_fwd (the plain recurrence, saturation off: every op "
+                               "applied, each level's results forwarded through LDS)",
+                     "algorithmic_bytes": alg, "avg_launch_ms": plain_ms,
+                     "traffic_frac": (plain_traffic / (plain_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if plain_traffic else None),
+                     "row_bytes_moved": 8.0 * (pld + pst),
+                     "note": "algorithmic bytes = 4 row transfers per undirected pair (the "
+                             "plain recurrence) + the schedule once, over the mean launch time; "
+                             "traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch"}
+    r["plain"] = {"events_per_s": m / (plain_ms * 1e-3), "avg_launch_ms": plain_ms,
+                  "launch_ms_all": pper.get("rowor", []),
+                  "row_words_loaded": pld, "row_words_stored": pst}
+    r["saturating"] = {"kernel": "k_rowor_global (zero-phase launch + the remaining levels)",
+                       "avg_launch_ms": sat_ms, "moved_bytes": moved,
+                       "moved_achieved": moved / (sat_ms * 1e-3) / 1e9,
+                       "moved_frac": moved / (sat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "traffic": sat_traffic,
+                       "traffic_frac": (sat_traffic / (sat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                        if sat_traffic else None),
+                       "dense_equivalent_frac": alg / (sat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "dense_equivalent_note": "the plain recurrence's bytes over the "
+                                                "saturating launch: not a bandwidth (saturated "
+                                                "rows are skipped), so it exceeds 1",
+                       "levels": st["op_levels"],
+                       "us_per_level": 1e3 * sat_ms / max(1, st["op_levels"])}
     r["kernels_ms"] = kms
     r["plan"] = {"levels": st["levels"], "op_levels": st["op_levels"], "ops": st["ops"],
                  "pairs": st["pairs"], "gathers": st["gathers"],
@@ -244,6 +290,10 @@ def run_exact(args):
                        "what": "host events -> streamed build (host planning overlapped with "
                                "the device, stop once every slice is full) -> sizes",
                        "stream": sst}
+    del C, C2
+    torch.cuda.empty_cache()
+    if not args.no_hashed:
+        r["hashed"] = hashed_block(args)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
         r["cpu_baseline"] = cpu_baseline_exact(n, s, d, t, args.cpu_budget)
@@ -443,6 +493,144 @@ def run_hashed(args):
                                        f"{dt:.2f} s single-threaded, scaled by {nwk * H}",
                              "seconds": dt, "host_nproc": os.cpu_count()}
     proxies.close()
+    return r
+
+
+# ---------------------------------------------------------------------------
+FUSION_WORKLOAD = "fusion_activity_n200000_m40000_K4096"
+
+
+def fusion_timing(args):
+    """Fusion (Sec. 4.2) timed where it intersects: 2*10^5 nodes, 4*10^4
+    activity-driven events, H = 16 hashes to K = 4096 super-nodes, so that
+    proxy rows are mostly not full and every estimate is below n.  The
+    AND/popcount kernel reads one word per (node, chunk of 64 nodes, hash)
+    from the lifted tables it stages in LDS: its algorithmic bytes are
+    8 * nlist * ceil(n/64) * H for the nlist nodes whose rows are not full
+    in every hash."""
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+
+    n, m, Tm, H, K = 200_000, 40_000, 400_000, 16, 4096
+    s, d, t = T.activity_driven(n, m, Tm, seed=K + H)
+    A = T.hash_coefficients(H, seed=K + 1)
+    ctx = tn.get_context()
+    bucket, count, P, _ = tn.hash_build_proxies(n, s, d, t, A, K)
+    # nodes whose proxy rows are full in every hash skip the AND (est = n)
+    Ph = P.cpu().numpy().view(np.uint64)[:, :, :tn.words(K)]
+    full_rows = (Ph == np.uint64(0xFFFFFFFFFFFFFFFF)).all(axis=2)
+    bh = bucket.cpu().numpy().view(np.uint32)
+    node_full = full_rows[np.arange(H)[:, None], bh].all(axis=0)
+    nlist = int(n - node_full.sum())
+    nq = (n + 63) // 64
+    and_bytes = 8.0 * nlist * nq * H
+    elapsed, kms, per = timed(ctx, lambda: tn.recombine(P, bucket, count, n), 3, 1)
+    est, _ = tn.recombine(P, bucket, count, n)
+    e = est.cpu().numpy()
+    est_ms = float(np.sum(per.get("recombine", [0.0]))) / 3
+    aux_ms = float(np.sum(per.get("aux", [0.0]))) / 3
+    traffic = load_traffic("recombine", FUSION_WORKLOAD)
+    return {"workload": FUSION_WORKLOAD, "n": n, "m": m, "T": Tm, "H": H, "K": K,
+            "nodes_not_full": nlist, "estimates_below_n": float((e < n).mean()),
+            "mean_estimate": float(e.mean()),
+            "call_ms": 1e3 * elapsed / 3, "recombine_est_ms": est_ms, "other_kernels_ms": aux_ms,
+            "and_bytes": and_bytes, "bound": "lds",
+            "achieved_GBs": and_bytes / (est_ms * 1e-3) / 1e9,
+            "frac": and_bytes / (est_ms * 1e-3) / 1e9 / LDS_PEAK_GBS,
+            "traffic": traffic,
+            "traffic_frac": (traffic / (est_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None),
+            "note": "k_recombine_est: the AND words come from lifted tables staged in LDS "
+                    "(LDS peak 256 CU x 128 B/clk x 2.4 GHz); traffic = rocprofv3 FETCH_SIZE + "
+                    "WRITE_SIZE of its dispatches, against HBM"}
+
+
+def hashed_block(args):
+    """The hashed half of the metric (Sec. 4.3) in the default run: the
+    10^6-node, 10^8-event activity-driven stream hashed with H = 16, (a) end
+    to end from host events at K = 4096 (hash, streamed proxy build, fusion),
+    (b) all 16 proxies at K = 65,536 in one launch (8 GiB of proxies, HBM
+    bound), and (c) fusion timed where it intersects."""
+    import numpy as np
+    import torch
+
+    import paper_2307_04890_amd as tn
+    import tn_inputs as T
+
+    out = {}
+    wl = "activity_n1M_m100M"
+    spec = T.WORKLOADS[wl]
+    n, H = spec["n"], 16
+    log(f"[bench] generating {wl}")
+    t0 = time.perf_counter()
+    s, d, t = T.make_workload(wl, progress=lambda msg: log(f"[bench] {wl}: {msg}"))
+    out["generate_s"] = time.perf_counter() - t0
+    m = int(s.shape[0])
+    A = T.hash_coefficients(H, seed=1003)
+    ctx = tn.get_context()
+    K = 4096
+    P = torch.empty((H, K, tn.words(K)), dtype=torch.int64, device="cuda")
+    ee = []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bucket, count, P, sst = tn.hash_build_proxies(n, s, d, t, A, K, P=P)
+        est, _ = tn.recombine(P, bucket, count, n)
+        torch.cuda.synchronize()
+        ee.append(time.perf_counter() - t0)
+    out["end_to_end_K4096"] = {
+        "workload": wl, "n": n, "m": m, "H": H, "K": K, "hash_seed": 1003,
+        "events_per_s": m / min(ee), "seconds": min(ee), "seconds_all": ee,
+        "what": "host events -> hash -> streamed proxy build -> fusion", "stream": sst,
+        "mean_estimate": float(est.float().mean().item())}
+    del P, bucket, count, est
+    log("[bench] hashed: the K = 65536 proxies in one launch")
+    K = 65536
+    t0 = time.perf_counter()
+    bucket, count, proxies = tn.hash_compress(n, s, d, t, A, K)
+    torch.cuda.synchronize()
+    compress_s = time.perf_counter() - t0
+    stats, _, _ = proxies.stats()
+    P = torch.empty((H, K, tn.words(K)), dtype=torch.int64, device="cuda")
+    Ps = [P[j] for j in range(H)]
+    proxies.execute(Ps)  # tunes the tile shape, captures the graph
+    _, tiles, lds_tiles = proxies.stats()
+    elapsed, kms, per = timed(ctx, lambda: proxies.execute(Ps), 3, 0)
+    pms = kms["batch"]
+    dense = sum(algorithmic_bytes(x, K) for x in stats)
+    traffic = load_traffic("batch", f"{wl}_K{K}")
+    out["proxies_K65536"] = {
+        "workload": wl, "H": H, "K": K, "kernel": "k_batch_persistent (global-memory tiles)",
+        "events_per_s": m / (pms * 1e-3), "H_times_m_events_per_s": H * m / (pms * 1e-3),
+        "avg_launch_ms": pms, "launch_ms_all": per.get("batch", []), "traffic": traffic,
+        "traffic_frac": traffic / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+        "dense_equivalent_bytes": dense,
+        "dense_equivalent_frac": dense / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "dense_equivalent_note": "row transfers of the plain recurrence on the 16 proxy streams; "
+                                 "saturated rows are skipped, so not a bandwidth",
+        "tiles": tiles, "lds_tiles": lds_tiles, "host_hash_and_plan_s": compress_s}
+    proxies.close()
+    del P, Ps, bucket, count
+    torch.cuda.empty_cache()
+    log("[bench] hashed: fusion where it intersects")
+    out["fusion"] = fusion_timing(args)
+    return out
+
+
+def run_fusion(args):
+    """--mode fusion: the fusion timing alone (for profiles of its kernels)."""
+    f = fusion_timing(args)
+    config = {"workload": f["workload"], "n": f["n"], "m": f["m"], "T": f["T"], "H": f["H"],
+              "K": f["K"], "generator": "activity", "parallelism": "single-gpu"}
+    r = base_result(args, f["n"] / (f["call_ms"] * 1e-3), "nodes/s", 3, f["call_ms"], config)
+    r["value_note"] = "fusion estimates of every node per second (one tn_recombine call)"
+    r["roofline"] = {"bound": "lds", "achieved": f["achieved_GBs"], "peak": LDS_PEAK_GBS,
+                     "unit": "GB/s", "frac": f["frac"], "traffic": f["traffic"],
+                     "kernel": "k_recombine_est", "algorithmic_bytes": f["and_bytes"],
+                     "avg_launch_ms": f["recombine_est_ms"]}
+    r["fusion"] = f
     return r
 
 
@@ -823,8 +1011,8 @@ def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, la
     for the plain device copy of calib_mib MiB in the same run.  last > 0
     keeps only the kernel's last `last` dispatches (the timed ones, after
     autotuning); a launch is `per_launch` consecutive dispatches."""
-    match = match or {"rowor": "k_rowor_global", "batch": "k_batch_persistent",
-                      "recombine": "k_recombine_est"}[kernel]
+    match = match or {"rowor": "k_rowor_global", "rowor_plain": "k_rowor_fwd",
+                      "batch": "k_batch_persistent", "recombine": "k_recombine_est"}[kernel]
     out = {"kernel": match, "workload": workload, "command": command,
            "kernel_source_sha": kernel_source_hash(KERNEL_SOURCES[kernel])}
     known_kib = calib_mib * 1024.0
@@ -908,7 +1096,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="exact",
-                    choices=["exact", "hashed", "batched", "combiner", "sweep", "hll", "online"])
+                    choices=["exact", "hashed", "batched", "combiner", "sweep", "hll", "online",
+                             "fusion"])
     ap.add_argument("--online-batches", type=int, default=10,
                     help="event batches of the online mode")
     ap.add_argument("--hll-log2s", type=int, default=8,
@@ -920,6 +1109,8 @@ def main():
     ap.add_argument("--no-end-to-end", action="store_true",
                     help="exact and hashed modes: skip the streamed end-to-end runs (for "
                          "profiles of the resident launches alone)")
+    ap.add_argument("--no-hashed", action="store_true",
+                    help="exact mode: skip the hashed block (the 10^6-node stream)")
     ap.add_argument("--hashes", type=int, default=16)
     ap.add_argument("--buckets", type=int, default=4096)
     ap.add_argument("--networks", type=int, default=256)
@@ -940,7 +1131,7 @@ def main():
     torch.cuda.set_device(0)
     run = {"exact": run_exact, "hashed": run_hashed, "batched": run_batched,
            "combiner": run_combiner, "sweep": run_sweep, "hll": run_hll,
-           "online": run_online}[args.mode]
+           "online": run_online, "fusion": run_fusion}[args.mode]
     print(json.dumps(run(args)), flush=True)
 
 

@@ -215,21 +215,28 @@ k_split_full(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bu
 }
 
 // est[u] += sum over the chunks q of this launch of popcount(AND_j Lt[q][j][h_j(u)]).
-// A workgroup owns kUPT nodes u per thread and a range of chunks; with LDS,
+// A workgroup owns kUPT nodes u per thread (blockIdx.x) and one of the
+// launch's ranges of `per` chunks (blockIdx.y); the counts of the ranges add
+// up in est (integer atomics, so the order does not matter); with LDS,
 // the tables of G hashes of one chunk are staged in LDS at a time (K words
 // each), else (tables too large for LDS) they are read where they are, in
 // L2; the AND of a chunk is carried in registers across the hash groups.
 constexpr int kUPT = 8;
-constexpr int kQB = 4;
+constexpr int kQB = 2;
+constexpr uint32_t kRecombineThreads = 1024;
 template <bool LDS>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(kRecombineThreads)
 k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *__restrict__ bucket,
-                const uint64_t *__restrict__ Lt, uint32_t q_begin, uint32_t q_end, uint32_t q0,
-                const uint32_t *__restrict__ list, uint32_t nlist, int32_t *__restrict__ est) {
+                const uint64_t *__restrict__ Lt, uint32_t q_first, uint32_t q_last, uint32_t per,
+                uint32_t q0, const uint32_t *__restrict__ list, uint32_t nlist,
+                int32_t *__restrict__ est) {
     extern __shared__ uint64_t tab[];
     const uint32_t tid = threadIdx.x;
     const uint64_t ubase = (uint64_t)blockIdx.x * blockDim.x * kUPT;
-    if (ubase >= nlist) return;  // uniform: the whole workgroup leaves
+    const uint32_t q_begin = q_first + blockIdx.y * per;
+    const uint32_t q_end = min(q_last, q_begin + per);
+    // uniform: the whole workgroup leaves
+    if (ubase >= nlist || q_begin >= q_end) return;
     uint32_t u[kUPT];
     int32_t cnt[kUPT];
 #pragma unroll
@@ -382,23 +389,18 @@ hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const uint32_t threads = 512;
+    const uint32_t threads = kRecombineThreads;
     const uint32_t utiles = (uint32_t)((nlist + (size_t)threads * kUPT - 1) / ((size_t)threads * kUPT));
     if (utiles == 0) return hipSuccess;
-    // split the chunk range so that the launch has enough workgroups
+    // split the chunk range over the second grid dimension so that the
+    // launch has enough workgroups
     uint32_t splits = 1;
     while ((size_t)utiles * splits < 1024 && splits * kQB * 2 <= nq) splits *= 2;
     const uint32_t per = ((nq + splits - 1) / splits + kQB - 1) / kQB * kQB;
-    for (uint32_t s = 0; s < splits; ++s) {
-        const uint32_t qb = q0 + s * per;
-        const uint32_t qe = min(q0 + nq, qb + per);
-        if (qb >= qe) break;
-        hipLaunchKernelGGL(kern, dim3(utiles), dim3(threads), lds, st, n, H, K, G, bucket, Lt, qb,
-                           qe, q0, list, nlist, est);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    splits = (nq + per - 1) / per;
+    hipLaunchKernelGGL(kern, dim3(utiles, splits), dim3(threads), lds, st, n, H, K, G, bucket, Lt,
+                       q0, q0 + nq, per, q0, list, nlist, est);
+    return hipGetLastError();
 }
 
 }  // namespace tn

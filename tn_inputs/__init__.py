@@ -76,7 +76,7 @@ def activities(n: int, seed: int, gamma: float = 2.1, eps: float = 1e-3):
 
 
 def activity_driven(n: int, m: int, T: int, seed: int, gamma: float = 2.1,
-                    eps: float = 1e-3):
+                    eps: float = 1e-3, progress=None):
     """Activity-driven temporal network with ``m`` undirected events.
 
     Each node fires as an independent Poisson process of rate proportional to
@@ -101,6 +101,8 @@ def activity_driven(n: int, m: int, T: int, seed: int, gamma: float = 2.1,
         out_u[lo:hi] = u
         out_v[lo:hi] = v
         out_t[lo:hi] = g.integers(0, T, size=k, dtype=np.int64)
+        if progress:
+            progress(f"{hi} of {m} events drawn")
     return sort_events(out_u, out_v, out_t)
 
 
@@ -270,11 +272,11 @@ WORKLOADS = {
 }
 
 
-def make_workload(name: str, **override):
+def make_workload(name: str, progress=None, **override):
     w = dict(WORKLOADS[name])
     w.update(override)
     if w["kind"] == "uniform":
         return uniform_pairs(w["n"], w["m"], w["T"], w["seed"])
     if w["kind"] == "activity":
-        return activity_driven(w["n"], w["m"], w["T"], w["seed"])
+        return activity_driven(w["n"], w["m"], w["T"], w["seed"], progress=progress)
     raise ValueError(w["kind"])
