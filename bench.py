@@ -621,6 +621,8 @@ def hashed_block(args):
 
 def run_fusion(args):
     """--mode fusion: the fusion timing alone (for profiles of its kernels)."""
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib)
     f = fusion_timing(args)
     config = {"workload": f["workload"], "n": f["n"], "m": f["m"], "T": f["T"], "H": f["H"],
               "K": f["K"], "generator": "activity", "parallelism": "single-gpu"}
