@@ -3,6 +3,7 @@ tensors on a HIP device, the stream is torch's current stream.  Argument
 marshalling only; every step of the computation runs in the library."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 
 import numpy as np
@@ -94,6 +95,22 @@ class Context:
 
 
 _contexts: dict[int, Context] = {}
+
+
+def _close_contexts():
+    """Destroys every context at interpreter exit, first thing: atexit
+    handlers run before modules are torn down, while torch's streams and the
+    HIP runtime are still alive (a context's destruction waits for its
+    stream and frees its device scratch and pinned host staging)."""
+    for c in list(_contexts.values()):
+        try:
+            c.close()
+        except Exception:
+            pass
+    _contexts.clear()
+
+
+atexit.register(_close_contexts)
 
 
 def get_context(device: int | None = None) -> Context:

@@ -59,6 +59,7 @@ tn_status ensure_host_staging(tn_ctx *ctx, size_t bytes) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (ctx->host_staging) (void)hipHostFree(ctx->host_staging);
+    tn::ring_free(ctx);
     ctx->host_staging = nullptr;
     ctx->host_staging_bytes = 0;
     e = hipHostMalloc(&ctx->host_staging, bytes, 0);
@@ -122,6 +123,7 @@ void tn_destroy(tn_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->host_staging) (void)hipHostFree(ctx->host_staging);
+    tn::ring_free(ctx);
     if (ctx->traffic) (void)hipFree(ctx->traffic);
     for (auto &r : ctx->recs) {
         (void)hipEventDestroy(r.a);

@@ -414,16 +414,29 @@ tn_status batch_from_plans(tn_ctx *ctx, int32_t B, const uint32_t *n, uint32_t f
         delete b;
         return fail(TN_E_NOMEM, "batch schedule allocation failed");
     }
-    std::vector<unsigned char> img;
+    // the schedules go up array by array through the context's pinned ring
+    // (SDMA copies on its stream, overlapped with the host copies into the
+    // next slots); the alignment gaps between arrays are cleared first
+    std::vector<SchedPiece> pieces;
     b->stats.resize(B);
+    e = hipMemsetAsync(b->dev_sched, 0, total, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(b->dev_sched);
+        delete b;
+        return hip_fail(e, "batch schedule clear");
+    }
     for (int32_t i = 0; i < B; ++i) {
-        schedule_pack(hs[i], img);
-        e = hipMemcpy((unsigned char *)b->dev_sched + offs[i], img.data(), img.size(),
-                      hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
+        schedule_pieces(hs[i], pieces);
+        tn_status us = TN_OK;
+        for (const SchedPiece &pc : pieces) {
+            us = ring_upload(ctx, (unsigned char *)b->dev_sched + offs[i] + pc.off, pc.src, pc.bytes);
+            if (us != TN_OK) break;
+        }
+        if (us != TN_OK) {
+            (void)hipStreamSynchronize(ctx->stream);
             (void)hipFree(b->dev_sched);
             delete b;
-            return hip_fail(e, "batch schedule upload");
+            return us;
         }
         b->views.push_back(schedule_view(hs[i], (unsigned char *)b->dev_sched + offs[i]));
         fill_stats(hs[i], b->stats[i]);
@@ -568,3 +581,55 @@ tn_status tn_build_component_matrix_batched(tn_ctx *ctx, int32_t B, const uint32
 }
 
 }  // extern "C"
+
+namespace tn {
+
+tn_status ring_upload(tn_ctx *ctx, void *dst, const void *src, size_t bytes) {
+    constexpr size_t kSlot = (size_t)32 << 20;
+    hipError_t e;
+    if (!ctx->ring_buf[0]) {
+        for (int i = 0; i < tn_ctx::kRingSlots; ++i) {
+            e = hipHostMalloc(&ctx->ring_buf[i], kSlot, 0);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ring_ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) {
+                ring_free(ctx);
+                return fail(TN_E_NOMEM, "pinned upload ring allocation failed");
+            }
+        }
+    }
+    const unsigned char *p = (const unsigned char *)src;
+    unsigned char *d = (unsigned char *)dst;
+    while (bytes > 0) {
+        const int k = ctx->ring_next;
+        if (ctx->ring_busy[k]) {
+            e = hipEventSynchronize(ctx->ring_ev[k]);
+            if (e != hipSuccess) return hip_fail(e, "upload ring wait");
+            ctx->ring_busy[k] = false;
+        }
+        const size_t c = std::min(bytes, kSlot);
+        std::memcpy(ctx->ring_buf[k], p, c);
+        e = hipMemcpyAsync(d, ctx->ring_buf[k], c, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(ctx->ring_ev[k], ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "upload ring copy");
+        ctx->ring_busy[k] = true;
+        ctx->ring_next = (k + 1) % tn_ctx::kRingSlots;
+        p += c;
+        d += c;
+        bytes -= c;
+    }
+    return TN_OK;
+}
+
+// Frees the ring (the caller has waited for the context's stream).
+void ring_free(tn_ctx *ctx) {
+    for (int i = 0; i < tn_ctx::kRingSlots; ++i) {
+        if (ctx->ring_ev[i]) (void)hipEventDestroy(ctx->ring_ev[i]);
+        if (ctx->ring_buf[i]) (void)hipHostFree(ctx->ring_buf[i]);
+        ctx->ring_ev[i] = nullptr;
+        ctx->ring_buf[i] = nullptr;
+        ctx->ring_busy[i] = false;
+    }
+    ctx->ring_next = 0;
+}
+
+}  // namespace tn

@@ -148,6 +148,14 @@ struct tn_ctx {
     size_t host_staging_bytes = 0;
     // row words loaded / stored by the last tn_plan_execute (device)
     unsigned long long *traffic = nullptr;
+    // ring of pinned slots for host-to-device uploads (tn::ring_upload):
+    // each slot's copy is an SDMA transfer on the context's stream, and its
+    // event says when the slot may be refilled
+    static constexpr int kRingSlots = 4;
+    void *ring_buf[kRingSlots] = {};
+    hipEvent_t ring_ev[kRingSlots] = {};
+    bool ring_busy[kRingSlots] = {};
+    int ring_next = 0;
     bool saturation = true;
     int num_cus = 0;
     // kernel timing (tn_profile_enable)
@@ -217,6 +225,21 @@ struct ProfScope {
         if (idx != (size_t)-1) (void)hipEventRecord(c->recs[idx].b, c->stream);
     }
 };
+
+// Copies `bytes` from host memory to device memory through the context's
+// ring of pinned slots (allocated on first use, freed by tn_destroy):
+// asynchronous on the context's stream, and the source may be reused or
+// freed as soon as the call returns.
+tn_status ring_upload(tn_ctx *ctx, void *dst, const void *src, size_t bytes);
+void ring_free(tn_ctx *ctx);
+// The arrays of a schedule's device image (schedule_pack): offset in the
+// image, host data, bytes.
+struct SchedPiece {
+    size_t off;
+    const void *src;
+    size_t bytes;
+};
+void schedule_pieces(const HostSchedule &s, std::vector<SchedPiece> &out);
 
 // Grows the context scratch to at least `bytes`.
 tn_status ensure_scratch(tn_ctx *ctx, size_t bytes);

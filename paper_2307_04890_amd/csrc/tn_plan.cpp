@@ -565,6 +565,20 @@ Layout layout_of(const HostSchedule &s) {
 
 size_t schedule_device_bytes(const HostSchedule &s) { return layout_of(s).total; }
 
+void schedule_pieces(const HostSchedule &s, std::vector<SchedPiece> &out) {
+    const Layout o = layout_of(s);
+    out.clear();
+    auto put = [&](size_t off, const std::vector<uint32_t> &v) {
+        if (!v.empty()) out.push_back({off, v.data(), 4 * v.size()});
+    };
+    put(o.lvl_pair, s.lvl_pair);
+    put(o.lvl_gat, s.lvl_gat);
+    put(o.pairs, s.pairs);
+    put(o.gat_tgt, s.gat_tgt);
+    put(o.gat_ptr, s.gat_ptr);
+    put(o.gat_src, s.gat_src);
+}
+
 size_t ops_device_bytes(const HostSchedule &s) {
     return align256(4 * s.lvl_op.size()) + align256(4 * std::max<size_t>(s.ops.size(), 4));
 }
