@@ -327,7 +327,7 @@ tn_status tn_plan_get_stats(const tn_plan *plan, tn_plan_stats *out) {
 void tn_plan_destroy(tn_plan *plan) {
     if (!plan) return;
     DeviceGuard g(plan->device);
-    if (plan->hll_exec) (void)hipGraphExecDestroy(plan->hll_exec);
+    for (auto x : plan->hll_execs) (void)hipGraphExecDestroy(x);
     if (plan->fwd_dev) (void)hipFree(plan->fwd_dev);
     if (plan->dev) (void)hipFree(plan->dev);
     delete plan;
@@ -481,40 +481,48 @@ namespace {
 // of its own, then launched on the context's): one launch per level costs
 // the host more than the device, and a graph replays them back to back.
 // Captured again when the rows, the scratch or the row width change.
-tn_status hll_graph(tn_ctx *ctx, const tn_plan *plan, uint32_t nwords, uint8_t *M) {
+tn_status hll_graph(tn_ctx *ctx, const tn_plan *plan, uint32_t nwords, uint8_t *M,
+                    const uint64_t *Grow, unsigned int *left, bool sat) {
     if (plan->gview.L == 0) return TN_OK;
-    if (plan->hll_exec && plan->hll_M == M && plan->hll_scr == ctx->scratch &&
-        plan->hll_nwords == nwords)
+    if (!plan->hll_execs.empty() && plan->hll_M == M && plan->hll_scr == ctx->scratch &&
+        plan->hll_nwords == nwords && plan->hll_sat == sat)
         return TN_OK;
-    if (plan->hll_exec) {
-        // a queued replay may still run the old graph
+    if (!plan->hll_execs.empty()) {
+        // a queued replay may still run the old graphs
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        (void)hipGraphExecDestroy(plan->hll_exec);
-        plan->hll_exec = nullptr;
+        for (auto x : plan->hll_execs) (void)hipGraphExecDestroy(x);
+        plan->hll_execs.clear();
     }
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "capture stream");
-    hipGraph_t g = nullptr;
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
+    for (uint32_t l0 = 0; l0 < plan->gview.L && e == hipSuccess; l0 += tn::kHllSegmentLevels) {
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) break;
         hipError_t le = tn::launch_hll_levels(plan->gview, plan->lvl_pair.data(),
-                                              plan->lvl_gat.data(), nwords, (uint64_t *)M,
-                                              (uint64_t *)ctx->scratch, cs);
+                                              plan->lvl_gat.data(), l0,
+                                              l0 + tn::kHllSegmentLevels, nwords, (uint64_t *)M,
+                                              (uint64_t *)ctx->scratch, sat ? Grow : nullptr,
+                                              sat ? left : nullptr, cs);
         e = hipStreamEndCapture(cs, &g);
         if (le != hipSuccess) e = le;
+        hipGraphExec_t x = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) plan->hll_execs.push_back(x);
+        if (g) (void)hipGraphDestroy(g);
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&plan->hll_exec, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
-        plan->hll_exec = nullptr;
+        for (auto x : plan->hll_execs) (void)hipGraphExecDestroy(x);
+        plan->hll_execs.clear();
         return hip_fail(e, "HLL level graph");
     }
     plan->hll_M = M;
     plan->hll_scr = ctx->scratch;
     plan->hll_nwords = nwords;
+    plan->hll_sat = sat;
     return TN_OK;
 }
 }  // namespace
@@ -531,16 +539,23 @@ tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
     const uint32_t nwords = (1u << log2s) / 8;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
+    // TN_HLL plans: one scratch row per gather of the widest level, then
+    // the saturation row G, the count of rows not yet G and 2^log2s uint32
+    // for the register maxima; others: per-workgroup sink words, then the
+    // compound scratch rows
+    const size_t gat_words = (size_t)std::max<uint32_t>(plan->gview.max_gat, 1) * nwords;
     {
-        // TN_HLL plans: one scratch row per gather of the widest level;
-        // others: per-workgroup sink words, then the compound scratch rows
         const size_t words =
-            plan->hll ? (size_t)std::max<uint32_t>(plan->gview.max_gat, 1) * nwords
+            plan->hll ? gat_words + nwords + 1 + ((size_t)1 << log2s) / 2
                       : (size_t)tn::rowmax_workgroups(nwords) * tn::kRoworSinkWords +
                             (size_t)plan->scratch_rows * (size_t)nwords;
         tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * words);
         if (st != TN_OK) return st;
     }
+    uint64_t *Grow = (uint64_t *)ctx->scratch + gat_words;
+    unsigned int *left = (unsigned int *)(Grow + nwords);
+    unsigned int *gmax = (unsigned int *)(Grow + nwords + 1);
+    const bool sat = plan->hll && ctx->saturation;
     hipError_t e;
     if (!ctx->traffic) {
         e = hipMalloc((void **)&ctx->traffic, 2 * sizeof(unsigned long long));
@@ -553,15 +568,44 @@ tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
         tn::ProfScope ps(ctx, TN_K_AUX);
         e = tn::launch_fill_u32((uint32_t *)ctx->traffic, 4, 0u, ctx->stream);
         if (e == hipSuccess) e = tn::launch_hll_init(n, log2s, node_hash, M, ctx->stream);
+        if (e == hipSuccess && sat)
+            e = tn::launch_hll_saturation_setup(n, log2s, node_hash, M, gmax, Grow, left,
+                                                ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "HLL init launch");
     {
         if (plan->hll) {
             std::lock_guard<std::mutex> lk(plan->hll_mu);
-            tn_status st = hll_graph(ctx, plan, nwords, M);
+            tn_status st = hll_graph(ctx, plan, nwords, M, Grow, left, sat);
             if (st != TN_OK) return st;
-            tn::ProfScope ps(ctx, TN_K_ROWOR);
-            e = plan->hll_exec ? hipGraphLaunch(plan->hll_exec, ctx->stream) : hipSuccess;
+            unsigned int *snap = nullptr;  // pinned copies of *left, two slots
+            hipEvent_t ev[2] = {nullptr, nullptr};
+            if (sat && plan->hll_execs.size() > 2) {
+                st = tn::ensure_host_staging(ctx, 2 * sizeof(unsigned int));
+                if (st != TN_OK) return st;
+                snap = (unsigned int *)ctx->host_staging;
+                for (int k = 0; k < 2 && e == hipSuccess; ++k)
+                    e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+            }
+            {
+                // segments in order; with saturation, two in flight, and none
+                // launched once one has ended with every row equal to G
+                tn::ProfScope ps(ctx, TN_K_ROWOR);
+                for (size_t k = 0; k < plan->hll_execs.size() && e == hipSuccess; ++k) {
+                    if (snap && k >= 2) {
+                        e = hipEventSynchronize(ev[k % 2]);
+                        if (e != hipSuccess || snap[k % 2] == 0u) break;
+                    }
+                    e = hipGraphLaunch(plan->hll_execs[k], ctx->stream);
+                    if (snap && e == hipSuccess) {
+                        e = hipMemcpyAsync(&snap[k % 2], left, sizeof(unsigned int),
+                                           hipMemcpyDeviceToHost, ctx->stream);
+                        if (e == hipSuccess) e = hipEventRecord(ev[k % 2], ctx->stream);
+                    }
+                }
+            }
+            for (int k = 0; k < 2; ++k)
+                if (ev[k]) (void)hipEventDestroy(ev[k]);
         } else {
             tn::ProfScope ps(ctx, TN_K_ROWOR);
             e = tn::launch_rowmax_global(plan->view, n, nwords, (uint64_t *)M, nwords,

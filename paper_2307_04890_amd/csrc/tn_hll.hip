@@ -57,37 +57,95 @@ __device__ __forceinline__ void hll_gather_read(const uint64_t *__restrict__ M, 
     }
 }
 
+// Saturation.  No row can exceed G, the register-wise maximum over every
+// node's own registers (every row is the maximum over a set of nodes), and
+// a row equal to G stays G.  *left counts the rows not yet equal to G: each
+// row that reaches G takes one off (a row does so once), and once it is 0
+// the rest of the stream changes nothing, so every later level returns at
+// once.  `all` over a group of G lanes: each lane folds its own words, then
+// a ballot over the group's lanes.
+__device__ __forceinline__ bool group_all(bool mine, uint32_t G) {
+    const uint64_t b = __ballot(mine);
+    const uint32_t first = (threadIdx.x & 63u) / G * G;
+    const uint64_t mask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << first;
+    return (b & mask) == mask;
+}
+
 __global__ void __launch_bounds__(256)
 k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *__restrict__ pairs,
             uint32_t np, const uint32_t *__restrict__ gat_ptr,
             const uint32_t *__restrict__ gat_src, const uint32_t *__restrict__ gat_tgt,
-            uint32_t ng, uint32_t inline_gathers, uint64_t *__restrict__ scr) {
+            uint32_t ng, uint32_t inline_gathers, uint64_t *__restrict__ scr,
+            const uint64_t *__restrict__ Grow, unsigned int *__restrict__ left) {
+    // every row is G: nothing changes (one read per wavefront, so that its
+    // lanes leave together)
+    if (left && __builtin_amdgcn_readfirstlane(*left) == 0u) return;
     const uint32_t lane = threadIdx.x % G;
     const uint32_t ngroups = gridDim.x * (blockDim.x / G);
     const uint32_t items = np + (inline_gathers ? (ng > 0 ? 1u : 0u) : ng);
-    for (uint32_t i = blockIdx.x * (blockDim.x / G) + threadIdx.x / G; i < items; i += ngroups) {
-        if (i >= np && inline_gathers) {
+    // groups never straddle a wavefront (G divides 64), and every lane of a
+    // group runs the same iterations, so the ballots below see whole groups
+    const uint32_t rounds = (items + ngroups - 1) / ngroups;
+    const uint32_t i0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+    for (uint32_t rr = 0; rr < rounds; ++rr) {
+        const uint32_t i = i0 + rr * ngroups;
+        bool ru_was = true, rv_was = true, r_is = true, one_way = true, pair = false;
+        if (i >= items) {
+            // no item: takes part in the ballots only
+        } else if (i >= np && inline_gathers) {
             for (uint32_t g = 0; g < ng; ++g)
                 hll_gather_read(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
                                 scr + (size_t)g * nwords);
-            for (uint32_t g = 0; g < ng; ++g)
-                for (uint32_t w = lane; w < nwords; w += G)
-                    M[(size_t)gat_tgt[g] * nwords + w] = scr[(size_t)g * nwords + w];
+            for (uint32_t g = 0; g < ng; ++g) {
+                bool was = true, is = true;
+                for (uint32_t w = lane; w < nwords; w += G) {
+                    const uint64_t old = M[(size_t)gat_tgt[g] * nwords + w];
+                    const uint64_t nw = scr[(size_t)g * nwords + w];
+                    M[(size_t)gat_tgt[g] * nwords + w] = nw;
+                    if (Grow) {
+                        was &= old == Grow[w];
+                        is &= nw == Grow[w];
+                    }
+                }
+                // one group runs every gather of the level: its ballots see
+                // only its own lanes' bits
+                if (Grow) {
+                    const bool reached = group_all(is, G), before = group_all(was, G);
+                    if (reached && !before && lane == 0) atomicSub(left, 1u);
+                }
+            }
         } else if (i < np) {
             const uint2 it = pairs[i];
             const uint32_t v = it.y & kNodeMask;
             const bool dir = it.y & kDirBit;
             uint64_t *ru = M + (size_t)it.x * nwords;
             uint64_t *rv = M + (size_t)v * nwords;
+            pair = true;
+            one_way = dir;
             for (uint32_t w = lane; w < nwords; w += G) {
-                const uint64_t r = max_bytes7(ru[w], rv[w]);
+                const uint64_t a = ru[w], b = rv[w];
+                const uint64_t r = max_bytes7(a, b);
                 ru[w] = r;
                 if (!dir) rv[w] = r;
+                if (Grow) {
+                    const uint64_t gw = Grow[w];
+                    ru_was &= a == gw;
+                    rv_was &= b == gw;
+                    r_is &= r == gw;
+                }
             }
         } else {
             const uint32_t g = i - np;
             hll_gather_read(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
                             scr + (size_t)g * nwords);
+        }
+        if (Grow) {
+            const bool is = group_all(r_is, G);
+            const bool u_was = group_all(ru_was, G), v_was = group_all(rv_was, G);
+            if (pair && lane == 0 && is) {
+                const unsigned int k = (u_was ? 0u : 1u) + ((one_way || v_was) ? 0u : 1u);
+                if (k) atomicSub(left, k);
+            }
         }
     }
 }
@@ -95,16 +153,78 @@ k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *
 // Gathers of a level handled in one group of its launch, at most.
 constexpr uint32_t kHllInlineGathers = 4;
 
-// The level's gathers write their targets from scratch.
+// The level's gathers write their targets from scratch, one group of G
+// lanes per target (so that a target reaching G is counted once).
 __global__ void __launch_bounds__(256)
-k_hll_gathers_write(uint64_t *__restrict__ M, uint32_t nwords, const uint32_t *__restrict__ gat_tgt,
-                    uint32_t ng, const uint64_t *__restrict__ scr) {
-    const size_t total = (size_t)ng * nwords;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t g = (uint32_t)(i / nwords), w = (uint32_t)(i % nwords);
-        M[(size_t)gat_tgt[g] * nwords + w] = scr[i];
+k_hll_gathers_write(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G,
+                    const uint32_t *__restrict__ gat_tgt, uint32_t ng,
+                    const uint64_t *__restrict__ scr, const uint64_t *__restrict__ Grow,
+                    unsigned int *__restrict__ left) {
+    // every row is G: the level changes nothing, and its gather launch may
+    // have left scratch unwritten (the count only falls, so a count above 0
+    // here means the gather launch before saw one too and wrote all of it)
+    if (left && __builtin_amdgcn_readfirstlane(*left) == 0u) return;
+    const uint32_t lane = threadIdx.x % G;
+    const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+    const uint32_t rounds = (ng + ngroups - 1) / ngroups;
+    const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+    for (uint32_t rr = 0; rr < rounds; ++rr) {
+        const uint32_t g = g0 + rr * ngroups;
+        bool was = true, is = true;
+        if (g < ng)
+            for (uint32_t w = lane; w < nwords; w += G) {
+                const uint64_t old = M[(size_t)gat_tgt[g] * nwords + w];
+                const uint64_t nw = scr[(size_t)g * nwords + w];
+                M[(size_t)gat_tgt[g] * nwords + w] = nw;
+                if (Grow) {
+                    was &= old == Grow[w];
+                    is &= nw == Grow[w];
+                }
+            }
+        if (Grow) {
+            const bool reached = group_all(is, G), before = group_all(was, G);
+            if (reached && !before && lane == 0 && g < ng) atomicSub(left, 1u);
+        }
     }
+}
+
+// gmax[j] = the largest register j over every node's own registers.
+__global__ void __launch_bounds__(256)
+k_hll_gmax(uint32_t n, uint32_t b, const uint64_t *__restrict__ node_hash,
+           unsigned int *__restrict__ gmax) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const uint64_t x = node_hash[u];
+        const uint32_t j = (uint32_t)(x >> (64 - b));
+        const uint64_t tail = x & ((~0ull) >> b);
+        const uint32_t rho = tail ? (uint32_t)__clzll((long long)tail) - b + 1 : 64 - b + 1;
+        atomicMax(gmax + j, rho);
+    }
+}
+
+// The row G from gmax, one byte per register.
+__global__ void __launch_bounds__(256)
+k_hll_pack_g(uint32_t nwords, const unsigned int *__restrict__ gmax, uint64_t *__restrict__ Grow) {
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += gridDim.x * blockDim.x) {
+        uint64_t x = 0;
+        for (uint32_t k = 0; k < 8; ++k) x |= (uint64_t)(gmax[8 * w + k] & 0xffu) << (8 * k);
+        Grow[w] = x;
+    }
+}
+
+// *left = the rows not equal to G (one wavefront per row).
+__global__ void __launch_bounds__(256)
+k_hll_count_left(uint32_t n, uint32_t nwords, const uint64_t *__restrict__ M,
+                 const uint64_t *__restrict__ Grow, unsigned int *__restrict__ left) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
+    unsigned int mine = 0;
+    for (uint32_t u = wave; u < n; u += nwave) {
+        bool eq = true;
+        for (uint32_t w = lane; w < nwords; w += 64) eq &= M[(size_t)u * nwords + w] == Grow[w];
+        if (__ballot(!eq) != 0 && lane == 0) ++mine;
+    }
+    if (lane == 0 && mine) atomicAdd(left, mine);
 }
 
 double __device__ hll_alpha(uint32_t s) {
@@ -157,11 +277,34 @@ hipError_t launch_hll_init(uint32_t n, uint32_t log2s, const uint64_t *node_hash
     return hipGetLastError();
 }
 
+hipError_t launch_hll_saturation_setup(uint32_t n, uint32_t log2s, const uint64_t *node_hash,
+                                       const uint8_t *M, unsigned int *gmax, uint64_t *Grow,
+                                       unsigned int *left, hipStream_t st) {
+    const uint32_t s = 1u << log2s, nwords = s / 8;
+    hipError_t e = launch_fill_u32(gmax, s, 0u, st);
+    if (e == hipSuccess) e = launch_fill_u32(left, 1, 0u, st);
+    if (e != hipSuccess) return e;
+    uint32_t blocks = (n + 255) / 256;
+    if (blocks > 4096u) blocks = 4096u;
+    hipLaunchKernelGGL(k_hll_gmax, dim3(blocks), dim3(256), 0, st, n, log2s, node_hash, gmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hll_pack_g, dim3((nwords + 255) / 256), dim3(256), 0, st, nwords, gmax, Grow);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint32_t cb = (n + 3) / 4;
+    if (cb > 16384u) cb = 16384u;
+    hipLaunchKernelGGL(k_hll_count_left, dim3(cb), dim3(256), 0, st, n, nwords,
+                       (const uint64_t *)M, Grow, left);
+    return hipGetLastError();
+}
+
 hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
-                             const uint32_t *lvl_gat, uint32_t nwords, uint64_t *M,
-                             uint64_t *scratch, hipStream_t st) {
+                             const uint32_t *lvl_gat, uint32_t l0, uint32_t l1, uint32_t nwords,
+                             uint64_t *M, uint64_t *scratch, const uint64_t *Grow,
+                             unsigned int *left, hipStream_t st) {
     const uint32_t G = nwords < 64 ? nwords : 64;  // nwords is a power of two >= 2
-    for (uint32_t l = 0; l < s.L; ++l) {
+    for (uint32_t l = l0; l < l1 && l < s.L; ++l) {
         const uint32_t p0 = lvl_pair[l], np = lvl_pair[l + 1] - p0;
         const uint32_t g0 = lvl_gat[l], ng = lvl_gat[l + 1] - g0;
         if (np + ng == 0) continue;
@@ -172,14 +315,14 @@ hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
         const uint32_t blocks = (uint32_t)std::min<size_t>((threads + 255) / 256, 4096);
         hipLaunchKernelGGL(k_hll_level, dim3(blocks), dim3(256), 0, st, M, nwords, G,
                            s.pairs + p0, np, s.gat_ptr + g0, s.gat_src, s.gat_tgt + g0, ng, inl,
-                           scratch);
+                           scratch, Grow, left);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (ng == 0 || inl) continue;
-        const size_t words = (size_t)ng * nwords;
-        const uint32_t wb = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_hll_gathers_write, dim3(wb), dim3(256), 0, st, M, nwords,
-                           s.gat_tgt + g0, ng, scratch);
+        const size_t gthreads = (size_t)ng * G;
+        const uint32_t wb = (uint32_t)std::min<size_t>((gthreads + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_hll_gathers_write, dim3(wb), dim3(256), 0, st, M, nwords, G,
+                           s.gat_tgt + g0, ng, scratch, Grow, left);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -193,9 +193,10 @@ struct tn_plan {
     // rows, scratch and row width they were captured with (replaced when one
     // changes; the mutex keeps concurrent calls on one plan apart)
     mutable std::mutex hll_mu;
-    mutable hipGraphExec_t hll_exec = nullptr;
+    mutable std::vector<hipGraphExec_t> hll_execs;  // segments of tn::kHllSegmentLevels levels
     mutable const void *hll_M = nullptr, *hll_scr = nullptr;
     mutable uint32_t hll_nwords = 0;
+    mutable bool hll_sat = false;
     tn_plan_stats stats{};
 };
 
@@ -328,12 +329,24 @@ uint32_t rowmax_workgroups(uint32_t nwords);
 // and the size estimates
 hipError_t launch_hll_init(uint32_t n, uint32_t log2s, const uint64_t *node_hash, uint8_t *M,
                            hipStream_t st);
-// The register stream of a TN_HLL plan: one launch per level (pairs, and
-// compound items' reads into scratch), then one writing the compound items'
-// rows; scratch: s.max_gat rows of nwords words.
+// The register stream of a TN_HLL plan, levels [l0, l1): one launch per
+// level (pairs, and compound items' reads into scratch), then one writing
+// the compound items' rows; scratch: s.max_gat rows of nwords words.  With
+// Grow and left (saturation; both nullable): Grow is the register-wise
+// maximum over every node's own registers and *left the rows not equal to
+// it; a row that reaches Grow takes one off, and a level returns at once
+// when *left is 0 (launch_hll_saturation_setup computes both, with gmax
+// 2^log2s uint32 of scratch).
 hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
-                             const uint32_t *lvl_gat, uint32_t nwords, uint64_t *M,
-                             uint64_t *scratch, hipStream_t st);
+                             const uint32_t *lvl_gat, uint32_t l0, uint32_t l1, uint32_t nwords,
+                             uint64_t *M, uint64_t *scratch, const uint64_t *Grow,
+                             unsigned int *left, hipStream_t st);
+hipError_t launch_hll_saturation_setup(uint32_t n, uint32_t log2s, const uint64_t *node_hash,
+                                       const uint8_t *M, unsigned int *gmax, uint64_t *Grow,
+                                       unsigned int *left, hipStream_t st);
+// Levels per captured graph of a TN_HLL plan; between graphs the host reads
+// *left and stops once it is 0.
+constexpr uint32_t kHllSegmentLevels = 256;
 hipError_t launch_hll_estimate(uint32_t n, uint32_t log2s, const uint8_t *M, double *est,
                                hipStream_t st);
 // streamed one-shot build (tn_stream.cpp)

@@ -112,3 +112,39 @@ def test_hll_plan_graph_replays_with_other_work_between():
         torch.cuda.synchronize()
     p.close()
     other.close()
+
+
+@pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.TIES_SEQUENTIAL, tn.FORWARD])
+def test_saturating_streams_over_many_segments(flags):
+    # streams of thousands of levels (several captured segments of 256) on
+    # networks whose rows all reach the register-wise maximum G partway: the
+    # TN_HLL plan stops replaying once every row is G, and must give the
+    # oracle's registers with saturation on and off, compound steps included
+    ctx = tn.get_context()
+    cases = [(120, 30_000, 20_000, 6, "random"), (300, None, 8_000, 8, "star"),
+             (64, 12_000, 12_000, 4, "random")]
+    try:
+        for case, (n, m, Tm, b, kind) in enumerate(cases):
+            if kind == "star":
+                s, d, t = T.star_steps(n, Tm, 6, seed=760 + case)
+            else:
+                s, d, t = T.random_tiny(n, m, Tm, seed=750 + case)
+            h = T.hll_node_hashes(n, seed=75 + case)
+            want = hll.stream_registers(n, s, d, t, h, b, directed=bool(flags & tn.DIRECTED),
+                                        sequential=bool(flags & tn.TIES_SEQUENTIAL),
+                                        forward=bool(flags & tn.FORWARD))
+            p = tn.Plan(n, s, d, t, flags | tn.HLL)
+            assert p.stats["levels"] > 512, (case, p.stats["levels"])
+            for sat in (True, False):
+                ctx.saturation(sat)
+                M, est = p.hll(h, b)
+                assert (M.cpu().numpy() == want).all(), (case, sat)
+            p.close()
+            if flags == 0 and case == 0:
+                # every row ends at G (the saturating case the stop is for)
+                G = np.zeros(1 << b, dtype=np.uint8)
+                for u in range(n):
+                    G = np.maximum(G, hll.registers_of_set(h[u:u + 1], b))
+                assert (want == G).all()
+    finally:
+        ctx.saturation(True)
