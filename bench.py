@@ -853,7 +853,8 @@ def run_sweep(args):
     from paper_2307_04890_amd.evaluate import emd_1d, relative_memory
 
     ns = [100, 200, 500, 1000, 2000, 5000, 10000]
-    ms = [m for m in (10**4, 10**5, 10**6, 10**7, 10**8) if m <= args.sweep_max_m]
+    ms = [m for m in (10**4, 10**5, 10**6, 10**7, 10**8)
+          if args.sweep_min_m <= m <= args.sweep_max_m]
     H = 5
     rows = []
     tot_events = tot_exact = 0.0
@@ -870,9 +871,10 @@ def run_sweep(args):
 
     for i, n in enumerate(ns):
         for j, m in enumerate(ms):
-            s, d, t = T.er_poisson(n, m, 100 * m, seed=100 * i + j)
+            jj = [10**4, 10**5, 10**6, 10**7, 10**8].index(m)  # seeds as in the full grid
+            s, d, t = T.er_poisson(n, m, 100 * m, seed=100 * i + jj)
             K = max(1, int(round(0.3 * n)))
-            A = T.hash_coefficients(H, seed=7000 + 100 * i + j)
+            A = T.hash_coefficients(H, seed=7000 + 100 * i + jj)
 
             def exact():
                 C, st = tn.build_component_matrix_streamed(n, s, d, t)
@@ -1122,6 +1124,8 @@ def main():
                     help="log2 of the HyperLogLog registers per node (--mode hll)")
     ap.add_argument("--sweep-max-m", type=float, default=1e7,
                     help="largest event count of the ER + Poisson sweep")
+    ap.add_argument("--sweep-min-m", type=float, default=0,
+                    help="smallest event count of the ER + Poisson sweep")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--slice-words", type=int, default=0)
     ap.add_argument("--no-end-to-end", action="store_true",
