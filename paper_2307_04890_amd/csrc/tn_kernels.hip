@@ -719,7 +719,7 @@ k_out_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwo
 // in[w] = number of rows with bit w: each lane owns one word column over a
 // chunk of rows and adds the words into 16 bit-planes (a bit-sliced ripple
 // counter, 64 column counters at once), then adds the 64 counts to in[].
-constexpr uint32_t kInRowsPerChunk = 2048;  // < 2^16: 16 planes suffice
+constexpr uint32_t kInRowsPerChunk = 512;  // < 2^16: 16 planes suffice; 4x the wavefronts of 2048
 __global__ void __launch_bounds__(64)
 k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwords,
            int32_t *__restrict__ in) {
