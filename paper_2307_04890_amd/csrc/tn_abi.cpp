@@ -213,6 +213,13 @@ tn_status tn_plan_create(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src
         if (flat) p->flat = (const uint32_t *)((unsigned char *)p->dev + flat_off);
         p->scratch_rows = hs.scratch_rows;
         p->zero_levels = tn::zero_phase_levels(hs, n);
+        {
+            // the saturating path's forwarding phase ends where the ops reach
+            // kFwdPhaseOpsPerNode * n
+            uint32_t l = p->zero_levels;
+            while (l < hs.Lops && (int64_t)hs.lvl_op[l] < tn::kFwdPhaseOpsPerNode * (int64_t)n) ++l;
+            p->mid_end = l;
+        }
         p->host_lvl_op = std::move(hs.lvl_op);
         p->host_ops = std::move(hs.ops);
     }
@@ -329,6 +336,7 @@ void tn_plan_destroy(tn_plan *plan) {
     DeviceGuard g(plan->device);
     for (auto x : plan->hll_execs) (void)hipGraphExecDestroy(x);
     if (plan->fwd_dev) (void)hipFree(plan->fwd_dev);
+    if (plan->mid_dev) (void)hipFree(plan->mid_dev);
     if (plan->dev) (void)hipFree(plan->dev);
     delete plan;
 }
@@ -339,14 +347,19 @@ int64_t tn_recommended_ld(uint32_t n) {
 }
 
 namespace {
-// The plan's forwarded schedule on the device, made on first use (waits for
-// the upload).
-tn_status plan_fwd(tn_ctx *ctx, const tn_plan *plan) {
+// A forwarded schedule of the plan's op levels [l0, l1) on the device,
+// made on first use (waits for the upload): the whole plan for the plain
+// recurrence, the middle range for the saturating path's forwarding phase.
+tn_status plan_fwd(tn_ctx *ctx, const tn_plan *plan, uint32_t l0, uint32_t l1, void **dev,
+                   tn::DevOps *view) {
     std::lock_guard<std::mutex> lk(plan->fwd_mu);
-    if (plan->fwd_dev) return TN_OK;
+    if (*dev) return TN_OK;
+    std::vector<uint32_t> lvl, ops;
+    const std::vector<uint32_t> &hl = plan->host_lvl_op;
+    for (uint32_t l = l0; l <= l1; ++l) lvl.push_back(hl[l] - hl[l0]);
+    ops.assign(plan->host_ops.begin() + 4 * (size_t)hl[l0], plan->host_ops.begin() + 4 * (size_t)hl[l1]);
     std::vector<uint32_t> flvl, fops;
-    tn::fwd_schedule(plan->host_lvl_op, plan->host_ops, plan->stats.n, plan->scratch_rows, flvl,
-                     fops);
+    tn::fwd_schedule(lvl, ops, plan->stats.n, plan->scratch_rows, flvl, fops);
     const size_t lb = (4 * flvl.size() + 255) & ~(size_t)255;
     const size_t bytes = lb + 4 * std::max<size_t>(fops.size(), 4);
     void *d = nullptr;
@@ -361,11 +374,11 @@ tn_status plan_fwd(tn_ctx *ctx, const tn_plan *plan) {
         (void)hipFree(d);
         return hip_fail(e, "forwarded schedule upload");
     }
-    plan->fwd_view.L = (uint32_t)flvl.size() - 1;
-    plan->fwd_view.nops = (uint32_t)(fops.size() / 4);
-    plan->fwd_view.lvl = (const uint32_t *)d;
-    plan->fwd_view.ops = (const uint4 *)((unsigned char *)d + lb);
-    plan->fwd_dev = d;
+    view->L = (uint32_t)flvl.size() - 1;
+    view->nops = (uint32_t)(fops.size() / 4);
+    view->lvl = (const uint32_t *)d;
+    view->ops = (const uint4 *)((unsigned char *)d + lb);
+    *dev = d;
     return TN_OK;
 }
 }  // namespace
@@ -420,15 +433,45 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     const bool fwd = !wave && (!ctx->saturation || !tn::rowor_saturates(n, plan->scratch_rows)) &&
                      tn::rowor_fwd_supported(n, slice_words) && plan->stats.ops > 0;
     if (fwd) {
-        tn_status st = plan_fwd(ctx, plan);
+        tn_status st = plan_fwd(ctx, plan, 0, plan->stats.op_levels, &plan->fwd_dev,
+                                &plan->fwd_view);
+        if (st != TN_OK) return st;
+    }
+    // the saturating path of a large network: the zero phase, then the
+    // forwarding kernel while most ops still move rows, then the per-slice
+    // state rebuilt from the matrix and the saturating kernel for the rest
+    const bool three = !fwd && zero_phase && n >= 16384 && tn::rowor_saturates(n, plan->scratch_rows) &&
+                       tn::rowor_fwd_supported(n, slice_words) &&
+                       plan->mid_end > plan->zero_levels && plan->mid_end < plan->stats.op_levels;
+    if (three) {
+        tn_status st = plan_fwd(ctx, plan, plan->zero_levels, plan->mid_end, &plan->mid_dev,
+                                &plan->mid_view);
         if (st != TN_OK) return st;
     }
     {
         tn::ProfScope ps(ctx, TN_K_ROWOR);
-        if (fwd)
+        if (fwd) {
             e = tn::launch_rowor_fwd(plan->fwd_view, n, C, ld, slice_words,
                                      (uint64_t *)ctx->scratch, ctx->traffic, ctx->stream);
-        else if (wave && plan->flat)
+        } else if (three) {
+            tn::DevOps head = plan->view, tail = plan->view;
+            head.L = plan->zero_levels;
+            tail.L = plan->view.L - plan->mid_end;
+            tail.lvl = plan->view.lvl + plan->mid_end;
+            unsigned int *done = persist + pwords - 1;
+            e = tn::launch_rowor_global(head, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
+                                        plan->scratch_rows, ctx->traffic, true, persist, done,
+                                        plan->zero_levels, ctx->stream);
+            if (e == hipSuccess)
+                e = tn::launch_rowor_fwd(plan->mid_view, n, C, ld, slice_words,
+                                         (uint64_t *)ctx->scratch, ctx->traffic, ctx->stream);
+            if (e == hipSuccess)
+                e = tn::launch_slice_full_state(C, ld, n, slice_words, persist, ctx->stream);
+            if (e == hipSuccess)
+                e = tn::launch_rowor_global(tail, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
+                                            plan->scratch_rows, ctx->traffic, true, persist, done,
+                                            0u, ctx->stream);
+        } else if (wave && plan->flat)
             e = tn::launch_rowor_wave_flat1(plan->flat, plan->view.nops, n, C, ld,
                                             plan->scratch_rows, ctx->traffic, ctx->saturation,
                                             ctx->stream);

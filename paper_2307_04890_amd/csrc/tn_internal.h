@@ -184,6 +184,11 @@ struct tn_plan {
     mutable std::mutex fwd_mu;
     mutable void *fwd_dev = nullptr;
     mutable tn::DevOps fwd_view{};
+    // ... and of op levels [zero_levels, mid_end) alone: the forwarding phase
+    // of the saturating path (tn::kFwdPhaseOpsPerNode)
+    uint32_t mid_end = 0;
+    mutable void *mid_dev = nullptr;
+    mutable tn::DevOps mid_view{};
     // TN_HLL plans: the time-step schedule (pairs and gathers by level) on
     // the device, its level boundaries on the host, instead of the ops
     bool hll = false;
@@ -288,6 +293,18 @@ bool rowor_fwd_supported(uint32_t n, uint32_t slice_words);
 hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                             uint32_t slice_words, uint64_t *scratch,
                             unsigned long long *traffic, hipStream_t st);
+// Rebuilds launch_rowor_global's per-slice state (persist, zeroed here
+// first) from the matrix: the full-row bits and count of every slice, so
+// that a saturating launch can resume after launches that kept no state
+// (slice_words 1, 2, 4 or 8, else hipErrorInvalidValue).
+hipError_t launch_slice_full_state(const uint64_t *C, int64_t ld, uint32_t n,
+                                   uint32_t slice_words, uint32_t *persist, hipStream_t st);
+// The saturating path's middle phase: from the end of the zero phase until
+// its ops reach kFwdPhaseOpsPerNode * n, the forwarding kernel (no skips,
+// each level's results through LDS) runs instead of the saturating one;
+// timed on the 10^5-node activity-driven workload, it is cheaper over that
+// range and dearer after it, when most ops have a full operand.
+constexpr int64_t kFwdPhaseOpsPerNode = 10;
 // Levels of the zero phase of a schedule: those before the level at which
 // its ops reach `budget`.  Applied to the identity the budget is n (about
 // one op per row), by when few row slices are still all zero; a streamed

@@ -9,6 +9,8 @@
 // touch the same word.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tn_device.h"
 #include "tn_internal.h"
 
@@ -695,6 +697,62 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     count_add(traffic + 1, A.stored);
 }
 
+// The per-slice state of the saturating kernel (launch_rowor_global's
+// persist) rebuilt from the matrix itself: for slice s, bit r of its full
+// row bits is set iff row r holds every column of the slice, and its count
+// is the number of such rows.  One wavefront per 64 rows of a slice, the
+// slices of the same rows on neighbouring wavefronts (a row's words are
+// contiguous): groups of SW lanes read one row slice each, SW rows per lane
+// with every load issued before the first compare; a group's lanes AND
+// their checks, lane r of the wave collects row r's result, and the wave's
+// ballot gives two bitmap words.  The state must be zero before
+// (launch_fill_u32).
+template <int SW>
+__global__ void __launch_bounds__(256)
+k_slice_full_state(const uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords,
+                   uint32_t slices, uint32_t *__restrict__ persist) {
+    constexpr uint32_t G = 64 / SW;  // rows per load instruction
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t g = lane / SW, j = lane % SW;
+    const uint32_t rwords = ((n + 31u) & ~31u) / 32;
+    const size_t pslice = 2 * (size_t)rwords + 2;
+    const uint32_t blocks = (n + 63) / 64;
+    const uint32_t tail = n & 63u;
+    const uint64_t last = tail ? (1ull << tail) - 1ull : ~0ull;
+    const size_t jobs = (size_t)slices * blocks;
+    for (size_t job = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; job < jobs;
+         job += ((size_t)gridDim.x * blockDim.x) >> 6) {
+        const uint32_t slice = (uint32_t)(job % slices);
+        const uint32_t rb = (uint32_t)(job / slices);
+        const uint32_t r0 = rb * 64;
+        const uint32_t w = slice * SW + j;
+        const bool wok = w < nwords;  // words past the last one check as full
+        const uint64_t want = w + 1 == nwords ? last : ~0ull;
+        uint64_t v[SW];
+#pragma unroll
+        for (int k = 0; k < SW; ++k) {
+            const uint32_t r = r0 + k * G + g;
+            v[k] = (wok && r < n) ? C[(size_t)r * (size_t)ld + w] : want;
+        }
+        bool mine = false;
+#pragma unroll
+        for (int k = 0; k < SW; ++k) {
+            int f = (r0 + k * G + g < n && v[k] == want) ? 1 : 0;
+#pragma unroll
+            for (uint32_t off = 1; off < SW; off <<= 1) f &= __shfl_xor(f, off);
+            // row r0 + lane is row k * G + g of iteration k = lane / G
+            const int t = __shfl(f, (int)((lane % G) * SW));
+            if (lane / G == (uint32_t)k) mine = t != 0;
+        }
+        const uint64_t b = __ballot(mine);
+        uint32_t *pst = persist + (size_t)slice * pslice;
+        const uint32_t word = rb * 2;
+        if (lane == 0 && word < rwords) pst[2 + word] = (uint32_t)b;
+        if (lane == 1 && word + 1 < rwords) pst[2 + word + 1] = (uint32_t)(b >> 32);
+        if (lane == 0 && b) atomicAdd(pst + 1, (uint32_t)__popcll(b));
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -942,6 +1000,24 @@ hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld
         case 8: return rowor_fwd_variant<8, 7>(s, n, C, ld, scratch, traffic, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_slice_full_state(const uint64_t *C, int64_t ld, uint32_t n,
+                                   uint32_t slice_words, uint32_t *persist, hipStream_t st) {
+    const uint32_t nwords = (n + 63) / 64;
+    const uint32_t slices = rowor_workgroups(n, slice_words);
+    hipError_t e = launch_fill_u32(persist, rowor_persist_words(n, slice_words), 0u, st);
+    if (e != hipSuccess) return e;
+    const size_t waves = (size_t)slices * ((n + 63) / 64);
+    const uint32_t blocks = (uint32_t)std::min<size_t>((waves + 3) / 4, 65536);
+    switch (slice_words) {
+        case 1: hipLaunchKernelGGL(k_slice_full_state<1>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 2: hipLaunchKernelGGL(k_slice_full_state<2>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 4: hipLaunchKernelGGL(k_slice_full_state<4>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 8: hipLaunchKernelGGL(k_slice_full_state<8>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *out_sizes,

@@ -289,3 +289,37 @@ def test_wavefront_kernel_stops_full_columns():
                 assert (host(C)[:, :oracle.words(n)] == want).all(), (n, sat)
     finally:
         ctx.saturation(True)
+
+
+@pytest.mark.parametrize("sw", [1, 2, 4, 8, 16])
+def test_saturating_path_with_a_forwarding_phase(sw):
+    # n = 256 * 64 + 1: every slice width ends on a one-column slice.  Past
+    # the zero phase, a network of this size runs the forwarding kernel until
+    # its ops reach 10 n, then the saturating kernel from slice state rebuilt
+    # out of the matrix (up to 8 words per slice; 16 keeps the two-launch
+    # path); the matrix must be the plain recurrence's and the oracle's
+    n = 16385
+    s, d, t = T.uniform_pairs(n, 400_000, 2000, seed=8400)
+    sch = tn.host_schedule(n, s, d, t)
+    lv, L = sch["lvl_op"], sch["stats"]["op_levels"]
+    zl = int(np.searchsorted(lv[:L], n, side="left"))
+    mid = int(np.searchsorted(lv[:L], 10 * n, side="left"))
+    assert 0 < zl < mid < L
+    ctx = tn.get_context()
+    p = tn.Plan(n, s, d, t)
+    try:
+        C1 = p.execute(slice_words=sw).clone()
+        ld1, _ = ctx.last_traffic()
+        ctx.saturation(False)
+        C0 = p.execute(slice_words=sw)
+        ld0, _ = ctx.last_traffic()
+    finally:
+        ctx.saturation(True)
+        p.close()
+    assert torch.equal(C1, C0)
+    assert ld1 < ld0
+    got = host(C1)
+    nw = oracle.words(n)
+    for w0 in (0, 130, nw - 1):
+        want = oracle.reverse_matrix(n, s, d, t, w0=w0, nw=1)
+        assert (got[:, w0:w0 + 1] == want).all(), (sw, w0)
