@@ -196,14 +196,18 @@ tn_status tn_schedule_arrays(const tn_host_schedule *s, tn_plan_stats *stats,
 tn_status tn_schedule_op_arrays(const tn_host_schedule *s,
                                 const uint32_t **lvl_op, const uint32_t **ops);
 /* The forwarded form of the binary-op schedule that the plain row-OR kernel
- * runs (host only, for inspection and tests): levels of at most 768 ops,
- * *levels of them, level l owning ops [lvl[l], lvl[l+1]), 4 uint32 each
- * {a, b, d1, d2} as in the op form, except that an operand with bit 30 set
- * is the result r of op (operand & 0x3ff) of level l - 1, and a
- * destination with bit 30 set is not written to memory (level l + 1
+ * runs (host only, for inspection and tests): levels of at most level_cap
+ * ops (0 or more than 768: 768, the form the kernel runs; smaller caps
+ * split more levels), *levels of them, level l owning ops [lvl[l], lvl[l+1]),
+ * 4 uint32 each {a, b, d1, d2} as in the op form, except that an operand
+ * with bit 30 set is the result r of op (operand & 0x3ff) of level l - 1,
+ * and a destination with bit 30 set is not written to memory (level l + 1
  * overwrites that row, reading it, if at all, through the same
- * forwarding).  The arrays live until tn_schedule_destroy. */
-tn_status tn_schedule_fwd_arrays(tn_host_schedule *s, uint32_t *levels,
+ * forwarding).  Within a level, an op with exactly one operand read from
+ * memory has it as b, and the ops with both read from memory come first.
+ * The arrays live until tn_schedule_destroy or the next call with another
+ * level_cap. */
+tn_status tn_schedule_fwd_arrays(tn_host_schedule *s, uint32_t level_cap, uint32_t *levels,
                                  const uint32_t **lvl, const uint32_t **ops);
 void tn_schedule_destroy(tn_host_schedule *s);
 

@@ -86,7 +86,7 @@ SIGNATURES = {
     "tn_schedule_build": (_i32, [_u32, _i64, _P, _P, _P, _u32, _PP]),
     "tn_schedule_arrays": (_i32, [_P, ctypes.POINTER(PlanStats), _PP, _PP, _PP, _PP, _PP, _PP]),
     "tn_schedule_destroy": (None, [_P]),
-    "tn_schedule_fwd_arrays": (_i32, [_P, _P, _PP, _PP]),
+    "tn_schedule_fwd_arrays": (_i32, [_P, _u32, _P, _PP, _PP]),
     "tn_schedule_op_arrays": (_i32, [_P, _PP, _PP]),
     "tn_plan_execute": (_i32, [_P, _P, _P, _i64, _u32]),
     "tn_set_saturation": (_i32, [_P, ctypes.c_int]),

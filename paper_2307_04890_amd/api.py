@@ -293,8 +293,10 @@ def component_sizes(C: torch.Tensor, n: int, out: bool = True, inn: bool = True,
     return o, i
 
 
-def host_schedule(n: int, src, dst, t, flags: int = 0) -> dict:
-    """The level schedule the planner builds (host only, no device), as numpy arrays."""
+def host_schedule(n: int, src, dst, t, flags: int = 0, fwd_level_cap: int = 0) -> dict:
+    """The level schedule the planner builds (host only, no device), as numpy arrays;
+    ``fwd_lvl``/``fwd_ops`` are its forwarded form with levels of at most
+    ``fwd_level_cap`` ops (0: 768, the form the kernels run)."""
     src, dst, t = _events(src, dst, t)
     h = ctypes.c_void_p()
     check(lib.tn_schedule_build(int(n), src.shape[0], _hp(src), _hp(dst), _hp(t), int(flags),
@@ -322,8 +324,8 @@ def host_schedule(n: int, src, dst, t, flags: int = 0) -> dict:
                    lvl_op=arr(optr[0], Lo + 1), ops=arr(optr[1], 4 * nops).reshape(nops, 4))
         fl = ctypes.c_uint32()
         fptr = [ctypes.c_void_p() for _ in range(2)]
-        check(lib.tn_schedule_fwd_arrays(h, ctypes.byref(fl), ctypes.byref(fptr[0]),
-                                         ctypes.byref(fptr[1])))
+        check(lib.tn_schedule_fwd_arrays(h, int(fwd_level_cap), ctypes.byref(fl),
+                                         ctypes.byref(fptr[0]), ctypes.byref(fptr[1])))
         out["fwd_lvl"] = arr(fptr[0], fl.value + 1)
         out["fwd_ops"] = arr(fptr[1], 4 * nops).reshape(nops, 4)
     finally:

@@ -270,6 +270,7 @@ extern "C" {
 struct tn_host_schedule {
     tn::HostSchedule hs;
     std::vector<uint32_t> flvl, fops;  // the forwarded op form, made on request
+    uint32_t fcap = 0;                 // ... with levels of at most this many ops
 };
 
 tn_status tn_schedule_build(uint32_t n, int64_t m, const uint32_t *src, const uint32_t *dst,
@@ -312,11 +313,15 @@ tn_status tn_schedule_op_arrays(const tn_host_schedule *s, const uint32_t **lvl_
     return TN_OK;
 }
 
-tn_status tn_schedule_fwd_arrays(tn_host_schedule *s, uint32_t *levels,
+tn_status tn_schedule_fwd_arrays(tn_host_schedule *s, uint32_t level_cap, uint32_t *levels,
                                  const uint32_t **lvl, const uint32_t **ops) {
     if (!s || !levels) return fail(TN_E_ARG, "schedule or levels is NULL");
-    if (s->flvl.empty())
-        tn::fwd_schedule(s->hs.lvl_op, s->hs.ops, s->hs.n, s->hs.scratch_rows, s->flvl, s->fops);
+    if (level_cap == 0 || level_cap > tn::kFwdLevelCap) level_cap = tn::kFwdLevelCap;
+    if (s->flvl.empty() || s->fcap != level_cap) {
+        tn::fwd_schedule(s->hs.lvl_op, s->hs.ops, s->hs.n, s->hs.scratch_rows, level_cap, s->flvl,
+                         s->fops);
+        s->fcap = level_cap;
+    }
     *levels = (uint32_t)s->flvl.size() - 1;
     if (lvl) *lvl = s->flvl.data();
     if (ops) *ops = s->fops.data();
@@ -359,7 +364,7 @@ tn_status plan_fwd(tn_ctx *ctx, const tn_plan *plan, uint32_t l0, uint32_t l1, v
     for (uint32_t l = l0; l <= l1; ++l) lvl.push_back(hl[l] - hl[l0]);
     ops.assign(plan->host_ops.begin() + 4 * (size_t)hl[l0], plan->host_ops.begin() + 4 * (size_t)hl[l1]);
     std::vector<uint32_t> flvl, fops;
-    tn::fwd_schedule(lvl, ops, plan->stats.n, plan->scratch_rows, flvl, fops);
+    tn::fwd_schedule(lvl, ops, plan->stats.n, plan->scratch_rows, tn::kFwdLevelCap, flvl, fops);
     const size_t lb = (4 * flvl.size() + 255) & ~(size_t)255;
     const size_t bytes = lb + 4 * std::max<size_t>(fops.size(), 4);
     void *d = nullptr;
@@ -452,7 +457,8 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         tn::ProfScope ps(ctx, TN_K_ROWOR);
         if (fwd) {
             e = tn::launch_rowor_fwd(plan->fwd_view, n, C, ld, slice_words,
-                                     (uint64_t *)ctx->scratch, ctx->traffic, ctx->stream);
+                                     (uint64_t *)ctx->scratch, plan->scratch_rows, ctx->traffic,
+                                     ctx->stream);
         } else if (three) {
             tn::DevOps head = plan->view, tail = plan->view;
             head.L = plan->zero_levels;
@@ -464,7 +470,8 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
                                         plan->zero_levels, ctx->stream);
             if (e == hipSuccess)
                 e = tn::launch_rowor_fwd(plan->mid_view, n, C, ld, slice_words,
-                                         (uint64_t *)ctx->scratch, ctx->traffic, ctx->stream);
+                                         (uint64_t *)ctx->scratch, plan->scratch_rows,
+                                         ctx->traffic, ctx->stream);
             if (e == hipSuccess)
                 e = tn::launch_slice_full_state(C, ld, n, slice_words, persist, ctx->stream);
             if (e == hipSuccess)

@@ -65,13 +65,20 @@ struct HostSchedule {
 // other operand is a row id as in the op form (last written two or more
 // levels before).  A destination with kFwdNoStore set is not stored: the
 // next level overwrites that row (kNoRow carries the bit too).  Row and
-// scratch ids stay below 2^30.
+// scratch ids stay below 2^30.  Levels hold at most `cap` ops (0 or more
+// than kFwdLevelCap: kFwdLevelCap, what the kernels take; smaller caps are
+// for tests of the splitting).  A level split into parts loses forwarding
+// between them: an op moved to a later part no longer directly follows the
+// writes of the level before.  Within a level, an op with one operand from
+// memory has it second (y; the OR is symmetric), and ops with both operands
+// from memory come first: the 16-word kernel holds x registers for the
+// first ops only.
 constexpr uint32_t kFwdLevelCap = 768;
 constexpr uint32_t kFwdHot = 0x40000000u;
 constexpr uint32_t kFwdNoStore = 0x40000000u;
 constexpr uint32_t kFwdSlotMask = 0x3ffu;
 void fwd_schedule(const std::vector<uint32_t> &lvl_op, const std::vector<uint32_t> &ops,
-                  uint32_t n, uint32_t scratch_rows, std::vector<uint32_t> &flvl,
+                  uint32_t n, uint32_t scratch_rows, uint32_t cap, std::vector<uint32_t> &flvl,
                   std::vector<uint32_t> &fops);
 
 // Device view of one schedule (all pointers into one allocation).
@@ -291,12 +298,12 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
 // each level's results stay in LDS for the next level.
 bool rowor_fwd_supported(uint32_t n, uint32_t slice_words);
 hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                            uint32_t slice_words, uint64_t *scratch,
+                            uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
                             unsigned long long *traffic, hipStream_t st);
 // Rebuilds launch_rowor_global's per-slice state (persist, zeroed here
 // first) from the matrix: the full-row bits and count of every slice, so
 // that a saturating launch can resume after launches that kept no state
-// (slice_words 1, 2, 4 or 8, else hipErrorInvalidValue).
+// (slice_words 1, 2, 4, 8 or 16, else hipErrorInvalidValue).
 hipError_t launch_slice_full_state(const uint64_t *C, int64_t ld, uint32_t n,
                                    uint32_t slice_words, uint32_t *persist, hipStream_t st);
 // The saturating path's middle phase: from the end of the zero phase until

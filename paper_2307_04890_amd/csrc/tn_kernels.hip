@@ -85,6 +85,7 @@ struct OpArgs {
     bool zon;                 // some real row is still zero (uniform per level)
     uint32_t loaded, stored;  // row words this lane moved
     bool lead;                // first lane of its group
+    uint32_t ld32;            // ldz, for 32-bit row offsets (fwd_addr)
 };
 
 // Branch-free: every candidate address is formed, then one is selected, so
@@ -96,6 +97,19 @@ __device__ __forceinline__ uint64_t *op_addr(const OpArgs &A, uint32_t id, bool 
     const uintptr_t pick = (id & kScratchBit) ? scr : real;
     const bool ok = valid && A.wok && id != kNoRow;
     return (uint64_t *)(ok ? pick : (uintptr_t)A.sink);
+}
+
+// op_addr with 32-bit row offsets: a 24-bit multiply instead of 64-bit
+// ones, when rows and strides are below 2^24 and every offset below 2^32
+// (the host checks; rowor_fwd_off32).
+template <bool OFF32>
+__device__ __forceinline__ uint64_t *fwd_addr(const OpArgs &A, uint32_t id, bool valid) {
+    if (!OFF32) return op_addr(A, id, valid);
+    const bool scr = id & kScratchBit;
+    const uint32_t off = __umul24(id & kNodeMask, scr ? A.nwords : A.ld32) + A.w;
+    uint64_t *base = scr ? A.rows : A.C;
+    const bool ok = valid && A.wok && id != kNoRow;
+    return ok ? base + off : A.sink;
 }
 
 __device__ __forceinline__ uint32_t sat_index(const OpArgs &A, uint32_t id) {
@@ -556,12 +570,22 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
 // depend on the level just before, so their loads are issued one level
 // early: right after the barrier that starts level l, the compute waves
 // issue the cold loads of level l + 1, then run level l on the values that
-// arrived meanwhile.  The barrier waits for every wave's loads and stores,
-// so the stores of level l - 1 are in memory before any load of level l + 1
-// can read them.  Loader waves keep a ring of three op frames (the level
-// run, the level whose cold loads are in flight, the level being loaded);
-// results alternate between two LDS frames.
+// arrived meanwhile.  A load of level l + 1 reads a row stored at level
+// l - 1 or earlier, by a store issued before that barrier: the workgroup's
+// waves share one CU and its in-order vector memory path, so the load sees
+// it (the barrier itself does not wait for memory operations, which keeps
+// the loads in flight across it).  Loader waves keep a ring of three op
+// frames (the level run, the level whose cold loads are in flight, the
+// level being loaded); results alternate between two LDS frames.
 constexpr uint32_t kFwdFrames = 3;
+
+// The lane group's index, opaque to the optimizer: the op indices derived
+// from it are then formed where they are used instead of being hoisted out
+// of the level loop into registers of their own (one per op slot).
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 template <int UC>
 struct ColdVals {
@@ -569,29 +593,33 @@ struct ColdVals {
 };
 
 // The cold operands of the level in `frame` (forwarded ones read the sink).
-template <int SW, int UC>
+template <int SW, int UC, bool OFF32>
 __device__ __forceinline__ void fwd_issue(OpArgs &A, const op4 *frame, uint32_t cnt,
                                           ColdVals<UC> &c) {
+    constexpr uint32_t NG = (1024 - kLoaderThreads) / SW;
+    const uint32_t g = opaque(A.grp);
 #pragma unroll
     for (int k = 0; k < UC; ++k) {
-        const uint32_t j = A.grp + k * A.ngrp;
+        const uint32_t j = g + k * NG;
         const op4 o = frame[min(j, kOpsLevelCap - 1)];
         const bool v = j < cnt;
         const bool hx = o.x & kFwdHot, hy = o.y & kFwdHot;
-        c.x[k] = *op_addr(A, o.x, v && !hx);
-        c.y[k] = *op_addr(A, o.y, v && !hy);
+        c.x[k] = *fwd_addr<OFF32>(A, o.x, v && !hx);
+        c.y[k] = *fwd_addr<OFF32>(A, o.y, v && !hy);
         A.loaded += ((v && A.wok && !hx) ? 1u : 0u) + ((v && A.wok && !hy) ? 1u : 0u);
     }
 }
 
 // Runs the level in `frame` with its cold values in c.
-template <int SW, int UC>
+template <int SW, int UC, bool OFF32>
 __device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t cnt,
                                           const ColdVals<UC> &c, const uint64_t *res_prev,
                                           uint64_t *res_cur, uint32_t lig) {
+    constexpr uint32_t NG = (1024 - kLoaderThreads) / SW;
+    const uint32_t g = opaque(A.grp);
 #pragma unroll
     for (int k = 0; k < UC; ++k) {
-        const uint32_t j = A.grp + k * A.ngrp;
+        const uint32_t j = g + k * NG;
         const op4 o = frame[min(j, kOpsLevelCap - 1)];
         const bool v = j < cnt;
         // a cold operand's low bits are a row id: its (unused) read is
@@ -604,13 +632,13 @@ __device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t 
         // kNoRow has the no-store bit too: it is never stored
         const bool s1 = v && !(o.z & kFwdNoStore);
         const bool s2 = v && !(o.w & kFwdNoStore);
-        *op_addr(A, o.z, s1) = r;
-        *op_addr(A, o.w, s2) = r;
+        *fwd_addr<OFF32>(A, o.z, s1) = r;
+        *fwd_addr<OFF32>(A, o.w, s2) = r;
         A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
     }
 }
 
-template <int SW, int UC>
+template <int SW, int UC, bool OFF32>
 __global__ void __launch_bounds__(1024)
 k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
             uint64_t *__restrict__ scratch, unsigned long long *__restrict__ traffic) {
@@ -638,6 +666,7 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
     A.rows = scratch + (size_t)gridDim.x * kRoworSinkWords;
     A.loaded = A.stored = 0;
+    A.ld32 = (uint32_t)ld;
     if (loader) {
         // levels 0 and 1 before the first barrier; at the barrier that
         // starts level l, frame (l + 2) % 3 receives level l + 2.  Starts
@@ -675,23 +704,199 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     }
     const uint32_t lig = ctid % SW;
     ColdVals<UC> cA, cB;
-    // runs level l with cur holding its cold values, after issuing level
-    // l + 1's into nxt
+    // Runs level l with cur holding its cold values, after issuing level
+    // l + 1's into nxt.  The issue is unconditional (a level past the last
+    // has no ops: every lane loads its sink) and level 0's own issue comes
+    // before the loop, so the code between a load and its use is the same on
+    // every path: the compiler's wait before the use then leaves the loads
+    // issued after it in flight (a join with a path that skipped them would
+    // make it wait for those too).
     auto period = [&](uint32_t l, ColdVals<UC> &cur, ColdVals<UC> &nxt) {
         __syncthreads();
-        if (l == 0) fwd_issue<SW, UC>(A, frame[0], fcount[0], cur);
-        if (l + 1 < L) {
-            const uint32_t nf = (l + 1) % kFwdFrames;
-            fwd_issue<SW, UC>(A, frame[nf], fcount[nf], nxt);
-        }
+        const uint32_t nf = (l + 1) % kFwdFrames;
+        fwd_issue<SW, UC, OFF32>(A, frame[nf], fcount[nf], nxt);
         const uint32_t cf = l % kFwdFrames;
-        fwd_apply<SW, UC>(A, frame[cf], fcount[cf], cur, results + (size_t)((l + 1) & 1u) * kFrameWords,
-                          results + (size_t)(l & 1u) * kFrameWords, lig);
+        fwd_apply<SW, UC, OFF32>(A, frame[cf], fcount[cf], cur,
+                                 results + (size_t)((l + 1) & 1u) * kFrameWords,
+                                 results + (size_t)(l & 1u) * kFrameWords, lig);
     };
-    for (uint32_t l = 0; l < L; l += 2) {
-        period(l, cA, cB);
+    // level 0's cold values (frame 0 is written before the loaders' first
+    // barrier, which the first period waits at)
+    __syncthreads();
+    fwd_issue<SW, UC, OFF32>(A, frame[0], fcount[0], cA);
+    {
+        fwd_issue<SW, UC, OFF32>(A, frame[1], fcount[1], cB);
+        fwd_apply<SW, UC, OFF32>(A, frame[0], fcount[0], cA, results + kFrameWords, results, lig);
+    }
+    for (uint32_t l = 1; l < L; l += 2) {
+        period(l, cB, cA);
         if (l + 1 >= L) break;
-        period(l + 1, cB, cA);
+        period(l + 1, cA, cB);
+    }
+    count_add(traffic, A.loaded);
+    count_add(traffic + 1, A.stored);
+}
+
+// The same recurrence on 16-word slices (whole 128-byte lines of a row):
+// two result frames of 769 x 128 bytes would not fit in LDS beside the op
+// frames, so one frame serves both levels.  A level reads its forwarded
+// operands from the frame, stores its results to memory, waits at a second
+// barrier (LDS only: the next level's cold loads stay in flight) until
+// every wave has read the frame, then writes its results into it.  Cold
+// values are held for y of every op and for x of the first UCX ops per lane
+// group only (the schedule puts the ops with both operands from memory
+// first; about 1 % of an activity-driven stream's ops).  A lane whose op
+// past those has x from memory too (levels right after the identity)
+// loads it on the spot and waits for all its loads.  At n = 10^5 its 98
+// workgroups take 174 ms for the plain recurrence where 196 of 8 words
+// take 121 ms; it is the kernel of slice_words = 16.
+template <int UC, int UCX>
+struct ColdY {
+    uint64_t y[UC], x[UCX];
+};
+
+template <int SW, int UC, int UCX, bool OFF32>
+__device__ __forceinline__ void fwd1_issue(OpArgs &A, const op4 *frame, uint32_t cnt,
+                                           ColdY<UC, UCX> &c) {
+    constexpr uint32_t NG = (1024 - kLoaderThreads) / SW;
+    const uint32_t g = opaque(A.grp);
+#pragma unroll
+    for (int k = 0; k < UC; ++k) {
+        const uint32_t j = g + k * NG;
+        const op4 o = frame[min(j, kOpsLevelCap - 1)];
+        const bool v = j < cnt;
+        const bool hy = o.y & kFwdHot;
+        c.y[k] = *fwd_addr<OFF32>(A, o.y, v && !hy);
+        A.loaded += (v && A.wok && !hy) ? 1u : 0u;
+        if (k < UCX) {
+            const bool hx = o.x & kFwdHot;
+            c.x[k] = *fwd_addr<OFF32>(A, o.x, v && !hx);
+            A.loaded += (v && A.wok && !hx) ? 1u : 0u;
+        }
+    }
+}
+
+// Waits for this wave's LDS accesses, then for every wave of the workgroup;
+// memory operations in flight stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int SW, int UC, int UCX, bool OFF32>
+__device__ __forceinline__ void fwd1_apply(OpArgs &A, const op4 *frame, uint32_t cnt,
+                                           const ColdY<UC, UCX> &c, uint64_t *res,
+                                           uint32_t lig) {
+    constexpr uint32_t NG = (1024 - kLoaderThreads) / SW;
+    uint64_t r[UC];
+    const uint32_t g = opaque(A.grp);
+#pragma unroll
+    for (int k = 0; k < UC; ++k) {
+        const uint32_t j = g + k * NG;
+        const op4 o = frame[min(j, kOpsLevelCap - 1)];
+        const bool v = j < cnt;
+        const uint64_t lx = res[min(o.x & kFwdSlotMask, kFwdLevelCap) * SW + lig];
+        const uint64_t ly = res[min(o.y & kFwdSlotMask, kFwdLevelCap) * SW + lig];
+        uint64_t x = (o.x & kFwdHot) ? lx : (k < UCX ? c.x[k < UCX ? k : 0] : 0ull);
+        if (k >= UCX && v && !(o.x & kFwdHot)) {
+            x = *fwd_addr<OFF32>(A, o.x, true);
+            // vmcnt(0) (expcnt and lgkmcnt left at their maxima): the wait
+            // pass then knows the value has landed
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            A.loaded += A.wok ? 1u : 0u;
+        }
+        r[k] = x | ((o.y & kFwdHot) ? ly : c.y[k]);
+        const bool s1 = v && !(o.z & kFwdNoStore);
+        const bool s2 = v && !(o.w & kFwdNoStore);
+        *fwd_addr<OFF32>(A, o.z, s1) = r[k];
+        *fwd_addr<OFF32>(A, o.w, s2) = r[k];
+        A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+    }
+    lds_barrier();
+    const uint32_t g2 = opaque(A.grp);
+#pragma unroll
+    for (int k = 0; k < UC; ++k) {
+        const uint32_t j = g2 + k * NG;
+        res[(j < cnt ? j : kFwdLevelCap) * SW + lig] = r[k];
+    }
+}
+
+template <int SW, int UC, int UCX, bool OFF32>
+__global__ void __launch_bounds__(1024)
+k_rowor_fwd1(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
+             uint64_t *__restrict__ scratch, unsigned long long *__restrict__ traffic) {
+    static_assert(((1024 - kLoaderThreads) / SW) * UC >= kFwdLevelCap, "a level per pass");
+    __shared__ op4 frame[kFwdFrames][kOpsLevelCap];
+    __shared__ uint32_t fcount[kFwdFrames];
+    // dynamic: one result frame of kFwdLevelCap + 1 slots (the last one a
+    // sink) of SW words
+    extern __shared__ uint64_t results[];
+    const uint32_t L = s.L;
+    if (L == 0 || s.nops == 0) return;
+    const uint32_t tid = threadIdx.x;
+    const bool loader = tid < kLoaderThreads;
+    const uint32_t ctid = tid - kLoaderThreads;
+    const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
+    OpArgs A;
+    A.C = C;
+    A.ldz = (size_t)ld;
+    A.nwords = nwords;
+    A.w = slice * SW + (ctid % SW);
+    A.wok = !loader && A.w < nwords;
+    A.grp = ctid / SW;
+    A.ngrp = (blockDim.x - kLoaderThreads) / SW;
+    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
+    A.rows = scratch + (size_t)gridDim.x * kRoworSinkWords;
+    A.loaded = A.stored = 0;
+    A.ld32 = (uint32_t)ld;
+    if (loader) {
+        // as in k_rowor_fwd, with the second barrier of every level
+        put_level(frame[0], fetch_ops(s, level_start(s, 0), tid), tid);
+        put_level(frame[1], fetch_ops(s, level_start(s, 1), tid), tid);
+        if (tid == 0) {
+            fcount[0] = level_start(s, 1) - level_start(s, 0);
+            fcount[1] = level_start(s, 2) - level_start(s, 1);
+        }
+        uint32_t p2 = level_start(s, 2), p3 = level_start(s, 3);
+        HeldOps hA = fetch_ops(s, p2, tid);
+        uint32_t p4 = level_start(s, 4);
+        HeldOps hB = fetch_ops(s, p3, tid);
+        auto feed = [&](uint32_t l, HeldOps &h) {
+            __syncthreads();
+            const uint32_t nf = (l + 2) % kFwdFrames;
+            put_level(frame[nf], h, tid);
+            if (tid == 0) fcount[nf] = p3 - p2;
+            const uint32_t q = p4;
+            p2 = p3;
+            p3 = q;
+            p4 = level_start(s, l + 5);
+            h = fetch_ops(s, q, tid);
+            lds_barrier();
+        };
+        for (uint32_t l = 0; l < L; l += 2) {
+            feed(l, hA);
+            if (l + 1 >= L) break;
+            feed(l + 1, hB);
+        }
+        return;
+    }
+    const uint32_t lig = ctid % SW;
+    ColdY<UC, UCX> cA, cB;
+    // as in k_rowor_fwd: level 0 peeled, every issue unconditional
+    auto period = [&](uint32_t l, ColdY<UC, UCX> &cur, ColdY<UC, UCX> &nxt) {
+        __syncthreads();
+        const uint32_t nf = (l + 1) % kFwdFrames;
+        fwd1_issue<SW, UC, UCX, OFF32>(A, frame[nf], fcount[nf], nxt);
+        const uint32_t cf = l % kFwdFrames;
+        fwd1_apply<SW, UC, UCX, OFF32>(A, frame[cf], fcount[cf], cur, results, lig);
+    };
+    __syncthreads();
+    fwd1_issue<SW, UC, UCX, OFF32>(A, frame[0], fcount[0], cA);
+    fwd1_issue<SW, UC, UCX, OFF32>(A, frame[1], fcount[1], cB);
+    fwd1_apply<SW, UC, UCX, OFF32>(A, frame[0], fcount[0], cA, results, lig);
+    for (uint32_t l = 1; l < L; l += 2) {
+        period(l, cB, cA);
+        if (l + 1 >= L) break;
+        period(l + 1, cA, cB);
     }
     count_add(traffic, A.loaded);
     count_add(traffic + 1, A.stored);
@@ -971,11 +1176,27 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
 
 template <int SW, int UC>
 hipError_t rowor_fwd_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                             uint64_t *scratch, unsigned long long *traffic, hipStream_t st) {
+                             uint64_t *scratch, bool off32, unsigned long long *traffic,
+                             hipStream_t st) {
     const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
     const size_t lds = sizeof(uint64_t) * 2 * (kFwdLevelCap + 1) * SW;
-    auto k = k_rowor_fwd<SW, UC>;
+    auto k = off32 ? k_rowor_fwd<SW, UC, true> : k_rowor_fwd<SW, UC, false>;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, nwords, s, scratch, traffic);
+    return hipGetLastError();
+}
+
+template <int SW, int UC, int UCX>
+hipError_t rowor_fwd1_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
+                              uint64_t *scratch, bool off32, unsigned long long *traffic,
+                              hipStream_t st) {
+    const uint32_t nwords = (n + 63) / 64;
+    const uint32_t slices = (nwords + SW - 1) / SW;
+    const size_t lds = sizeof(uint64_t) * (kFwdLevelCap + 1) * SW;
+    auto k = off32 ? k_rowor_fwd1<SW, UC, UCX, true> : k_rowor_fwd1<SW, UC, UCX, false>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
@@ -984,20 +1205,31 @@ hipError_t rowor_fwd_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t l
 }
 
 bool rowor_fwd_supported(uint32_t n, uint32_t slice_words) {
-    return slice_words <= 8 && n < (1u << 30);
+    return slice_words <= 16 && n < (1u << 30);
+}
+
+// Row offsets (row * stride + word) of the matrix and of the scratch rows
+// fit 32 bits, with rows and strides below 2^24 (fwd_addr).
+static bool rowor_fwd_off32(uint32_t n, int64_t ld, uint32_t scratch_rows) {
+    const uint64_t nwords = (n + 63) / 64;
+    return n < (1u << 24) && ld < (1 << 24) && scratch_rows + 1 < (1u << 24) &&
+           (uint64_t)n * (uint64_t)ld < (1ull << 32) &&
+           (uint64_t)(scratch_rows + 1) * nwords < (1ull << 32);
 }
 
 hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                            uint32_t slice_words, uint64_t *scratch,
+                            uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
                             unsigned long long *traffic, hipStream_t st) {
     if (s.L == 0) return hipSuccess;
     if (!rowor_fwd_supported(n, slice_words)) return hipErrorInvalidValue;
+    const bool o32 = rowor_fwd_off32(n, ld, scratch_rows);
     switch (slice_words) {
         // UC: ops per lane group, so that (896 / SW) * UC >= kFwdLevelCap
-        case 1: return rowor_fwd_variant<1, 1>(s, n, C, ld, scratch, traffic, st);
-        case 2: return rowor_fwd_variant<2, 2>(s, n, C, ld, scratch, traffic, st);
-        case 4: return rowor_fwd_variant<4, 4>(s, n, C, ld, scratch, traffic, st);
-        case 8: return rowor_fwd_variant<8, 7>(s, n, C, ld, scratch, traffic, st);
+        case 1: return rowor_fwd_variant<1, 1>(s, n, C, ld, scratch, o32, traffic, st);
+        case 2: return rowor_fwd_variant<2, 2>(s, n, C, ld, scratch, o32, traffic, st);
+        case 4: return rowor_fwd_variant<4, 4>(s, n, C, ld, scratch, o32, traffic, st);
+        case 8: return rowor_fwd_variant<8, 7>(s, n, C, ld, scratch, o32, traffic, st);
+        case 16: return rowor_fwd1_variant<16, 14, 2>(s, n, C, ld, scratch, o32, traffic, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1015,6 +1247,7 @@ hipError_t launch_slice_full_state(const uint64_t *C, int64_t ld, uint32_t n,
         case 2: hipLaunchKernelGGL(k_slice_full_state<2>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
         case 4: hipLaunchKernelGGL(k_slice_full_state<4>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
         case 8: hipLaunchKernelGGL(k_slice_full_state<8>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 16: hipLaunchKernelGGL(k_slice_full_state<16>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -644,40 +644,68 @@ namespace tn {
 // level reads the row, if at all, from the forwarded copy, so memory never
 // needs the value.  Rows are keyed n + id for scratch rows.
 void fwd_schedule(const std::vector<uint32_t> &lvl_op, const std::vector<uint32_t> &ops,
-                  uint32_t n, uint32_t scratch_rows, std::vector<uint32_t> &flvl,
+                  uint32_t n, uint32_t scratch_rows, uint32_t cap, std::vector<uint32_t> &flvl,
                   std::vector<uint32_t> &fops) {
+    if (cap == 0 || cap > kFwdLevelCap) cap = kFwdLevelCap;
     const uint32_t Lops = lvl_op.empty() ? 0 : (uint32_t)lvl_op.size() - 1;
-    flvl.clear();
-    flvl.push_back(0);
-    for (uint32_t l = 0; l < Lops; ++l) {
-        const uint32_t a = lvl_op[l], b = lvl_op[l + 1], k = b - a;
-        const uint32_t parts = (k + kFwdLevelCap - 1) / kFwdLevelCap;
-        for (uint32_t p = 1; p <= parts; ++p) flvl.push_back(a + (uint32_t)((uint64_t)k * p / parts));
-    }
-    const uint32_t L = (uint32_t)flvl.size() - 1;
-    fops.assign(ops.begin(), ops.end());
     const size_t keys = (size_t)n + scratch_rows + 1;
     auto key = [n](uint32_t id) -> size_t {
         return (id & kScratchBit) ? (size_t)n + (id & kNodeMask) : (size_t)id;
     };
+    flvl.assign(1, 0);
+    fops.clear();
+    fops.reserve(ops.size());
+    // the ops in their new order, without the forwarding bits
+    std::vector<uint32_t> rops;
+    rops.reserve(ops.size());
     // forward: the level and index of each row's last write
     std::vector<uint32_t> wl(keys, 0xffffffffu), wj(keys, 0);
-    for (uint32_t l = 0; l < L; ++l) {
-        const uint32_t q0 = flvl[l], q1 = flvl[l + 1];
-        for (uint32_t q = q0; q < q1; ++q) {
-            uint32_t *o = &fops[4 * (size_t)q];
-            for (int i = 0; i < 2; ++i) {
-                const size_t k = key(ops[4 * (size_t)q + i]);
-                if (l > 0 && wl[k] == l - 1) o[i] = kFwdHot | wj[k];
+    std::vector<uint32_t> rest, next, both, other;
+    uint32_t L = 0;  // forwarded levels so far
+    for (uint32_t l = 0; l < Lops; ++l) {
+        rest.clear();
+        for (uint32_t q = lvl_op[l]; q < lvl_op[l + 1]; ++q) rest.push_back(q);
+        // an op level becomes parts of at most cap ops, of even size; an
+        // operand is forwarded iff its row was written by the part just
+        // before, so it is decided part by part (ops of one op level touch
+        // disjoint rows)
+        while (!rest.empty()) {
+            const size_t parts = (rest.size() + cap - 1) / cap;
+            const size_t target = (rest.size() + parts - 1) / parts;
+            auto hot = [&](uint32_t id) { return L > 0 && wl[key(id)] == L - 1; };
+            both.clear();
+            other.clear();
+            next.clear();
+            for (uint32_t q : rest) {
+                const bool cold2 = !hot(ops[4 * (size_t)q]) && !hot(ops[4 * (size_t)q + 1]);
+                if (both.size() + other.size() >= target)
+                    next.push_back(q);
+                else
+                    (cold2 ? both : other).push_back(q);
             }
+            const uint32_t base = (uint32_t)(rops.size() / 4);
+            uint32_t j = 0;
+            for (const std::vector<uint32_t> *grp : {&both, &other})
+                for (uint32_t q : *grp) {
+                    uint32_t x = ops[4 * (size_t)q], y = ops[4 * (size_t)q + 1];
+                    if (!hot(x) && hot(y)) std::swap(x, y);  // the one from memory goes second
+                    const uint32_t d1 = ops[4 * (size_t)q + 2], d2 = ops[4 * (size_t)q + 3];
+                    rops.insert(rops.end(), {x, y, d1, d2});
+                    fops.insert(fops.end(), {hot(x) ? kFwdHot | wj[key(x)] : x,
+                                             hot(y) ? kFwdHot | wj[key(y)] : y, d1, d2});
+                    ++j;
+                }
+            for (uint32_t q = base; q < base + j; ++q)
+                for (int i = 2; i < 4; ++i) {
+                    const uint32_t d = rops[4 * (size_t)q + i];
+                    if (d == kNoRow) continue;
+                    wl[key(d)] = L;
+                    wj[key(d)] = q - base;
+                }
+            flvl.push_back(base + j);
+            ++L;
+            rest.swap(next);
         }
-        for (uint32_t q = q0; q < q1; ++q)
-            for (int i = 2; i < 4; ++i) {
-                const uint32_t d = ops[4 * (size_t)q + i];
-                if (d == kNoRow) continue;
-                wl[key(d)] = l;
-                wj[key(d)] = q - q0;
-            }
     }
     // backward: the level of each row's next write
     std::fill(wl.begin(), wl.end(), 0xffffffffu);
@@ -685,13 +713,13 @@ void fwd_schedule(const std::vector<uint32_t> &lvl_op, const std::vector<uint32_
         const uint32_t q0 = flvl[l], q1 = flvl[l + 1];
         for (uint32_t q = q0; q < q1; ++q)
             for (int i = 2; i < 4; ++i) {
-                const uint32_t d = ops[4 * (size_t)q + i];
+                const uint32_t d = rops[4 * (size_t)q + i];
                 if (d == kNoRow) continue;
                 if (wl[key(d)] == l + 1) fops[4 * (size_t)q + i] = d | kFwdNoStore;
             }
         for (uint32_t q = q0; q < q1; ++q)
             for (int i = 2; i < 4; ++i) {
-                const uint32_t d = ops[4 * (size_t)q + i];
+                const uint32_t d = rops[4 * (size_t)q + i];
                 if (d != kNoRow) wl[key(d)] = l;
             }
     }

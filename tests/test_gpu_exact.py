@@ -139,10 +139,10 @@ def test_saturation_counts_match_host_model(flags):
             p = tn.Plan(n, s, d, t, flags)
             for sat in (True, False):
                 ctx.saturation(sat)
-                for sw in (1, 4, 8, 64):
+                for sw in (1, 4, 8, 16, 64):
                     C = p.execute(slice_words=sw)
                     assert (host(C) == want).all(), (case, sat, sw)
-                    if not sat and sw <= 8:
+                    if not sat and sw <= 16:
                         # the plain recurrence on the forwarded schedule
                         ld, st = satmodel.fwd_traffic(n, sch)
                     else:
@@ -217,6 +217,24 @@ def test_full_size_saturation_off_gives_same_matrix(c2):
     nw = oracle.words(100_000)
     assert ld_off < 2 * c2["plan"].stats["ops"] * nw
     assert ld_on < ld_off and st_on < st_off
+
+
+def test_full_size_sixteen_word_slices(c2):
+    # whole 128-byte lines per row access: the one-frame forwarding kernel
+    # (saturation off) and, with saturation, its forwarding phase and the
+    # slice state of 16-word slices
+    import satmodel
+    ctx = tn.get_context()
+    C1 = c2["plan"].execute(slice_words=16).clone()
+    ctx.saturation(False)
+    try:
+        C0 = c2["plan"].execute(slice_words=16)
+        traffic = ctx.last_traffic()
+    finally:
+        ctx.saturation(True)
+    assert torch.equal(C0, c2["C"]) and torch.equal(C1, c2["C"])
+    sch = tn.host_schedule(100_000, c2["s"], c2["d"], c2["t"])
+    assert traffic == satmodel.fwd_traffic(100_000, sch)
 
 
 def test_full_size_streamed_build_stops_early(c2):

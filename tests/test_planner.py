@@ -294,6 +294,48 @@ def test_forwarded_schedule_replay_matches_oracle(flags):
         assert (fo[:, :2] & FWD).any() and ((fo[:, 2:] != NOROW) & (fo[:, 2:] & FWD != 0)).any()
 
 
+def fwd_layout_ok(sch):
+    """Layout rules of the forwarded form: within a level the ops with both
+    operands from memory come first, an op with one operand from memory has
+    it second, and a forwarded operand names an op of the level before."""
+    lv, fo = sch["fwd_lvl"], sch["fwd_ops"].astype(np.int64)
+    cx, cy = (fo[:, 0] & FWD) == 0, (fo[:, 1] & FWD) == 0
+    assert not (cx & ~cy).any()
+    prev = 0
+    for l in range(len(lv) - 1):
+        both = (cx & cy)[lv[l]:lv[l + 1]]
+        k = int(both.sum())
+        assert both[:k].all(), l
+        for c in (0, 1):
+            hot = fo[lv[l]:lv[l + 1], c]
+            hot = hot[(hot & FWD) != 0] & 0x3FF
+            assert (hot < prev).all(), l
+        prev = lv[l + 1] - lv[l]
+
+
+@pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.FORWARD])
+@pytest.mark.parametrize("cap", [0, 300, 97])
+def test_forwarded_schedule_layout_and_level_caps(cap, flags):
+    # the kernels' form (cap 0 = 768) and smaller caps, which split most
+    # levels into parts decided one after the other: the replay must still
+    # give the oracle's matrix, and splitting must only lose forwarding
+    cases = [T.activity_driven(400, 6000, 300, seed=67), T.uniform_pairs(2000, 40000, 400, seed=68),
+             T.star_steps(300, 400, 12, seed=69)]
+    for k, (s_, d_, t_) in enumerate(cases):
+        n = (400, 2000, 300)[k]
+        sch = tn.host_schedule(n, s_, d_, t_, flags, fwd_level_cap=cap)
+        fwd_layout_ok(sch)
+        assert np.diff(sch["fwd_lvl"]).max() <= (cap or 768)
+        ref = oracle.forward_matrix if flags & tn.FORWARD else oracle.reverse_matrix
+        want = ref(n, s_, d_, t_, directed=bool(flags & tn.DIRECTED),
+                   sequential=bool(flags & tn.TIES_SEQUENTIAL))
+        assert (simulate_fwd(n, sch) == want).all(), (k, cap)
+        if cap:
+            full = tn.host_schedule(n, s_, d_, t_, flags)
+            hot = lambda sc: int(((sc["fwd_ops"][:, :2].astype(np.int64) & FWD) != 0).sum())
+            assert hot(sch) <= hot(full)
+
+
 def test_forwarded_schedule_splits_wide_levels():
     # one time step of 3000 events: levels of up to 1024 ops become parts of
     # at most 768, and the replay still matches
