@@ -72,7 +72,10 @@ def kernel_source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h", "tn_device.h"),
+# the kernels of one saturating launch on a network of 16,384+ nodes: the
+# zero phase, the forwarding phase, the slice state, the saturating rest
+ROWOR_SAT_KERNELS = "k_rowor_global|k_rowor_fwd|k_slice_full_state"
+KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h", "tn_device.h", "tn_plan.cpp"),
                   "rowor_plain": ("tn_kernels.hip", "tn_internal.h", "tn_device.h", "tn_plan.cpp"),
                   "batch": ("tn_batch.hip", "tn_batch.h", "tn_batch.cpp", "tn_internal.h"),
                   "recombine": ("tn_hash.hip", "tn_hash.h")}
@@ -169,6 +172,23 @@ def cpu_baseline_exact(n, s, d, t, budget_s: float, forward: bool = False):
     return rec
 
 
+def counter_roofline(traffic, ms, kernel, dense, dense_gbs, rows_in):
+    """Roofline of a launch that skips saturated rows: the HBM bytes rocprofv3
+    counted per launch (FETCH_SIZE + WRITE_SIZE, committed profile of the
+    same kernel source) over its mean time.  The plain recurrence's bytes
+    are no measure of such a launch (most rows are never moved), so they are
+    reported apart, as a dense equivalent."""
+    achieved = traffic / (ms * 1e-3) / 1e9 if traffic else None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+            "kernel": kernel, "avg_launch_ms": ms, "rows_in": rows_in,
+            "basis": "counted HBM bytes per launch / mean launch time (saturated rows are "
+                     "skipped; null when no profile of the current source is committed)",
+            "dense_equivalent": {"bytes": dense, "GBs": dense_gbs,
+                                 "note": "the plain recurrence's row transfers over the same "
+                                         "time: not a bandwidth, it exceeds the peak"}}
+
+
 def run_exact(args):
     import numpy as np
     import torch
@@ -213,18 +233,21 @@ def run_exact(args):
     assert o.sum() == i.sum(), "sum of out-sizes differs from sum of in-sizes"
     # the plain leg: the same plan with saturation off, so that every op moves
     # its rows (the forwarded kernel); its launches give the roofline
-    ctx.saturation(False)
-    try:
-        p_elapsed, pkms, pper = timed(ctx, lambda: plan.execute(C, slice_words=args.slice_words),
-                                      max(2, args.steps // 2), 1)
-        pld, pst = ctx.last_traffic()
-    finally:
-        ctx.saturation(True)
-    # (the tests compare whole matrices; here the sizes of both legs)
-    tn._lib.check(tn.lib.tn_component_sizes(ctx.bind_stream(), n, cp(C), C.stride(0), cp(out),
-                                            cp(inn)))
-    assert np.array_equal(out.cpu().numpy(), o) and np.array_equal(inn.cpu().numpy(), i), \
-        "plain recurrence differs from the saturating kernel"
+    if args.no_plain:
+        pkms, pper, pld, pst = {"rowor": float("nan")}, {}, 0, 0
+    else:
+        ctx.saturation(False)
+        try:
+            p_elapsed, pkms, pper = timed(ctx, lambda: plan.execute(C, slice_words=args.slice_words),
+                                          max(2, args.steps // 2), 1)
+            pld, pst = ctx.last_traffic()
+        finally:
+            ctx.saturation(True)
+        # (the tests compare whole matrices; here the sizes of both legs)
+        tn._lib.check(tn.lib.tn_component_sizes(ctx.bind_stream(), n, cp(C), C.stride(0), cp(out),
+                                                cp(inn)))
+        assert np.array_equal(out.cpu().numpy(), o) and np.array_equal(inn.cpu().numpy(), i), \
+            "plain recurrence differs from the saturating kernel"
     plain_ms = pkms["rowor"]
     achieved = alg / (plain_ms * 1e-3) / 1e9
     plain_traffic = load_traffic("rowor_plain", workload)
@@ -252,7 +275,10 @@ def run_exact(args):
     r["plain"] = {"events_per_s": m / (plain_ms * 1e-3), "avg_launch_ms": plain_ms,
                   "launch_ms_all": pper.get("rowor", []),
                   "row_words_loaded": pld, "row_words_stored": pst}
-    r["saturating"] = {"kernel": "k_rowor_global (zero-phase launch + the remaining levels)",
+    if args.no_plain:
+        r["roofline"] = r["plain"] = None
+    r["saturating"] = {"kernel": "k_rowor_global zero phase, k_rowor_fwd until the ops reach "
+                                 "10 n, k_slice_full_state, k_rowor_global for the rest",
                        "avg_launch_ms": sat_ms, "moved_bytes": moved,
                        "moved_achieved": moved / (sat_ms * 1e-3) / 1e9,
                        "moved_frac": moved / (sat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -326,7 +352,17 @@ def run_online(args):
     C = tn.api.alloc_matrix(n)
     elapsed, kms, _ = timed(ctx, lambda: plan.execute(C), args.steps, args.warmup)
     alg = algorithmic_bytes(st, n)
-    achieved = alg / (kms["rowor"] * 1e-3) / 1e9
+    # the plain leg (saturation off: every op moves its rows) gives the roofline
+    ctx.saturation(False)
+    try:
+        C0 = tn.api.alloc_matrix(n)
+        _, pkms, _ = timed(ctx, lambda: plan.execute(C0), max(2, args.steps // 2), 1)
+        pld, pst = ctx.last_traffic()
+    finally:
+        ctx.saturation(True)
+    assert torch.equal(C0, C), "plain forward recurrence differs from the saturating kernel"
+    del C0
+    achieved = alg / (pkms["rowor"] * 1e-3) / 1e9
     plan.close()
     # batch boundaries at the first event of a time step (a batch starts
     # strictly after the last time step applied)
@@ -359,10 +395,11 @@ def run_online(args):
                        "host threads and applied to the live matrix (one step = one batch)")
     r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rowor_global on the resident forward plan",
-                     "algorithmic_bytes": alg, "avg_launch_ms": kms["rowor"],
-                     "levels": st["op_levels"],
-                     "us_per_level": 1e3 * kms["rowor"] / max(1, st["op_levels"])}
+                     "kernel": "k_rowor_fwd on the resident forward plan, saturation off "
+                               "(every op applied)",
+                     "algorithmic_bytes": alg, "avg_launch_ms": pkms["rowor"],
+                     "row_bytes_moved": 8.0 * (pld + pst),
+                     "saturating_launch_ms": kms["rowor"], "levels": st["op_levels"]}
     r["kernels_ms"] = kms
     r["forward_plan"] = {"events_per_s": m * args.steps / elapsed, "levels": st["levels"],
                          "op_levels": st["op_levels"], "ops": st["ops"],
@@ -443,16 +480,10 @@ def run_hashed(args):
     # where the proxy rows live in the tuned shape: LDS-resident slices
     # (K = 4096), or global-memory tiles streaming through L2 and HBM
     lds_bound = 2 * lds_tiles >= tiles
-    peak = LDS_PEAK_GBS if lds_bound else HBM_PEAK_GBS
-    pmc_key = workload if K == 4096 else f"{workload}_K{K}"
-    r["roofline"] = {"bound": "lds" if lds_bound else "hbm", "achieved": achieved, "peak": peak,
-                     "unit": "GB/s", "frac": achieved / peak,
-                     "traffic": load_traffic("batch", pmc_key),
-                     "kernel": "k_batch_persistent", "algorithmic_bytes": dense,
-                     "bytes_note": "dense-equivalent row transfers of the H proxy streams "
-                                   "(saturated rows are skipped, so this can exceed the peak)",
-                     "hbm_equivalent_frac": achieved / HBM_PEAK_GBS,
-                     "avg_launch_ms": proxy_ms}
+    pmc_key = f"{workload}_K{K}"
+    r["roofline"] = counter_roofline(load_traffic("batch", pmc_key), proxy_ms,
+                                     "k_batch_persistent", dense, achieved,
+                                     "lds" if lds_bound else "global")
     r["hashed"] = {"H_times_m_events_per_s": H * m / (proxy_ms * 1e-3),
                    "recombine_ms": rec_ms,
                    "end_to_end_ms": 1e3 * compress_wall + proxy_ms + rec_ms,
@@ -683,12 +714,9 @@ def run_batched(args):
     # the tuned shape decides where the rows live: LDS-resident slices, or
     # global-memory tiles whose rows stream through L2 and HBM
     lds_bound = 2 * lds_tiles >= tiles
-    peak = LDS_PEAK_GBS if lds_bound else HBM_PEAK_GBS
-    r["roofline"] = {"bound": "lds" if lds_bound else "hbm", "achieved": achieved, "peak": peak,
-                     "unit": "GB/s", "frac": achieved / peak,
-                     "traffic": load_traffic("batch", config["workload"]),
-                     "kernel": "k_batch_persistent", "algorithmic_bytes": dense,
-                     "hbm_equivalent_frac": achieved / HBM_PEAK_GBS, "avg_launch_ms": batch_ms}
+    r["roofline"] = counter_roofline(load_traffic("batch", config["workload"]), batch_ms,
+                                     "k_batch_persistent", dense, achieved,
+                                     "lds" if lds_bound else "global")
     r["batched"] = {"graph_launch_ms": batch_ms, "plain_network_by_network_ms": plain_ms,
                     "speedup_vs_plain": plain_ms / batch_ms, "tiles": tiles,
                     "lds_tiles": lds_tiles, "shape": b.shape(), "host_plan_wall_s": plan_wall,
@@ -1031,8 +1059,9 @@ def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, la
     for the plain device copy of calib_mib MiB in the same run.  last > 0
     keeps only the kernel's last `last` dispatches (the timed ones, after
     autotuning); a launch is `per_launch` consecutive dispatches."""
-    match = match or {"rowor": "k_rowor_global", "rowor_plain": "k_rowor_fwd",
+    match = match or {"rowor": ROWOR_SAT_KERNELS, "rowor_plain": "k_rowor_fwd",
                       "batch": "k_batch_persistent", "recombine": "k_recombine_est"}[kernel]
+    alts = match.split("|")
     out = {"kernel": match, "workload": workload, "command": command,
            "kernel_source_sha": kernel_source_hash(KERNEL_SOURCES[kernel])}
     known_kib = calib_mib * 1024.0
@@ -1042,7 +1071,8 @@ def summarize_pmc(fetch_csv, write_csv, kernel, workload, command, calib_mib, la
                   or "elementwise" in r["Kernel_Name"]]
         # the calibration copy is the largest copy dispatch of the run
         calib = max(copies) if copies else float("nan")
-        vals = [float(r["Counter_Value"]) for r in rows if match in r["Kernel_Name"]]
+        vals = [float(r["Counter_Value"]) for r in rows
+                if any(a in r["Kernel_Name"] for a in alts)]
         if last:
             vals = vals[-last:]
         factor = known_kib / calib
@@ -1059,8 +1089,9 @@ def summarize_trace(stats_csv, command, top=12, trace_csv=None, match=None, last
                     per_launch=1):
     """Per-kernel stats of a --kernel-trace --stats run; with trace_csv, match
     and last, also the mean duration of the last `last` dispatches of the
-    kernel whose name contains `match` (the timed ones, after autotuning),
-    summed over each launch of `per_launch` consecutive dispatches."""
+    kernels whose names contain `match` (alternatives separated by '|'; the
+    timed ones, after autotuning), summed over each launch of `per_launch`
+    consecutive dispatches."""
     rows = _read_csv(stats_csv)
     lines = [f"command: {command}", "",
              f"{'calls':>6} {'avg ms':>10} {'total ms':>10} {'%':>6}  kernel"]
@@ -1069,8 +1100,9 @@ def summarize_trace(stats_csv, command, top=12, trace_csv=None, match=None, last
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}  "
                      f"{r['Name'][:110]}")
     if trace_csv and match and last:
+        alts = match.split("|")
         ds = [(int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-              for r in _read_csv(trace_csv) if match in r["Kernel_Name"]]
+              for r in _read_csv(trace_csv) if any(a in r["Kernel_Name"] for a in alts)]
         ds.sort()
         tail = [d for _, d in ds[-last:]]
         k = max(1, per_launch)
@@ -1133,6 +1165,9 @@ def main():
                          "profiles of the resident launches alone)")
     ap.add_argument("--no-hashed", action="store_true",
                     help="exact mode: skip the hashed block (the 10^6-node stream)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="exact mode: skip the plain leg (for profiles of the saturating "
+                         "launches alone; the line then has no roofline)")
     ap.add_argument("--hashes", type=int, default=16)
     ap.add_argument("--buckets", type=int, default=4096)
     ap.add_argument("--networks", type=int, default=256)

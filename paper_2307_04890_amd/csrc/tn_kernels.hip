@@ -980,28 +980,46 @@ k_out_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwo
 }
 
 // in[w] = number of rows with bit w: each lane owns one word column over a
-// chunk of rows and adds the words into 16 bit-planes (a bit-sliced ripple
-// counter, 64 column counters at once), then adds the 64 counts to in[].
-constexpr uint32_t kInRowsPerChunk = 512;  // < 2^16: 16 planes suffice; 4x the wavefronts of 2048
-__global__ void __launch_bounds__(64)
+// share of a chunk of rows and adds the words into 16 bit-planes (a
+// bit-sliced ripple counter, 64 column counters at once).  The four waves of
+// a workgroup take quarters of the chunk, add their 64 counts per lane into
+// LDS, and the workgroup adds each column's total to in[] once: one global
+// atomic per column and chunk of kInRowsPerChunk rows.
+constexpr uint32_t kInRowsPerChunk = 4096;  // per wave 1024 < 2^16: 16 planes suffice
+__global__ void __launch_bounds__(256)
 k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwords,
            int32_t *__restrict__ in) {
-    const uint32_t j = blockIdx.x * 64 + threadIdx.x;
-    if (j >= nwords) return;
-    const uint32_t r0 = blockIdx.y * kInRowsPerChunk;
-    const uint32_t r1 = min(n, r0 + kInRowsPerChunk);
-    uint64_t c[16];
+    __shared__ int32_t cnt[64 * 64];  // [bit][column word]: a wave's lanes on distinct banks
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const uint32_t j = blockIdx.x * 64 + lane;
+    const uint32_t share = kInRowsPerChunk / 4;
+    const uint32_t r0 = blockIdx.y * kInRowsPerChunk + wave * share;
+    const uint32_t r1 = min(n, r0 + share);
+    if (j < nwords && r0 < r1) {
+        uint64_t c[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) c[i] = 0;
-    const uint64_t *col = C + j;
-    uint32_t r = r0;
-    for (; r + 8 <= r1; r += 8) {
-        uint64_t x[8];
+        for (int i = 0; i < 16; ++i) c[i] = 0;
+        const uint64_t *col = C + j;
+        uint32_t r = r0;
+        for (; r + 8 <= r1; r += 8) {
+            uint64_t x[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = col[(size_t)(r + q) * (size_t)ld];
+            for (int q = 0; q < 8; ++q) x[q] = col[(size_t)(r + q) * (size_t)ld];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            uint64_t carry = x[q];
+            for (int q = 0; q < 8; ++q) {
+                uint64_t carry = x[q];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const uint64_t t = c[i] & carry;
+                    c[i] ^= carry;
+                    carry = t;
+                }
+            }
+        }
+        for (; r < r1; ++r) {
+            uint64_t carry = col[(size_t)r * (size_t)ld];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const uint64_t t = c[i] & carry;
@@ -1009,23 +1027,18 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
                 carry = t;
             }
         }
-    }
-    for (; r < r1; ++r) {
-        uint64_t carry = col[(size_t)r * (size_t)ld];
+        for (uint32_t b = 0; b < 64; ++b) {
+            int32_t v = 0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const uint64_t t = c[i] & carry;
-            c[i] ^= carry;
-            carry = t;
+            for (int i = 0; i < 16; ++i) v |= (int32_t)((c[i] >> b) & 1ull) << i;
+            if (v) atomicAdd(&cnt[b * 64 + lane], v);
         }
     }
-    for (uint32_t b = 0; b < 64; ++b) {
-        const uint32_t node = 64 * j + b;
-        if (node >= n) break;
-        int32_t cnt = 0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) cnt |= (int32_t)((c[i] >> b) & 1ull) << i;
-        if (cnt) atomicAdd(in + node, cnt);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+        const uint32_t node = blockIdx.x * 64 * 64 + i;  // (column word) * 64 + bit
+        const int32_t v = cnt[(i & 63u) * 64 + (i >> 6)];
+        if (node < n && v) atomicAdd(in + node, v);
     }
 }
 
@@ -1271,7 +1284,7 @@ hipError_t launch_in_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid((nwords + 63) / 64, (n + kInRowsPerChunk - 1) / kInRowsPerChunk);
-    hipLaunchKernelGGL(k_in_sizes, grid, dim3(64), 0, st, C, n, ld, nwords, in_sizes);
+    hipLaunchKernelGGL(k_in_sizes, grid, dim3(256), 0, st, C, n, ld, nwords, in_sizes);
     return hipGetLastError();
 }
 
