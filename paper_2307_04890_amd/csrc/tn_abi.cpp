@@ -407,17 +407,24 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         return fail(TN_E_ARG, "slice_words must be a power of two <= 64");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
-    // per-workgroup sink words, then the compound scratch rows, then (for a
-    // zero phase) the slice state the two launches share and its done counter
-    const size_t sink_rows_words = (size_t)tn::rowor_workgroups(n, slice_words) * tn::kRoworSinkWords +
+    // per-workgroup sink words (for the widest grid of the launches below,
+    // so that every launch finds the compound scratch rows at one place),
+    // then those rows, then (for a zero phase) the slice state the launches
+    // share, its done counter and the slice order of the last launch
+    const uint32_t tail_sw = tn::tail_slice_words(n, slice_words, ctx->num_cus);
+    const uint32_t sinks = tn::rowor_workgroups(n, tail_sw);
+    const size_t sink_rows_words = (size_t)sinks * tn::kRoworSinkWords +
                                    (size_t)plan->scratch_rows * (size_t)nwords;
     const bool zero_phase = !wave && ctx->saturation && plan->zero_levels > 0;
-    const size_t pwords = zero_phase ? tn::rowor_persist_words(n, slice_words) + 1 : 0;
+    const size_t pwords = zero_phase ? tn::rowor_persist_words(n, tail_sw) + 1 : 0;
+    const size_t owords = zero_phase ? sinks : 0;
     {
-        tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * sink_rows_words + 4 * pwords);
+        tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * sink_rows_words +
+                                                   4 * (pwords + owords));
         if (st != TN_OK) return st;
     }
     uint32_t *persist = zero_phase ? (uint32_t *)((uint64_t *)ctx->scratch + sink_rows_words) : nullptr;
+    uint32_t *order = zero_phase ? persist + pwords : nullptr;
     hipError_t e;
     if (!ctx->traffic) {
         e = hipMalloc((void **)&ctx->traffic, 2 * sizeof(unsigned long long));
@@ -457,8 +464,8 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         tn::ProfScope ps(ctx, TN_K_ROWOR);
         if (fwd) {
             e = tn::launch_rowor_fwd(plan->fwd_view, n, C, ld, slice_words,
-                                     (uint64_t *)ctx->scratch, plan->scratch_rows, ctx->traffic,
-                                     ctx->stream);
+                                     (uint64_t *)ctx->scratch, sinks, plan->scratch_rows,
+                                     ctx->traffic, ctx->stream);
         } else if (three) {
             tn::DevOps head = plan->view, tail = plan->view;
             head.L = plan->zero_levels;
@@ -466,18 +473,21 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
             tail.lvl = plan->view.lvl + plan->mid_end;
             unsigned int *done = persist + pwords - 1;
             e = tn::launch_rowor_global(head, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
-                                        plan->scratch_rows, ctx->traffic, true, persist, done,
-                                        plan->zero_levels, ctx->stream);
+                                        sinks, plan->scratch_rows, ctx->traffic, true, persist,
+                                        done, plan->zero_levels, nullptr, ctx->stream);
             if (e == hipSuccess)
                 e = tn::launch_rowor_fwd(plan->mid_view, n, C, ld, slice_words,
-                                         (uint64_t *)ctx->scratch, plan->scratch_rows,
+                                         (uint64_t *)ctx->scratch, sinks, plan->scratch_rows,
                                          ctx->traffic, ctx->stream);
+            // the rest on narrower slices, the slices with the most rows
+            // still not full first
             if (e == hipSuccess)
-                e = tn::launch_slice_full_state(C, ld, n, slice_words, persist, ctx->stream);
+                e = tn::launch_slice_full_state(C, ld, n, tail_sw, persist, ctx->stream);
+            if (e == hipSuccess) e = tn::launch_slice_order(persist, n, tail_sw, order, ctx->stream);
             if (e == hipSuccess)
-                e = tn::launch_rowor_global(tail, n, C, ld, slice_words, (uint64_t *)ctx->scratch,
-                                            plan->scratch_rows, ctx->traffic, true, persist, done,
-                                            0u, ctx->stream);
+                e = tn::launch_rowor_global(tail, n, C, ld, tail_sw, (uint64_t *)ctx->scratch,
+                                            sinks, plan->scratch_rows, ctx->traffic, true, persist,
+                                            done, 0u, order, ctx->stream);
         } else if (wave && plan->flat)
             e = tn::launch_rowor_wave_flat1(plan->flat, plan->view.nops, n, C, ld,
                                             plan->scratch_rows, ctx->traffic, ctx->saturation,
@@ -487,10 +497,10 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
                                       ctx->saturation, nullptr, nullptr, ctx->stream);
         else
             e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words,
-                                        (uint64_t *)ctx->scratch, plan->scratch_rows,
+                                        (uint64_t *)ctx->scratch, sinks, plan->scratch_rows,
                                         ctx->traffic, ctx->saturation, persist,
                                         persist ? persist + pwords - 1 : nullptr,
-                                        zero_phase ? plan->zero_levels : 0u, ctx->stream);
+                                        zero_phase ? plan->zero_levels : 0u, nullptr, ctx->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "row-OR kernel launch");
     return TN_OK;

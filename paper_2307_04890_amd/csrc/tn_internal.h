@@ -272,8 +272,12 @@ constexpr size_t kRoworSinkWords = 1024;
 // LDS bytes the saturation bitmap may take next to the op frames and work
 // lists (gfx950: 160 KiB per workgroup).
 constexpr size_t kRoworSatLds = 163840 - 40960;
-// scratch: kRoworSinkWords words per workgroup, then scratch_rows rows of
-// ceil(n/64) words.  rowor_workgroups gives the number of workgroups.
+// scratch: kRoworSinkWords words for each of sink_slots workgroups (at
+// least rowor_workgroups(n, slice_words), else hipErrorInvalidValue), then
+// scratch_rows rows of ceil(n/64) words; launches that hand scratch rows
+// over to each other pass the same sink_slots.  order (nullable): the
+// slice each workgroup takes, in dispatch order (launch_slice_order), for
+// the launch of the levels after zero_levels.
 // The kernel adds the row words it loaded to traffic[0] and stored to
 // traffic[1] (device counters, zeroed by the caller).  With saturation, and
 // when a bit per row and scratch row fits kRoworSatLds, it skips the loads
@@ -288,24 +292,38 @@ constexpr size_t kRoworSatLds = 163840 - 40960;
 // done word and adds 1 to *done_count.
 uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words);
 hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                               uint32_t slice_words, uint64_t *scratch,
+                               uint32_t slice_words, uint64_t *scratch, uint32_t sink_slots,
                                uint32_t scratch_rows, unsigned long long *traffic,
                                bool saturation, uint32_t *persist, unsigned int *done_count,
-                               uint32_t zero_levels, hipStream_t st);
+                               uint32_t zero_levels, const uint32_t *order, hipStream_t st);
 // The plain recurrence (no saturation) on a forwarded op schedule
 // (fwd_schedule), one workgroup per slice of slice_words <= 8 words as in
 // launch_rowor_global, with the same scratch layout and traffic counters;
 // each level's results stay in LDS for the next level.
 bool rowor_fwd_supported(uint32_t n, uint32_t slice_words);
 hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                            uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
-                            unsigned long long *traffic, hipStream_t st);
+                            uint32_t slice_words, uint64_t *scratch, uint32_t sink_slots,
+                            uint32_t scratch_rows, unsigned long long *traffic, hipStream_t st);
 // Rebuilds launch_rowor_global's per-slice state (persist, zeroed here
 // first) from the matrix: the full-row bits and count of every slice, so
 // that a saturating launch can resume after launches that kept no state
 // (slice_words 1, 2, 4, 8 or 16, else hipErrorInvalidValue).
 hipError_t launch_slice_full_state(const uint64_t *C, int64_t ld, uint32_t n,
                                    uint32_t slice_words, uint32_t *persist, hipStream_t st);
+// The dispatch order of a saturating launch's slices (order: one uint32 per
+// slice of slice_words words) from a slice state: fewest full real rows
+// first, ties by slice index.
+hipError_t launch_slice_order(const uint32_t *persist, uint32_t n, uint32_t slice_words,
+                              uint32_t *order, hipStream_t st);
+// The slice width of the saturating launch after the forwarding phase: a
+// workgroup's busy level is bound by its own memory pipeline (the
+// instructions and row segments it issues), so a slice still far from full
+// takes time in proportion to its width, and the slowest slice sets the
+// launch's time.  slice_words is halved while the slices stay within two
+// per compute unit (one resident workgroup each; light slices fill the
+// units that free up).  n = 10^5, m = 10^7 activity-driven: 8 words 6.5 ms,
+// 4 words 3.4 ms, 2 words 4.5 ms.
+uint32_t tail_slice_words(uint32_t n, uint32_t slice_words, int num_cus);
 // The saturating path's middle phase: from the end of the zero phase until
 // its ops reach kFwdPhaseOpsPerNode * n, the forwarding kernel (no skips,
 // each level's results through LDS) runs instead of the saturating one;

@@ -212,8 +212,11 @@ __device__ __forceinline__ void level_counts(OpArgs &A) {
 
 // The wave's nwork items (wave-uniform), one per lane group at a time.
 // Batching several items' loads per lane before their stores measured
-// slower: in the phase where most ops still need rows, the time goes to
-// random row-segment traffic, not to serialized round trips.
+// slower, both where most ops still need rows and in the sparse tail, where
+// one pass of U items per lane group took 5.6 us per busy level against
+// 5.1 us and 1.7 us per one-item level against 1.1 us (the idle items' sink
+// stores): a busy level is bound by the workgroup's memory throughput, not
+// by serialized round trips.
 template <int SW, bool ZERO>
 __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint32_t *work,
                                          uint32_t nwork) {
@@ -224,13 +227,41 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
         const uint32_t e = work[min(j, kWaveShare - 1)];
         const op4 o = frame[e & (kOpsLevelCap - 1)];
         const bool v = j < nwork, skip = e & kWorkSkip;
+        const bool f1 = e & kWorkF1, f2 = e & kWorkF2;
+        if (__ballot(v && !skip) == 0) {
+            // Every item of the batch has a full operand, so every result is
+            // the full slice: nothing is read, and the stores take the full
+            // word, whose register nothing overwrites.  (A store's data
+            // register may not be rewritten before the store retires, and
+            // loads and stores retire in order: a result register rewritten
+            // item after item, or a wait for a load, would wait for every
+            // earlier store of the wave.)  Most batches look like this once
+            // most rows are full.
+            const bool s1 = v && o.z != kNoRow && !f1;
+            const bool s2 = v && o.w != kNoRow && !f2;
+            *op_addr(A, o.z, s1) = A.fullw;
+            *op_addr(A, o.w, s2) = A.fullw;
+            A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+            if (v && A.lead) {
+                if (s1) sat_set<ZERO>(A, o.z, true);
+                if (s2) sat_set<ZERO>(A, o.w, true);
+                if (ZERO && A.zon) {
+                    if (o.z != kNoRow && (e & kWorkZ1)) zero_set(A, o.z, false);
+                    if (o.w != kNoRow && (e & kWorkZ2)) zero_set(A, o.w, false);
+                }
+            }
+            continue;
+        }
         // an operand known zero in this slice is not loaded
         const bool ldx = v && !skip && !(ZERO && (e & (kWorkZero | kWorkZX)));
         const bool ldy = v && !skip && !(ZERO && (e & (kWorkZero | kWorkZY)));
-        const uint64_t x = *op_addr(A, o.x, ldx);
-        const uint64_t y = *op_addr(A, o.y, ldy);
-        A.loaded += ((ldx && A.wok) ? 1u : 0u) + ((ldy && A.wok) ? 1u : 0u);
-        const uint64_t r = skip ? A.fullw : ((ldx ? x : 0ull) | (ldy ? y : 0ull));
+        uint64_t r = skip ? A.fullw : 0ull;
+        if (__ballot(ldx || ldy) != 0) {
+            const uint64_t x = *op_addr(A, o.x, ldx);
+            const uint64_t y = *op_addr(A, o.y, ldy);
+            A.loaded += ((ldx && A.wok) ? 1u : 0u) + ((ldy && A.wok) ? 1u : 0u);
+            if (!skip) r = (ldx ? x : 0ull) | (ldy ? y : 0ull);
+        }
         // the group's SW lanes agree on whether the whole row slice is full
         const uint64_t ball = __ballot(r == A.fullw || !A.wok);
         const bool full = (ball & A.gmask) == A.gmask;
@@ -239,7 +270,6 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
             const uint64_t zb = __ballot(r == 0ull || !A.wok);
             zero = (zb & A.gmask) == A.gmask;
         }
-        const bool f1 = e & kWorkF1, f2 = e & kWorkF2;
         const bool z1 = ZERO && (e & kWorkZ1), z2 = ZERO && (e & kWorkZ2);
         // a full result into a full row, or a zero result into a zero row,
         // changes nothing
@@ -342,9 +372,10 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
 template <int SW, int UC, bool SAT, bool CHUNK, bool MAX8 = false, bool ZERO = false>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
-               uint64_t *__restrict__ scratch, uint32_t sbase, uint32_t sbits,
-               unsigned long long *__restrict__ traffic, uint32_t *__restrict__ persist,
-               unsigned int *__restrict__ done_count) {
+               uint64_t *__restrict__ scratch, uint64_t *__restrict__ rows, uint32_t sbase,
+               uint32_t sbits, unsigned long long *__restrict__ traffic,
+               uint32_t *__restrict__ persist, unsigned int *__restrict__ done_count,
+               const uint32_t *__restrict__ order) {
     __shared__ op4 frame[kFrames][kOpsLevelCap];
     __shared__ uint32_t fcount[kFrames];
     __shared__ uint32_t worklist[SAT ? kComputeWaves : 1][kWaveShare];
@@ -362,7 +393,8 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     const uint32_t tid = threadIdx.x;
     const bool loader = tid < kLoaderThreads;
     const uint32_t ctid = tid - kLoaderThreads;  // compute-thread index
-    const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
+    // order (nullable): the slice of each workgroup, in dispatch order
+    const uint32_t slice = order ? order[blockIdx.x] : xcd_slice(blockIdx.x, gridDim.x);
     OpArgs A;
     A.C = C;
     A.ldz = (size_t)ld;
@@ -372,7 +404,7 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     A.grp = ctid / SW;
     A.ngrp = (blockDim.x - kLoaderThreads) / SW;
     A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
-    A.rows = scratch + (size_t)gridDim.x * kRoworSinkWords;
+    A.rows = rows;
     A.sat = satbits;
     A.sbase = sbase;
     A.sbits = sbits;
@@ -454,58 +486,71 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     A.nzero = zdelta;
     A.zon = false;
     // all waves add the same deltas at the same barriers, so they agree
+    // A slice may stop only at the start of a level that is a multiple of 3:
+    // the loaders' loop, unrolled by three, then has one exit, at the top (an
+    // exit after each level's feed let the compiler's waits in that loop
+    // drain the loads of the levels ahead).  Both loops run to L rounded up
+    // to a multiple of 3; the levels past L have no ops.  done(l) must be
+    // called once for every level, after the barrier that ends level l - 1.
+    const uint32_t L3 = (L + 2) / 3 * 3;
     auto done = [&](uint32_t l) -> bool {
         if (!SAT) return false;
         if (l > 0) nfull += fdelta[(l - 1) % 3];
-        return nfull == (int32_t)n;
+        return l % 3 == 0 && nfull == (int32_t)n;
     };
     constexpr bool WIDE = ((1024 - kLoaderThreads) / SW) * UC < kOpsLevelCap;
     // Loader and compute waves run separate loops with one barrier per level
     // each (the branch is uniform per wave, and s_barrier only counts
     // waves), so the compiler tracks the loaders' loads apart from the
-    // compute waves' row traffic.  Loader waves keep two levels in flight in
-    // registers (hA, hB): a schedule load has two level periods to land
-    // before its frame is written.  Their loop is unrolled by two so that hA
-    // and hB never change registers (a register copy would wait for the
-    // load).
+    // compute waves' row traffic.  Loader waves keep three levels in flight
+    // in registers (hA, hB, hC): a schedule load has three level periods to
+    // land before its frame is written.  Their loop is unrolled by three so
+    // that the sets never change registers (a register copy would wait for
+    // the load).
     if (loader) {
         // Every loader lane reads the level starts too (the same address in
         // all lanes); a start is loaded one level before the ops it locates,
         // and ahead of them, so each wait below leaves the newer loads in
         // flight.
-        uint32_t p1 = level_start(s, 1), p2 = level_start(s, 2);
+        uint32_t p1 = level_start(s, 1), p2 = level_start(s, 2), p3 = level_start(s, 3);
         put_level(frame[0], fetch_ops(s, level_start(s, 0), tid), tid);
         if (tid == 0) fcount[0] = p1 - level_start(s, 0);
         HeldOps hA = fetch_ops(s, p1, tid);
-        uint32_t p3 = level_start(s, 3);
         HeldOps hB = fetch_ops(s, p2, tid);
+        uint32_t p4 = level_start(s, 4);
+        HeldOps hC = fetch_ops(s, p3, tid);
         __syncthreads();
-        // at level l: h holds the ops of level l + 1, p1..p3 the starts of
-        // levels l + 1 .. l + 3
+        // at level l: h holds the ops of level l + 1, fetched three levels
+        // before (a level whose ops need no memory takes less than a memory
+        // round trip, so two levels of lead were not enough); p1..p4 the
+        // starts of levels l + 1 .. l + 4
         auto feed = [&](uint32_t l, HeldOps &h) {
             // past the last level frames and counts are never read, and the
             // level starts clamp to L
             const uint32_t nf = (l + 1) % kFrames;
             put_level(frame[nf], h, tid);
             if (tid == 0) fcount[nf] = p2 - p1;
-            const uint32_t q = p3;
+            const uint32_t q = p4;
             p1 = p2;
-            p2 = q;
-            p3 = level_start(s, l + 4);
+            p2 = p3;
+            p3 = q;
+            p4 = level_start(s, l + 5);
             h = fetch_ops(s, q, tid);
             __syncthreads();
         };
-        for (uint32_t l = 0; l < L; l += 2) {
+        for (uint32_t l = 0; l < L3; l += 3) {
             if (done(l)) break;
             feed(l, hA);
-            if (l + 1 >= L || done(l + 1)) break;
+            (void)done(l + 1);  // counts only: not a multiple of 3
             feed(l + 1, hB);
+            (void)done(l + 2);
+            feed(l + 2, hC);
         }
         return;
     }
     __syncthreads();
     bool stopped = false;
-    for (uint32_t l = 0; l < L; ++l) {
+    for (uint32_t l = 0; l < L3; ++l) {
         if (done(l)) {
             stopped = true;
             break;
@@ -543,7 +588,7 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     count_add(traffic + 1, A.stored);
     if (pst) {
         // the last level's delta settled at the loop's final barrier
-        if (!stopped) nfull += fdelta[(L - 1) % 3];
+        if (!stopped) nfull += fdelta[(L3 - 1) % 3];
         for (uint32_t i = ctid; i < rwords; i += blockDim.x - kLoaderThreads) {
             pst[2 + i] = satbits[i];
             pst[2 + rwords + i] = ZERO ? ~zbits[i] : ~0u;
@@ -641,7 +686,8 @@ __device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t 
 template <int SW, int UC, bool OFF32>
 __global__ void __launch_bounds__(1024)
 k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
-            uint64_t *__restrict__ scratch, unsigned long long *__restrict__ traffic) {
+            uint64_t *__restrict__ scratch, uint64_t *__restrict__ rows,
+            unsigned long long *__restrict__ traffic) {
     static_assert(((1024 - kLoaderThreads) / SW) * UC >= kFwdLevelCap, "a level per pass");
     __shared__ op4 frame[kFwdFrames][kOpsLevelCap];
     __shared__ uint32_t fcount[kFwdFrames];
@@ -664,7 +710,7 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     A.grp = ctid / SW;
     A.ngrp = (blockDim.x - kLoaderThreads) / SW;
     A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
-    A.rows = scratch + (size_t)gridDim.x * kRoworSinkWords;
+    A.rows = rows;
     A.loaded = A.stored = 0;
     A.ld32 = (uint32_t)ld;
     if (loader) {
@@ -823,7 +869,8 @@ __device__ __forceinline__ void fwd1_apply(OpArgs &A, const op4 *frame, uint32_t
 template <int SW, int UC, int UCX, bool OFF32>
 __global__ void __launch_bounds__(1024)
 k_rowor_fwd1(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
-             uint64_t *__restrict__ scratch, unsigned long long *__restrict__ traffic) {
+             uint64_t *__restrict__ scratch, uint64_t *__restrict__ rows,
+             unsigned long long *__restrict__ traffic) {
     static_assert(((1024 - kLoaderThreads) / SW) * UC >= kFwdLevelCap, "a level per pass");
     __shared__ op4 frame[kFwdFrames][kOpsLevelCap];
     __shared__ uint32_t fcount[kFwdFrames];
@@ -845,7 +892,7 @@ k_rowor_fwd1(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     A.grp = ctid / SW;
     A.ngrp = (blockDim.x - kLoaderThreads) / SW;
     A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
-    A.rows = scratch + (size_t)gridDim.x * kRoworSinkWords;
+    A.rows = rows;
     A.loaded = A.stored = 0;
     A.ld32 = (uint32_t)ld;
     if (loader) {
@@ -958,6 +1005,32 @@ k_slice_full_state(const uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint3
     }
 }
 
+// The order in which a saturating launch takes its slices: by the count of
+// full real rows in the slice state, fewest first, ties by slice index, so
+// the slices with the most work left start first and the lightest fill the
+// compute units that free up.  One thread per slice counts the slices that
+// come before it (a strict total order, so the ranks are a permutation).
+__global__ void __launch_bounds__(256)
+k_slice_order(const uint32_t *__restrict__ persist, uint32_t pslice, uint32_t slices,
+              uint32_t *__restrict__ order) {
+    __shared__ uint32_t key[256];
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t mine = s < slices ? persist[(size_t)s * pslice + 1] : 0u;
+    uint32_t rank = 0;
+    for (uint32_t j0 = 0; j0 < slices; j0 += 256u) {
+        const uint32_t j = j0 + threadIdx.x;
+        __syncthreads();
+        key[threadIdx.x] = j < slices ? persist[(size_t)j * pslice + 1] : 0u;
+        __syncthreads();
+        const uint32_t m = min(256u, slices - j0);
+        for (uint32_t k = 0; k < m; ++k) {
+            const uint32_t c = key[k];
+            rank += (c < mine || (c == mine && j0 + k < s)) ? 1u : 0u;
+        }
+    }
+    if (s < slices) order[rank] = s;
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint32_t n, int32_t v) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -1044,9 +1117,9 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
 
 template <int SW, int UC>
 hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, uint64_t *scratch,
-                         uint32_t scratch_rows, unsigned long long *traffic, bool saturation,
-                         uint32_t *persist, unsigned int *done_count, uint32_t zero_levels,
-                         hipStream_t st) {
+                         uint64_t *rows, uint32_t scratch_rows, unsigned long long *traffic,
+                         bool saturation, uint32_t *persist, unsigned int *done_count,
+                         uint32_t zero_levels, const uint32_t *order, hipStream_t st) {
     const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
     const uint32_t sbase = (n + 31u) & ~31u;
@@ -1068,7 +1141,8 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
                                                (int)(2 * lds));
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kz, dim3(slices), dim3(1024), 2 * lds, st, C, ld, n, nwords, head,
-                               scratch, sbase, (uint32_t)sbits, traffic, persist, done_count);
+                               scratch, rows, sbase, (uint32_t)sbits, traffic, persist, done_count,
+                               (const uint32_t *)nullptr);
             e = hipGetLastError();
             if (e != hipSuccess || head.L == s.L) return e;
             rest.L = s.L - head.L;
@@ -1079,11 +1153,11 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, n, nwords, rest, scratch,
-                           sbase, (uint32_t)sbits, traffic, persist, done_count);
+                           rows, sbase, (uint32_t)sbits, traffic, persist, done_count, order);
     } else {
         hipLaunchKernelGGL((k_rowor_global<SW, UC, false, false>), dim3(slices), dim3(1024), 0,
-                           st, C, ld, n, nwords, s, scratch, 0u, 1u, traffic, (uint32_t *)nullptr,
-                           (unsigned int *)nullptr);
+                           st, C, ld, n, nwords, s, scratch, rows, 0u, 1u, traffic,
+                           (uint32_t *)nullptr, (unsigned int *)nullptr, order);
     }
     return hipGetLastError();
 }
@@ -1103,26 +1177,31 @@ hipError_t launch_rowmax_global(const DevOps &s, uint32_t rows, uint32_t nwords,
     if (s.L == 0) return hipSuccess;
     const uint32_t sw = rowmax_slice_words(nwords);
     const uint32_t slices = (nwords + sw - 1) / sw;
+    uint64_t *mrows = scratch + (size_t)slices * kRoworSinkWords;
     switch (sw) {
         case 1:
             hipLaunchKernelGGL((k_rowor_global<1, 2, false, false, true>), dim3(slices), dim3(1024),
-                               0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
-                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+                               0, st, M, ld, rows, nwords, s, scratch, mrows, 0u, 1u,
+                               traffic, (uint32_t *)nullptr, (unsigned int *)nullptr,
+                               (const uint32_t *)nullptr);
             break;
         case 2:
             hipLaunchKernelGGL((k_rowor_global<2, 3, false, false, true>), dim3(slices), dim3(1024),
-                               0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
-                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+                               0, st, M, ld, rows, nwords, s, scratch, mrows, 0u, 1u,
+                               traffic, (uint32_t *)nullptr, (unsigned int *)nullptr,
+                               (const uint32_t *)nullptr);
             break;
         case 4:
             hipLaunchKernelGGL((k_rowor_global<4, 5, false, false, true>), dim3(slices), dim3(1024),
-                               0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
-                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+                               0, st, M, ld, rows, nwords, s, scratch, mrows, 0u, 1u,
+                               traffic, (uint32_t *)nullptr, (unsigned int *)nullptr,
+                               (const uint32_t *)nullptr);
             break;
         case 8:
             hipLaunchKernelGGL((k_rowor_global<8, 10, false, false, true>), dim3(slices),
-                               dim3(1024), 0, st, M, ld, rows, nwords, s, scratch, 0u, 1u, traffic,
-                               (uint32_t *)nullptr, (unsigned int *)nullptr);
+                               dim3(1024), 0, st, M, ld, rows, nwords, s, scratch, mrows, 0u, 1u,
+                               traffic, (uint32_t *)nullptr, (unsigned int *)nullptr,
+                               (const uint32_t *)nullptr);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1170,27 +1249,30 @@ uint32_t rowor_workgroups(uint32_t n, uint32_t slice_words) {
 }
 
 hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                               uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
-                               unsigned long long *traffic, bool saturation, uint32_t *persist,
-                               unsigned int *done_count, uint32_t zero_levels, hipStream_t st) {
+                               uint32_t slice_words, uint64_t *scratch, uint32_t sink_slots,
+                               uint32_t scratch_rows, unsigned long long *traffic,
+                               bool saturation, uint32_t *persist, unsigned int *done_count,
+                               uint32_t zero_levels, const uint32_t *order, hipStream_t st) {
     if (s.L == 0) return hipSuccess;
+    if (slice_words == 0 || sink_slots < rowor_workgroups(n, slice_words)) return hipErrorInvalidValue;
+    uint64_t *rows = scratch + (size_t)sink_slots * kRoworSinkWords;
     switch (slice_words) {
         // UC: ops per lane group and level, so that (896 / SW) * UC >= 1024
-        case 1: return rowor_variant<1, 2>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
-        case 2: return rowor_variant<2, 3>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
-        case 4: return rowor_variant<4, 5>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
-        case 8: return rowor_variant<8, 10>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
-        case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
-        case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
-        case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, scratch_rows, traffic, saturation, persist, done_count, zero_levels, st);
+        case 1: return rowor_variant<1, 2>(s, n, C, ld, scratch, rows, scratch_rows, traffic, saturation, persist, done_count, zero_levels, order, st);
+        case 2: return rowor_variant<2, 3>(s, n, C, ld, scratch, rows, scratch_rows, traffic, saturation, persist, done_count, zero_levels, order, st);
+        case 4: return rowor_variant<4, 5>(s, n, C, ld, scratch, rows, scratch_rows, traffic, saturation, persist, done_count, zero_levels, order, st);
+        case 8: return rowor_variant<8, 10>(s, n, C, ld, scratch, rows, scratch_rows, traffic, saturation, persist, done_count, zero_levels, order, st);
+        case 16: return rowor_variant<16, 8>(s, n, C, ld, scratch, rows, scratch_rows, traffic, saturation, persist, done_count, zero_levels, order, st);
+        case 32: return rowor_variant<32, 8>(s, n, C, ld, scratch, rows, scratch_rows, traffic, saturation, persist, done_count, zero_levels, order, st);
+        case 64: return rowor_variant<64, 8>(s, n, C, ld, scratch, rows, scratch_rows, traffic, saturation, persist, done_count, zero_levels, order, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int SW, int UC>
 hipError_t rowor_fwd_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                             uint64_t *scratch, bool off32, unsigned long long *traffic,
-                             hipStream_t st) {
+                             uint64_t *scratch, uint64_t *rows, bool off32,
+                             unsigned long long *traffic, hipStream_t st) {
     const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
     const size_t lds = sizeof(uint64_t) * 2 * (kFwdLevelCap + 1) * SW;
@@ -1198,14 +1280,15 @@ hipError_t rowor_fwd_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t l
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, nwords, s, scratch, traffic);
+    hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, nwords, s, scratch, rows,
+                       traffic);
     return hipGetLastError();
 }
 
 template <int SW, int UC, int UCX>
 hipError_t rowor_fwd1_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                              uint64_t *scratch, bool off32, unsigned long long *traffic,
-                              hipStream_t st) {
+                              uint64_t *scratch, uint64_t *rows, bool off32,
+                              unsigned long long *traffic, hipStream_t st) {
     const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
     const size_t lds = sizeof(uint64_t) * (kFwdLevelCap + 1) * SW;
@@ -1213,7 +1296,8 @@ hipError_t rowor_fwd1_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t 
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, nwords, s, scratch, traffic);
+    hipLaunchKernelGGL(k, dim3(slices), dim3(1024), lds, st, C, ld, nwords, s, scratch, rows,
+                       traffic);
     return hipGetLastError();
 }
 
@@ -1231,18 +1315,21 @@ static bool rowor_fwd_off32(uint32_t n, int64_t ld, uint32_t scratch_rows) {
 }
 
 hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
-                            uint32_t slice_words, uint64_t *scratch, uint32_t scratch_rows,
-                            unsigned long long *traffic, hipStream_t st) {
+                            uint32_t slice_words, uint64_t *scratch, uint32_t sink_slots,
+                            uint32_t scratch_rows, unsigned long long *traffic, hipStream_t st) {
     if (s.L == 0) return hipSuccess;
-    if (!rowor_fwd_supported(n, slice_words)) return hipErrorInvalidValue;
+    if (!rowor_fwd_supported(n, slice_words) || slice_words == 0 ||
+        sink_slots < rowor_workgroups(n, slice_words))
+        return hipErrorInvalidValue;
+    uint64_t *rows = scratch + (size_t)sink_slots * kRoworSinkWords;
     const bool o32 = rowor_fwd_off32(n, ld, scratch_rows);
     switch (slice_words) {
         // UC: ops per lane group, so that (896 / SW) * UC >= kFwdLevelCap
-        case 1: return rowor_fwd_variant<1, 1>(s, n, C, ld, scratch, o32, traffic, st);
-        case 2: return rowor_fwd_variant<2, 2>(s, n, C, ld, scratch, o32, traffic, st);
-        case 4: return rowor_fwd_variant<4, 4>(s, n, C, ld, scratch, o32, traffic, st);
-        case 8: return rowor_fwd_variant<8, 7>(s, n, C, ld, scratch, o32, traffic, st);
-        case 16: return rowor_fwd1_variant<16, 14, 2>(s, n, C, ld, scratch, o32, traffic, st);
+        case 1: return rowor_fwd_variant<1, 1>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        case 2: return rowor_fwd_variant<2, 2>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        case 4: return rowor_fwd_variant<4, 4>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        case 8: return rowor_fwd_variant<8, 7>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        case 16: return rowor_fwd1_variant<16, 14, 2>(s, n, C, ld, scratch, rows, o32, traffic, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1264,6 +1351,24 @@ hipError_t launch_slice_full_state(const uint64_t *C, int64_t ld, uint32_t n,
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_slice_order(const uint32_t *persist, uint32_t n, uint32_t slice_words,
+                              uint32_t *order, hipStream_t st) {
+    if (slice_words == 0) return hipErrorInvalidValue;
+    const uint32_t slices = rowor_workgroups(n, slice_words);
+    const size_t pslice = rowor_persist_words(n, slice_words) / slices;
+    if (slices == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slice_order, dim3((slices + 255) / 256), dim3(256), 0, st, persist,
+                       (uint32_t)pslice, slices, order);
+    return hipGetLastError();
+}
+
+uint32_t tail_slice_words(uint32_t n, uint32_t slice_words, int num_cus) {
+    uint32_t sw = slice_words;
+    const uint32_t cap = 2u * (uint32_t)(num_cus > 0 ? num_cus : 1);
+    while (sw > 1 && rowor_workgroups(n, sw / 2) <= cap) sw /= 2;
+    return sw;
 }
 
 hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *out_sizes,

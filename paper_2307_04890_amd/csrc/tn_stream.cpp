@@ -399,9 +399,9 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
                                       ctx->stream);
             else
                 e = launch_rowor_global(ops_view(ch.hs, r.dev), s.n, s.C, s.ld, s.sw,
-                                        (uint64_t *)ctx->scratch, ch.hs.scratch_rows,
+                                        (uint64_t *)ctx->scratch, s.slices, ch.hs.scratch_rows,
                                         ctx->traffic, ctx->saturation, s.persist, s.done_count,
-                                        zl, ctx->stream);
+                                        zl, nullptr, ctx->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(r.done_host, s.done_count, sizeof(unsigned int),

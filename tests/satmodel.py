@@ -7,7 +7,9 @@ result into a zero row are not stored.  Zero flags start set on every real
 row except the slice's own nodes (the identity) and unknown on scratch rows,
 and are used in the zero phase (the levels before the one at which the ops
 so far reach n), while some real row of the slice is still zero.  A slice stops
-at the first level that starts with every real row full.  The matrix it ends
+at the first level that starts with every real row full and whose index within
+its launch (the zero phase is a launch of its own) is a multiple of 3.  The
+matrix it ends
 with must be the plain recurrence's; the counts are what the kernel's own
 counters must report for the same slice width."""
 import numpy as np
@@ -51,7 +53,10 @@ def replay(n, sch, slice_words, saturation=True, zero=True):
         return x
 
     for l in range(sch["stats"]["op_levels"]):
-        if saturation:
+        # a slice stops only at a level that is a multiple of 3 within its
+        # launch (the zero phase is a launch of its own)
+        rel = l - zero_levels if 0 < zero_levels <= l else l
+        if saturation and rel % 3 == 0:
             alive &= ~flag[:n].all(axis=0)
         live = valid * alive
         O = ops[lv[l]:lv[l + 1]]

@@ -314,8 +314,11 @@ def test_saturating_path_with_a_forwarding_phase(sw):
     # n = 256 * 64 + 1: every slice width ends on a one-column slice.  Past
     # the zero phase, a network of this size runs the forwarding kernel until
     # its ops reach 10 n, then the saturating kernel from slice state rebuilt
-    # out of the matrix (up to 8 words per slice; 16 keeps the two-launch
-    # path); the matrix must be the plain recurrence's and the oracle's
+    # out of the matrix, on one-word slices in a grid of its own (257
+    # workgroups, against 17..257 before) and the slices with the most rows
+    # still not full first; compound scratch rows live across that cut
+    # (test_planner).  The matrix must be the plain recurrence's and the
+    # oracle's
     n = 16385
     s, d, t = T.uniform_pairs(n, 400_000, 2000, seed=8400)
     sch = tn.host_schedule(n, s, d, t)
@@ -339,5 +342,38 @@ def test_saturating_path_with_a_forwarding_phase(sw):
     got = host(C1)
     nw = oracle.words(n)
     for w0 in (0, 130, nw - 1):
+        want = oracle.reverse_matrix(n, s, d, t, w0=w0, nw=1)
+        assert (got[:, w0:w0 + 1] == want).all(), (sw, w0)
+
+
+@pytest.mark.parametrize("sw", [2, 8])
+def test_saturating_path_on_two_blocks(sw):
+    # the same three launches on a network whose matrix never fills: events
+    # only among the even and among the odd nodes.  Where the matrix ends all
+    # ones, a row-OR that read a wrong row (say a scratch row looked up at
+    # another place after the forwarding phase) only saturates sooner; here
+    # any bit across the blocks is an error
+    n = 16385
+    s, d, t = T.two_block_pairs(n, 600_000, 2000, seed=8410)
+    sch = tn.host_schedule(n, s, d, t)
+    lv, L = sch["lvl_op"], sch["stats"]["op_levels"]
+    zl = int(np.searchsorted(lv[:L], n, side="left"))
+    mid = int(np.searchsorted(lv[:L], 10 * n, side="left"))
+    assert 0 < zl < mid < L
+    ctx = tn.get_context()
+    p = tn.Plan(n, s, d, t)
+    try:
+        C1 = p.execute(slice_words=sw).clone()
+        ctx.saturation(False)
+        C0 = p.execute(slice_words=sw)
+    finally:
+        ctx.saturation(True)
+        p.close()
+    assert torch.equal(C1, C0)
+    got = host(C1)
+    nw = oracle.words(n)
+    even = np.uint64(0x5555555555555555)  # the even columns of a word
+    assert not (got[0::2, :nw] & ~even).any() and not (got[1::2, :nw] & even).any()
+    for w0 in (0, 131, nw - 1):
         want = oracle.reverse_matrix(n, s, d, t, w0=w0, nw=1)
         assert (got[:, w0:w0 + 1] == want).all(), (sw, w0)

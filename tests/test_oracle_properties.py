@@ -49,3 +49,19 @@ def test_reverse_matrix_is_si_brute_force_and_forward_transpose(net):
         R2 = oracle.reverse_matrix(n, np.append(s, np.uint32(0)), np.append(d, np.uint32(n - 1)),
                                    t2, directed=directed, sequential=sequential)
         assert ((R2 & R) == R).all()
+
+
+def test_two_blocks_never_join():
+    # events only among the even and among the odd nodes: no node reaches one
+    # of the other parity, and with enough events every node reaches its
+    # whole block (the brute force agrees on a small case)
+    import tn_inputs as T
+    for n in (4, 9, 64):
+        s, d, t = T.two_block_pairs(n, 40 * n, 8, seed=8500 + n)
+        assert (s % 2 == d % 2).all() and (s != d).all()
+        D = oracle.to_dense(oracle.reverse_matrix(n, s, d, t), n)
+        par = np.arange(n) % 2
+        assert not D[par[:, None] != par[None, :]].any(), n
+        oc = si.out_components(n, s, d, t)
+        for u in range(n):
+            assert set(np.nonzero(D[u])[0]) == oc[u], (n, u)

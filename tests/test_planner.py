@@ -406,3 +406,34 @@ def test_saturation_model_stops_full_slices():
     assert (got == want).all()
     _, ld0, st0 = satmodel.replay(n, sch, 1, saturation=False)
     assert ld < ld0 // 4
+
+
+@pytest.mark.parametrize("blocks", [False, True])
+def test_scratch_rows_live_across_the_forwarding_cut(blocks):
+    # the premise of the GPU tests of the saturating path with a forwarding
+    # phase: some compound items' scratch rows are written before the level
+    # at which the ops reach 10 n and read after it, so the launches on
+    # either side must find them at the same place
+    n = 16385
+    if blocks:
+        s, d, t = T.two_block_pairs(n, 600_000, 2000, seed=8410)
+    else:
+        s, d, t = T.uniform_pairs(n, 400_000, 2000, seed=8400)
+    sch = tn.host_schedule(n, s, d, t)
+    lv, L = sch["lvl_op"].astype(np.int64), sch["stats"]["op_levels"]
+    ops = sch["ops"].astype(np.int64)
+    mid = int(np.searchsorted(lv[:L], 10 * n, side="left"))
+    lvl = np.repeat(np.arange(L), np.diff(lv[:L + 1]))
+    SCR, NOROW = 0x80000000, 0xFFFFFFFF
+    last = {}
+    crossing = 0
+    for i in range(ops.shape[0]):
+        for c in (0, 1):
+            x = int(ops[i, c])
+            if x != NOROW and x & SCR and last.get(x, mid) < mid <= lvl[i]:
+                crossing += 1
+        for c in (2, 3):
+            x = int(ops[i, c])
+            if x != NOROW and x & SCR:
+                last[x] = lvl[i]
+    assert crossing > 100

@@ -66,6 +66,27 @@ def uniform_pairs(n: int, m: int, T: int, seed: int):
     return sort_events(u.astype(np.uint32), v.astype(np.uint32), t)
 
 
+def two_block_pairs(n: int, m: int, T: int, seed: int):
+    """``m`` undirected events inside two blocks, the even and the odd nodes:
+    ``u`` uniform in [n], ``v`` uniform over the nodes of ``u``'s parity
+    minus ``u``, ``t`` uniform integer in [0, T).  No path ever joins the
+    blocks, so the component matrix keeps zero where a row's and a column's
+    parities differ, however many events there are.
+    """
+    if n < 4 and m > 0:
+        raise ValueError("need n >= 4 for two blocks of two nodes")
+    g = rng(seed)
+    u = g.integers(0, n, size=m, dtype=np.int64)
+    p = u % 2
+    size = (n - p + 1) // 2  # nodes of u's parity
+    j = (g.random(m) * (size - 1)).astype(np.int64)
+    j = np.minimum(j, size - 2)
+    j += j >= u // 2  # skip u itself
+    v = 2 * j + p
+    t = g.integers(0, T, size=m, dtype=np.int64)
+    return sort_events(u.astype(np.uint32), v.astype(np.uint32), t)
+
+
 def activities(n: int, seed: int, gamma: float = 2.1, eps: float = 1e-3):
     """Node activities with density proportional to a^-gamma on [eps, 1] (inverse CDF)."""
     g = rng(seed ^ 0x5A5A5A5A)
