@@ -74,7 +74,7 @@ def kernel_source_hash(files) -> str:
 
 # the kernels of one saturating launch on a network of 16,384+ nodes: the
 # zero phase, the forwarding phase, the slice state, the saturating rest
-ROWOR_SAT_KERNELS = "k_rowor_global|k_rowor_fwd|k_slice_full_state"
+ROWOR_SAT_KERNELS = "k_rowor_global|k_rowor_fwd|k_slice_full_state|k_slice_order"
 KERNEL_SOURCES = {"rowor": ("tn_kernels.hip", "tn_internal.h", "tn_device.h", "tn_plan.cpp"),
                   "rowor_plain": ("tn_kernels.hip", "tn_internal.h", "tn_device.h", "tn_plan.cpp"),
                   "batch": ("tn_batch.hip", "tn_batch.h", "tn_batch.cpp", "tn_internal.h"),
@@ -278,7 +278,8 @@ def run_exact(args):
     if args.no_plain:
         r["roofline"] = r["plain"] = None
     r["saturating"] = {"kernel": "k_rowor_global zero phase, k_rowor_fwd until the ops reach "
-                                 "10 n, k_slice_full_state, k_rowor_global for the rest",
+                                 "10 n, k_slice_full_state and k_slice_order on narrower "
+                                 "slices, k_rowor_global for the rest",
                        "avg_launch_ms": sat_ms, "moved_bytes": moved,
                        "moved_achieved": moved / (sat_ms * 1e-3) / 1e9,
                        "moved_frac": moved / (sat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,

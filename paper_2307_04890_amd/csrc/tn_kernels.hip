@@ -177,17 +177,13 @@ constexpr uint32_t kWorkZero = 1u << 19, kWorkZX = 1u << 20, kWorkZY = 1u << 21;
 constexpr uint32_t kWorkZ1 = 1u << 22, kWorkZ2 = 1u << 23;
 
 // Flips the bit of a row whose state changed; a real row also moves this
-// level's count of full real rows: at once, or with AGG kept per lane and
-// added once per wave (level_counts).
-template <bool AGG>
+// lane's part of the level's count of full real rows, added once per wave
+// (level_counts).
 __device__ __forceinline__ void sat_set(OpArgs &A, uint32_t id, bool full) {
     const uint32_t i = sat_index(A, id);
     if (full) atomicOr(&A.sat[i >> 5], 1u << (i & 31u));
     else atomicAnd(&A.sat[i >> 5], ~(1u << (i & 31u)));
-    if (!(id & kScratchBit)) {
-        if (AGG) A.dfull += full ? 1 : -1;
-        else atomicAdd(A.nfull, full ? 1 : -1);
-    }
+    if (!(id & kScratchBit)) A.dfull += full ? 1 : -1;
 }
 
 // Adds the wave's changes of the full and zero real-row counts to this
@@ -243,8 +239,8 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
             *op_addr(A, o.w, s2) = A.fullw;
             A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
             if (v && A.lead) {
-                if (s1) sat_set<ZERO>(A, o.z, true);
-                if (s2) sat_set<ZERO>(A, o.w, true);
+                if (s1) sat_set(A, o.z, true);
+                if (s2) sat_set(A, o.w, true);
                 if (ZERO && A.zon) {
                     if (o.z != kNoRow && (e & kWorkZ1)) zero_set(A, o.z, false);
                     if (o.w != kNoRow && (e & kWorkZ2)) zero_set(A, o.w, false);
@@ -280,8 +276,8 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
         A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
         // one lane per group refreshes the destinations' bits
         if (v && A.lead) {
-            if (o.z != kNoRow && f1 != full) sat_set<ZERO>(A, o.z, full);
-            if (o.w != kNoRow && f2 != full) sat_set<ZERO>(A, o.w, full);
+            if (o.z != kNoRow && f1 != full) sat_set(A, o.z, full);
+            if (o.w != kNoRow && f2 != full) sat_set(A, o.w, full);
             if (ZERO && A.zon) {
                 if (o.z != kNoRow && z1 != zero) zero_set(A, o.z, zero);
                 if (o.w != kNoRow && z2 != zero) zero_set(A, o.w, zero);
@@ -305,15 +301,17 @@ __device__ __forceinline__ uint32_t classify(const OpArgs &A, const op4 *frame, 
         const uint32_t i = r0 + lane;
         const bool v = i < hi;
         const op4 o = frame[min(i, kOpsLevelCap - 1)];
-        const bool skip = sat_get(A, o.x) || sat_get(A, o.y);
-        const bool f1 = o.z != kNoRow && sat_get(A, o.z);
-        const bool f2 = o.w != kNoRow && sat_get(A, o.w);
+        // every bit read is issued at once (no short-circuit: one LDS round
+        // trip, not four; sat_index keeps kNoRow in range)
+        const bool skip = sat_get(A, o.x) | sat_get(A, o.y);
+        const bool f1 = (o.z != kNoRow) & sat_get(A, o.z);
+        const bool f2 = (o.w != kNoRow) & sat_get(A, o.w);
         bool zx = false, zy = false, z1 = false, z2 = false;
         if (ZERO && A.zon) {
             zx = zero_get(A, o.x);
             zy = zero_get(A, o.y);
-            z1 = o.z != kNoRow && zero_get(A, o.z);
-            z2 = o.w != kNoRow && zero_get(A, o.w);
+            z1 = (o.z != kNoRow) & zero_get(A, o.z);
+            z2 = (o.w != kNoRow) & zero_get(A, o.w);
         }
         const bool zres = !skip && zx && zy;
         const bool need =
@@ -495,7 +493,9 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     const uint32_t L3 = (L + 2) / 3 * 3;
     auto done = [&](uint32_t l) -> bool {
         if (!SAT) return false;
-        if (l > 0) nfull += fdelta[(l - 1) % 3];
+        // the delta of level l - 1 (slot 2 is still zero at level 0): read
+        // unconditionally, beside the level's other LDS reads
+        nfull += fdelta[(l + 2) % 3];
         return l % 3 == 0 && nfull == (int32_t)n;
     };
     constexpr bool WIDE = ((1024 - kLoaderThreads) / SW) * UC < kOpsLevelCap;
@@ -534,9 +534,13 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
             p1 = p2;
             p2 = p3;
             p3 = q;
-            p4 = level_start(s, l + 5);
             h = fetch_ops(s, q, tid);
             __syncthreads();
+            // after the barrier, so that its latency overlaps the next
+            // level's frame writes: issued before it, the wait for those LDS
+            // writes at the barrier would wait for this load too (scalar
+            // loads and LDS share one counter)
+            p4 = level_start(s, l + 5);
         };
         for (uint32_t l = 0; l < L3; l += 3) {
             if (done(l)) break;
@@ -551,12 +555,12 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     __syncthreads();
     bool stopped = false;
     for (uint32_t l = 0; l < L3; ++l) {
+        const uint32_t cf = l % kFrames;
+        const uint32_t cnt = fcount[cf];
         if (done(l)) {
             stopped = true;
             break;
         }
-        const uint32_t cf = l % kFrames;
-        const uint32_t cnt = fcount[cf];
         if (SAT) {
             A.nfull = &fdelta[l % 3];
             if (ctid == 0) fdelta[(l + 1) % 3] = 0;
@@ -573,7 +577,7 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
             const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
             uint32_t *work = worklist[SAT ? cw : 0];
             run_work<SW, ZERO>(A, frame[cf], work, classify<ZERO>(A, frame[cf], lo, hi, work));
-            if (ZERO) level_counts(A);
+            level_counts(A);
         } else {
             apply_frame<UC, MAX8>(A, frame[cf], 0, cnt);
             if (WIDE) {

@@ -95,29 +95,30 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_summarize_pmc_adds_the_kernels_of_one_launch(tmp_path):
-    # the saturating path of a large network is four dispatches of three
+    # the saturating path of a large network is five dispatches of four
     # kernels per launch; other kernels between them are not counted
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
     names = ["void tn::k_rowor_global<8, 10, true, true, false, true>(...)",
              "void tn::k_rowor_fwd<8, 7, true>(...)",
-             "void tn::k_slice_full_state<8>(...)",
-             "void tn::k_rowor_global<8, 10, true, true, false, false>(...)"]
+             "void tn::k_slice_full_state<4>(...)",
+             "tn::k_slice_order(unsigned int const*, unsigned int, unsigned int, unsigned int*)",
+             "void tn::k_rowor_global<4, 5, true, true, false, false>(...)"]
     rows_f = [{"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "FETCH_SIZE",
                "Counter_Value": "524288"}]
     rows_w = [{"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "WRITE_SIZE",
                "Counter_Value": "1048576"}]
-    for name, v in zip(names, (1, 10, 100, 1000)):
+    for name, v in zip(names, (1, 10, 100, 1000, 10000)):
         rows_f.append({"Kernel_Name": name, "Counter_Name": "FETCH_SIZE", "Counter_Value": str(v)})
         rows_w.append({"Kernel_Name": name, "Counter_Name": "WRITE_SIZE", "Counter_Value": str(v)})
         rows_f.append({"Kernel_Name": "tn::k_out_sizes(...)", "Counter_Name": "FETCH_SIZE",
                        "Counter_Value": "7"})
     _write_csv(fetch, rows_f)
     _write_csv(write, rows_w)
-    rec = bench.summarize_pmc(str(fetch), str(write), "rowor", "w", "cmd", 1024, last=4,
-                              per_launch=4)
+    rec = bench.summarize_pmc(str(fetch), str(write), "rowor", "w", "cmd", 1024, last=5,
+                              per_launch=5)
     assert rec["kernel"] == bench.ROWOR_SAT_KERNELS
-    assert rec["FETCH_SIZE"]["bytes_per_launch"] == pytest.approx(1024 * 2.0 * 1111)
-    assert rec["WRITE_SIZE"]["bytes_per_launch"] == pytest.approx(1024 * 1.0 * 1111)
+    assert rec["FETCH_SIZE"]["bytes_per_launch"] == pytest.approx(1024 * 2.0 * 11111)
+    assert rec["WRITE_SIZE"]["bytes_per_launch"] == pytest.approx(1024 * 1.0 * 11111)
 
 
 def test_counter_roofline_is_a_bandwidth():
