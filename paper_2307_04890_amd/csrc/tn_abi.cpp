@@ -413,8 +413,9 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     // share, its done counter and the slice order of the last launch
     const uint32_t tail_sw = tn::tail_slice_words(n, slice_words, ctx->num_cus);
     const uint32_t sinks = tn::rowor_workgroups(n, tail_sw);
-    const size_t sink_rows_words = (size_t)sinks * tn::kRoworSinkWords +
-                                   (size_t)plan->scratch_rows * (size_t)nwords;
+    const size_t sink_rows_words =
+        (size_t)sinks * tn::kRoworSinkWords +
+        (size_t)plan->scratch_rows * (size_t)tn::scratch_stride((uint32_t)nwords);
     const bool zero_phase = !wave && ctx->saturation && plan->zero_levels > 0;
     const size_t pwords = zero_phase ? tn::rowor_persist_words(n, tail_sw) + 1 : 0;
     const size_t owords = zero_phase ? sinks : 0;
@@ -608,7 +609,8 @@ tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
         const size_t words =
             plan->hll ? gat_words + nwords + 1 + ((size_t)1 << log2s) / 2
                       : (size_t)tn::rowmax_workgroups(nwords) * tn::kRoworSinkWords +
-                            (size_t)plan->scratch_rows * (size_t)nwords;
+                            (size_t)plan->scratch_rows *
+                                (size_t)tn::scratch_stride((uint32_t)nwords);
         tn_status st = tn::ensure_scratch(ctx, sizeof(uint64_t) * words);
         if (st != TN_OK) return st;
     }

@@ -268,16 +268,21 @@ hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t st
 // traffic (nullable): two device counters the identity kernel zeroes.
 hipError_t launch_identity(uint64_t *C, uint32_t n, int64_t ld, unsigned long long *traffic,
                            hipStream_t st);
-constexpr size_t kRoworSinkWords = 1024;
+// sink words per workgroup: one 16-byte slot per thread
+constexpr size_t kRoworSinkWords = 2048;
+// Scratch rows lie an even number of words apart, so that an access of two
+// words at an even word stays on a 16-byte boundary.
+inline uint32_t scratch_stride(uint32_t nwords) { return (nwords + 1u) & ~1u; }
 // LDS bytes the saturation bitmap may take next to the op frames and work
 // lists (gfx950: 160 KiB per workgroup).
 constexpr size_t kRoworSatLds = 163840 - 40960;
 // scratch: kRoworSinkWords words for each of sink_slots workgroups (at
 // least rowor_workgroups(n, slice_words), else hipErrorInvalidValue), then
-// scratch_rows rows of ceil(n/64) words; launches that hand scratch rows
-// over to each other pass the same sink_slots.  order (nullable): the
-// slice each workgroup takes, in dispatch order (launch_slice_order), for
-// the launch of the levels after zero_levels.
+// scratch_rows rows of ceil(n/64) words, scratch_stride(ceil(n/64)) apart;
+// launches that hand scratch rows over to each other pass the same
+// sink_slots.  order (nullable): the slice each workgroup takes, in
+// dispatch order (launch_slice_order), for the launch of the levels after
+// zero_levels.
 // The kernel adds the row words it loaded to traffic[0] and stored to
 // traffic[1] (device counters, zeroed by the caller).  With saturation, and
 // when a bit per row and scratch row fits kRoworSatLds, it skips the loads

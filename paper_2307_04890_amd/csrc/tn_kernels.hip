@@ -66,7 +66,7 @@ constexpr uint32_t kFrames = 2;  // LDS op frames: the level being run and the n
 struct OpArgs {
     uint64_t *C;
     size_t ldz;
-    uint64_t *rows;  // scratch rows, nwords words each
+    uint64_t *rows;  // scratch rows of nwords words, sld apart
     uint64_t *sink;  // this thread's sink word
     uint32_t w, nwords, grp, ngrp;
     bool wok;
@@ -86,6 +86,8 @@ struct OpArgs {
     uint32_t loaded, stored;  // row words this lane moved
     bool lead;                // first lane of its group
     uint32_t ld32;            // ldz, for 32-bit row offsets (fwd_addr)
+    uint32_t sld;             // scratch row stride: nwords rounded up to even
+    uint32_t vw;              // row words this lane covers (forwarding kernel)
 };
 
 // Branch-free: every candidate address is formed, then one is selected, so
@@ -93,7 +95,7 @@ struct OpArgs {
 __device__ __forceinline__ uint64_t *op_addr(const OpArgs &A, uint32_t id, bool valid) {
     const uint64_t row = (uint64_t)(id & kNodeMask);
     const uintptr_t real = (uintptr_t)(A.C + row * A.ldz + A.w);
-    const uintptr_t scr = (uintptr_t)(A.rows + row * A.nwords + A.w);
+    const uintptr_t scr = (uintptr_t)(A.rows + row * A.sld + A.w);
     const uintptr_t pick = (id & kScratchBit) ? scr : real;
     const bool ok = valid && A.wok && id != kNoRow;
     return (uint64_t *)(ok ? pick : (uintptr_t)A.sink);
@@ -106,7 +108,7 @@ template <bool OFF32>
 __device__ __forceinline__ uint64_t *fwd_addr(const OpArgs &A, uint32_t id, bool valid) {
     if (!OFF32) return op_addr(A, id, valid);
     const bool scr = id & kScratchBit;
-    const uint32_t off = __umul24(id & kNodeMask, scr ? A.nwords : A.ld32) + A.w;
+    const uint32_t off = __umul24(id & kNodeMask, scr ? A.sld : A.ld32) + A.w;
     uint64_t *base = scr ? A.rows : A.C;
     const bool ok = valid && A.wok && id != kNoRow;
     return ok ? base + off : A.sink;
@@ -390,6 +392,7 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     A.C = C;
     A.ldz = (size_t)ld;
     A.nwords = nwords;
+    A.sld = (nwords + 1u) & ~1u;
     A.w = slice * SW + (ctid % SW);
     A.wok = !loader && A.w < nwords;
     A.grp = ctid / SW;
@@ -629,16 +632,33 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
     return v;
 }
 
-template <int UC>
+// A lane's words of a row: one (8-byte accesses) or two (16-byte accesses:
+// per wave instruction twice the bytes for the same address work, which is
+// what the texture address and data units of a CU spend their cycles on
+// when 64 lanes touch 8 to 16 scattered row segments).
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+template <int LW>
+struct LaneT;
+template <>
+struct LaneT<1> {
+    using T = uint64_t;
+};
+template <>
+struct LaneT<2> {
+    using T = u64x2;
+};
+
+template <int UC, int LW>
 struct ColdVals {
-    uint64_t x[UC], y[UC];
+    typename LaneT<LW>::T x[UC], y[UC];
 };
 
 // The cold operands of the level in `frame` (forwarded ones read the sink).
-template <int SW, int UC, bool OFF32>
+template <int SW, int UC, bool OFF32, int LW>
 __device__ __forceinline__ void fwd_issue(OpArgs &A, const op4 *frame, uint32_t cnt,
-                                          ColdVals<UC> &c) {
-    constexpr uint32_t NG = (1024 - kLoaderThreads) / SW;
+                                          ColdVals<UC, LW> &c) {
+    using T = typename LaneT<LW>::T;
+    constexpr uint32_t NG = (1024 - kLoaderThreads) / (SW / LW);
     const uint32_t g = opaque(A.grp);
 #pragma unroll
     for (int k = 0; k < UC; ++k) {
@@ -646,18 +666,24 @@ __device__ __forceinline__ void fwd_issue(OpArgs &A, const op4 *frame, uint32_t 
         const op4 o = frame[min(j, kOpsLevelCap - 1)];
         const bool v = j < cnt;
         const bool hx = o.x & kFwdHot, hy = o.y & kFwdHot;
-        c.x[k] = *fwd_addr<OFF32>(A, o.x, v && !hx);
-        c.y[k] = *fwd_addr<OFF32>(A, o.y, v && !hy);
-        A.loaded += ((v && A.wok && !hx) ? 1u : 0u) + ((v && A.wok && !hy) ? 1u : 0u);
+        c.x[k] = *(const T *)fwd_addr<OFF32>(A, o.x, v && !hx);
+        c.y[k] = *(const T *)fwd_addr<OFF32>(A, o.y, v && !hy);
+        A.loaded += ((v && !hx) ? A.vw : 0u) + ((v && !hy) ? A.vw : 0u);
     }
 }
 
-// Runs the level in `frame` with its cold values in c.
-template <int SW, int UC, bool OFF32>
+// Runs the level in `frame` with its cold values in c.  keep clears a
+// lane's word past the row's last one (LW = 2), so padding stays zero.
+template <int SW, int UC, bool OFF32, int LW>
 __device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t cnt,
-                                          const ColdVals<UC> &c, const uint64_t *res_prev,
-                                          uint64_t *res_cur, uint32_t lig) {
-    constexpr uint32_t NG = (1024 - kLoaderThreads) / SW;
+                                          const ColdVals<UC, LW> &c, const uint64_t *res_prev,
+                                          uint64_t *res_cur, uint32_t lig,
+                                          typename LaneT<LW>::T keep) {
+    using T = typename LaneT<LW>::T;
+    constexpr uint32_t SL = SW / LW;  // lanes per op
+    constexpr uint32_t NG = (1024 - kLoaderThreads) / SL;
+    const T *rp = reinterpret_cast<const T *>(res_prev);
+    T *rc = reinterpret_cast<T *>(res_cur);
     const uint32_t g = opaque(A.grp);
 #pragma unroll
     for (int k = 0; k < UC; ++k) {
@@ -666,31 +692,34 @@ __device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t 
         const bool v = j < cnt;
         // a cold operand's low bits are a row id: its (unused) read is
         // clamped into the frame
-        const uint64_t lx = res_prev[min(o.x & kFwdSlotMask, kFwdLevelCap) * SW + lig];
-        const uint64_t ly = res_prev[min(o.y & kFwdSlotMask, kFwdLevelCap) * SW + lig];
-        const uint64_t r = ((o.x & kFwdHot) ? lx : c.x[k]) | ((o.y & kFwdHot) ? ly : c.y[k]);
+        const T lx = rp[min(o.x & kFwdSlotMask, kFwdLevelCap) * SL + lig];
+        const T ly = rp[min(o.y & kFwdSlotMask, kFwdLevelCap) * SL + lig];
+        const T r = (((o.x & kFwdHot) ? lx : c.x[k]) | ((o.y & kFwdHot) ? ly : c.y[k])) & keep;
         // slot kFwdLevelCap takes the writes of lanes with no op
-        res_cur[(v ? j : kFwdLevelCap) * SW + lig] = r;
+        rc[(v ? j : kFwdLevelCap) * SL + lig] = r;
         // kNoRow has the no-store bit too: it is never stored
         const bool s1 = v && !(o.z & kFwdNoStore);
         const bool s2 = v && !(o.w & kFwdNoStore);
-        *fwd_addr<OFF32>(A, o.z, s1) = r;
-        *fwd_addr<OFF32>(A, o.w, s2) = r;
-        A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+        *(T *)fwd_addr<OFF32>(A, o.z, s1) = r;
+        *(T *)fwd_addr<OFF32>(A, o.w, s2) = r;
+        A.stored += (s1 ? A.vw : 0u) + (s2 ? A.vw : 0u);
     }
 }
 
-template <int SW, int UC, bool OFF32>
+// LW words per lane: SW / LW lanes per op (LW = 2 needs even ld and a
+// 16-byte aligned matrix).
+template <int SW, int UC, bool OFF32, int LW>
 __global__ void __launch_bounds__(1024)
 k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
             uint64_t *__restrict__ scratch, uint64_t *__restrict__ rows,
             unsigned long long *__restrict__ traffic) {
-    static_assert(((1024 - kLoaderThreads) / SW) * UC >= kFwdLevelCap, "a level per pass");
+    static_assert(((1024 - kLoaderThreads) / (SW / LW)) * UC >= kFwdLevelCap, "a level per pass");
+    constexpr uint32_t SL = SW / LW;
     __shared__ op4 frame[kFwdFrames][kOpsLevelCap];
     __shared__ uint32_t fcount[kFwdFrames];
     // dynamic: two result frames of kFwdLevelCap + 1 slots (the last one a
     // sink) of SW words
-    extern __shared__ uint64_t results[];
+    extern __shared__ __attribute__((aligned(16))) uint64_t results[];
     constexpr uint32_t kFrameWords = (kFwdLevelCap + 1) * SW;
     const uint32_t L = s.L;
     if (L == 0 || s.nops == 0) return;
@@ -702,11 +731,13 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     A.C = C;
     A.ldz = (size_t)ld;
     A.nwords = nwords;
-    A.w = slice * SW + (ctid % SW);
+    A.sld = (nwords + 1u) & ~1u;
+    A.w = slice * SW + LW * (ctid % SL);
     A.wok = !loader && A.w < nwords;
-    A.grp = ctid / SW;
-    A.ngrp = (blockDim.x - kLoaderThreads) / SW;
-    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
+    A.vw = A.wok ? min((uint32_t)LW, nwords - A.w) : 0u;
+    A.grp = ctid / SL;
+    A.ngrp = (blockDim.x - kLoaderThreads) / SL;
+    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + LW * tid;
     A.rows = rows;
     A.loaded = A.stored = 0;
     A.ld32 = (uint32_t)ld;
@@ -745,8 +776,14 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
         }
         return;
     }
-    const uint32_t lig = ctid % SW;
-    ColdVals<UC> cA, cB;
+    const uint32_t lig = ctid % SL;
+    typename LaneT<LW>::T keep;
+    if constexpr (LW == 1) {
+        keep = ~0ull;
+    } else {
+        keep = u64x2{~0ull, A.w + 1 < nwords ? ~0ull : 0ull};
+    }
+    ColdVals<UC, LW> cA, cB;
     // Runs level l with cur holding its cold values, after issuing level
     // l + 1's into nxt.  The issue is unconditional (a level past the last
     // has no ops: every lane loads its sink) and level 0's own issue comes
@@ -754,22 +791,23 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     // every path: the compiler's wait before the use then leaves the loads
     // issued after it in flight (a join with a path that skipped them would
     // make it wait for those too).
-    auto period = [&](uint32_t l, ColdVals<UC> &cur, ColdVals<UC> &nxt) {
+    auto period = [&](uint32_t l, ColdVals<UC, LW> &cur, ColdVals<UC, LW> &nxt) {
         __syncthreads();
         const uint32_t nf = (l + 1) % kFwdFrames;
-        fwd_issue<SW, UC, OFF32>(A, frame[nf], fcount[nf], nxt);
+        fwd_issue<SW, UC, OFF32, LW>(A, frame[nf], fcount[nf], nxt);
         const uint32_t cf = l % kFwdFrames;
-        fwd_apply<SW, UC, OFF32>(A, frame[cf], fcount[cf], cur,
-                                 results + (size_t)((l + 1) & 1u) * kFrameWords,
-                                 results + (size_t)(l & 1u) * kFrameWords, lig);
+        fwd_apply<SW, UC, OFF32, LW>(A, frame[cf], fcount[cf], cur,
+                                     results + (size_t)((l + 1) & 1u) * kFrameWords,
+                                     results + (size_t)(l & 1u) * kFrameWords, lig, keep);
     };
     // level 0's cold values (frame 0 is written before the loaders' first
     // barrier, which the first period waits at)
     __syncthreads();
-    fwd_issue<SW, UC, OFF32>(A, frame[0], fcount[0], cA);
+    fwd_issue<SW, UC, OFF32, LW>(A, frame[0], fcount[0], cA);
     {
-        fwd_issue<SW, UC, OFF32>(A, frame[1], fcount[1], cB);
-        fwd_apply<SW, UC, OFF32>(A, frame[0], fcount[0], cA, results + kFrameWords, results, lig);
+        fwd_issue<SW, UC, OFF32, LW>(A, frame[1], fcount[1], cB);
+        fwd_apply<SW, UC, OFF32, LW>(A, frame[0], fcount[0], cA, results + kFrameWords, results,
+                                     lig, keep);
     }
     for (uint32_t l = 1; l < L; l += 2) {
         period(l, cB, cA);
@@ -884,6 +922,7 @@ k_rowor_fwd1(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     A.C = C;
     A.ldz = (size_t)ld;
     A.nwords = nwords;
+    A.sld = (nwords + 1u) & ~1u;
     A.w = slice * SW + (ctid % SW);
     A.wok = !loader && A.w < nwords;
     A.grp = ctid / SW;
@@ -1266,14 +1305,14 @@ hipError_t launch_rowor_global(const DevOps &s, uint32_t n, uint64_t *C, int64_t
     }
 }
 
-template <int SW, int UC>
+template <int SW, int UC, int LW>
 hipError_t rowor_fwd_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
                              uint64_t *scratch, uint64_t *rows, bool off32,
                              unsigned long long *traffic, hipStream_t st) {
     const uint32_t nwords = (n + 63) / 64;
     const uint32_t slices = (nwords + SW - 1) / SW;
     const size_t lds = sizeof(uint64_t) * 2 * (kFwdLevelCap + 1) * SW;
-    auto k = off32 ? k_rowor_fwd<SW, UC, true> : k_rowor_fwd<SW, UC, false>;
+    auto k = off32 ? k_rowor_fwd<SW, UC, true, LW> : k_rowor_fwd<SW, UC, false, LW>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
@@ -1308,7 +1347,7 @@ static bool rowor_fwd_off32(uint32_t n, int64_t ld, uint32_t scratch_rows) {
     const uint64_t nwords = (n + 63) / 64;
     return n < (1u << 24) && ld < (1 << 24) && scratch_rows + 1 < (1u << 24) &&
            (uint64_t)n * (uint64_t)ld < (1ull << 32) &&
-           (uint64_t)(scratch_rows + 1) * nwords < (1ull << 32);
+           (uint64_t)(scratch_rows + 1) * scratch_stride((uint32_t)nwords) < (1ull << 32);
 }
 
 hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld,
@@ -1320,12 +1359,21 @@ hipError_t launch_rowor_fwd(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld
         return hipErrorInvalidValue;
     uint64_t *rows = scratch + (size_t)sink_slots * kRoworSinkWords;
     const bool o32 = rowor_fwd_off32(n, ld, scratch_rows);
+    // two words per lane where every row starts on 16 bytes (scratch rows
+    // always do: scratch_stride)
+    const bool two = ld % 2 == 0 && ((uintptr_t)C & 15u) == 0;
     switch (slice_words) {
-        // UC: ops per lane group, so that (896 / SW) * UC >= kFwdLevelCap
-        case 1: return rowor_fwd_variant<1, 1>(s, n, C, ld, scratch, rows, o32, traffic, st);
-        case 2: return rowor_fwd_variant<2, 2>(s, n, C, ld, scratch, rows, o32, traffic, st);
-        case 4: return rowor_fwd_variant<4, 4>(s, n, C, ld, scratch, rows, o32, traffic, st);
-        case 8: return rowor_fwd_variant<8, 7>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        // UC: ops per lane group, so that (896 / (SW / LW)) * UC >= kFwdLevelCap
+        case 1: return rowor_fwd_variant<1, 1, 1>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        case 2:
+            return two ? rowor_fwd_variant<2, 1, 2>(s, n, C, ld, scratch, rows, o32, traffic, st)
+                       : rowor_fwd_variant<2, 2, 1>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        case 4:
+            return two ? rowor_fwd_variant<4, 2, 2>(s, n, C, ld, scratch, rows, o32, traffic, st)
+                       : rowor_fwd_variant<4, 4, 1>(s, n, C, ld, scratch, rows, o32, traffic, st);
+        case 8:
+            return two ? rowor_fwd_variant<8, 4, 2>(s, n, C, ld, scratch, rows, o32, traffic, st)
+                       : rowor_fwd_variant<8, 7, 1>(s, n, C, ld, scratch, rows, o32, traffic, st);
         case 16: return rowor_fwd1_variant<16, 14, 2>(s, n, C, ld, scratch, rows, o32, traffic, st);
         default: return hipErrorInvalidValue;
     }

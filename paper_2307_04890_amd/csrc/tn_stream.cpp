@@ -372,7 +372,8 @@ tn_status state_apply(tn_ctx *ctx, StreamState &s, int64_t m, const uint32_t *sr
             std::memcpy((unsigned char *)r.pinned + net_off, &net, sizeof(WaveNet));
         }
         const size_t need = sizeof(uint64_t) * ((size_t)s.slices * kRoworSinkWords +
-                                                (size_t)ch.hs.scratch_rows * (size_t)nwords);
+                                                (size_t)ch.hs.scratch_rows *
+                                                    (size_t)scratch_stride((uint32_t)nwords));
         st = ensure_scratch(ctx, need);
         if (st != TN_OK) break;
         e = hipMemcpyAsync(r.dev, r.pinned, bytes, hipMemcpyHostToDevice, ctx->stream);
