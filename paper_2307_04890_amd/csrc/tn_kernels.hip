@@ -87,8 +87,53 @@ struct OpArgs {
     bool lead;                // first lane of its group
     uint32_t ld32;            // ldz, for 32-bit row offsets (fwd_addr)
     uint32_t sld;             // scratch row stride: nwords rounded up to even
-    uint32_t vw;              // row words this lane covers (forwarding kernel)
+    uint32_t vw;              // row words this lane covers (two-word lanes)
+    uint64_t fullw1;          // fullw of the lane's second word (two-word lanes)
 };
+
+// A lane's words of a row: one (8-byte accesses) or two (16-byte accesses:
+// per wave instruction twice the bytes for the same address work, which is
+// what the texture address and data units of a CU spend their cycles on
+// when 64 lanes touch 8 to 16 scattered row segments).
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+template <int LW>
+struct LaneT;
+template <>
+struct LaneT<1> {
+    using T = uint64_t;
+};
+template <>
+struct LaneT<2> {
+    using T = u64x2;
+};
+
+// The lane's full row-slice value, and its words compared with another
+// value's.
+template <int LW>
+__device__ __forceinline__ typename LaneT<LW>::T lane_full(const OpArgs &A) {
+    if constexpr (LW == 1) {
+        return A.fullw;
+    } else {
+        return u64x2{A.fullw, A.fullw1};
+    }
+}
+// Clears a two-word lane's word past the row's last one (padding).
+template <int LW>
+__device__ __forceinline__ typename LaneT<LW>::T lane_keep(const OpArgs &A) {
+    if constexpr (LW == 1) {
+        return ~0ull;
+    } else {
+        return u64x2{~0ull, A.w + 1 < A.nwords ? ~0ull : 0ull};
+    }
+}
+template <int LW>
+__device__ __forceinline__ bool lane_eq(typename LaneT<LW>::T a, typename LaneT<LW>::T b) {
+    if constexpr (LW == 1) {
+        return a == b;
+    } else {
+        return a.x == b.x && a.y == b.y;
+    }
+}
 
 // Branch-free: every candidate address is formed, then one is selected, so
 // the load or store that uses it is issued by every lane.
@@ -208,11 +253,14 @@ __device__ __forceinline__ void level_counts(OpArgs &A) {
 // 5.1 us and 1.7 us per one-item level against 1.1 us (the idle items' sink
 // stores): a busy level is bound by the workgroup's memory throughput, not
 // by serialized round trips.
-template <int SW, bool ZERO>
+template <int SW, bool ZERO, int LW>
 __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint32_t *work,
                                          uint32_t nwork) {
-    constexpr uint32_t G = 64 / SW;  // lane groups per wave
-    const uint32_t g = (threadIdx.x & 63u) / SW;
+    using T = typename LaneT<LW>::T;
+    constexpr uint32_t SL = SW / LW;  // lanes per op
+    constexpr uint32_t G = 64 / SL;   // lane groups per wave
+    const uint32_t g = (threadIdx.x & 63u) / SL;
+    const T fullv = lane_full<LW>(A);
     for (uint32_t j0 = 0; j0 < nwork; j0 += G) {
         const uint32_t j = j0 + g;
         const uint32_t e = work[min(j, kWaveShare - 1)];
@@ -230,9 +278,9 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
             // most rows are full.
             const bool s1 = v && o.z != kNoRow && !f1;
             const bool s2 = v && o.w != kNoRow && !f2;
-            *op_addr(A, o.z, s1) = A.fullw;
-            *op_addr(A, o.w, s2) = A.fullw;
-            A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+            *(T *)op_addr(A, o.z, s1) = fullv;
+            *(T *)op_addr(A, o.w, s2) = fullv;
+            A.stored += (s1 ? A.vw : 0u) + (s2 ? A.vw : 0u);
             if (v && A.lead) {
                 if (s1) sat_set(A, o.z, true);
                 if (s2) sat_set(A, o.w, true);
@@ -246,19 +294,22 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
         // an operand known zero in this slice is not loaded
         const bool ldx = v && !skip && !(ZERO && (e & (kWorkZero | kWorkZX)));
         const bool ldy = v && !skip && !(ZERO && (e & (kWorkZero | kWorkZY)));
-        uint64_t r = skip ? A.fullw : 0ull;
+        const T none = T(0);
+        T r = skip ? fullv : none;
         if (__ballot(ldx || ldy) != 0) {
-            const uint64_t x = *op_addr(A, o.x, ldx);
-            const uint64_t y = *op_addr(A, o.y, ldy);
-            A.loaded += ((ldx && A.wok) ? 1u : 0u) + ((ldy && A.wok) ? 1u : 0u);
-            if (!skip) r = (ldx ? x : 0ull) | (ldy ? y : 0ull);
+            const T x = *(const T *)op_addr(A, o.x, ldx);
+            const T y = *(const T *)op_addr(A, o.y, ldy);
+            A.loaded += (ldx ? A.vw : 0u) + (ldy ? A.vw : 0u);
+            // a word past the row's last one (two-word lanes) is padding:
+            // its full value is zero, and it is kept zero
+            if (!skip) r = ((ldx ? x : none) | (ldy ? y : none)) & lane_keep<LW>(A);
         }
-        // the group's SW lanes agree on whether the whole row slice is full
-        const uint64_t ball = __ballot(r == A.fullw || !A.wok);
+        // the group's lanes agree on whether the whole row slice is full
+        const uint64_t ball = __ballot(lane_eq<LW>(r, fullv) || !A.wok);
         const bool full = (ball & A.gmask) == A.gmask;
         bool zero = false;
         if (ZERO && A.zon) {
-            const uint64_t zb = __ballot(r == 0ull || !A.wok);
+            const uint64_t zb = __ballot(lane_eq<LW>(r, none) || !A.wok);
             zero = (zb & A.gmask) == A.gmask;
         }
         const bool z1 = ZERO && (e & kWorkZ1), z2 = ZERO && (e & kWorkZ2);
@@ -266,9 +317,9 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
         // changes nothing
         const bool s1 = v && o.z != kNoRow && !(full && f1) && !(zero && z1);
         const bool s2 = v && o.w != kNoRow && !(full && f2) && !(zero && z2);
-        *op_addr(A, o.z, s1) = r;
-        *op_addr(A, o.w, s2) = r;
-        A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
+        *(T *)op_addr(A, o.z, s1) = r;
+        *(T *)op_addr(A, o.w, s2) = r;
+        A.stored += (s1 ? A.vw : 0u) + (s2 ? A.vw : 0u);
         // one lane per group refreshes the destinations' bits
         if (v && A.lead) {
             if (o.z != kNoRow && f1 != full) sat_set(A, o.z, full);
@@ -362,7 +413,9 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
 // CHUNK: one launch per chunk of a streamed build, with the slice state in
 // `persist` (a separate instantiation, so traces and counters keep the two
 // kinds of launch apart).
-template <int SW, int UC, bool SAT, bool CHUNK, bool MAX8 = false, bool ZERO = false>
+// LW words per lane (2: 16-byte row accesses, saturating launches only;
+// rows must start on 16 bytes).
+template <int SW, int UC, bool SAT, bool CHUNK, bool MAX8 = false, bool ZERO = false, int LW = 1>
 __global__ void __launch_bounds__(1024)
 k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords, DevOps s,
                uint64_t *__restrict__ scratch, uint64_t *__restrict__ rows, uint32_t sbase,
@@ -392,23 +445,27 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     A.C = C;
     A.ldz = (size_t)ld;
     A.nwords = nwords;
+    static_assert(LW == 1 || SAT, "two-word lanes in saturating launches only");
+    constexpr uint32_t SL = SW / LW;  // lanes per op
     A.sld = (nwords + 1u) & ~1u;
-    A.w = slice * SW + (ctid % SW);
+    A.w = slice * SW + LW * (ctid % SL);
     A.wok = !loader && A.w < nwords;
-    A.grp = ctid / SW;
-    A.ngrp = (blockDim.x - kLoaderThreads) / SW;
-    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + tid;
+    A.vw = A.wok ? min((uint32_t)LW, nwords - A.w) : 0u;
+    A.grp = ctid / SL;
+    A.ngrp = (blockDim.x - kLoaderThreads) / SL;
+    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + LW * tid;
     A.rows = rows;
     A.sat = satbits;
     A.sbase = sbase;
     A.sbits = sbits;
     A.loaded = A.stored = 0;
-    A.lead = (ctid % SW) == 0;
+    A.lead = (ctid % SL) == 0;
     {
         const uint32_t tail = n & 63u;
         const uint64_t last = tail ? (1ull << tail) - 1ull : ~0ull;
         A.fullw = !A.wok ? 0ull : (A.w + 1 < nwords ? ~0ull : last);
-        A.gmask = (SW == 64 ? ~0ull : ((1ull << SW) - 1ull)) << ((tid & 63u) / SW * SW);
+        A.fullw1 = !A.wok || A.w + 1 >= nwords ? 0ull : (A.w + 2 < nwords ? ~0ull : last);
+        A.gmask = (SL == 64 ? ~0ull : ((1ull << SL) - 1ull)) << ((tid & 63u) / SL * SL);
     }
     // Once every real row is full in this slice, all later ops are full
     // results into full rows: the workgroup stops.  A slice with a single
@@ -572,7 +629,7 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
             const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
             const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
             uint32_t *work = worklist[SAT ? cw : 0];
-            run_work<SW, ZERO>(A, frame[cf], work, classify<ZERO>(A, frame[cf], lo, hi, work));
+            run_work<SW, ZERO, LW>(A, frame[cf], work, classify<ZERO>(A, frame[cf], lo, hi, work));
             level_counts(A);
         } else {
             apply_frame<UC, MAX8>(A, frame[cf], 0, cnt);
@@ -631,22 +688,6 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
     asm volatile("" : "+v"(v));
     return v;
 }
-
-// A lane's words of a row: one (8-byte accesses) or two (16-byte accesses:
-// per wave instruction twice the bytes for the same address work, which is
-// what the texture address and data units of a CU spend their cycles on
-// when 64 lanes touch 8 to 16 scattered row segments).
-typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-template <int LW>
-struct LaneT;
-template <>
-struct LaneT<1> {
-    using T = uint64_t;
-};
-template <>
-struct LaneT<2> {
-    using T = u64x2;
-};
 
 template <int UC, int LW>
 struct ColdVals {
@@ -1161,6 +1202,10 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
     const uint32_t sbase = (n + 31u) & ~31u;
     const uint64_t sbits = (uint64_t)sbase + scratch_rows + 1;
     const size_t lds = (size_t)((sbits + 31) / 32) * 4;
+    // two words per lane where every matrix row starts on 16 bytes (scratch
+    // rows always do: scratch_stride)
+    constexpr int LW2 = (SW >= 2 && SW <= 16) ? 2 : 1;
+    const bool two = LW2 == 2 && ld % 2 == 0 && ((uintptr_t)C & 15u) == 0;
     if (saturation && lds <= kRoworSatLds) {
         DevOps rest = s;
         // zero phase: the first levels, while most row slices are still all
@@ -1171,7 +1216,8 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
         if (zero_levels > 0 && persist && 2 * lds <= kRoworSatLds) {
             DevOps head = s;
             head.L = min(zero_levels, s.L);
-            auto kz = k_rowor_global<SW, UC, true, true, false, true>;
+            auto kz = two ? k_rowor_global<SW, UC, true, true, false, true, LW2>
+                          : k_rowor_global<SW, UC, true, true, false, true, 1>;
             hipError_t e = hipFuncSetAttribute((const void *)kz,
                                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)(2 * lds));
@@ -1184,7 +1230,10 @@ hipError_t rowor_variant(const DevOps &s, uint32_t n, uint64_t *C, int64_t ld, u
             rest.L = s.L - head.L;
             rest.lvl = s.lvl + head.L;
         }
-        auto k = persist ? k_rowor_global<SW, UC, true, true> : k_rowor_global<SW, UC, true, false>;
+        auto k = persist ? (two ? k_rowor_global<SW, UC, true, true, false, false, LW2>
+                                : k_rowor_global<SW, UC, true, true, false, false, 1>)
+                         : (two ? k_rowor_global<SW, UC, true, false, false, false, LW2>
+                                : k_rowor_global<SW, UC, true, false, false, false, 1>);
         hipError_t e = hipFuncSetAttribute((const void *)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
