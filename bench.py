@@ -278,7 +278,7 @@ def run_exact(args):
     if args.no_plain:
         r["roofline"] = r["plain"] = None
     r["saturating"] = {"kernel": "k_rowor_global zero phase, k_rowor_fwd until the ops reach "
-                                 "10 n, k_slice_full_state and k_slice_order on narrower "
+                                 "9 n, k_slice_full_state and k_slice_order on narrower "
                                  "slices, k_rowor_global for the rest",
                        "avg_launch_ms": sat_ms, "moved_bytes": moved,
                        "moved_achieved": moved / (sat_ms * 1e-3) / 1e9,

@@ -324,17 +324,20 @@ hipError_t launch_slice_order(const uint32_t *persist, uint32_t n, uint32_t slic
 // workgroup's busy level is bound by its own memory pipeline (the
 // instructions and row segments it issues), so a slice still far from full
 // takes time in proportion to its width, and the slowest slice sets the
-// launch's time.  slice_words is halved while the slices stay within two
-// per compute unit (one resident workgroup each; light slices fill the
-// units that free up).  n = 10^5, m = 10^7 activity-driven: 8 words 6.5 ms,
-// 4 words 3.4 ms, 2 words 4.5 ms.
+// launch's time.  slice_words is halved while the slices stay within four
+// per compute unit (one resident workgroup each; the slices with the most
+// work go first and light ones fill the units that free up).  Row-OR at
+// n = 10^5, m = 10^7 activity-driven, forwarding phase to 9 n: 2-word
+// slices (782 workgroups) 15.1 ms, 4-word 15.5 ms; to 10 n: 2, 4 and 8 words
+// 15.5, 15.8 and 15.9 ms.
 uint32_t tail_slice_words(uint32_t n, uint32_t slice_words, int num_cus);
 // The saturating path's middle phase: from the end of the zero phase until
 // its ops reach kFwdPhaseOpsPerNode * n, the forwarding kernel (no skips,
 // each level's results through LDS) runs instead of the saturating one;
 // timed on the 10^5-node activity-driven workload, it is cheaper over that
-// range and dearer after it, when most ops have a full operand.
-constexpr int64_t kFwdPhaseOpsPerNode = 10;
+// range and dearer after it, when most ops have a full operand (row-OR with
+// the phase to 7, 8, 9, 10 and 11 n: 15.95, 15.30, 15.12, 15.46, 15.83 ms).
+constexpr int64_t kFwdPhaseOpsPerNode = 9;
 // Levels of the zero phase of a schedule: those before the level at which
 // its ops reach `budget`.  Applied to the identity the budget is n (about
 // one op per row), by when few row slices are still all zero; a streamed

@@ -1460,7 +1460,7 @@ hipError_t launch_slice_order(const uint32_t *persist, uint32_t n, uint32_t slic
 
 uint32_t tail_slice_words(uint32_t n, uint32_t slice_words, int num_cus) {
     uint32_t sw = slice_words;
-    const uint32_t cap = 2u * (uint32_t)(num_cus > 0 ? num_cus : 1);
+    const uint32_t cap = 4u * (uint32_t)(num_cus > 0 ? num_cus : 1);
     while (sw > 1 && rowor_workgroups(n, sw / 2) <= cap) sw /= 2;
     return sw;
 }

@@ -313,7 +313,7 @@ def test_wavefront_kernel_stops_full_columns():
 def test_saturating_path_with_a_forwarding_phase(sw):
     # n = 256 * 64 + 1: every slice width ends on a one-column slice.  Past
     # the zero phase, a network of this size runs the forwarding kernel until
-    # its ops reach 10 n, then the saturating kernel from slice state rebuilt
+    # its ops reach 9 n, then the saturating kernel from slice state rebuilt
     # out of the matrix, on one-word slices in a grid of its own (257
     # workgroups, against 17..257 before) and the slices with the most rows
     # still not full first; compound scratch rows live across that cut
@@ -324,7 +324,7 @@ def test_saturating_path_with_a_forwarding_phase(sw):
     sch = tn.host_schedule(n, s, d, t)
     lv, L = sch["lvl_op"], sch["stats"]["op_levels"]
     zl = int(np.searchsorted(lv[:L], n, side="left"))
-    mid = int(np.searchsorted(lv[:L], 10 * n, side="left"))
+    mid = int(np.searchsorted(lv[:L], 9 * n, side="left"))
     assert 0 < zl < mid < L
     ctx = tn.get_context()
     p = tn.Plan(n, s, d, t)
@@ -358,7 +358,7 @@ def test_saturating_path_on_two_blocks(sw):
     sch = tn.host_schedule(n, s, d, t)
     lv, L = sch["lvl_op"], sch["stats"]["op_levels"]
     zl = int(np.searchsorted(lv[:L], n, side="left"))
-    mid = int(np.searchsorted(lv[:L], 10 * n, side="left"))
+    mid = int(np.searchsorted(lv[:L], 9 * n, side="left"))
     assert 0 < zl < mid < L
     ctx = tn.get_context()
     p = tn.Plan(n, s, d, t)

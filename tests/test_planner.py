@@ -412,7 +412,7 @@ def test_saturation_model_stops_full_slices():
 def test_scratch_rows_live_across_the_forwarding_cut(blocks):
     # the premise of the GPU tests of the saturating path with a forwarding
     # phase: some compound items' scratch rows are written before the level
-    # at which the ops reach 10 n and read after it, so the launches on
+    # at which the ops reach 9 n and read after it, so the launches on
     # either side must find them at the same place
     n = 16385
     if blocks:
@@ -422,7 +422,7 @@ def test_scratch_rows_live_across_the_forwarding_cut(blocks):
     sch = tn.host_schedule(n, s, d, t)
     lv, L = sch["lvl_op"].astype(np.int64), sch["stats"]["op_levels"]
     ops = sch["ops"].astype(np.int64)
-    mid = int(np.searchsorted(lv[:L], 10 * n, side="left"))
+    mid = int(np.searchsorted(lv[:L], 9 * n, side="left"))
     lvl = np.repeat(np.arange(L), np.diff(lv[:L + 1]))
     SCR, NOROW = 0x80000000, 0xFFFFFFFF
     last = {}
