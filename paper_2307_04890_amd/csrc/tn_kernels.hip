@@ -1029,56 +1029,71 @@ k_rowor_fwd1(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
 // The per-slice state of the saturating kernel (launch_rowor_global's
 // persist) rebuilt from the matrix itself: for slice s, bit r of its full
 // row bits is set iff row r holds every column of the slice, and its count
-// is the number of such rows.  One wavefront per 64 rows of a slice, the
-// slices of the same rows on neighbouring wavefronts (a row's words are
-// contiguous): groups of SW lanes read one row slice each, SW rows per lane
-// with every load issued before the first compare; a group's lanes AND
-// their checks, lane r of the wave collects row r's result, and the wave's
-// ballot gives two bitmap words.  The state must be zero before
+// is the number of such rows.  One wavefront per 64 rows of a span of RW
+// words (RW / SW slices; at least 8 words, so that narrow slices still read
+// 64-byte row segments), neighbouring wavefronts on the neighbouring spans
+// of the same rows (a row's words are contiguous): groups of RW lanes read
+// one row segment each, RW rows per lane with every load issued before the
+// first compare; the SW lanes of a slice AND their checks, lane r of the
+// wave collects row r's result for each slice of the span, and one ballot
+// per slice gives two bitmap words.  The state must be zero before
 // (launch_fill_u32).
-template <int SW>
+template <int SW, int RW>
 __global__ void __launch_bounds__(256)
 k_slice_full_state(const uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords,
                    uint32_t slices, uint32_t *__restrict__ persist) {
-    constexpr uint32_t G = 64 / SW;  // rows per load instruction
+    static_assert(RW % SW == 0 && RW <= 64, "a span holds whole slices");
+    constexpr uint32_t G = 64 / RW;  // rows per load instruction
+    constexpr uint32_t S = RW / SW;  // slices per span
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t g = lane / SW, j = lane % SW;
+    const uint32_t g = lane / RW, j = lane % RW;
     const uint32_t rwords = ((n + 31u) & ~31u) / 32;
     const size_t pslice = 2 * (size_t)rwords + 2;
     const uint32_t blocks = (n + 63) / 64;
     const uint32_t tail = n & 63u;
     const uint64_t last = tail ? (1ull << tail) - 1ull : ~0ull;
-    const size_t jobs = (size_t)slices * blocks;
+    const uint32_t spans = (slices + S - 1) / S;
+    const size_t jobs = (size_t)spans * blocks;
     for (size_t job = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; job < jobs;
          job += ((size_t)gridDim.x * blockDim.x) >> 6) {
-        const uint32_t slice = (uint32_t)(job % slices);
-        const uint32_t rb = (uint32_t)(job / slices);
+        const uint32_t span = (uint32_t)(job % spans);
+        const uint32_t rb = (uint32_t)(job / spans);
         const uint32_t r0 = rb * 64;
-        const uint32_t w = slice * SW + j;
+        const uint32_t w = span * RW + j;
         const bool wok = w < nwords;  // words past the last one check as full
         const uint64_t want = w + 1 == nwords ? last : ~0ull;
-        uint64_t v[SW];
+        uint64_t v[RW];
 #pragma unroll
-        for (int k = 0; k < SW; ++k) {
+        for (int k = 0; k < RW; ++k) {
             const uint32_t r = r0 + k * G + g;
             v[k] = (wok && r < n) ? C[(size_t)r * (size_t)ld + w] : want;
         }
-        bool mine = false;
+        bool mine[S];
 #pragma unroll
-        for (int k = 0; k < SW; ++k) {
+        for (int q = 0; q < (int)S; ++q) mine[q] = false;
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
             int f = (r0 + k * G + g < n && v[k] == want) ? 1 : 0;
 #pragma unroll
             for (uint32_t off = 1; off < SW; off <<= 1) f &= __shfl_xor(f, off);
             // row r0 + lane is row k * G + g of iteration k = lane / G
-            const int t = __shfl(f, (int)((lane % G) * SW));
-            if (lane / G == (uint32_t)k) mine = t != 0;
+#pragma unroll
+            for (int q = 0; q < (int)S; ++q) {
+                const int t = __shfl(f, (int)((lane % G) * RW + q * SW));
+                if (lane / G == (uint32_t)k) mine[q] = t != 0;
+            }
         }
-        const uint64_t b = __ballot(mine);
-        uint32_t *pst = persist + (size_t)slice * pslice;
         const uint32_t word = rb * 2;
-        if (lane == 0 && word < rwords) pst[2 + word] = (uint32_t)b;
-        if (lane == 1 && word + 1 < rwords) pst[2 + word + 1] = (uint32_t)(b >> 32);
-        if (lane == 0 && b) atomicAdd(pst + 1, (uint32_t)__popcll(b));
+#pragma unroll
+        for (int q = 0; q < (int)S; ++q) {
+            const uint32_t slice = span * S + q;
+            const uint64_t b = __ballot(mine[q]);
+            if (slice >= slices) break;
+            uint32_t *pst = persist + (size_t)slice * pslice;
+            if (lane == 0 && word < rwords) pst[2 + word] = (uint32_t)b;
+            if (lane == 1 && word + 1 < rwords) pst[2 + word + 1] = (uint32_t)(b >> 32);
+            if (lane == 0 && b) atomicAdd(pst + 1, (uint32_t)__popcll(b));
+        }
     }
 }
 
@@ -1434,14 +1449,17 @@ hipError_t launch_slice_full_state(const uint64_t *C, int64_t ld, uint32_t n,
     const uint32_t slices = rowor_workgroups(n, slice_words);
     hipError_t e = launch_fill_u32(persist, rowor_persist_words(n, slice_words), 0u, st);
     if (e != hipSuccess) return e;
-    const size_t waves = (size_t)slices * ((n + 63) / 64);
+    // spans of at least 8 words
+    const uint32_t span_words = slice_words < 8 ? 8 : slice_words;
+    const size_t spans = ((size_t)nwords + span_words - 1) / span_words;
+    const size_t waves = spans * ((n + 63) / 64);
     const uint32_t blocks = (uint32_t)std::min<size_t>((waves + 3) / 4, 65536);
     switch (slice_words) {
-        case 1: hipLaunchKernelGGL(k_slice_full_state<1>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
-        case 2: hipLaunchKernelGGL(k_slice_full_state<2>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
-        case 4: hipLaunchKernelGGL(k_slice_full_state<4>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
-        case 8: hipLaunchKernelGGL(k_slice_full_state<8>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
-        case 16: hipLaunchKernelGGL(k_slice_full_state<16>, dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 1: hipLaunchKernelGGL((k_slice_full_state<1, 8>), dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 2: hipLaunchKernelGGL((k_slice_full_state<2, 8>), dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 4: hipLaunchKernelGGL((k_slice_full_state<4, 8>), dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 8: hipLaunchKernelGGL((k_slice_full_state<8, 8>), dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
+        case 16: hipLaunchKernelGGL((k_slice_full_state<16, 16>), dim3(blocks), dim3(256), 0, st, C, ld, n, nwords, slices, persist); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
