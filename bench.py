@@ -216,9 +216,10 @@ def run_exact(args):
     cp = tn.api._dp
 
     def step():
-        plan.execute(C, slice_words=args.slice_words)
-        tn._lib.check(tn.lib.tn_component_sizes(ctx.bind_stream(), n, cp(C), C.stride(0),
-                                                cp(out), cp(inn)))
+        # the row-OR, then the sizes from the matrix and the slice state the
+        # execution left (slices left all ones are counted without a read)
+        tn._lib.check(tn.lib.tn_plan_execute_sizes(ctx.bind_stream(), plan.h, cp(C), C.stride(0),
+                                                   int(args.slice_words), cp(out), cp(inn)))
 
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
@@ -260,7 +261,9 @@ def run_exact(args):
                     1e3 * elapsed / args.steps, config)
     r["value_note"] = ("one step = identity + the saturating row-OR kernel (rows that are all "
                        "ones in a column slice are not moved again; the matrix is bit-identical "
-                       "to the plain recurrence) + out- and in-sizes")
+                       "to the plain recurrence) + out- and in-sizes (tn_plan_execute_sizes: "
+                       "the columns of slices the execution left all ones are counted from its "
+                       "slice state, the rest from the matrix)")
     r["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": plain_traffic,
                      "kernel": "k_rowor_fwd (the plain recurrence, saturation off: every op "

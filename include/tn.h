@@ -335,6 +335,19 @@ tn_status tn_hll_build(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
                        uint32_t log2s, const uint64_t *node_hash, uint8_t *M,
                        double *est);
 
+/* tn_plan_execute, then the component sizes of the matrix it wrote (as
+ * tn_component_sizes; Sec. 3.1, Eq. 1).  A saturating execution leaves a
+ * per-slice state in which a slice whose every row ended all ones is marked
+ * (Sec. 3.4: rows only gain bits); its columns then count in every row's
+ * out-size and have in-size n without a read of the matrix, so a saturated
+ * network's sizes cost no second pass over C.  Other slices, and executions
+ * that keep no state (saturation off, small networks on one wavefront per
+ * word column), are counted from C.  Arguments and errors as
+ * tn_plan_execute and tn_component_sizes; out_sizes, in_sizes: DEVICE
+ * int32[n], either may be NULL. */
+tn_status tn_plan_execute_sizes(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t ld,
+                                uint32_t slice_words, int32_t *out_sizes, int32_t *in_sizes);
+
 /* Component sizes (Sec. 3.1, Eq. 1): out_sizes[u] = ones in row u (the
  * maximum out-component size of u), in_sizes[w] = ones in column w (the
  * in-component size of w).  C: DEVICE n x ld.  out_sizes, in_sizes: DEVICE

@@ -89,6 +89,7 @@ SIGNATURES = {
     "tn_schedule_fwd_arrays": (_i32, [_P, _u32, _P, _PP, _PP]),
     "tn_schedule_op_arrays": (_i32, [_P, _PP, _PP]),
     "tn_plan_execute": (_i32, [_P, _P, _P, _i64, _u32]),
+    "tn_plan_execute_sizes": (_i32, [_P, _P, _P, _i64, _u32, _P, _P]),
     "tn_set_saturation": (_i32, [_P, ctypes.c_int]),
     "tn_hll_execute": (_i32, [_P, _P, _u32, _P, _P, _P]),
     "tn_hll_build": (_i32, [_P, _u32, _i64, _P, _P, _P, _u32, _u32, _P, _P, _P]),

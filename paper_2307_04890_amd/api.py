@@ -190,6 +190,26 @@ class Plan:
                                   int(slice_words)))
         return C
 
+    def execute_sizes(self, C: torch.Tensor | None = None, slice_words: int = 0,
+                      out: torch.Tensor | None = None, inn: torch.Tensor | None = None):
+        """execute(), then (out_sizes, in_sizes) from the matrix and the slice
+        state the execution left: (C, out, inn), int32 device tensors."""
+        if C is None:
+            C = alloc_matrix(self.n, device=self.ctx.device)
+        if C.dtype != torch.int64 or C.dim() != 2 or C.shape[0] != self.n:
+            raise ValueError("C must be an int64 (n, ld) device tensor")
+        dev = C.device
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.int32, device=dev)
+        if inn is None:
+            inn = torch.empty(self.n, dtype=torch.int32, device=dev)
+        for a in (out, inn):
+            if a.dtype != torch.int32 or a.numel() != self.n or not a.is_contiguous():
+                raise ValueError("out and inn must be contiguous int32 tensors of n entries")
+        check(lib.tn_plan_execute_sizes(self.ctx.bind_stream(), self.h, _dp(C), C.stride(0),
+                                        int(slice_words), _dp(out), _dp(inn)))
+        return C, out, inn
+
     def close(self):
         if getattr(self, "h", None):
             lib.tn_plan_destroy(self.h)

@@ -426,6 +426,8 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
     }
     uint32_t *persist = zero_phase ? (uint32_t *)((uint64_t *)ctx->scratch + sink_rows_words) : nullptr;
     uint32_t *order = zero_phase ? persist + pwords : nullptr;
+    ctx->state = nullptr;
+    ctx->state_sw = 0;
     hipError_t e;
     if (!ctx->traffic) {
         e = hipMalloc((void **)&ctx->traffic, 2 * sizeof(unsigned long long));
@@ -489,6 +491,10 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
                 e = tn::launch_rowor_global(tail, n, C, ld, tail_sw, (uint64_t *)ctx->scratch,
                                             sinks, plan->scratch_rows, ctx->traffic, true, persist,
                                             done, 0u, order, ctx->stream);
+            if (e == hipSuccess) {
+                ctx->state = persist;
+                ctx->state_sw = tail_sw;
+            }
         } else if (wave && plan->flat)
             e = tn::launch_rowor_wave_flat1(plan->flat, plan->view.nops, n, C, ld,
                                             plan->scratch_rows, ctx->traffic, ctx->saturation,
@@ -496,12 +502,19 @@ tn_status tn_plan_execute(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t
         else if (wave)
             e = tn::launch_rowor_wave(plan->view, n, C, ld, plan->scratch_rows, ctx->traffic,
                                       ctx->saturation, nullptr, nullptr, ctx->stream);
-        else
+        else {
             e = tn::launch_rowor_global(plan->view, n, C, ld, slice_words,
                                         (uint64_t *)ctx->scratch, sinks, plan->scratch_rows,
                                         ctx->traffic, ctx->saturation, persist,
                                         persist ? persist + pwords - 1 : nullptr,
                                         zero_phase ? plan->zero_levels : 0u, nullptr, ctx->stream);
+            // a launch that kept no state (no room for the bitmap) left the
+            // zeroed state: no slice counts as done
+            if (e == hipSuccess && persist) {
+                ctx->state = persist;
+                ctx->state_sw = slice_words;
+            }
+        }
     }
     if (e != hipSuccess) return hip_fail(e, "row-OR kernel launch");
     return TN_OK;
@@ -702,8 +715,10 @@ tn_status tn_hll_build(tn_ctx *ctx, uint32_t n, int64_t m, const uint32_t *src,
     return st;
 }
 
-tn_status tn_component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C, int64_t ld,
-                             int32_t *out_sizes, int32_t *in_sizes) {
+namespace {
+tn_status component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C, int64_t ld,
+                          int32_t *out_sizes, int32_t *in_sizes, const uint32_t *state,
+                          uint32_t state_sw) {
     if (!ctx) return fail(TN_E_ARG, "ctx is NULL");
     if (n == 0) return fail(TN_E_ARG, "n must be > 0");
     if (!C) return fail(TN_E_ARG, "C is NULL");
@@ -713,15 +728,30 @@ tn_status tn_component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C, int64_t
     if (!g.ok) return fail(TN_E_HIP, "cannot select the context's device");
     if (out_sizes) {
         tn::ProfScope ps(ctx, TN_K_OUT_SIZES);
-        hipError_t e = tn::launch_out_sizes(C, n, ld, out_sizes, ctx->stream);
+        hipError_t e = tn::launch_out_sizes(C, n, ld, out_sizes, ctx->stream, state, state_sw);
         if (e != hipSuccess) return hip_fail(e, "out-size kernel launch");
     }
     if (in_sizes) {
         tn::ProfScope ps(ctx, TN_K_IN_SIZES);
-        hipError_t e = tn::launch_in_sizes(C, n, ld, in_sizes, ctx->stream);
+        hipError_t e = tn::launch_in_sizes(C, n, ld, in_sizes, ctx->stream, state, state_sw);
         if (e != hipSuccess) return hip_fail(e, "in-size kernel launch");
     }
     return TN_OK;
+}
+}  // namespace
+
+tn_status tn_component_sizes(tn_ctx *ctx, uint32_t n, const uint64_t *C, int64_t ld,
+                             int32_t *out_sizes, int32_t *in_sizes) {
+    return component_sizes(ctx, n, C, ld, out_sizes, in_sizes, nullptr, 0);
+}
+
+tn_status tn_plan_execute_sizes(tn_ctx *ctx, const tn_plan *plan, uint64_t *C, int64_t ld,
+                                uint32_t slice_words, int32_t *out_sizes, int32_t *in_sizes) {
+    tn_status st = tn_plan_execute(ctx, plan, C, ld, slice_words);
+    if (st != TN_OK) return st;
+    // the state the execution just left describes exactly this matrix
+    return component_sizes(ctx, plan->stats.n, C, ld, out_sizes, in_sizes, ctx->state,
+                           ctx->state_sw);
 }
 
 }  // extern "C"

@@ -155,6 +155,11 @@ struct tn_ctx {
     size_t host_staging_bytes = 0;
     // row words loaded / stored by the last tn_plan_execute (device)
     unsigned long long *traffic = nullptr;
+    // the slice state the last tn_plan_execute left in scratch (null: none)
+    // and its slice width: a slice with its done word set is all ones in
+    // every row of the matrix that execution wrote
+    const uint32_t *state = nullptr;
+    uint32_t state_sw = 0;
     // ring of pinned slots for host-to-device uploads (tn::ring_upload):
     // each slot's copy is an SDMA transfer on the context's stream, and its
     // event says when the slot may be refilled
@@ -408,10 +413,15 @@ inline bool rowor_saturates(uint32_t n, uint32_t scratch_rows) {
     const uint64_t sbits = (((uint64_t)n + 31) & ~31ull) + scratch_rows + 1;
     return ((sbits + 31) / 32) * 4 <= kRoworSatLds;
 }
-hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld,
-                            int32_t *out_sizes, hipStream_t st);
-hipError_t launch_in_sizes(const uint64_t *C, uint32_t n, int64_t ld,
-                           int32_t *in_sizes, hipStream_t st);
+// Row and column popcounts of C; with a slice state (persist of slices of
+// state_sw words, nullable) the words of slices left all ones are counted
+// without a read.
+hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *out_sizes,
+                            hipStream_t st, const uint32_t *persist = nullptr,
+                            uint32_t state_sw = 0);
+hipError_t launch_in_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *in_sizes,
+                           hipStream_t st, const uint32_t *persist = nullptr,
+                           uint32_t state_sw = 0);
 uint32_t default_slice_words(uint32_t n, int64_t ld);
 
 }  // namespace tn

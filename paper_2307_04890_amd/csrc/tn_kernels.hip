@@ -1127,17 +1127,39 @@ __global__ void __launch_bounds__(256) k_fill_i32(int32_t *__restrict__ p, uint3
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Whether word column w lies in a slice that a saturating launch left all
+// ones in every row (its done word in the slice state; no state: none).
+__device__ __forceinline__ bool word_done(const uint32_t *persist, uint32_t pslice, uint32_t sw,
+                                          uint32_t w) {
+    return persist && persist[(size_t)(w / sw) * pslice] != 0u;
+}
+
 // out[u] = popcount of row u: one wavefront per row, lanes stride the words.
+// With a slice state (persist: pslice words per slice of sw words), a word
+// of a slice left all ones counts its valid columns without a read.
 __global__ void __launch_bounds__(256)
 k_out_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwords,
-            int32_t *__restrict__ out) {
+            int32_t *__restrict__ out, const uint32_t *__restrict__ persist, uint32_t pslice,
+            uint32_t sw) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
+    // this lane's done words: their columns once, a row read for the rest
+    int base = 0;
+    bool any_open = false;
+    for (uint32_t j = lane; j < nwords; j += 64) {
+        if (word_done(persist, pslice, sw, j))
+            base += (j + 1 < nwords || (n & 63u) == 0) ? 64 : (int)(n & 63u);
+        else
+            any_open = true;
+    }
     for (uint32_t r = wave; r < n; r += nwave) {
         const uint64_t *row = C + (size_t)r * (size_t)ld;
-        int c = 0;
-        for (uint32_t j = lane; j < nwords; j += 64) c += __popcll(row[j]);
+        int c = base;
+        if (any_open) {
+            for (uint32_t j = lane; j < nwords; j += 64)
+                if (!word_done(persist, pslice, sw, j)) c += __popcll(row[j]);
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
         if (lane == 0) out[r] = c;
@@ -1151,9 +1173,12 @@ k_out_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwo
 // LDS, and the workgroup adds each column's total to in[] once: one global
 // atomic per column and chunk of kInRowsPerChunk rows.
 constexpr uint32_t kInRowsPerChunk = 4096;  // per wave 1024 < 2^16: 16 planes suffice
+// With a slice state, a word column of a slice left all ones has n in
+// every column: the first chunk adds it, no chunk reads the column.
 __global__ void __launch_bounds__(256)
 k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwords,
-           int32_t *__restrict__ in) {
+           int32_t *__restrict__ in, const uint32_t *__restrict__ persist, uint32_t pslice,
+           uint32_t sw) {
     __shared__ int32_t cnt[64 * 64];  // [bit][column word]: a wave's lanes on distinct banks
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) cnt[i] = 0;
@@ -1162,7 +1187,12 @@ k_in_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwor
     const uint32_t share = kInRowsPerChunk / 4;
     const uint32_t r0 = blockIdx.y * kInRowsPerChunk + wave * share;
     const uint32_t r1 = min(n, r0 + share);
-    if (j < nwords && r0 < r1) {
+    const bool done = j < nwords && word_done(persist, pslice, sw, j);
+    if (done && blockIdx.y == 0 && wave == 0) {
+        const uint32_t bits = (j + 1 < nwords || (n & 63u) == 0) ? 64u : (n & 63u);
+        for (uint32_t b = 0; b < bits; ++b) atomicAdd(&cnt[b * 64 + lane], (int32_t)n);
+    }
+    if (j < nwords && r0 < r1 && !done) {
         uint64_t c[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) c[i] = 0;
@@ -1484,16 +1514,18 @@ uint32_t tail_slice_words(uint32_t n, uint32_t slice_words, int num_cus) {
 }
 
 hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *out_sizes,
-                            hipStream_t st) {
+                            hipStream_t st, const uint32_t *persist, uint32_t state_sw) {
     const uint32_t nwords = (n + 63) / 64;
     uint32_t blocks = (n + 3) / 4;
     if (blocks > 16384u) blocks = 16384u;
-    hipLaunchKernelGGL(k_out_sizes, dim3(blocks), dim3(256), 0, st, C, n, ld, nwords, out_sizes);
+    const uint32_t pslice = persist ? (uint32_t)(2 * (((size_t)n + 31) / 32) + 2) : 0u;
+    hipLaunchKernelGGL(k_out_sizes, dim3(blocks), dim3(256), 0, st, C, n, ld, nwords, out_sizes,
+                       persist, pslice, state_sw ? state_sw : 1u);
     return hipGetLastError();
 }
 
 hipError_t launch_in_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *in_sizes,
-                           hipStream_t st) {
+                           hipStream_t st, const uint32_t *persist, uint32_t state_sw) {
     const uint32_t nwords = (n + 63) / 64;
     uint32_t fb = (n + 255) / 256;
     if (fb > 4096u) fb = 4096u;
@@ -1501,7 +1533,9 @@ hipError_t launch_in_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid((nwords + 63) / 64, (n + kInRowsPerChunk - 1) / kInRowsPerChunk);
-    hipLaunchKernelGGL(k_in_sizes, grid, dim3(256), 0, st, C, n, ld, nwords, in_sizes);
+    const uint32_t pslice = persist ? (uint32_t)(2 * (((size_t)n + 31) / 32) + 2) : 0u;
+    hipLaunchKernelGGL(k_in_sizes, grid, dim3(256), 0, st, C, n, ld, nwords, in_sizes, persist,
+                       pslice, state_sw ? state_sw : 1u);
     return hipGetLastError();
 }
 

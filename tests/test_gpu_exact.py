@@ -377,3 +377,61 @@ def test_saturating_path_on_two_blocks(sw):
     for w0 in (0, 131, nw - 1):
         want = oracle.reverse_matrix(n, s, d, t, w0=w0, nw=1)
         assert (got[:, w0:w0 + 1] == want).all(), (sw, w0)
+
+
+def _partial_network(n, m, word, seed):
+    # directed events; the nodes of one word column never receive, so no
+    # other node reaches them: that column never fills, every other one does
+    s, d, t = T.uniform_pairs(n, m, 2000, seed=seed)
+    s, d = s.astype(np.int64), d.astype(np.int64)
+    bad = (d >= 64 * word) & (d < 64 * (word + 1))
+    d[bad] = (d[bad] + 64 * 7) % n
+    keep = s != d
+    return n, s[keep].astype(np.uint32), d[keep].astype(np.uint32), t[keep], tn.DIRECTED
+
+
+@pytest.mark.parametrize("case", ["partial", "two_blocks", "small_partial"])
+def test_sizes_from_the_slice_state(case):
+    # tn_plan_execute_sizes counts the columns of slices that the execution
+    # left all ones from its slice state, without reading them.  Through the
+    # three-phase path (last launch on one-word slices): a network where all
+    # but one word column fill (256 of 257 slices counted from the state) and
+    # one where no slice fills (two blocks); through the two launches of a
+    # smaller network, 4-word slices with all but one filled
+    if case == "partial":
+        n, s, d, t, flags = _partial_network(16385, 500_000, 100, 8420)
+        widths = (0, 2, 8)
+    elif case == "small_partial":
+        n, s, d, t, flags = _partial_network(8001, 400_000, 50, 8430)
+        widths = (0, 4)
+    else:
+        n = 16385
+        s, d, t = T.two_block_pairs(n, 600_000, 2000, seed=8410)
+        flags = 0
+        widths = (0, 2, 8)
+    want = oracle.reverse_matrix(n, s, d, t, **flag_kw(flags))
+    nw = oracle.words(n)
+    full = np.full(nw, np.uint64(0xFFFFFFFFFFFFFFFF))
+    full[-1] = np.uint64((1 << (n % 64)) - 1)
+    filled = int((want[:, :nw] == full[None, :]).all(axis=0).sum())
+    assert filled == (0 if case == "two_blocks" else nw - 1)
+    wo, wi = oracle.sizes(want, n)
+    p = tn.Plan(n, s, d, t, flags)
+    try:
+        for sw in widths:
+            C, out, inn = p.execute_sizes(slice_words=sw)
+            assert (host(C)[:, :nw] == want).all(), (case, sw)
+            assert (out.cpu().numpy() == wo).all(), (case, sw)
+            assert (inn.cpu().numpy() == wi).all(), (case, sw)
+    finally:
+        p.close()
+
+
+def test_full_size_sizes_from_the_slice_state(c2):
+    # at n = 10^5 every slice ends all ones: the sizes come from the state
+    # alone, and equal the ones counted from the matrix
+    C, out, inn = c2["plan"].execute_sizes()
+    assert torch.equal(C, c2["C"])
+    o2, i2 = tn.component_sizes(C, 100_000)
+    assert torch.equal(out, o2) and torch.equal(inn, i2)
+    assert (out == 100_000).all() and (inn == 100_000).all()
