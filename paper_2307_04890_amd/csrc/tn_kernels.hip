@@ -1153,6 +1153,15 @@ k_out_sizes(const uint64_t *__restrict__ C, uint32_t n, int64_t ld, uint32_t nwo
         else
             any_open = true;
     }
+    if (__ballot(any_open) == 0) {
+        // every word of the row is done: the same count for every row,
+        // reduced once (a shuffle step is an LDS permute)
+        int total = base;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
+        for (uint32_t r = wave * 64 + lane; r < n; r += nwave * 64) out[r] = total;
+        return;
+    }
     for (uint32_t r = wave; r < n; r += nwave) {
         const uint64_t *row = C + (size_t)r * (size_t)ld;
         int c = base;
@@ -1518,6 +1527,9 @@ hipError_t launch_out_sizes(const uint64_t *C, uint32_t n, int64_t ld, int32_t *
     const uint32_t nwords = (n + 63) / 64;
     uint32_t blocks = (n + 3) / 4;
     if (blocks > 16384u) blocks = 16384u;
+    // with a state every wave first reads the done words of its lanes: fewer
+    // waves, each taking more rows
+    if (persist && blocks > 2048u) blocks = 2048u;
     const uint32_t pslice = persist ? (uint32_t)(2 * (((size_t)n + 31) / 32) + 2) : 0u;
     hipLaunchKernelGGL(k_out_sizes, dim3(blocks), dim3(256), 0, st, C, n, ld, nwords, out_sizes,
                        persist, pslice, state_sw ? state_sw : 1u);
