@@ -144,7 +144,7 @@ tn_status apply_shape(tn_ctx *ctx, tn_batch *b, const BatchShape &shape) {
         }
         if (b->mode[i] == kTileGlobal && b->max_gat[i] > 0) {
             gscr_off[i] = gscr_words;
-            gscr_words += (size_t)b->max_gat[i] * nw;
+            gscr_words += (size_t)b->max_gat[i] * scratch_stride(nw);
         }
         if (!b->streamed) w = std::max<uint32_t>(1, w >> policy);
         b->lw[i] = ilog2(w);
@@ -237,8 +237,11 @@ tn_status bind_outputs(tn_ctx *ctx, tn_batch *b, uint64_t *const *C, const int64
     hipError_t se = hipStreamSynchronize(ctx->stream);
     if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
     for (int32_t i = 0; i < b->B; ++i) {
-        b->h_nets[i].C = C[i];
-        b->h_nets[i].ld = ld[i];
+        NetDesc &nd = b->h_nets[i];
+        nd.C = C[i];
+        nd.ld = ld[i];
+        nd.pair = nd.lw >= 1 && (nd.mode == kTileLds ||
+                                 (ld[i] % 2 == 0 && ((uintptr_t)C[i] & 15u) == 0));
     }
     hipError_t e = hipMemcpy(b->d_nets, b->h_nets.data(), sizeof(NetDesc) * b->B,
                              hipMemcpyHostToDevice);

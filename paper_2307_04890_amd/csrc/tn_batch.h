@@ -23,6 +23,10 @@ struct NetDesc {
     // one stream (nullable; sat only): {done, full-row count, ceil(n/32)
     // words of row bits} per slice, zero before the first chunk
     uint32_t *persist;
+    // 1: lanes take two words of a row (16-byte accesses): slices of two or
+    // more words whose rows start on 16 bytes (LDS tiles always, global
+    // tiles with even ld and an aligned matrix)
+    uint32_t pair;
 };
 
 // Bytes of the saturation bitmap of an n-node network (one bit per row).

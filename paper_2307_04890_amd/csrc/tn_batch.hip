@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "tn_batch.h"
+#include "tn_device.h"
 
 namespace tn {
 
@@ -33,28 +34,37 @@ namespace {
 
 constexpr uint32_t kWin = 64;  // levels of boundaries staged in LDS per window
 
+// Rows of a tile; a lane holds LW consecutive words of a row (LW = 2:
+// 16-byte accesses, which need every row to start on 16 bytes).
+template <int LW>
 struct LdsRows {
+    using T = typename LaneT<LW>::T;
     uint64_t *M;
     uint32_t lw;  // log2(words per row)
-    __device__ __forceinline__ uint64_t &at(uint32_t r, uint32_t lane) const {
-        return M[((size_t)r << lw) + lane];
+    __device__ __forceinline__ T &at(uint32_t r, uint32_t lane) const {
+        return *reinterpret_cast<T *>(&M[((size_t)r << lw) + LW * lane]);
     }
 };
 
+template <int LW>
 struct GlobalRows {
+    using T = typename LaneT<LW>::T;
     uint64_t *C;
     size_t ld;
     uint32_t word0;
-    __device__ __forceinline__ uint64_t &at(uint32_t r, uint32_t lane) const {
-        return C[(size_t)r * ld + word0 + lane];
+    __device__ __forceinline__ T &at(uint32_t r, uint32_t lane) const {
+        return *reinterpret_cast<T *>(&C[(size_t)r * ld + word0 + LW * lane]);
     }
 };
 
 // Saturation state of one tile.
+template <int LW>
 struct Sat {
+    using T = typename LaneT<LW>::T;
     uint32_t *bits;  // LDS bitmap, bit r = row r is full in the slice
     int32_t *delta;  // per-level change of the full-row count, 3 slots
-    uint64_t fullw;  // this lane's word of a full row slice
+    T fullw;         // this lane's words of a full row slice (0 past the last word)
+    T keep;          // clears a word past the last one (the matrix's padding)
     uint64_t gmask;  // ballot bits of this lane's group
     bool lead;       // first lane of its group
     __device__ __forceinline__ bool get(uint32_t r) const { return (bits[r >> 5] >> (r & 31u)) & 1u; }
@@ -77,14 +87,16 @@ struct Sat {
 // registers; level boundaries come from an LDS window refilled every kWin
 // levels.
 // Returns the number of full rows after the last level it ran (SAT).
-template <int U, bool SAT, class Rows>
+template <int U, bool SAT, int LW, class Rows>
 __device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows scr, uint32_t lw,
-                              bool ok, uint32_t *winp, uint32_t *wing, const Sat &sat,
+                              bool ok, uint32_t *winp, uint32_t *wing, const Sat<LW> &sat,
                               int32_t nfull) {
+    using T = typename LaneT<LW>::T;
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & ((1u << lw) - 1u);
-    const uint32_t grp = tid >> lw;
-    const uint32_t ngrp = blockDim.x >> lw;
+    const uint32_t glw = lw - (LW == 2 ? 1u : 0u);  // log2 lanes per item
+    const uint32_t lane = tid & ((1u << glw) - 1u);
+    const uint32_t grp = tid >> glw;
+    const uint32_t ngrp = blockDim.x >> glw;
     const uint32_t chunk = ngrp * U;
     const uint32_t L = s.L;
     for (uint32_t i = tid; i < 2 * kWin; i += blockDim.x) {
@@ -141,7 +153,7 @@ __device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows 
                     it[k] = idx < p1 ? s.pairs[idx] : make_uint2(0xffffffffu, 0u);
                 }
             }
-            uint64_t a[U], b[U];
+            T a[U], b[U];
             bool fx[U], fy[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
@@ -149,7 +161,7 @@ __device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows 
                 const uint32_t x = it[k].x, y = it[k].y & kNodeMask;
                 fx[k] = SAT && v && sat.get(x);
                 fy[k] = SAT && v && sat.get(y);
-                a[k] = b[k] = 0;
+                a[k] = b[k] = T(0);
                 if (v && ok && !fx[k] && !fy[k]) {
                     a[k] = rows.at(x, lane);
                     b[k] = rows.at(y, lane);
@@ -159,9 +171,9 @@ __device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows 
             for (int k = 0; k < U; ++k) {
                 const bool v = it[k].x != 0xffffffffu, dir = it[k].y & kDirBit;
                 const uint32_t x = it[k].x, y = it[k].y & kNodeMask;
-                const uint64_t r = (fx[k] || fy[k]) ? sat.fullw : (a[k] | b[k]);
+                const T r = (fx[k] || fy[k]) ? sat.fullw : ((a[k] | b[k]) & sat.keep);
                 bool full = false;
-                if (SAT) full = sat.group_all(!v || !ok || r == sat.fullw);
+                if (SAT) full = sat.group_all(!v || !ok || lane_eq<LW>(r, sat.fullw));
                 if (v && ok) {
                     if (!(full && fx[k])) rows.at(x, lane) = r;
                     if (!dir && !(full && fy[k])) rows.at(y, lane) = r;
@@ -175,7 +187,7 @@ __device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows 
         if (g1 > g0) {
             // compound items: read every old row, then write
             for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp) {
-                uint64_t acc = 0;
+                T acc = T(0);
                 const uint32_t s0 = s.gat_ptr[gi], s1 = s.gat_ptr[gi + 1];
                 bool any_full = false;
                 if (SAT)
@@ -184,19 +196,19 @@ __device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows 
                     if (any_full) acc = sat.fullw;
                     else
                         for (uint32_t q = s0; q < s1; ++q) acc |= rows.at(s.gat_src[q], lane);
-                    scr.at(gi - g0, lane) = acc;
+                    scr.at(gi - g0, lane) = acc & sat.keep;
                 }
             }
             __syncthreads();
             for (uint32_t gi = g0 + grp; gi < g1; gi += ngrp) {
                 const uint32_t tg = s.gat_tgt[gi];
-                const uint64_t val = ok ? scr.at(gi - g0, lane) : 0ull;
+                const T val = ok ? scr.at(gi - g0, lane) : T(0);
                 if (!SAT) {
                     if (ok) rows.at(tg, lane) = val;
                     continue;
                 }
                 const bool ft = sat.get(tg);
-                const bool full = sat.group_all(!ok || val == sat.fullw);
+                const bool full = sat.group_all(!ok || lane_eq<LW>(val, sat.fullw));
                 if (ok && !(full && ft)) rows.at(tg, lane) = val;
                 if (sat.lead && full != ft) sat.flip(tg, full, l);
             }
@@ -213,31 +225,45 @@ __device__ int32_t run_levels(const DevSchedule &s, const Rows rows, const Rows 
     return nfull;
 }
 
-template <int U, bool SAT>
+template <int U, bool SAT, int LW>
 __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint32_t *winp,
                          uint32_t *wing, int32_t *fdelta, unsigned int *done_count) {
+    using T = typename LaneT<LW>::T;
     const uint32_t tid = threadIdx.x;
     const uint32_t lw = nd.lw;
     const uint32_t w = 1u << lw;
+    const uint32_t gw = w / LW;  // lanes per item
     const uint32_t n = nd.s.n;
     const uint32_t word0 = slice << lw;
     const size_t ld = (size_t)nd.ld;
-    const uint32_t lane = tid & (w - 1u);
+    const uint32_t lane = tid & (gw - 1u);
+    const uint32_t word = word0 + LW * lane;  // this lane's first word
     // saturation state; the bitmap is set up before the first barrier
     const uint32_t rwords = (n + 31) / 32;
     uint32_t *pst = (SAT && nd.persist) ? nd.persist + (size_t)slice * (rwords + 2) : nullptr;
     if (pst && pst[0]) return;  // this slice is all ones already (uniform)
-    Sat sat;
+    Sat<LW> sat;
+    {
+        // full value and padding mask of each of the lane's words
+        const uint32_t tail = n & 63u;
+        auto fw = [&](uint32_t wd) {
+            return wd + 1 < nd.nwords ? ~0ull
+                                      : (wd + 1 == nd.nwords ? (tail ? (1ull << tail) - 1ull : ~0ull)
+                                                             : 0ull);
+        };
+        if constexpr (LW == 1) {
+            sat.fullw = fw(word);
+            sat.keep = ~0ull;
+        } else {
+            sat.fullw = u64x2{fw(word), fw(word + 1)};
+            sat.keep = u64x2{~0ull, word + 1 < nd.nwords ? ~0ull : 0ull};
+        }
+    }
     int32_t nfull = 0;
     if (SAT) {
         sat.bits = (uint32_t *)(smem + nd.sat_off);
         sat.delta = fdelta;
-        const uint32_t word = word0 + lane;
-        const uint32_t tail = n & 63u;
-        sat.fullw = word + 1 < nd.nwords ? ~0ull
-                                         : (word + 1 == nd.nwords ? (tail ? (1ull << tail) - 1ull : ~0ull)
-                                                                  : 0ull);
-        sat.gmask = (w == 64 ? ~0ull : ((1ull << w) - 1ull)) << ((tid & 63u) / w * w);
+        sat.gmask = (gw == 64 ? ~0ull : ((1ull << gw) - 1ull)) << ((tid & 63u) / gw * gw);
         sat.lead = lane == 0;
         // a slice with a single valid column starts with that row full
         const uint32_t c0 = word0 * 64u;
@@ -265,26 +291,27 @@ __device__ void run_tile(const NetDesc &nd, uint32_t slice, uint64_t *smem, uint
                 smem[i] = (word == (r >> 6)) ? (1ull << (r & 63u)) : 0ull;
         }
         __syncthreads();
-        LdsRows rows{smem, lw};
-        LdsRows scr{smem + total, lw};
-        nfull = run_levels<U, SAT>(nd.s, rows, scr, lw, true, winp, wing, sat, nfull);
+        LdsRows<LW> rows{smem, lw};
+        LdsRows<LW> scr{smem + total, lw};
+        nfull = run_levels<U, SAT, LW>(nd.s, rows, scr, lw, true, winp, wing, sat, nfull);
         // write the slice back (the level loop ended with a barrier)
         for (uint32_t i = tid; i < total; i += blockDim.x) {
             const uint32_t r = i >> lw, word = word0 + (i & (w - 1u));
             if (word < nd.nwords) nd.C[(size_t)r * ld + word] = smem[i];
         }
     } else {
-        const bool ok = word0 + lane < nd.nwords;
+        const bool ok = word < nd.nwords;
         if (!nd.resume)
-            for (uint32_t r = tid >> lw; r < n; r += blockDim.x >> lw)
-                if (ok) {
-                    const uint32_t word = word0 + lane;
-                    nd.C[(size_t)r * ld + word] = (word == (r >> 6)) ? (1ull << (r & 63u)) : 0ull;
-                }
+            for (size_t i = tid; i < ((size_t)n << lw); i += blockDim.x) {
+                const uint32_t r = (uint32_t)(i >> lw), wd = word0 + (uint32_t)(i & (w - 1u));
+                if (wd < nd.nwords)
+                    nd.C[(size_t)r * ld + wd] = (wd == (r >> 6)) ? (1ull << (r & 63u)) : 0ull;
+            }
         __syncthreads();
-        GlobalRows rows{nd.C, ld, word0};
-        GlobalRows scr{nd.gscratch, (size_t)nd.nwords, word0};
-        nfull = run_levels<U, SAT>(nd.s, rows, scr, lw, ok, winp, wing, sat, nfull);
+        GlobalRows<LW> rows{nd.C, ld, word0};
+        // compound scratch rows lie an even number of words apart
+        GlobalRows<LW> scr{nd.gscratch, (size_t)((nd.nwords + 1u) & ~1u), word0};
+        nfull = run_levels<U, SAT, LW>(nd.s, rows, scr, lw, ok, winp, wing, sat, nfull);
     }
     if (pst) {
         for (uint32_t i = tid; i < rwords; i += blockDim.x) pst[2 + i] = sat.bits[i];
@@ -326,8 +353,15 @@ k_batch_persistent(const NetDesc *__restrict__ nets, const uint2 *__restrict__ t
             if (t >= qn) break;
             const uint2 tile = tiles[q0 + t];
             const NetDesc &nd = nets[tile.x];
-            if (nd.sat) run_tile<U, true>(nd, tile.y, smem, winp, wing, fdelta, done_count);
-            else run_tile<U, false>(nd, tile.y, smem, winp, wing, fdelta, done_count);
+            // two words per lane where the tile is at least two words wide
+            // and its rows start on 16 bytes (NetDesc::pair)
+            if (nd.sat) {
+                if (nd.pair) run_tile<U, true, 2>(nd, tile.y, smem, winp, wing, fdelta, done_count);
+                else run_tile<U, true, 1>(nd, tile.y, smem, winp, wing, fdelta, done_count);
+            } else {
+                if (nd.pair) run_tile<U, false, 2>(nd, tile.y, smem, winp, wing, fdelta, done_count);
+                else run_tile<U, false, 1>(nd, tile.y, smem, winp, wing, fdelta, done_count);
+            }
         }
     }
 }

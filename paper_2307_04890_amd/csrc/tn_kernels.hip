@@ -91,24 +91,7 @@ struct OpArgs {
     uint64_t fullw1;          // fullw of the lane's second word (two-word lanes)
 };
 
-// A lane's words of a row: one (8-byte accesses) or two (16-byte accesses:
-// per wave instruction twice the bytes for the same address work, which is
-// what the texture address and data units of a CU spend their cycles on
-// when 64 lanes touch 8 to 16 scattered row segments).
-typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-template <int LW>
-struct LaneT;
-template <>
-struct LaneT<1> {
-    using T = uint64_t;
-};
-template <>
-struct LaneT<2> {
-    using T = u64x2;
-};
-
-// The lane's full row-slice value, and its words compared with another
-// value's.
+// The lane's full row-slice value.
 template <int LW>
 __device__ __forceinline__ typename LaneT<LW>::T lane_full(const OpArgs &A) {
     if constexpr (LW == 1) {
@@ -124,14 +107,6 @@ __device__ __forceinline__ typename LaneT<LW>::T lane_keep(const OpArgs &A) {
         return ~0ull;
     } else {
         return u64x2{~0ull, A.w + 1 < A.nwords ? ~0ull : 0ull};
-    }
-}
-template <int LW>
-__device__ __forceinline__ bool lane_eq(typename LaneT<LW>::T a, typename LaneT<LW>::T b) {
-    if constexpr (LW == 1) {
-        return a == b;
-    } else {
-        return a.x == b.x && a.y == b.y;
     }
 }
 
