@@ -54,10 +54,11 @@ __global__ void __launch_bounds__(256) k_identity(uint64_t *__restrict__ C, uint
 // Compute waves issue only row loads and stores.  On gfx9 loads and stores
 // share one in-order completion counter, so this split keeps the loaders'
 // waits from ever covering row stores, and the compute waves never wait for
-// a schedule load.  Every compute memory op is unconditional: a lane with no
-// op, a skipped access, no second destination, or a word past the last word
-// column reads and writes its own sink word.  The barrier that ends a level
-// orders the workgroup's row stores and bit updates before the next level.
+// a schedule load.  A row access is issued only by the lanes that need it
+// (exec-masked): a lane aimed at a sink word instead costs the CU's texture
+// address and data units, which bound these kernels, as much as a real
+// access.  The barrier that ends a level orders the workgroup's row stores
+// and bit updates before the next level.
 constexpr uint32_t kLoaderThreads = 128;
 constexpr uint32_t kLoaderOps = kOpsLevelCap / kLoaderThreads;  // ops per loader lane and level
 constexpr uint32_t kFrames = 2;  // LDS op frames: the level being run and the next
@@ -110,8 +111,8 @@ __device__ __forceinline__ typename LaneT<LW>::T lane_keep(const OpArgs &A) {
     }
 }
 
-// Branch-free: every candidate address is formed, then one is selected, so
-// the load or store that uses it is issued by every lane.
+// The address of a row or scratch row word, chosen without a branch (the
+// lane's sink word where not valid).
 __device__ __forceinline__ uint64_t *op_addr(const OpArgs &A, uint32_t id, bool valid) {
     const uint64_t row = (uint64_t)(id & kNodeMask);
     const uintptr_t real = (uintptr_t)(A.C + row * A.ldz + A.w);
@@ -168,19 +169,21 @@ __device__ __forceinline__ void apply_frame(OpArgs &A, const op4 *frame, uint32_
     uint64_t x[UC], y[UC];
 #pragma unroll
     for (int k = 0; k < UC; ++k) o[k] = frame[min(base + A.grp + k * A.ngrp, kOpsLevelCap - 1)];
+    // only lanes with a row to move access memory (see fwd_issue)
 #pragma unroll
     for (int k = 0; k < UC; ++k) {
-        const bool v = base + A.grp + k * A.ngrp < n;
-        x[k] = *op_addr(A, o[k].x, v);
-        y[k] = *op_addr(A, o[k].y, v);
-        A.loaded += (v && A.wok) ? 2u : 0u;
+        const bool v = base + A.grp + k * A.ngrp < n && A.wok;
+        x[k] = y[k] = 0ull;
+        if (v) x[k] = *op_addr(A, o[k].x, true);
+        if (v) y[k] = *op_addr(A, o[k].y, true);
+        A.loaded += v ? 2u : 0u;
     }
 #pragma unroll
     for (int k = 0; k < UC; ++k) {
-        const bool v = base + A.grp + k * A.ngrp < n;
+        const bool v = base + A.grp + k * A.ngrp < n && A.wok;
         const uint64_t r = MAX8 ? max_bytes7(x[k], y[k]) : (x[k] | y[k]);
-        *op_addr(A, o[k].z, v) = r;
-        *op_addr(A, o[k].w, v) = r;
+        if (v && o[k].z != kNoRow) *op_addr(A, o[k].z, true) = r;
+        if (v && o[k].w != kNoRow) *op_addr(A, o[k].w, true) = r;
         A.stored += ((v && A.wok && o[k].z != kNoRow) ? 1u : 0u) +
                     ((v && A.wok && o[k].w != kNoRow) ? 1u : 0u);
     }
@@ -253,8 +256,8 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
             // most rows are full.
             const bool s1 = v && o.z != kNoRow && !f1;
             const bool s2 = v && o.w != kNoRow && !f2;
-            *(T *)op_addr(A, o.z, s1) = fullv;
-            *(T *)op_addr(A, o.w, s2) = fullv;
+            if (s1 && A.wok) *(T *)op_addr(A, o.z, true) = fullv;
+            if (s2 && A.wok) *(T *)op_addr(A, o.w, true) = fullv;
             A.stored += (s1 ? A.vw : 0u) + (s2 ? A.vw : 0u);
             if (v && A.lead) {
                 if (s1) sat_set(A, o.z, true);
@@ -272,8 +275,9 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
         const T none = T(0);
         T r = skip ? fullv : none;
         if (__ballot(ldx || ldy) != 0) {
-            const T x = *(const T *)op_addr(A, o.x, ldx);
-            const T y = *(const T *)op_addr(A, o.y, ldy);
+            T x = none, y = none;
+            if (ldx && A.wok) x = *(const T *)op_addr(A, o.x, true);
+            if (ldy && A.wok) y = *(const T *)op_addr(A, o.y, true);
             A.loaded += (ldx ? A.vw : 0u) + (ldy ? A.vw : 0u);
             // a word past the row's last one (two-word lanes) is padding:
             // its full value is zero, and it is kept zero
@@ -292,8 +296,8 @@ __device__ __forceinline__ void run_work(OpArgs &A, const op4 *frame, const uint
         // changes nothing
         const bool s1 = v && o.z != kNoRow && !(full && f1) && !(zero && z1);
         const bool s2 = v && o.w != kNoRow && !(full && f2) && !(zero && z2);
-        *(T *)op_addr(A, o.z, s1) = r;
-        *(T *)op_addr(A, o.w, s2) = r;
+        if (s1 && A.wok) *(T *)op_addr(A, o.z, true) = r;
+        if (s2 && A.wok) *(T *)op_addr(A, o.w, true) = r;
         A.stored += (s1 ? A.vw : 0u) + (s2 ? A.vw : 0u);
         // one lane per group refreshes the destinations' bits
         if (v && A.lead) {
@@ -669,7 +673,7 @@ struct ColdVals {
     typename LaneT<LW>::T x[UC], y[UC];
 };
 
-// The cold operands of the level in `frame` (forwarded ones read the sink).
+// The cold operands of the level in `frame` (forwarded ones are not read).
 template <int SW, int UC, bool OFF32, int LW>
 __device__ __forceinline__ void fwd_issue(OpArgs &A, const op4 *frame, uint32_t cnt,
                                           ColdVals<UC, LW> &c) {
@@ -682,8 +686,10 @@ __device__ __forceinline__ void fwd_issue(OpArgs &A, const op4 *frame, uint32_t 
         const op4 o = frame[min(j, kOpsLevelCap - 1)];
         const bool v = j < cnt;
         const bool hx = o.x & kFwdHot, hy = o.y & kFwdHot;
-        c.x[k] = *(const T *)fwd_addr<OFF32>(A, o.x, v && !hx);
-        c.y[k] = *(const T *)fwd_addr<OFF32>(A, o.y, v && !hy);
+        // only the lanes that need a row read it: a lane sent to a sink
+        // instead costs the CU's texture units as much as a real access
+        if (v && !hx && A.wok) c.x[k] = *(const T *)fwd_addr<OFF32>(A, o.x, true);
+        if (v && !hy && A.wok) c.y[k] = *(const T *)fwd_addr<OFF32>(A, o.y, true);
         A.loaded += ((v && !hx) ? A.vw : 0u) + ((v && !hy) ? A.vw : 0u);
     }
 }
@@ -716,8 +722,8 @@ __device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t 
         // kNoRow has the no-store bit too: it is never stored
         const bool s1 = v && !(o.z & kFwdNoStore);
         const bool s2 = v && !(o.w & kFwdNoStore);
-        *(T *)fwd_addr<OFF32>(A, o.z, s1) = r;
-        *(T *)fwd_addr<OFF32>(A, o.w, s2) = r;
+        if (s1 && A.wok) *(T *)fwd_addr<OFF32>(A, o.z, true) = r;
+        if (s2 && A.wok) *(T *)fwd_addr<OFF32>(A, o.w, true) = r;
         A.stored += (s1 ? A.vw : 0u) + (s2 ? A.vw : 0u);
     }
 }
@@ -801,12 +807,15 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
     }
     ColdVals<UC, LW> cA, cB;
     // Runs level l with cur holding its cold values, after issuing level
-    // l + 1's into nxt.  The issue is unconditional (a level past the last
-    // has no ops: every lane loads its sink) and level 0's own issue comes
-    // before the loop, so the code between a load and its use is the same on
-    // every path: the compiler's wait before the use then leaves the loads
-    // issued after it in flight (a join with a path that skipped them would
-    // make it wait for those too).
+    // l + 1's into nxt.  The issue runs on every path (a level past the last
+    // has no ops and issues nothing) and level 0's own issue comes before
+    // the loop, so the code between a load and its use is the same on every
+    // path: the compiler's wait before the use then leaves the loads issued
+    // after it in flight (a join with a path that skipped the issue would
+    // make it wait for those too).  Within an issue, each load is masked to
+    // the lanes whose operand is cold: 109 -> 83 ms for the plain
+    // recurrence at n = 10^5, m = 10^7, where every lane had read a row or
+    // its sink.
     auto period = [&](uint32_t l, ColdVals<UC, LW> &cur, ColdVals<UC, LW> &nxt) {
         __syncthreads();
         const uint32_t nf = (l + 1) % kFwdFrames;
@@ -863,11 +872,11 @@ __device__ __forceinline__ void fwd1_issue(OpArgs &A, const op4 *frame, uint32_t
         const op4 o = frame[min(j, kOpsLevelCap - 1)];
         const bool v = j < cnt;
         const bool hy = o.y & kFwdHot;
-        c.y[k] = *fwd_addr<OFF32>(A, o.y, v && !hy);
+        if (v && !hy && A.wok) c.y[k] = *fwd_addr<OFF32>(A, o.y, true);
         A.loaded += (v && A.wok && !hy) ? 1u : 0u;
         if (k < UCX) {
             const bool hx = o.x & kFwdHot;
-            c.x[k] = *fwd_addr<OFF32>(A, o.x, v && !hx);
+            if (v && !hx && A.wok) c.x[k] = *fwd_addr<OFF32>(A, o.x, true);
             A.loaded += (v && A.wok && !hx) ? 1u : 0u;
         }
     }
@@ -904,8 +913,8 @@ __device__ __forceinline__ void fwd1_apply(OpArgs &A, const op4 *frame, uint32_t
         r[k] = x | ((o.y & kFwdHot) ? ly : c.y[k]);
         const bool s1 = v && !(o.z & kFwdNoStore);
         const bool s2 = v && !(o.w & kFwdNoStore);
-        *fwd_addr<OFF32>(A, o.z, s1) = r[k];
-        *fwd_addr<OFF32>(A, o.w, s2) = r[k];
+        if (s1 && A.wok) *fwd_addr<OFF32>(A, o.z, true) = r[k];
+        if (s2 && A.wok) *fwd_addr<OFF32>(A, o.w, true) = r[k];
         A.stored += ((s1 && A.wok) ? 1u : 0u) + ((s2 && A.wok) ? 1u : 0u);
     }
     lds_barrier();
