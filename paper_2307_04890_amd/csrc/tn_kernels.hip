@@ -389,6 +389,128 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, uint32_t x) {
     if ((threadIdx.x & 63u) == 0 && v) atomicAdd(ctr, v);
 }
 
+// The level loop of k_rowor_global over the levels of s, on loader and
+// compute waves (A, nfull and nzero set up by the caller); returns, on the
+// compute waves, whether the slice stopped with every real row full (then
+// nfull is n), else nfull after the last level.  Loader waves return after
+// their loop.
+template <int SW, int UC, bool SAT, bool MAX8, bool ZERO, int LW>
+__device__ __forceinline__ bool level_loop(OpArgs &A, const DevOps &s, uint32_t n, bool loader,
+                                           uint32_t tid, uint32_t ctid,
+                                           op4 (*frame)[kOpsLevelCap], uint32_t *fcount,
+                                           uint32_t (*worklist)[kWaveShare], int32_t *fdelta,
+                                           int32_t *zdelta, int32_t &nfull, int32_t &nzero) {
+    const uint32_t L = s.L;
+    // all waves add the same deltas at the same barriers, so they agree
+    // A slice may stop only at the start of a level that is a multiple of 3:
+    // the loaders' loop, unrolled by three, then has one exit, at the top (an
+    // exit after each level's feed let the compiler's waits in that loop
+    // drain the loads of the levels ahead).  Both loops run to L rounded up
+    // to a multiple of 3; the levels past L have no ops.  done(l) must be
+    // called once for every level, after the barrier that ends level l - 1.
+    const uint32_t L3 = (L + 2) / 3 * 3;
+    auto done = [&](uint32_t l) -> bool {
+        if (!SAT) return false;
+        // the delta of level l - 1 (slot 2 is still zero at level 0): read
+        // unconditionally, beside the level's other LDS reads
+        nfull += fdelta[(l + 2) % 3];
+        return l % 3 == 0 && nfull == (int32_t)n;
+    };
+    constexpr bool WIDE = ((1024 - kLoaderThreads) / SW) * UC < kOpsLevelCap;
+    // Loader and compute waves run separate loops with one barrier per level
+    // each (the branch is uniform per wave, and s_barrier only counts
+    // waves), so the compiler tracks the loaders' loads apart from the
+    // compute waves' row traffic.  Loader waves keep three levels in flight
+    // in registers (hA, hB, hC): a schedule load has three level periods to
+    // land before its frame is written.  Their loop is unrolled by three so
+    // that the sets never change registers (a register copy would wait for
+    // the load).
+    if (loader) {
+        // Every loader lane reads the level starts too (the same address in
+        // all lanes); a start is loaded one level before the ops it locates,
+        // and ahead of them, so each wait below leaves the newer loads in
+        // flight.
+        uint32_t p1 = level_start(s, 1), p2 = level_start(s, 2), p3 = level_start(s, 3);
+        put_level(frame[0], fetch_ops(s, level_start(s, 0), tid), tid);
+        if (tid == 0) fcount[0] = p1 - level_start(s, 0);
+        HeldOps hA = fetch_ops(s, p1, tid);
+        HeldOps hB = fetch_ops(s, p2, tid);
+        uint32_t p4 = level_start(s, 4);
+        HeldOps hC = fetch_ops(s, p3, tid);
+        __syncthreads();
+        // at level l: h holds the ops of level l + 1, fetched three levels
+        // before (a level whose ops need no memory takes less than a memory
+        // round trip, so two levels of lead were not enough); p1..p4 the
+        // starts of levels l + 1 .. l + 4
+        auto feed = [&](uint32_t l, HeldOps &h) {
+            // past the last level frames and counts are never read, and the
+            // level starts clamp to L
+            const uint32_t nf = (l + 1) % kFrames;
+            put_level(frame[nf], h, tid);
+            if (tid == 0) fcount[nf] = p2 - p1;
+            const uint32_t q = p4;
+            p1 = p2;
+            p2 = p3;
+            p3 = q;
+            h = fetch_ops(s, q, tid);
+            __syncthreads();
+            // after the barrier, so that its latency overlaps the next
+            // level's frame writes: issued before it, the wait for those LDS
+            // writes at the barrier would wait for this load too (scalar
+            // loads and LDS share one counter)
+            p4 = level_start(s, l + 5);
+        };
+        for (uint32_t l = 0; l < L3; l += 3) {
+            if (done(l)) break;
+            feed(l, hA);
+            (void)done(l + 1);  // counts only: not a multiple of 3
+            feed(l + 1, hB);
+            (void)done(l + 2);
+            feed(l + 2, hC);
+        }
+        return false;
+    }
+    __syncthreads();
+    bool stopped = false;
+    for (uint32_t l = 0; l < L3; ++l) {
+        const uint32_t cf = l % kFrames;
+        const uint32_t cnt = fcount[cf];
+        if (done(l)) {
+            stopped = true;
+            break;
+        }
+        if (SAT) {
+            A.nfull = &fdelta[l % 3];
+            if (ctid == 0) fdelta[(l + 1) % 3] = 0;
+            if (ZERO) {
+                // the zero count settles like the full count: every compute
+                // wave adds the same delta after the same barrier
+                if (l > 0) nzero += zdelta[(l - 1) % 3];
+                A.nzero = &zdelta[l % 3];
+                if (ctid == 0) zdelta[(l + 1) % 3] = 0;
+                A.zon = nzero > 0;
+            }
+            const uint32_t cw = ctid >> 6;
+            const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
+            const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
+            uint32_t *work = worklist[SAT ? cw : 0];
+            run_work<SW, ZERO, LW>(A, frame[cf], work, classify<ZERO>(A, frame[cf], lo, hi, work));
+            level_counts(A);
+        } else {
+            apply_frame<UC, MAX8>(A, frame[cf], 0, cnt);
+            if (WIDE) {
+                const uint32_t chunk = A.ngrp * UC;
+                for (uint32_t base = chunk; base < cnt; base += chunk)
+                    apply_frame<UC, MAX8>(A, frame[cf], base, cnt);
+            }
+        }
+        __syncthreads();
+    }
+    // the last level's delta settled at the loop's final barrier
+    if (SAT && !stopped) nfull += fdelta[(L3 - 1) % 3];
+    return stopped;
+}
+
 // CHUNK: one launch per chunk of a streamed build, with the slice state in
 // `persist` (a separate instantiation, so traces and counters keep the two
 // kinds of launch apart).
@@ -515,116 +637,12 @@ k_rowor_global(uint64_t *__restrict__ C, int64_t ld, uint32_t n, uint32_t nwords
     A.zb = zbits;
     A.nzero = zdelta;
     A.zon = false;
-    // all waves add the same deltas at the same barriers, so they agree
-    // A slice may stop only at the start of a level that is a multiple of 3:
-    // the loaders' loop, unrolled by three, then has one exit, at the top (an
-    // exit after each level's feed let the compiler's waits in that loop
-    // drain the loads of the levels ahead).  Both loops run to L rounded up
-    // to a multiple of 3; the levels past L have no ops.  done(l) must be
-    // called once for every level, after the barrier that ends level l - 1.
-    const uint32_t L3 = (L + 2) / 3 * 3;
-    auto done = [&](uint32_t l) -> bool {
-        if (!SAT) return false;
-        // the delta of level l - 1 (slot 2 is still zero at level 0): read
-        // unconditionally, beside the level's other LDS reads
-        nfull += fdelta[(l + 2) % 3];
-        return l % 3 == 0 && nfull == (int32_t)n;
-    };
-    constexpr bool WIDE = ((1024 - kLoaderThreads) / SW) * UC < kOpsLevelCap;
-    // Loader and compute waves run separate loops with one barrier per level
-    // each (the branch is uniform per wave, and s_barrier only counts
-    // waves), so the compiler tracks the loaders' loads apart from the
-    // compute waves' row traffic.  Loader waves keep three levels in flight
-    // in registers (hA, hB, hC): a schedule load has three level periods to
-    // land before its frame is written.  Their loop is unrolled by three so
-    // that the sets never change registers (a register copy would wait for
-    // the load).
-    if (loader) {
-        // Every loader lane reads the level starts too (the same address in
-        // all lanes); a start is loaded one level before the ops it locates,
-        // and ahead of them, so each wait below leaves the newer loads in
-        // flight.
-        uint32_t p1 = level_start(s, 1), p2 = level_start(s, 2), p3 = level_start(s, 3);
-        put_level(frame[0], fetch_ops(s, level_start(s, 0), tid), tid);
-        if (tid == 0) fcount[0] = p1 - level_start(s, 0);
-        HeldOps hA = fetch_ops(s, p1, tid);
-        HeldOps hB = fetch_ops(s, p2, tid);
-        uint32_t p4 = level_start(s, 4);
-        HeldOps hC = fetch_ops(s, p3, tid);
-        __syncthreads();
-        // at level l: h holds the ops of level l + 1, fetched three levels
-        // before (a level whose ops need no memory takes less than a memory
-        // round trip, so two levels of lead were not enough); p1..p4 the
-        // starts of levels l + 1 .. l + 4
-        auto feed = [&](uint32_t l, HeldOps &h) {
-            // past the last level frames and counts are never read, and the
-            // level starts clamp to L
-            const uint32_t nf = (l + 1) % kFrames;
-            put_level(frame[nf], h, tid);
-            if (tid == 0) fcount[nf] = p2 - p1;
-            const uint32_t q = p4;
-            p1 = p2;
-            p2 = p3;
-            p3 = q;
-            h = fetch_ops(s, q, tid);
-            __syncthreads();
-            // after the barrier, so that its latency overlaps the next
-            // level's frame writes: issued before it, the wait for those LDS
-            // writes at the barrier would wait for this load too (scalar
-            // loads and LDS share one counter)
-            p4 = level_start(s, l + 5);
-        };
-        for (uint32_t l = 0; l < L3; l += 3) {
-            if (done(l)) break;
-            feed(l, hA);
-            (void)done(l + 1);  // counts only: not a multiple of 3
-            feed(l + 1, hB);
-            (void)done(l + 2);
-            feed(l + 2, hC);
-        }
-        return;
-    }
-    __syncthreads();
-    bool stopped = false;
-    for (uint32_t l = 0; l < L3; ++l) {
-        const uint32_t cf = l % kFrames;
-        const uint32_t cnt = fcount[cf];
-        if (done(l)) {
-            stopped = true;
-            break;
-        }
-        if (SAT) {
-            A.nfull = &fdelta[l % 3];
-            if (ctid == 0) fdelta[(l + 1) % 3] = 0;
-            if (ZERO) {
-                // the zero count settles like the full count: every compute
-                // wave adds the same delta after the same barrier
-                if (l > 0) nzero += zdelta[(l - 1) % 3];
-                A.nzero = &zdelta[l % 3];
-                if (ctid == 0) zdelta[(l + 1) % 3] = 0;
-                A.zon = nzero > 0;
-            }
-            const uint32_t cw = ctid >> 6;
-            const uint32_t share = (cnt + kComputeWaves - 1) / kComputeWaves;
-            const uint32_t lo = min(cw * share, cnt), hi = min(lo + share, cnt);
-            uint32_t *work = worklist[SAT ? cw : 0];
-            run_work<SW, ZERO, LW>(A, frame[cf], work, classify<ZERO>(A, frame[cf], lo, hi, work));
-            level_counts(A);
-        } else {
-            apply_frame<UC, MAX8>(A, frame[cf], 0, cnt);
-            if (WIDE) {
-                const uint32_t chunk = A.ngrp * UC;
-                for (uint32_t base = chunk; base < cnt; base += chunk)
-                    apply_frame<UC, MAX8>(A, frame[cf], base, cnt);
-            }
-        }
-        __syncthreads();
-    }
+    const bool stopped = level_loop<SW, UC, SAT, MAX8, ZERO, LW>(
+        A, s, n, loader, tid, ctid, frame, fcount, worklist, fdelta, zdelta, nfull, nzero);
+    if (loader) return;
     count_add(traffic, A.loaded);
     count_add(traffic + 1, A.stored);
     if (pst) {
-        // the last level's delta settled at the loop's final barrier
-        if (!stopped) nfull += fdelta[(L3 - 1) % 3];
         for (uint32_t i = ctid; i < rwords; i += blockDim.x - kLoaderThreads) {
             pst[2 + i] = satbits[i];
             pst[2 + rwords + i] = ZERO ? ~zbits[i] : ~0u;
@@ -728,41 +746,16 @@ __device__ __forceinline__ void fwd_apply(OpArgs &A, const op4 *frame, uint32_t 
     }
 }
 
-// LW words per lane: SW / LW lanes per op (LW = 2 needs even ld and a
-// 16-byte aligned matrix).
+// The level loop of k_rowor_fwd over the levels of the forwarded schedule
+// s, on loader and compute waves (A set up by the caller; results: two
+// result frames of kFwdLevelCap + 1 slots of SW words).  Loader waves return
+// after their loop, compute waves after the last level's stores are issued.
 template <int SW, int UC, bool OFF32, int LW>
-__global__ void __launch_bounds__(1024)
-k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
-            uint64_t *__restrict__ scratch, uint64_t *__restrict__ rows,
-            unsigned long long *__restrict__ traffic) {
-    static_assert(((1024 - kLoaderThreads) / (SW / LW)) * UC >= kFwdLevelCap, "a level per pass");
-    constexpr uint32_t SL = SW / LW;
-    __shared__ op4 frame[kFwdFrames][kOpsLevelCap];
-    __shared__ uint32_t fcount[kFwdFrames];
-    // dynamic: two result frames of kFwdLevelCap + 1 slots (the last one a
-    // sink) of SW words
-    extern __shared__ __attribute__((aligned(16))) uint64_t results[];
+__device__ __forceinline__ void fwd_loop(OpArgs &A, const DevOps &s, bool loader, uint32_t tid,
+                                         uint32_t ctid, op4 (*frame)[kOpsLevelCap],
+                                         uint32_t *fcount, uint64_t *results) {
     constexpr uint32_t kFrameWords = (kFwdLevelCap + 1) * SW;
     const uint32_t L = s.L;
-    if (L == 0 || s.nops == 0) return;
-    const uint32_t tid = threadIdx.x;
-    const bool loader = tid < kLoaderThreads;
-    const uint32_t ctid = tid - kLoaderThreads;
-    const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
-    OpArgs A;
-    A.C = C;
-    A.ldz = (size_t)ld;
-    A.nwords = nwords;
-    A.sld = (nwords + 1u) & ~1u;
-    A.w = slice * SW + LW * (ctid % SL);
-    A.wok = !loader && A.w < nwords;
-    A.vw = A.wok ? min((uint32_t)LW, nwords - A.w) : 0u;
-    A.grp = ctid / SL;
-    A.ngrp = (blockDim.x - kLoaderThreads) / SL;
-    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + LW * tid;
-    A.rows = rows;
-    A.loaded = A.stored = 0;
-    A.ld32 = (uint32_t)ld;
     if (loader) {
         // levels 0 and 1 before the first barrier; at the barrier that
         // starts level l, frame (l + 2) % 3 receives level l + 2.  Starts
@@ -798,12 +791,13 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
         }
         return;
     }
+    constexpr uint32_t SL = SW / LW;
     const uint32_t lig = ctid % SL;
     typename LaneT<LW>::T keep;
     if constexpr (LW == 1) {
         keep = ~0ull;
     } else {
-        keep = u64x2{~0ull, A.w + 1 < nwords ? ~0ull : 0ull};
+        keep = u64x2{~0ull, A.w + 1 < A.nwords ? ~0ull : 0ull};
     }
     ColdVals<UC, LW> cA, cB;
     // Runs level l with cur holding its cold values, after issuing level
@@ -839,6 +833,43 @@ k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
         if (l + 1 >= L) break;
         period(l + 1, cA, cB);
     }
+}
+
+// LW words per lane: SW / LW lanes per op (LW = 2 needs even ld and a
+// 16-byte aligned matrix).
+template <int SW, int UC, bool OFF32, int LW>
+__global__ void __launch_bounds__(1024)
+k_rowor_fwd(uint64_t *__restrict__ C, int64_t ld, uint32_t nwords, DevOps s,
+            uint64_t *__restrict__ scratch, uint64_t *__restrict__ rows,
+            unsigned long long *__restrict__ traffic) {
+    static_assert(((1024 - kLoaderThreads) / (SW / LW)) * UC >= kFwdLevelCap, "a level per pass");
+    constexpr uint32_t SL = SW / LW;
+    __shared__ op4 frame[kFwdFrames][kOpsLevelCap];
+    __shared__ uint32_t fcount[kFwdFrames];
+    // dynamic: two result frames of kFwdLevelCap + 1 slots (the last one a
+    // sink) of SW words
+    extern __shared__ __attribute__((aligned(16))) uint64_t results[];
+    if (s.L == 0 || s.nops == 0) return;
+    const uint32_t tid = threadIdx.x;
+    const bool loader = tid < kLoaderThreads;
+    const uint32_t ctid = tid - kLoaderThreads;
+    const uint32_t slice = xcd_slice(blockIdx.x, gridDim.x);
+    OpArgs A;
+    A.C = C;
+    A.ldz = (size_t)ld;
+    A.nwords = nwords;
+    A.sld = (nwords + 1u) & ~1u;
+    A.w = slice * SW + LW * (ctid % SL);
+    A.wok = !loader && A.w < nwords;
+    A.vw = A.wok ? min((uint32_t)LW, nwords - A.w) : 0u;
+    A.grp = ctid / SL;
+    A.ngrp = (blockDim.x - kLoaderThreads) / SL;
+    A.sink = scratch + (size_t)blockIdx.x * kRoworSinkWords + LW * tid;
+    A.rows = rows;
+    A.loaded = A.stored = 0;
+    A.ld32 = (uint32_t)ld;
+    fwd_loop<SW, UC, OFF32, LW>(A, s, loader, tid, ctid, frame, fcount, results);
+    if (loader) return;
     count_add(traffic, A.loaded);
     count_add(traffic + 1, A.stored);
 }
