@@ -321,7 +321,7 @@ void tn_online_destroy(tn_online *online);
  * alpha_64 = 0.709, else 0.7213 / (1 + 1.079 / s)).
  * node_hash: DEVICE uint64[n], one uniform hash per node (an input: the
  * library draws no random numbers).  M: DEVICE n x s uint8, row-major,
- * written entirely.  est: DEVICE float64[n] or NULL.  log2s in [4, 16].
+ * written entirely, starting on 16 bytes (rows move in 16-byte words).  est: DEVICE float64[n] or NULL.  log2s in [4, 16].
  * tn_hll_execute runs on a plan's schedule (asynchronous): on a TN_HLL
  * plan one launch per level (two for a level with compound items) spreads
  * the level's items over the whole device, one group of lanes per item and

@@ -608,6 +608,7 @@ tn_status tn_hll_execute(tn_ctx *ctx, const tn_plan *plan, uint32_t log2s,
     if (!ctx || !plan) return fail(TN_E_ARG, "ctx or plan is NULL");
     if (!node_hash || !M) return fail(TN_E_ARG, "node_hash or M is NULL");
     if (log2s < 4 || log2s > 16) return fail(TN_E_ARG, "log2s must be in [4, 16]");
+    if ((uintptr_t)M % 16 != 0) return fail(TN_E_ARG, "M must start on 16 bytes");
     if (plan->device != ctx->device) return fail(TN_E_ARG, "plan lives on another device");
     const uint32_t n = plan->stats.n;
     const uint32_t nwords = (1u << log2s) / 8;

@@ -34,6 +34,20 @@ k_hll_init(uint32_t n, uint32_t b, const uint64_t *__restrict__ node_hash, uint6
     }
 }
 
+// Lane values of LW words and their register-wise maximum.
+template <int LW>
+__device__ __forceinline__ typename LaneT<LW>::T max_lane(typename LaneT<LW>::T a,
+                                                          typename LaneT<LW>::T b) {
+    if constexpr (LW == 1) {
+        return max_bytes7(a, b);
+    } else {
+        typename LaneT<LW>::T r;
+        r.x = max_bytes7(a.x, b.x);
+        r.y = max_bytes7(a.y, b.y);
+        return r;
+    }
+}
+
 // One level of the register stream of a TN_HLL plan.  Items [0, np) are
 // the level's pairs: both rows (one for a one-way pair) become their
 // register-wise maximum, in place (the items of a level touch disjoint
@@ -44,16 +58,20 @@ k_hll_init(uint32_t n, uint32_t b, const uint64_t *__restrict__ node_hash, uint6
 //    them to the targets, so no other lane ever reads what it writes;
 //  - else items [np, np + ng) are the gathers, each writing scratch row
 //    i - np, and k_hll_gathers_write copies them in a launch of its own.
-// A group of G lanes takes an item; lane k takes words k, k + G, ... of its
-// rows, so each row access is one contiguous segment.
+// A group of G lanes takes an item; lane k takes LW words at LW k,
+// LW (k + G), ... of its rows, so each row access is one contiguous segment
+// (LW = 2: 16-byte accesses, half the wave instructions of LW = 1).
+template <int LW>
 __device__ __forceinline__ void hll_gather_read(const uint64_t *__restrict__ M, uint32_t nwords,
                                                 uint32_t lane, uint32_t G, uint32_t s0, uint32_t s1,
                                                 const uint32_t *__restrict__ gat_src,
                                                 uint64_t *__restrict__ dst) {
-    for (uint32_t w = lane; w < nwords; w += G) {
-        uint64_t acc = 0;  // registers are never negative
-        for (uint32_t q = s0; q < s1; ++q) acc = max_bytes7(acc, M[(size_t)gat_src[q] * nwords + w]);
-        dst[w] = acc;
+    using T = typename LaneT<LW>::T;
+    for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
+        T acc = {};  // registers are never negative
+        for (uint32_t q = s0; q < s1; ++q)
+            acc = max_lane<LW>(acc, *(const T *)(M + (size_t)gat_src[q] * nwords + w));
+        *(T *)(dst + w) = acc;
     }
 }
 
@@ -71,22 +89,28 @@ __device__ __forceinline__ bool group_all(bool mine, uint32_t G) {
     return (b & mask) == mask;
 }
 
+template <int LW>
 __global__ void __launch_bounds__(256)
 k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *__restrict__ pairs,
             uint32_t np, const uint32_t *__restrict__ gat_ptr,
             const uint32_t *__restrict__ gat_src, const uint32_t *__restrict__ gat_tgt,
             uint32_t ng, uint32_t inline_gathers, uint64_t *__restrict__ scr,
             const uint64_t *__restrict__ Grow, unsigned int *__restrict__ left) {
-    // every row is G: nothing changes (one read per wavefront, so that its
-    // lanes leave together)
-    if (left && __builtin_amdgcn_readfirstlane(*left) == 0u) return;
+    using T = typename LaneT<LW>::T;
     const uint32_t lane = threadIdx.x % G;
     const uint32_t ngroups = gridDim.x * (blockDim.x / G);
     const uint32_t items = np + (inline_gathers ? (ng > 0 ? 1u : 0u) : ng);
+    const uint32_t i0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+    // the first pair is requested before the count is tested, so that the
+    // two reads overlap (the count's wait is on the scalar counter only)
+    uint2 first = make_uint2(0u, 0u);
+    if (i0 < np) first = pairs[i0];
+    // every row is G: nothing changes (one read per wavefront, so that its
+    // lanes leave together)
+    if (left && __builtin_amdgcn_readfirstlane(*left) == 0u) return;
     // groups never straddle a wavefront (G divides 64), and every lane of a
     // group runs the same iterations, so the ballots below see whole groups
     const uint32_t rounds = (items + ngroups - 1) / ngroups;
-    const uint32_t i0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
     for (uint32_t rr = 0; rr < rounds; ++rr) {
         const uint32_t i = i0 + rr * ngroups;
         bool ru_was = true, rv_was = true, r_is = true, one_way = true, pair = false;
@@ -94,17 +118,20 @@ k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *
             // no item: takes part in the ballots only
         } else if (i >= np && inline_gathers) {
             for (uint32_t g = 0; g < ng; ++g)
-                hll_gather_read(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
-                                scr + (size_t)g * nwords);
+                hll_gather_read<LW>(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
+                                    scr + (size_t)g * nwords);
             for (uint32_t g = 0; g < ng; ++g) {
                 bool was = true, is = true;
-                for (uint32_t w = lane; w < nwords; w += G) {
-                    const uint64_t old = M[(size_t)gat_tgt[g] * nwords + w];
-                    const uint64_t nw = scr[(size_t)g * nwords + w];
-                    M[(size_t)gat_tgt[g] * nwords + w] = nw;
+                for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
+                    T *tp = (T *)(M + (size_t)gat_tgt[g] * nwords + w);
+                    const T old = *tp;
+                    const T nw = *(const T *)(scr + (size_t)g * nwords + w);
+                    T gw = {};
+                    if (Grow) gw = *(const T *)(Grow + w);
+                    *tp = nw;
                     if (Grow) {
-                        was &= old == Grow[w];
-                        is &= nw == Grow[w];
+                        was &= lane_eq<LW>(old, gw);
+                        is &= lane_eq<LW>(nw, gw);
                     }
                 }
                 // one group runs every gather of the level: its ballots see
@@ -115,29 +142,32 @@ k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *
                 }
             }
         } else if (i < np) {
-            const uint2 it = pairs[i];
+            const uint2 it = rr == 0 ? first : pairs[i];
             const uint32_t v = it.y & kNodeMask;
             const bool dir = it.y & kDirBit;
             uint64_t *ru = M + (size_t)it.x * nwords;
             uint64_t *rv = M + (size_t)v * nwords;
             pair = true;
             one_way = dir;
-            for (uint32_t w = lane; w < nwords; w += G) {
-                const uint64_t a = ru[w], b = rv[w];
-                const uint64_t r = max_bytes7(a, b);
-                ru[w] = r;
-                if (!dir) rv[w] = r;
+            for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
+                const T a = *(const T *)(ru + w), b = *(const T *)(rv + w);
+                // G is read with the rows, not after the stores: loads and
+                // stores retire in order, so a later read would wait for them
+                T gw = {};
+                if (Grow) gw = *(const T *)(Grow + w);
+                const T r = max_lane<LW>(a, b);
+                *(T *)(ru + w) = r;
+                if (!dir) *(T *)(rv + w) = r;
                 if (Grow) {
-                    const uint64_t gw = Grow[w];
-                    ru_was &= a == gw;
-                    rv_was &= b == gw;
-                    r_is &= r == gw;
+                    ru_was &= lane_eq<LW>(a, gw);
+                    rv_was &= lane_eq<LW>(b, gw);
+                    r_is &= lane_eq<LW>(r, gw);
                 }
             }
         } else {
             const uint32_t g = i - np;
-            hll_gather_read(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
-                            scr + (size_t)g * nwords);
+            hll_gather_read<LW>(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
+                                scr + (size_t)g * nwords);
         }
         if (Grow) {
             const bool is = group_all(r_is, G);
@@ -155,11 +185,13 @@ constexpr uint32_t kHllInlineGathers = 4;
 
 // The level's gathers write their targets from scratch, one group of G
 // lanes per target (so that a target reaching G is counted once).
+template <int LW>
 __global__ void __launch_bounds__(256)
 k_hll_gathers_write(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G,
                     const uint32_t *__restrict__ gat_tgt, uint32_t ng,
                     const uint64_t *__restrict__ scr, const uint64_t *__restrict__ Grow,
                     unsigned int *__restrict__ left) {
+    using T = typename LaneT<LW>::T;
     // every row is G: the level changes nothing, and its gather launch may
     // have left scratch unwritten (the count only falls, so a count above 0
     // here means the gather launch before saw one too and wrote all of it)
@@ -172,13 +204,16 @@ k_hll_gathers_write(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G,
         const uint32_t g = g0 + rr * ngroups;
         bool was = true, is = true;
         if (g < ng)
-            for (uint32_t w = lane; w < nwords; w += G) {
-                const uint64_t old = M[(size_t)gat_tgt[g] * nwords + w];
-                const uint64_t nw = scr[(size_t)g * nwords + w];
-                M[(size_t)gat_tgt[g] * nwords + w] = nw;
+            for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
+                T *tp = (T *)(M + (size_t)gat_tgt[g] * nwords + w);
+                const T old = *tp;
+                const T nw = *(const T *)(scr + (size_t)g * nwords + w);
+                T gw = {};
+                if (Grow) gw = *(const T *)(Grow + w);
+                *tp = nw;
                 if (Grow) {
-                    was &= old == Grow[w];
-                    is &= nw == Grow[w];
+                    was &= lane_eq<LW>(old, gw);
+                    is &= lane_eq<LW>(nw, gw);
                 }
             }
         if (Grow) {
@@ -303,7 +338,10 @@ hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
                              const uint32_t *lvl_gat, uint32_t l0, uint32_t l1, uint32_t nwords,
                              uint64_t *M, uint64_t *scratch, const uint64_t *Grow,
                              unsigned int *left, hipStream_t st) {
-    const uint32_t G = nwords < 64 ? nwords : 64;  // nwords is a power of two >= 2
+    // two words per lane (nwords is a power of two >= 2, rows, scratch rows
+    // and G start on 16 bytes), a group of at most 64 lanes per item
+    constexpr int LW = 2;
+    const uint32_t G = nwords / LW < 64 ? nwords / LW : 64;
     for (uint32_t l = l0; l < l1 && l < s.L; ++l) {
         const uint32_t p0 = lvl_pair[l], np = lvl_pair[l + 1] - p0;
         const uint32_t g0 = lvl_gat[l], ng = lvl_gat[l + 1] - g0;
@@ -313,7 +351,7 @@ hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
         const uint32_t inl = ng <= kHllInlineGathers ? 1u : 0u;
         const size_t threads = (size_t)(np + (inl ? (ng > 0 ? 1u : 0u) : ng)) * G;
         const uint32_t blocks = (uint32_t)std::min<size_t>((threads + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_hll_level, dim3(blocks), dim3(256), 0, st, M, nwords, G,
+        hipLaunchKernelGGL(k_hll_level<LW>, dim3(blocks), dim3(256), 0, st, M, nwords, G,
                            s.pairs + p0, np, s.gat_ptr + g0, s.gat_src, s.gat_tgt + g0, ng, inl,
                            scratch, Grow, left);
         hipError_t e = hipGetLastError();
@@ -321,7 +359,7 @@ hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
         if (ng == 0 || inl) continue;
         const size_t gthreads = (size_t)ng * G;
         const uint32_t wb = (uint32_t)std::min<size_t>((gthreads + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_hll_gathers_write, dim3(wb), dim3(256), 0, st, M, nwords, G,
+        hipLaunchKernelGGL(k_hll_gathers_write<LW>, dim3(wb), dim3(256), 0, st, M, nwords, G,
                            s.gat_tgt + g0, ng, scratch, Grow, left);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
