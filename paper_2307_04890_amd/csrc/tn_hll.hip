@@ -53,14 +53,19 @@ __device__ __forceinline__ typename LaneT<LW>::T max_lane(typename LaneT<LW>::T 
 // register-wise maximum, in place (the items of a level touch disjoint
 // rows).  The level's gathers read each other's rows (those of one compound
 // item), so every source is read before any target is written:
-//  - inline (a narrow level): one group takes all ng gathers, item np; each
-//    lane writes the maxima of its own words to scratch rows, then copies
-//    them to the targets, so no other lane ever reads what it writes;
+//  - a level with at most hll_block_gathers(G) gathers (nearly all of them)
+//    hands them to one extra workgroup, the grid's last: each of its lane
+//    groups reads the sources of its gathers into scratch rows, a barrier
+//    of the workgroup ends every read, then each group writes its targets;
 //  - else items [np, np + ng) are the gathers, each writing scratch row
 //    i - np, and k_hll_gathers_write copies them in a launch of its own.
 // A group of G lanes takes an item; lane k takes LW words at LW k,
 // LW (k + G), ... of its rows, so each row access is one contiguous segment
 // (LW = 2: 16-byte accesses, half the wave instructions of LW = 1).
+//
+// A gather's sources are read four at a time (indices, then rows, each
+// four independent loads); a short last batch repeats its last source,
+// which the maximum ignores.
 template <int LW>
 __device__ __forceinline__ void hll_gather_read(const uint64_t *__restrict__ M, uint32_t nwords,
                                                 uint32_t lane, uint32_t G, uint32_t s0, uint32_t s1,
@@ -69,8 +74,16 @@ __device__ __forceinline__ void hll_gather_read(const uint64_t *__restrict__ M, 
     using T = typename LaneT<LW>::T;
     for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
         T acc = {};  // registers are never negative
-        for (uint32_t q = s0; q < s1; ++q)
-            acc = max_lane<LW>(acc, *(const T *)(M + (size_t)gat_src[q] * nwords + w));
+        for (uint32_t q = s0; q < s1; q += 4) {
+            uint32_t id[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) id[k] = gat_src[min(q + k, s1 - 1)];
+            T r[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r[k] = *(const T *)(M + (size_t)id[k] * nwords + w);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc = max_lane<LW>(acc, r[k]);
+        }
         *(T *)(dst + w) = acc;
     }
 }
@@ -89,18 +102,84 @@ __device__ __forceinline__ bool group_all(bool mine, uint32_t G) {
     return (b & mask) == mask;
 }
 
+// Target g of a level's gathers takes scratch row g; with saturation, a
+// target that reaches G takes one off *left (whole groups run this, so the
+// ballots see every lane of the group).
+template <int LW>
+__device__ __forceinline__ void hll_gather_write(uint64_t *__restrict__ M, uint32_t nwords,
+                                                 uint32_t lane, uint32_t G, uint32_t tgt,
+                                                 const uint64_t *__restrict__ srow,
+                                                 const uint64_t *__restrict__ Grow,
+                                                 unsigned int *__restrict__ left) {
+    using T = typename LaneT<LW>::T;
+    bool was = true, is = true;
+    for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
+        T *tp = (T *)(M + (size_t)tgt * nwords + w);
+        const T old = *tp;
+        const T nw = *(const T *)(srow + w);
+        T gw = {};
+        if (Grow) gw = *(const T *)(Grow + w);
+        *tp = nw;
+        if (Grow) {
+            was &= lane_eq<LW>(old, gw);
+            is &= lane_eq<LW>(nw, gw);
+        }
+    }
+    if (Grow) {
+        const bool reached = group_all(is, G), before = group_all(was, G);
+        if (reached && !before && lane == 0) atomicSub(left, 1u);
+    }
+}
+
+// Gathers one workgroup of 256 threads takes: four per lane group.
+__host__ __device__ constexpr uint32_t hll_block_gathers(uint32_t G) { return 4u * (256u / G); }
+
 template <int LW>
 __global__ void __launch_bounds__(256)
 k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *__restrict__ pairs,
             uint32_t np, const uint32_t *__restrict__ gat_ptr,
             const uint32_t *__restrict__ gat_src, const uint32_t *__restrict__ gat_tgt,
-            uint32_t ng, uint32_t inline_gathers, uint64_t *__restrict__ scr,
+            uint32_t ng, uint32_t block_gathers, uint64_t *__restrict__ scr,
             const uint64_t *__restrict__ Grow, unsigned int *__restrict__ left) {
     using T = typename LaneT<LW>::T;
     const uint32_t lane = threadIdx.x % G;
-    const uint32_t ngroups = gridDim.x * (blockDim.x / G);
-    const uint32_t items = np + (inline_gathers ? (ng > 0 ? 1u : 0u) : ng);
-    const uint32_t i0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+    const uint32_t grp = threadIdx.x / G, ngr = blockDim.x / G;
+    const bool gblock = block_gathers && ng > 0;
+    const uint32_t pblocks = gridDim.x - (gblock ? 1u : 0u);
+    if (blockIdx.x == pblocks) {
+        // the level's gathers (the launcher adds this block only when they
+        // number at most hll_block_gathers(G))
+        uint32_t tg[4], s0[4], s1[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t g = min(grp + k * ngr, ng - 1);
+            tg[k] = gat_tgt[g];
+            s0[k] = gat_ptr[g];
+            s1[k] = gat_ptr[g + 1];
+        }
+        if (left && __builtin_amdgcn_readfirstlane(*left) == 0u) return;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t g = grp + k * ngr;
+            if (g < ng)
+                hll_gather_read<LW>(M, nwords, lane, G, s0[k], s1[k], gat_src,
+                                    scr + (size_t)g * nwords);
+        }
+        // every source of the level is read before any target is written
+        // (a lane reads back only the scratch words it wrote itself)
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t g = grp + k * ngr;
+            if (g < ng)
+                hll_gather_write<LW>(M, nwords, lane, G, tg[k], scr + (size_t)g * nwords, Grow,
+                                     left);
+        }
+        return;
+    }
+    const uint32_t ngroups = pblocks * ngr;
+    const uint32_t items = np + (gblock ? 0u : ng);
+    const uint32_t i0 = blockIdx.x * ngr + grp;
     // the first pair is requested before the count is tested, so that the
     // two reads overlap (the count's wait is on the scalar counter only)
     uint2 first = make_uint2(0u, 0u);
@@ -116,31 +195,6 @@ k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *
         bool ru_was = true, rv_was = true, r_is = true, one_way = true, pair = false;
         if (i >= items) {
             // no item: takes part in the ballots only
-        } else if (i >= np && inline_gathers) {
-            for (uint32_t g = 0; g < ng; ++g)
-                hll_gather_read<LW>(M, nwords, lane, G, gat_ptr[g], gat_ptr[g + 1], gat_src,
-                                    scr + (size_t)g * nwords);
-            for (uint32_t g = 0; g < ng; ++g) {
-                bool was = true, is = true;
-                for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
-                    T *tp = (T *)(M + (size_t)gat_tgt[g] * nwords + w);
-                    const T old = *tp;
-                    const T nw = *(const T *)(scr + (size_t)g * nwords + w);
-                    T gw = {};
-                    if (Grow) gw = *(const T *)(Grow + w);
-                    *tp = nw;
-                    if (Grow) {
-                        was &= lane_eq<LW>(old, gw);
-                        is &= lane_eq<LW>(nw, gw);
-                    }
-                }
-                // one group runs every gather of the level: its ballots see
-                // only its own lanes' bits
-                if (Grow) {
-                    const bool reached = group_all(is, G), before = group_all(was, G);
-                    if (reached && !before && lane == 0) atomicSub(left, 1u);
-                }
-            }
         } else if (i < np) {
             const uint2 it = rr == 0 ? first : pairs[i];
             const uint32_t v = it.y & kNodeMask;
@@ -180,9 +234,6 @@ k_hll_level(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G, const uint2 *
     }
 }
 
-// Gathers of a level handled in one group of its launch, at most.
-constexpr uint32_t kHllInlineGathers = 4;
-
 // The level's gathers write their targets from scratch, one group of G
 // lanes per target (so that a target reaching G is counted once).
 template <int LW>
@@ -191,36 +242,16 @@ k_hll_gathers_write(uint64_t *__restrict__ M, uint32_t nwords, uint32_t G,
                     const uint32_t *__restrict__ gat_tgt, uint32_t ng,
                     const uint64_t *__restrict__ scr, const uint64_t *__restrict__ Grow,
                     unsigned int *__restrict__ left) {
-    using T = typename LaneT<LW>::T;
     // every row is G: the level changes nothing, and its gather launch may
     // have left scratch unwritten (the count only falls, so a count above 0
     // here means the gather launch before saw one too and wrote all of it)
     if (left && __builtin_amdgcn_readfirstlane(*left) == 0u) return;
     const uint32_t lane = threadIdx.x % G;
     const uint32_t ngroups = gridDim.x * (blockDim.x / G);
-    const uint32_t rounds = (ng + ngroups - 1) / ngroups;
     const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
-    for (uint32_t rr = 0; rr < rounds; ++rr) {
-        const uint32_t g = g0 + rr * ngroups;
-        bool was = true, is = true;
-        if (g < ng)
-            for (uint32_t w = lane * LW; w < nwords; w += G * LW) {
-                T *tp = (T *)(M + (size_t)gat_tgt[g] * nwords + w);
-                const T old = *tp;
-                const T nw = *(const T *)(scr + (size_t)g * nwords + w);
-                T gw = {};
-                if (Grow) gw = *(const T *)(Grow + w);
-                *tp = nw;
-                if (Grow) {
-                    was &= lane_eq<LW>(old, gw);
-                    is &= lane_eq<LW>(nw, gw);
-                }
-            }
-        if (Grow) {
-            const bool reached = group_all(is, G), before = group_all(was, G);
-            if (reached && !before && lane == 0 && g < ng) atomicSub(left, 1u);
-        }
-    }
+    // groups whose index passes ng have nothing to do: whole groups leave
+    for (uint32_t g = g0; g < ng; g += ngroups)
+        hll_gather_write<LW>(M, nwords, lane, G, gat_tgt[g], scr + (size_t)g * nwords, Grow, left);
 }
 
 // gmax[j] = the largest register j over every node's own registers.
@@ -346,11 +377,13 @@ hipError_t launch_hll_levels(const DevSchedule &s, const uint32_t *lvl_pair,
         const uint32_t p0 = lvl_pair[l], np = lvl_pair[l + 1] - p0;
         const uint32_t g0 = lvl_gat[l], ng = lvl_gat[l + 1] - g0;
         if (np + ng == 0) continue;
-        // a few gathers run in one group of the level's launch; many are
-        // spread over groups, then written by a second launch
-        const uint32_t inl = ng <= kHllInlineGathers ? 1u : 0u;
-        const size_t threads = (size_t)(np + (inl ? (ng > 0 ? 1u : 0u) : ng)) * G;
-        const uint32_t blocks = (uint32_t)std::min<size_t>((threads + 255) / 256, 4096);
+        // up to hll_block_gathers(G) gathers run in one extra workgroup of
+        // the level's launch; more are spread over groups, then written by a
+        // second launch
+        const uint32_t inl = ng <= hll_block_gathers(G) ? 1u : 0u;
+        const size_t threads = (size_t)(np + (inl ? 0u : ng)) * G;
+        const uint32_t blocks = (uint32_t)std::min<size_t>((threads + 255) / 256, 4096) +
+                                (inl && ng > 0 ? 1u : 0u);
         hipLaunchKernelGGL(k_hll_level<LW>, dim3(blocks), dim3(256), 0, st, M, nwords, G,
                            s.pairs + p0, np, s.gat_ptr + g0, s.gat_src, s.gat_tgt + g0, ng, inl,
                            scratch, Grow, left);

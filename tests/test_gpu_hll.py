@@ -86,6 +86,23 @@ def test_hll_errors():
     with pytest.raises(tn.TNError) as e:
         tn.hll_build(10, [0], [10], [0], T.hll_node_hashes(10, 1), 6)
     assert e.value.code == -2
+    # the register matrix must start on 16 bytes (rows move in 16-byte
+    # words): one 8 bytes past an allocation is refused before any launch
+    import ctypes
+    from paper_2307_04890_amd import _lib
+    n, b = 10, 6
+    ctx = tn.get_context()
+    h = torch.as_tensor(T.hll_node_hashes(n, 1).view(np.int64)).to(f"cuda:{ctx.device}")
+    M = torch.zeros(n * (1 << b) + 16, dtype=torch.uint8, device=h.device)
+    src, dst = np.array([0], np.uint32), np.array([1], np.uint32)
+    t = np.array([0], np.int64)
+    rc = _lib.lib.tn_hll_build(ctx.bind_stream(), n, 1, ctypes.c_void_p(src.ctypes.data),
+                               ctypes.c_void_p(dst.ctypes.data), ctypes.c_void_p(t.ctypes.data),
+                               0, b, ctypes.c_void_p(h.data_ptr()),
+                               ctypes.c_void_p(M.data_ptr() + 8), ctypes.c_void_p(0))
+    assert rc == -1
+    torch.cuda.synchronize()
+    assert int(M.sum()) == 0
 
 
 def test_hll_plan_graph_replays_with_other_work_between():
@@ -146,5 +163,34 @@ def test_saturating_streams_over_many_segments(flags):
                 for u in range(n):
                     G = np.maximum(G, hll.registers_of_set(h[u:u + 1], b))
                 assert (want == G).all()
+    finally:
+        ctx.saturation(True)
+
+
+@pytest.mark.parametrize("flags", [0, tn.DIRECTED, tn.FORWARD])
+def test_gather_levels_in_one_workgroup_and_in_two_launches(flags):
+    # star time steps on 600 nodes put from 1 to over 64 compound-item
+    # gathers in a level, of up to 10 sources each (several batches of four
+    # source reads): a level with at most 4 (256 / G) gathers runs them in
+    # one workgroup of its own launch, a wider one in a second launch; with
+    # 2^10 registers (G = 64 lanes, 16 gathers) and 2^8 (G = 16, 64) both
+    # kinds of level occur
+    n = 600
+    s, d, t = T.star_steps(n, 2000, 9, seed=2)
+    ng = np.diff(tn.host_schedule(n, s, d, t, flags)["lvl_gat"])
+    ctx = tn.get_context()
+    try:
+        for b, cap in ((10, 16), (8, 64)):
+            assert ((ng > 0) & (ng <= cap)).any() and (ng > cap).any(), b
+            h = T.hll_node_hashes(n, seed=90 + b)
+            want = hll.stream_registers(n, s, d, t, h, b, directed=bool(flags & tn.DIRECTED),
+                                        forward=bool(flags & tn.FORWARD))
+            p = tn.Plan(n, s, d, t, flags | tn.HLL)
+            for sat in (True, False):
+                ctx.saturation(sat)
+                M, est = p.hll(h, b)
+                assert (M.cpu().numpy() == want).all(), (b, sat)
+                assert np.allclose(est.cpu().numpy(), hll.estimate(want), rtol=1e-12, atol=0)
+            p.close()
     finally:
         ctx.saturation(True)
