@@ -14,6 +14,7 @@
 // with the tables of a chunk staged in LDS.
 #include <hip/hip_runtime.h>
 
+#include "tn_device.h"
 #include "tn_hash.h"
 
 namespace tn {
@@ -215,25 +216,32 @@ k_split_full(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bu
 }
 
 // est[u] += sum over the chunks q of this launch of popcount(AND_j Lt[q][j][h_j(u)]).
-// A workgroup owns kUPT nodes u per thread (blockIdx.x) and one of the
-// launch's ranges of `per` chunks (blockIdx.y); the counts of the ranges add
-// up in est (integer atomics, so the order does not matter); with LDS,
+// A workgroup owns kUPT nodes u per thread (a node block) and one of the
+// launch's ranges of `per` chunks; the counts of the ranges add up in est
+// (integer atomics, so the order does not matter).  Every node block stages
+// the same tables, so the workgroups of one chunk range are numbered
+// consecutively and given to one XCD (xcd_slice): they run there together
+// and read the tables through that XCD's L2 rather than each from HBM.  With
+// LDS,
 // the tables of G hashes of one chunk are staged in LDS at a time (K words
 // each), else (tables too large for LDS) they are read where they are, in
 // L2; the AND of a chunk is carried in registers across the hash groups.
 constexpr int kUPT = 8;
 constexpr int kQB = 2;
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
 constexpr uint32_t kRecombineThreads = 1024;
 template <bool LDS>
 __global__ void __launch_bounds__(kRecombineThreads)
 k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *__restrict__ bucket,
                 const uint64_t *__restrict__ Lt, uint32_t q_first, uint32_t q_last, uint32_t per,
-                uint32_t q0, const uint32_t *__restrict__ list, uint32_t nlist,
+                uint32_t q0, const uint32_t *__restrict__ list, uint32_t nlist, uint32_t ublocks,
                 int32_t *__restrict__ est) {
     extern __shared__ uint64_t tab[];
     const uint32_t tid = threadIdx.x;
-    const uint64_t ubase = (uint64_t)blockIdx.x * blockDim.x * kUPT;
-    const uint32_t q_begin = q_first + blockIdx.y * per;
+    const uint32_t L = xcd_slice(blockIdx.x, gridDim.x);
+    const uint64_t ubase = (uint64_t)(L % ublocks) * blockDim.x * kUPT;
+    const uint32_t q_begin = q_first + (L / ublocks) * per;
     const uint32_t q_end = min(q_last, q_begin + per);
     // uniform: the whole workgroup leaves
     if (ubase >= nlist || q_begin >= q_end) return;
@@ -273,8 +281,30 @@ k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *
                 const uint64_t *src = Lt + ((size_t)(qb + a - q0) * H + j0) * K;
                 const uint64_t *tb = src;
                 if (LDS) {
+                    // straight from memory into LDS, with no registers, so
+                    // every load of the stage is in flight at once: a wave's
+                    // 64 lanes fill 64 units from the wave's LDS base, lane l
+                    // at l units; 16-byte units where the tables start on 16
+                    // bytes (K even), else 4-byte ones; the barrier waits for
+                    // this wave's transfers, then for every wave's
                     __syncthreads();
-                    for (uint32_t i = tid; i < g * K; i += blockDim.x) tab[i] = src[i];
+                    const uint32_t lane = tid & 63u, wave = tid >> 6, waves = blockDim.x >> 6;
+                    if (K % 2 == 0) {
+                        const uint32_t units = g * K / 2;
+                        for (uint32_t c0 = wave * 64; c0 < units; c0 += waves * 64)
+                            if (c0 + lane < units)
+                                __builtin_amdgcn_global_load_lds(
+                                    (glb_void *)(src + 2 * (size_t)(c0 + lane)),
+                                    (lds_void *)(tab + 2 * (size_t)c0), 16, 0, 0);
+                    } else {
+                        const uint32_t units = g * K * 2;
+                        const uint32_t *s32 = (const uint32_t *)src;
+                        uint32_t *t32 = (uint32_t *)tab;
+                        for (uint32_t c0 = wave * 64; c0 < units; c0 += waves * 64)
+                            if (c0 + lane < units)
+                                __builtin_amdgcn_global_load_lds((glb_void *)(s32 + c0 + lane),
+                                                                 (lds_void *)(t32 + c0), 4, 0, 0);
+                    }
                     __syncthreads();
                     tb = tab;
                 }
@@ -398,8 +428,8 @@ hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32
     while ((size_t)utiles * splits < 1024 && splits * kQB * 2 <= nq) splits *= 2;
     const uint32_t per = ((nq + splits - 1) / splits + kQB - 1) / kQB * kQB;
     splits = (nq + per - 1) / per;
-    hipLaunchKernelGGL(kern, dim3(utiles, splits), dim3(threads), lds, st, n, H, K, G, bucket, Lt,
-                       q0, q0 + nq, per, q0, list, nlist, est);
+    hipLaunchKernelGGL(kern, dim3(utiles * splits), dim3(threads), lds, st, n, H, K, G, bucket, Lt,
+                       q0, q0 + nq, per, q0, list, nlist, utiles, est);
     return hipGetLastError();
 }
 

@@ -30,6 +30,9 @@ def run_hashed(n, s, d, t, H, K, seed, flags=0):
                                            (5000, 30000, 5, 1500, False),
                                            (3000, 12000, 2, 4096, False), (2000, 300, 2, 64, True),
                                            (3000, 250, 2, 40, True),
+                                           # odd K: tables staged in 4-byte units; H = 5
+                                           # leaves a group of one hash
+                                           (1200, 4000, 3, 45, False), (2500, 6000, 5, 999, False),
                                            # tables too large for LDS: read from global memory
                                            (1500, 3000, 2, 32768, False)])
 def test_hash_proxies_and_recombine_match_oracle(n, m, H, K, mixed):
