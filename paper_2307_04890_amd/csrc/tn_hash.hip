@@ -215,6 +215,35 @@ k_split_full(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bu
     }
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+
+// Tables of g hashes of one chunk (g K words at src) into LDS at dst,
+// straight from memory with no registers: a wave's 64 lanes fill 64 units
+// from the wave's LDS base, lane l at l units; 16-byte units where the
+// tables start on 16 bytes (K even), else 4-byte ones.  Completes at the
+// next barrier (which waits for the wave's own transfers).
+__device__ __forceinline__ void stage_tables(const uint64_t *src, uint32_t words, uint32_t K,
+                                             uint64_t *dst) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t waves = blockDim.x >> 6;
+    if (K % 2 == 0) {
+        const uint32_t units = words / 2;
+        for (uint32_t c0 = wave * 64; c0 < units; c0 += waves * 64)
+            if (c0 + lane < units)
+                __builtin_amdgcn_global_load_lds((glb_void *)(src + 2 * (size_t)(c0 + lane)),
+                                                 (lds_void *)(dst + 2 * (size_t)c0), 16, 0, 0);
+    } else {
+        const uint32_t units = words * 2;
+        const uint32_t *s32 = (const uint32_t *)src;
+        uint32_t *d32 = (uint32_t *)dst;
+        for (uint32_t c0 = wave * 64; c0 < units; c0 += waves * 64)
+            if (c0 + lane < units)
+                __builtin_amdgcn_global_load_lds((glb_void *)(s32 + c0 + lane),
+                                                 (lds_void *)(d32 + c0), 4, 0, 0);
+    }
+}
+
 // est[u] += sum over the chunks q of this launch of popcount(AND_j Lt[q][j][h_j(u)]).
 // A workgroup owns kUPT nodes u per thread (a node block) and one of the
 // launch's ranges of `per` chunks; the counts of the ranges add up in est
@@ -228,9 +257,8 @@ k_split_full(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bu
 // L2; the AND of a chunk is carried in registers across the hash groups.
 constexpr int kUPT = 8;
 constexpr int kQB = 2;
-typedef __attribute__((address_space(3))) void lds_void;
-typedef __attribute__((address_space(1))) void glb_void;
 constexpr uint32_t kRecombineThreads = 1024;
+constexpr size_t kRecombineLds = 160 * 1024;  // LDS of one CU
 template <bool LDS>
 __global__ void __launch_bounds__(kRecombineThreads)
 k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *__restrict__ bucket,
@@ -281,30 +309,8 @@ k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *
                 const uint64_t *src = Lt + ((size_t)(qb + a - q0) * H + j0) * K;
                 const uint64_t *tb = src;
                 if (LDS) {
-                    // straight from memory into LDS, with no registers, so
-                    // every load of the stage is in flight at once: a wave's
-                    // 64 lanes fill 64 units from the wave's LDS base, lane l
-                    // at l units; 16-byte units where the tables start on 16
-                    // bytes (K even), else 4-byte ones; the barrier waits for
-                    // this wave's transfers, then for every wave's
                     __syncthreads();
-                    const uint32_t lane = tid & 63u, wave = tid >> 6, waves = blockDim.x >> 6;
-                    if (K % 2 == 0) {
-                        const uint32_t units = g * K / 2;
-                        for (uint32_t c0 = wave * 64; c0 < units; c0 += waves * 64)
-                            if (c0 + lane < units)
-                                __builtin_amdgcn_global_load_lds(
-                                    (glb_void *)(src + 2 * (size_t)(c0 + lane)),
-                                    (lds_void *)(tab + 2 * (size_t)c0), 16, 0, 0);
-                    } else {
-                        const uint32_t units = g * K * 2;
-                        const uint32_t *s32 = (const uint32_t *)src;
-                        uint32_t *t32 = (uint32_t *)tab;
-                        for (uint32_t c0 = wave * 64; c0 < units; c0 += waves * 64)
-                            if (c0 + lane < units)
-                                __builtin_amdgcn_global_load_lds((glb_void *)(s32 + c0 + lane),
-                                                                 (lds_void *)(t32 + c0), 4, 0, 0);
-                    }
+                    stage_tables(src, g * K, K, tab);
                     __syncthreads();
                     tb = tab;
                 }
@@ -313,6 +319,114 @@ k_recombine_est(uint32_t n, uint32_t H, uint32_t K, uint32_t G, const uint32_t *
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj)
                         if (jj < (int)g) acc[a][k] &= tb[(size_t)jj * K + b[k][jj]];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < kQB; ++a)
+#pragma unroll
+            for (int k = 0; k < kUPT; ++k) cnt[k] += __popcll(acc[a][k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kUPT; ++k)
+        if (u[k] != 0xffffffffu && cnt[k]) atomicAdd(est + u[k], cnt[k]);
+}
+
+// The same sums as k_recombine_est with LDS, for tables of GB hashes whose
+// two copies fit in LDS together: while a stage (one chunk, one group of GB
+// hashes) is read from one buffer, the next stage's tables stream into the
+// other, and the next group's buckets are requested before them (loads
+// retire in order, so they must not queue behind the tables).
+template <int GB>
+__global__ void __launch_bounds__(kRecombineThreads)
+k_recombine_est2(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict__ bucket,
+                 const uint64_t *__restrict__ Lt, uint32_t q_first, uint32_t q_last, uint32_t per,
+                 uint32_t q0, const uint32_t *__restrict__ list, uint32_t nlist, uint32_t ublocks,
+                 int32_t *__restrict__ est) {
+    extern __shared__ uint64_t tab[];  // two buffers of GB K words
+    const uint32_t tid = threadIdx.x;
+    const uint32_t L = xcd_slice(blockIdx.x, gridDim.x);
+    const uint64_t ubase = (uint64_t)(L % ublocks) * blockDim.x * kUPT;
+    const uint32_t q_begin = q_first + (L / ublocks) * per;
+    const uint32_t q_end = min(q_last, q_begin + per);
+    // uniform: the whole workgroup leaves
+    if (ubase >= nlist || q_begin >= q_end) return;
+    uint32_t u[kUPT];
+    int32_t cnt[kUPT];
+#pragma unroll
+    for (int k = 0; k < kUPT; ++k) {
+        const uint64_t i = ubase + tid + (uint64_t)k * blockDim.x;
+        u[k] = i < nlist ? list[i] : 0xffffffffu;
+        cnt[k] = 0;
+    }
+    const uint32_t groups = (H + GB - 1) / GB;
+    const size_t bufw = (size_t)GB * K;
+    uint32_t bc[kUPT][GB], bn[kUPT][GB];
+    auto load_buckets = [&](uint32_t (&b)[kUPT][GB], uint32_t grp) {
+        const uint32_t g = min((uint32_t)GB, H - grp * GB);
+#pragma unroll
+        for (int k = 0; k < kUPT; ++k)
+#pragma unroll
+            for (int jj = 0; jj < GB; ++jj)
+                b[k][jj] = (u[k] != 0xffffffffu && jj < (int)g)
+                               ? bucket[(size_t)(grp * GB + jj) * n + u[k]]
+                               : 0u;
+    };
+    load_buckets(bc, 0);
+    stage_tables(Lt + (size_t)(q_begin - q0) * H * K, min((uint32_t)GB, H) * K, K, tab);
+    uint32_t buf = 0;
+    for (uint32_t qb = q_begin; qb < q_end; qb += kQB) {
+        const uint32_t nqb = min((uint32_t)kQB, q_end - qb);
+        uint64_t acc[kQB][kUPT];
+#pragma unroll
+        for (int a = 0; a < kQB; ++a) {
+            // nodes past n in the last chunk never count
+            const uint64_t first = (uint64_t)(qb + a) * 64;
+            const uint64_t valid = (a < (int)nqb && first < n)
+                                       ? ((n - first >= 64) ? ~0ull : ((1ull << (n - first)) - 1ull))
+                                       : 0ull;
+#pragma unroll
+            for (int k = 0; k < kUPT; ++k) acc[a][k] = valid;
+        }
+        for (uint32_t grp = 0; grp < groups; ++grp) {
+            const uint32_t g = min((uint32_t)GB, H - grp * GB);
+#pragma unroll
+            for (int a = 0; a < kQB; ++a) {
+                if (a >= (int)nqb) break;
+                // the stage after this one
+                const bool last_a = a + 1 == (int)nqb;
+                uint32_t qb2 = qb, grp2 = grp, a2 = a + 1;
+                if (last_a) {
+                    a2 = 0;
+                    grp2 = grp + 1;
+                    if (grp2 == groups) {
+                        grp2 = 0;
+                        qb2 = qb + kQB;
+                    }
+                }
+                const bool more = qb2 < q_end;
+                // this stage's tables are in, and every wave is done with
+                // the other buffer
+                __syncthreads();
+                if (more && last_a) load_buckets(bn, grp2);
+                if (more)
+                    stage_tables(Lt + ((size_t)(qb2 + a2 - q0) * H + grp2 * GB) * K,
+                                 min((uint32_t)GB, H - grp2 * GB) * K, K,
+                                 tab + (buf ^ 1u) * bufw);
+                const uint64_t *tb = tab + buf * bufw;
+#pragma unroll
+                for (int k = 0; k < kUPT; ++k)
+#pragma unroll
+                    for (int jj = 0; jj < GB; ++jj)
+                        if (jj < (int)g) acc[a][k] &= tb[(size_t)jj * K + bc[k][jj]];
+                if (more && last_a) {
+                    // after this stage's reads: the next group's buckets
+#pragma unroll
+                    for (int k = 0; k < kUPT; ++k)
+#pragma unroll
+                        for (int jj = 0; jj < GB; ++jj)
+                            asm volatile("" : "=v"(bc[k][jj]) : "0"(bn[k][jj]) : "memory");
+                }
+                buf ^= 1u;
             }
         }
 #pragma unroll
@@ -387,7 +501,7 @@ hipError_t launch_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, 
 // Hashes whose chunk tables fit in LDS together (at most 4); 0 when one
 // table does not fit, and the tables are read from global memory.
 uint32_t recombine_group(uint32_t K) {
-    const size_t budget = 160 * 1024;
+    const size_t budget = kRecombineLds;
     size_t g = budget / ((size_t)K * 8);
     if (g > 4) g = 4;
     return (uint32_t)g;
@@ -414,10 +528,18 @@ hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32
     const uint32_t GL = recombine_group(K);
     const bool in_lds = GL > 0;
     const uint32_t G = in_lds ? GL : 4u;
-    const size_t lds = in_lds ? (size_t)G * K * 8 : 0;
-    auto kern = in_lds ? k_recombine_est<true> : k_recombine_est<false>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // two copies of the tables of GB hashes when they fit (the next stage
+    // streams in while this one is read), else one copy of G hashes, else
+    // the tables are read where they are
+    const uint32_t GB = (size_t)K * 8 * 2 * 2 <= kRecombineLds ? 2u
+                      : (size_t)K * 8 * 2 <= kRecombineLds  ? 1u
+                                                            : 0u;
+    const size_t lds = GB ? (size_t)2 * GB * K * 8 : in_lds ? (size_t)G * K * 8 : 0;
+    const void *kern = GB == 2 ? (const void *)k_recombine_est2<2>
+                     : GB == 1 ? (const void *)k_recombine_est2<1>
+                     : in_lds  ? (const void *)k_recombine_est<true>
+                               : (const void *)k_recombine_est<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const uint32_t threads = kRecombineThreads;
     const uint32_t utiles = (uint32_t)((nlist + (size_t)threads * kUPT - 1) / ((size_t)threads * kUPT));
@@ -428,8 +550,18 @@ hipError_t launch_recombine_est(uint32_t n, uint32_t H, uint32_t K, const uint32
     while ((size_t)utiles * splits < 1024 && splits * kQB * 2 <= nq) splits *= 2;
     const uint32_t per = ((nq + splits - 1) / splits + kQB - 1) / kQB * kQB;
     splits = (nq + per - 1) / per;
-    hipLaunchKernelGGL(kern, dim3(utiles * splits), dim3(threads), lds, st, n, H, K, G, bucket, Lt,
-                       q0, q0 + nq, per, q0, list, nlist, utiles, est);
+    if (GB == 2)
+        hipLaunchKernelGGL(k_recombine_est2<2>, dim3(utiles * splits), dim3(threads), lds, st, n, H,
+                           K, bucket, Lt, q0, q0 + nq, per, q0, list, nlist, utiles, est);
+    else if (GB == 1)
+        hipLaunchKernelGGL(k_recombine_est2<1>, dim3(utiles * splits), dim3(threads), lds, st, n, H,
+                           K, bucket, Lt, q0, q0 + nq, per, q0, list, nlist, utiles, est);
+    else if (in_lds)
+        hipLaunchKernelGGL(k_recombine_est<true>, dim3(utiles * splits), dim3(threads), lds, st, n,
+                           H, K, G, bucket, Lt, q0, q0 + nq, per, q0, list, nlist, utiles, est);
+    else
+        hipLaunchKernelGGL(k_recombine_est<false>, dim3(utiles * splits), dim3(threads), lds, st, n,
+                           H, K, G, bucket, Lt, q0, q0 + nq, per, q0, list, nlist, utiles, est);
     return hipGetLastError();
 }
 

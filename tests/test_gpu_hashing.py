@@ -33,6 +33,10 @@ def run_hashed(n, s, d, t, H, K, seed, flags=0):
                                            # odd K: tables staged in 4-byte units; H = 5
                                            # leaves a group of one hash
                                            (1200, 4000, 3, 45, False), (2500, 6000, 5, 999, False),
+                                           # two copies of one hash's tables in LDS (the next
+                                           # chunk streams in while one is read); one copy
+                                           (2500, 10000, 3, 7000, False),
+                                           (2000, 8000, 2, 16000, False),
                                            # tables too large for LDS: read from global memory
                                            (1500, 3000, 2, 32768, False)])
 def test_hash_proxies_and_recombine_match_oracle(n, m, H, K, mixed):
