@@ -413,11 +413,21 @@ k_recombine_est2(uint32_t n, uint32_t H, uint32_t K, const uint32_t *__restrict_
                                  min((uint32_t)GB, H - grp2 * GB) * K, K,
                                  tab + (buf ^ 1u) * bufw);
                 const uint64_t *tb = tab + buf * bufw;
+                if (g == GB) {
+                    // a whole group: every read unconditional, so they can be
+                    // in flight together
 #pragma unroll
-                for (int k = 0; k < kUPT; ++k)
+                    for (int k = 0; k < kUPT; ++k)
 #pragma unroll
-                    for (int jj = 0; jj < GB; ++jj)
-                        if (jj < (int)g) acc[a][k] &= tb[(size_t)jj * K + bc[k][jj]];
+                        for (int jj = 0; jj < GB; ++jj)
+                            acc[a][k] &= tb[(size_t)jj * K + bc[k][jj]];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kUPT; ++k)
+#pragma unroll
+                        for (int jj = 0; jj < GB; ++jj)
+                            if (jj < (int)g) acc[a][k] &= tb[(size_t)jj * K + bc[k][jj]];
+                }
                 if (more && last_a) {
                     // after this stage's reads: the next group's buckets
 #pragma unroll
