@@ -154,29 +154,38 @@ k_lifted_sizes(uint32_t n, uint32_t H, const uint32_t *__restrict__ bucket,
 }
 
 // Lt[(q - q0) * H * K + j * K + r], bit i = P_j[r][h_j(64 q + i)] (0 past n):
-// one wavefront per (q, j, 64-row block); lane i gathers word br of the
-// transposed proxy row h_j(64 q + i), then the block is transposed.
+// one wavefront per (q, j, run of kLiftRun 64-row blocks); lane i gathers
+// words br of the transposed proxy row h_j(64 q + i) for the run's blocks
+// (consecutive words of one row, so the loads after the first hit the
+// sector it brought in), then each block is transposed and written.
+constexpr uint32_t kLiftRun = 8;
 __global__ void __launch_bounds__(256)
 k_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ PT,
                const uint32_t *__restrict__ bucket, uint32_t q0, uint32_t nq,
                uint64_t *__restrict__ Lt) {
     const uint32_t kw = (K + 63) / 64;
-    const size_t jobs = (size_t)nq * H * kw;
+    const uint32_t runs = (kw + kLiftRun - 1) / kLiftRun;
+    const size_t jobs = (size_t)nq * H * runs;
     const uint32_t lane = threadIdx.x & 63u;
     for (size_t job = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; job < jobs;
          job += ((size_t)gridDim.x * blockDim.x) >> 6) {
-        const uint32_t br = (uint32_t)(job % kw);
-        const uint32_t j = (uint32_t)((job / kw) % H);
-        const uint32_t qq = (uint32_t)(job / ((size_t)kw * H));
+        const uint32_t br0 = (uint32_t)(job % runs) * kLiftRun;
+        const uint32_t j = (uint32_t)((job / runs) % H);
+        const uint32_t qq = (uint32_t)(job / ((size_t)runs * H));
         const uint64_t w = (uint64_t)(q0 + qq) * 64 + lane;
-        uint64_t x = 0;
-        if (w < n) {
-            const uint32_t c = bucket[(size_t)j * n + w];
-            x = PT[(size_t)j * K * ldK + (size_t)c * ldK + br];
+        uint64_t x[kLiftRun];
+        const uint64_t *row = nullptr;
+        if (w < n) row = PT + (size_t)j * K * ldK + (size_t)bucket[(size_t)j * n + w] * ldK;
+#pragma unroll
+        for (uint32_t t = 0; t < kLiftRun; ++t)
+            x[t] = (row && br0 + t < kw) ? row[br0 + t] : 0ull;
+#pragma unroll
+        for (uint32_t t = 0; t < kLiftRun; ++t) {
+            if (br0 + t >= kw) break;  // uniform: the whole wave
+            const uint64_t y = wave_transpose64(x[t]);
+            const uint32_t r = (br0 + t) * 64 + lane;
+            if (r < K) Lt[((size_t)qq * H + j) * K + r] = y;
         }
-        const uint64_t y = wave_transpose64(x);
-        const uint32_t r = br * 64 + lane;
-        if (r < K) Lt[((size_t)qq * H + j) * K + r] = y;
     }
 }
 
@@ -503,7 +512,8 @@ hipError_t launch_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, 
                                const uint32_t *bucket, uint32_t q0, uint32_t nq, uint64_t *Lt,
                                hipStream_t st) {
     const size_t kw = (K + 63) / 64;
-    hipLaunchKernelGGL(k_build_lifted, dim3(grid_for((size_t)nq * H * kw * 64, 256)), dim3(256), 0,
+    const size_t runs = (kw + kLiftRun - 1) / kLiftRun;
+    hipLaunchKernelGGL(k_build_lifted, dim3(grid_for((size_t)nq * H * runs * 64, 256)), dim3(256), 0,
                        st, n, H, K, ldK, PT, bucket, q0, nq, Lt);
     return hipGetLastError();
 }
