@@ -611,8 +611,10 @@ tn_status tn_recombine(tn_ctx *ctx, uint32_t n, uint32_t H, uint32_t K, const ui
     const size_t rs_bytes = align256((size_t)H * K * 4);
     const size_t full_bytes = align256((size_t)H * K);
     const size_t list_bytes = align256((size_t)n * 4 + 4);
+    const size_t bs_bytes = align256((size_t)H * ((K + 63) / 64) * 4);
     const size_t lt_bytes = align256((size_t)qr * per_q);
-    tn_status st = ensure_scratch(ctx, pt_bytes + rs_bytes + full_bytes + list_bytes + lt_bytes);
+    tn_status st =
+        ensure_scratch(ctx, pt_bytes + rs_bytes + full_bytes + list_bytes + bs_bytes + lt_bytes);
     if (st != TN_OK) return st;
     unsigned char *base = (unsigned char *)ctx->scratch;
     uint64_t *PT = (uint64_t *)base;
@@ -620,21 +622,31 @@ tn_status tn_recombine(tn_ctx *ctx, uint32_t n, uint32_t H, uint32_t K, const ui
     uint8_t *full = base + pt_bytes + rs_bytes;
     uint32_t *list = (uint32_t *)(base + pt_bytes + rs_bytes + full_bytes);
     uint32_t *nlist_dev = list + n;
-    uint64_t *Lt = (uint64_t *)(base + pt_bytes + rs_bytes + full_bytes + list_bytes);
+    int32_t *bsum = (int32_t *)(base + pt_bytes + rs_bytes + full_bytes + list_bytes);
+    uint64_t *Lt = (uint64_t *)(base + pt_bytes + rs_bytes + full_bytes + list_bytes + bs_bytes);
     hipError_t e;
     uint32_t nlist = 0;
     {
         ProfScope ps(ctx, TN_K_AUX);
-        e = launch_transpose_proxies(H, K, ldK, P, PT, ctx->stream);
+        // one pass over the proxies: full rows, and the lifted row sums
+        e = launch_row_sums_full(H, K, ldK, P, count, bsum, lifted ? rowsum : nullptr, full,
+                                 ctx->stream);
         if (e == hipSuccess && lifted)
-            e = launch_lifted_sizes(n, H, K, ldK, P, bucket, count, rowsum, lifted, ctx->stream);
+            e = launch_lifted_sizes(n, H, K, bucket, rowsum, lifted, ctx->stream);
         if (e == hipSuccess)
-            e = launch_split_full(n, H, K, ldK, P, bucket, full, est, list, nlist_dev, ctx->stream);
+            e = launch_split_full(n, H, K, bucket, full, est, list, nlist_dev, ctx->stream);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(&nlist, nlist_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "recombine set-up kernels");
+    // the transposed proxies feed the lifted tables only: none are needed
+    // when every node's proxy rows are full in every hash (est = n)
+    if (nlist > 0) {
+        ProfScope ps(ctx, TN_K_AUX);
+        e = launch_transpose_proxies(H, K, ldK, P, PT, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "proxy transpose launch");
+    }
     for (uint32_t q0 = 0; nlist > 0 && q0 < nq; q0 += qr) {
         const uint32_t cnt = std::min(qr, nq - q0);
         {

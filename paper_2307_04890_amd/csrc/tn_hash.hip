@@ -97,48 +97,104 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
     return x;
 }
 
-// PT_j = transpose of P_j (K x K bits): one wavefront per 64 x 64 block.
+// PT_j = transpose of P_j (K x K bits): one wavefront per run of kLiftRun
+// 64 x 64 blocks along a row block; lane i reads kLiftRun consecutive words
+// of row 64 br + i (the loads after the first hit the sector the first
+// brought in), then each block is transposed and written.
+constexpr uint32_t kLiftRun = 8;
 __global__ void __launch_bounds__(256)
 k_transpose_proxies(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ P,
                     uint64_t *__restrict__ PT) {
     const uint32_t kw = (K + 63) / 64;
-    const size_t blocks = (size_t)H * kw * kw;
+    const uint32_t runs = (kw + kLiftRun - 1) / kLiftRun;
+    const size_t jobs = (size_t)H * kw * runs;
     const uint32_t lane = threadIdx.x & 63u;
-    for (size_t bidx = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; bidx < blocks;
-         bidx += ((size_t)gridDim.x * blockDim.x) >> 6) {
-        const uint32_t j = (uint32_t)(bidx / ((size_t)kw * kw));
-        const uint32_t rem = (uint32_t)(bidx - (size_t)j * kw * kw);
-        const uint32_t br = rem / kw, bc = rem % kw;  // row block, column-word block
+    for (size_t job = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; job < jobs;
+         job += ((size_t)gridDim.x * blockDim.x) >> 6) {
+        const uint32_t j = (uint32_t)(job / ((size_t)kw * runs));
+        const uint32_t rem = (uint32_t)(job - (size_t)j * kw * runs);
+        const uint32_t br = rem / runs, bc0 = rem % runs * kLiftRun;  // row block, first word block
         const uint64_t *Pj = P + (size_t)j * K * ldK;
         const uint32_t r = br * 64 + lane;
-        const uint64_t x = r < K ? Pj[(size_t)r * ldK + bc] : 0ull;
-        const uint64_t y = wave_transpose64(x);  // lane b: bits r of column 64*bc + b
-        const uint32_t c = bc * 64 + lane;
-        if (c < K) PT[(size_t)j * K * ldK + (size_t)c * ldK + br] = y;
+        uint64_t x[kLiftRun];
+#pragma unroll
+        for (uint32_t t = 0; t < kLiftRun; ++t)
+            x[t] = (r < K && bc0 + t < kw) ? Pj[(size_t)r * ldK + bc0 + t] : 0ull;
+#pragma unroll
+        for (uint32_t t = 0; t < kLiftRun; ++t) {
+            if (bc0 + t >= kw) break;  // uniform: the whole wave
+            const uint64_t y = wave_transpose64(x[t]);  // lane b: bits r of column 64 (bc0 + t) + b
+            const uint32_t c = (bc0 + t) * 64 + lane;
+            if (c < K) PT[(size_t)j * K * ldK + (size_t)c * ldK + br] = y;
+        }
     }
 }
 
-// rowsum[j][r] = sum of count[j][r'] over the super-nodes r' set in row r of P_j.
+// bsum[j][wd] = sum of count[j][c] over the 64 super-nodes c of word wd
+// (those below K): one wavefront per (j, wd).
 __global__ void __launch_bounds__(256)
-k_lifted_row_sums(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ P,
-                  const int32_t *__restrict__ count, int32_t *__restrict__ rowsum) {
+k_block_sums(uint32_t H, uint32_t K, const int32_t *__restrict__ count, int32_t *__restrict__ bsum) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t kw = (K + 63) / 64;
+    const size_t blocks = (size_t)H * kw;
+    for (size_t b = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < blocks;
+         b += ((size_t)gridDim.x * blockDim.x) >> 6) {
+        const uint32_t j = (uint32_t)(b / kw), c = (uint32_t)(b % kw) * 64 + lane;
+        int32_t v = c < K ? count[(size_t)j * K + c] : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) bsum[b] = v;
+    }
+}
+
+// One pass over every proxy row r of P_j, one wavefront per row, its lanes
+// on consecutive words: full[j][r] = 1 iff the row has all K bits set, and
+// (rowsum not NULL) rowsum[j][r] = sum of count[j][c] over the super-nodes
+// c set in the row.  A full word adds its block sum, an empty one nothing,
+// and each other word one count load per lane (lane l: super-node 64 wd + l).
+__global__ void __launch_bounds__(256)
+k_row_sums_full(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ P,
+                const int32_t *__restrict__ count, const int32_t *__restrict__ bsum,
+                int32_t *__restrict__ rowsum, uint8_t *__restrict__ full) {
     const uint32_t lane = threadIdx.x & 63u;
     const size_t rows = (size_t)H * K;
     const uint32_t kw = (K + 63) / 64;
+    const uint64_t last = (K % 64) ? ((1ull << (K % 64)) - 1ull) : ~0ull;
     for (size_t row = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < rows;
          row += ((size_t)gridDim.x * blockDim.x) >> 6) {
         const uint32_t j = (uint32_t)(row / K);
         const uint64_t *Pr = P + (size_t)j * K * ldK + (row - (size_t)j * K) * ldK;
         const int32_t *cj = count + (size_t)j * K;
         int32_t acc = 0;
-        for (uint32_t wd = 0; wd < kw; ++wd) {
-            const uint64_t word = Pr[wd];
-            const uint32_t c = wd * 64 + lane;
-            if (c < K && ((word >> lane) & 1ull)) acc += cj[c];
+        bool all = true;
+        for (uint32_t wd0 = 0; wd0 < kw; wd0 += 64) {
+            const uint32_t wd = wd0 + lane;
+            const uint64_t word = wd < kw ? Pr[wd] : 0ull;
+            const bool fullw = wd < kw && word == (wd + 1 == kw ? last : ~0ull);
+            all &= wd >= kw || fullw;
+            if (!rowsum) continue;
+            if (fullw) acc += bsum[(size_t)j * kw + wd];
+            // the other non-empty words, one at a time over the wavefront
+            uint64_t partial = __ballot(wd < kw && word != 0ull && !fullw);
+            while (partial) {
+                const uint32_t p = (uint32_t)__builtin_ctzll(partial);
+                partial &= partial - 1ull;
+                const uint64_t wp =
+                    ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(word >> 32), (int)p) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)word, (int)p);
+                const uint32_t c = (wd0 + p) * 64 + lane;
+                if (c < K && ((wp >> lane) & 1ull)) acc += cj[c];
+            }
         }
+        const bool row_full = __ballot(!all) == 0ull;
+        if (rowsum) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) rowsum[row] = acc;
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        }
+        if (lane == 0) {
+            if (rowsum) rowsum[row] = acc;
+            full[row] = row_full ? 1 : 0;
+        }
     }
 }
 
@@ -158,7 +214,6 @@ k_lifted_sizes(uint32_t n, uint32_t H, const uint32_t *__restrict__ bucket,
 // words br of the transposed proxy row h_j(64 q + i) for the run's blocks
 // (consecutive words of one row, so the loads after the first hit the
 // sector it brought in), then each block is transposed and written.
-constexpr uint32_t kLiftRun = 8;
 __global__ void __launch_bounds__(256)
 k_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ PT,
                const uint32_t *__restrict__ bucket, uint32_t q0, uint32_t nq,
@@ -186,23 +241,6 @@ k_build_lifted(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *
             const uint32_t r = (br0 + t) * 64 + lane;
             if (r < K) Lt[((size_t)qq * H + j) * K + r] = y;
         }
-    }
-}
-
-// full[j * K + r] = 1 iff row r of P_j has all K bits set.
-__global__ void __launch_bounds__(256)
-k_rows_full(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *__restrict__ P,
-            uint8_t *__restrict__ full) {
-    const size_t rows = (size_t)H * K;
-    const uint32_t kw = (K + 63) / 64;
-    const uint64_t last = (K % 64) ? ((1ull << (K % 64)) - 1ull) : ~0ull;
-    for (size_t row = (size_t)blockIdx.x * blockDim.x + threadIdx.x; row < rows;
-         row += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t j = (uint32_t)(row / K);
-        const uint64_t *Pr = P + (size_t)j * K * ldK + (row - (size_t)j * K) * ldK;
-        bool all = true;
-        for (uint32_t wd = 0; wd + 1 < kw && all; ++wd) all = Pr[wd] == ~0ull;
-        full[row] = (all && Pr[kw - 1] == last) ? 1 : 0;
     }
 }
 
@@ -486,18 +524,29 @@ hipError_t launch_hash_buckets(uint32_t n, uint32_t H, const uint64_t *coeffs, i
 hipError_t launch_transpose_proxies(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
                                     uint64_t *PT, hipStream_t st) {
     const size_t kw = (K + 63) / 64;
-    hipLaunchKernelGGL(k_transpose_proxies, dim3(grid_for((size_t)H * kw * kw * 64, 256)), dim3(256),
+    const size_t runs = (kw + kLiftRun - 1) / kLiftRun;
+    hipLaunchKernelGGL(k_transpose_proxies, dim3(grid_for((size_t)H * kw * runs * 64, 256)), dim3(256),
                        0, st, H, K, ldK, P, PT);
     return hipGetLastError();
 }
 
-hipError_t launch_lifted_sizes(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
-                               const uint32_t *bucket, const int32_t *count, int32_t *rowsum,
-                               int32_t *lifted, hipStream_t st) {
-    hipLaunchKernelGGL(k_lifted_row_sums, dim3(grid_for((size_t)H * K * 64, 256)), dim3(256), 0, st,
-                       H, K, ldK, P, count, rowsum);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_row_sums_full(uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
+                               const int32_t *count, int32_t *bsum, int32_t *rowsum, uint8_t *full,
+                               hipStream_t st) {
+    const size_t kw = (K + 63) / 64;
+    if (rowsum) {
+        hipLaunchKernelGGL(k_block_sums, dim3(grid_for((size_t)H * kw * 64, 256)), dim3(256), 0, st,
+                           H, K, count, bsum);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_row_sums_full, dim3(grid_for((size_t)H * K * 64, 256)), dim3(256), 0, st, H,
+                       K, ldK, P, count, bsum, rowsum, full);
+    return hipGetLastError();
+}
+
+hipError_t launch_lifted_sizes(uint32_t n, uint32_t H, uint32_t K, const uint32_t *bucket,
+                               const int32_t *rowsum, int32_t *lifted, hipStream_t st) {
     hipLaunchKernelGGL(k_lifted_sizes, dim3(grid_for((size_t)n * H, 256)), dim3(256), 0, st, n, H,
                        bucket, rowsum, K, lifted);
     return hipGetLastError();
@@ -527,15 +576,11 @@ uint32_t recombine_group(uint32_t K) {
     return (uint32_t)g;
 }
 
-hipError_t launch_split_full(uint32_t n, uint32_t H, uint32_t K, int64_t ldK, const uint64_t *P,
-                             const uint32_t *bucket, uint8_t *full, int32_t *est, uint32_t *list,
-                             uint32_t *count, hipStream_t st) {
+hipError_t launch_split_full(uint32_t n, uint32_t H, uint32_t K, const uint32_t *bucket,
+                             const uint8_t *full, int32_t *est, uint32_t *list, uint32_t *count,
+                             hipStream_t st) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (int32_t *)count, (size_t)1);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_full, dim3(grid_for((size_t)H * K, 256)), dim3(256), 0, st, H, K, ldK,
-                       P, full);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_split_full, dim3(grid_for(n, 256)), dim3(256), 0, st, n, H, K, bucket, full,
                        est, list, count);
